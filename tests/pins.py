@@ -1,0 +1,299 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` takes an oracle object (``oracle.Oracle``) and raises
+AssertionError when the oracle disagrees.  They are used twice: on the real
+oracle (tests/test_oracle_pins.py) and on copies of it with a planted mistake
+(tests/test_oracle_mutants.py), where at least one pin must fail.
+
+None of these compares the oracle with a retyping of its own formula in the
+same precision: the references are 50-digit mpmath evaluations of the
+paper's equations, exact floating-point identities, scipy's Gaussian
+log-density, and structural properties of the model (region permutation
+symmetry and the strict nesting of Sec. 4).
+"""
+from __future__ import annotations
+
+import math
+
+import mpmath as mp
+import numpy as np
+from scipy import stats
+
+NO_21CM = 1
+mp.mp.dps = 50
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _rand_problem(rng, N, F, T, lo=50.0, hi=200.0):
+    K = rng.lognormal(math.log(10.0), 0.7, size=(N, F, T)).astype(np.float32)
+    freqs = np.sort(rng.uniform(lo, hi, size=F))
+    return K, freqs
+
+
+def _rand_theta(rng, N, B=1):
+    th = np.empty((B, N + 4))
+    th[:, :N] = rng.uniform(2.0, 3.5, size=(B, N))
+    th[:, N] = rng.uniform(-0.5, 0.0, size=B)
+    th[:, N + 1] = rng.uniform(50, 200, size=B)
+    th[:, N + 2] = rng.uniform(5, 40, size=B)
+    th[:, N + 3] = np.exp(rng.uniform(math.log(1e-3), math.log(0.1), size=B))
+    return th
+
+
+def mp_model(K, freqs, nu_ref, t_cmb, th, no21=False):
+    """50-digit evaluation of Eqs. fast_forward_model and t21model."""
+    N, F, T = K.shape
+    beta = [mp.mpf(float(b)) for b in th[:N]]
+    out = [[None] * T for _ in range(F)]
+    for f in range(F):
+        nu = mp.mpf(float(freqs[f]))
+        x = nu / mp.mpf(float(nu_ref))
+        p = [mp.power(x, -b) for b in beta]
+        s21 = mp.mpf(0)
+        if not no21:
+            A, nu0, w = (mp.mpf(float(v)) for v in th[N:N + 3])
+            s21 = A * mp.exp(-(nu - nu0) ** 2 / (2 * w * w))
+        for t in range(T):
+            acc = mp.mpf(0)
+            for i in range(N):
+                acc += mp.mpf(float(K[i, f, t])) * p[i]
+            out[f][t] = acc + mp.mpf(float(t_cmb)) + s21
+    return out
+
+
+def mp_loglike(K, freqs, D, nu_ref, t_cmb, th, no21=False):
+    """50-digit evaluation of Eq. likelihood."""
+    N, F, T = K.shape
+    m = mp_model(K, freqs, nu_ref, t_cmb, th, no21)
+    sig = mp.mpf(float(th[-1]))
+    chi2 = mp.mpf(0)
+    for f in range(F):
+        for t in range(T):
+            r = mp.mpf(float(D[f, t])) - m[f][t]
+            chi2 += r * r
+    n = F * T
+    return -chi2 / (2 * sig * sig) - mp.mpf(n) / 2 * mp.log(2 * mp.pi * sig * sig)
+
+
+def _relerr(a, b):
+    return abs(float(a) - float(b)) / max(abs(float(b)), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+
+def pin_brute_force(orc, seeds=range(6)):
+    """Tiny random problems (N<=3, F<=4, T<=3) against 50-digit mpmath:
+    relative error of lnL <= 1e-13 and of every model value <= 1e-14."""
+    for s in seeds:
+        rng = _rng(100 + s)
+        N, F, T = int(rng.integers(1, 4)), int(rng.integers(1, 5)), int(rng.integers(1, 4))
+        K, freqs = _rand_problem(rng, N, F, T)
+        th = _rand_theta(rng, N, 3)
+        D = rng.normal(30.0, 10.0, size=(F, T))
+        got = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+        for b in range(3):
+            ref = mp_loglike(K, freqs, D, 230.0, 2.725, th[b])
+            assert _relerr(got[b], ref) <= 1e-13, (s, b, got[b], float(ref))
+            m = orc.model(K, freqs, 230.0, 2.725, th[b])
+            mref = mp_model(K, freqs, 230.0, 2.725, th[b])
+            for f in range(F):
+                for t in range(T):
+                    assert _relerr(m[f, t], mref[f][t]) <= 1e-14, (s, f, t)
+
+
+def pin_n1_closed_form(orc):
+    """N = 1: M = c (nu/nu_ref)^(-beta) + T_CMB + A exp(-(nu-nu0)^2/(2w^2)),
+    checked value by value against mpmath on a 151-channel band, T = 2."""
+    rng = _rng(7)
+    freqs = np.linspace(50.0, 200.0, 151)
+    c = np.float32(123.25)
+    K = np.full((1, 151, 2), c, dtype=np.float32)
+    K[0, :, 1] = np.float32(0.5)
+    th = np.array([2.71, -0.2, 95.0, 12.5, 0.03])
+    m = orc.model(K, freqs, 230.0, 2.725, th)
+    for f in range(0, 151, 10):
+        nu = mp.mpf(float(freqs[f]))
+        for t, cc in ((0, c), (1, np.float32(0.5))):
+            ref = (mp.mpf(float(cc)) * mp.power(nu / 230, -mp.mpf("2.71")) + mp.mpf("2.725")
+                   + mp.mpf("-0.2") * mp.exp(-(nu - 95) ** 2 / (2 * mp.mpf("12.5") ** 2)))
+            assert _relerr(m[f, t], ref) <= 1e-14, (f, t)
+
+
+def pin_unit_power(orc):
+    """beta = 0, or nu = nu_ref: every power is exactly one, so the
+    foreground is the plain region sum of K (exactly summed with fsum, then
+    rounded) and M = sum_i K + T_CMB."""
+    rng = _rng(11)
+    N, F, T = 5, 7, 3
+    K, freqs = _rand_problem(rng, N, F, T)
+    th = np.zeros(N + 1)
+    th[-1] = 0.1
+    m = orc.model(K, freqs, 230.0, 2.725, th, flags=NO_21CM)
+    for f in range(F):
+        for t in range(T):
+            s = math.fsum([float(K[i, f, t]) for i in range(N)])
+            assert abs(m[f, t] - (s + 2.725)) <= 4e-16 * (s + 2.725) * N, (f, t)
+    th2 = np.concatenate([rng.uniform(2, 3.5, N), [0.1]])
+    m2 = orc.model(K, np.full(F, 230.0), 230.0, 2.725, th2, flags=NO_21CM)
+    for f in range(F):
+        for t in range(T):
+            s = math.fsum([float(K[i, f, t]) for i in range(N)])
+            assert abs(m2[f, t] - (s + 2.725)) <= 4e-16 * (s + 2.725) * N
+
+
+def pin_t21_profile(orc):
+    """K = 0: M = T_CMB + A exp(-(nu-nu0)^2/(2 w^2)) (Eq. t21model): at
+    nu = nu0 the profile is A; at nu0 +- w it is A e^(-1/2); at nu0 +- 2w it
+    is A e^(-2); the sign of A is kept."""
+    freqs = np.array([60.0, 70.0, 80.0, 90.0, 100.0])
+    K = np.zeros((2, 5, 1), dtype=np.float32)
+    th = np.array([2.5, 3.0, -0.25, 80.0, 10.0, 0.05])
+    m = orc.model(K, freqs, 230.0, 2.725, th)[:, 0] - 2.725
+    want = -0.25 * np.exp(-0.5 * np.array([4.0, 1.0, 0.0, 1.0, 4.0]))
+    assert np.allclose(m, want, rtol=1e-14, atol=1e-16), (m, want)
+
+
+def pin_linearity(orc):
+    """The foreground is linear in K: with T_CMB = 0 and no 21-cm term,
+    doubling K doubles M exactly (every operation scales by two), and
+    M(K1 + K2) = M(K1) + M(K2) to rounding for K1, K2 whose FP32 sum is
+    exact."""
+    rng = _rng(13)
+    N, F, T = 4, 9, 5
+    K, freqs = _rand_problem(rng, N, F, T)
+    th = np.concatenate([rng.uniform(2, 3.5, N), [0.05]])
+    m1 = orc.model(K, freqs, 230.0, 0.0, th, flags=NO_21CM)
+    m2 = orc.model(2 * K, freqs, 230.0, 0.0, th, flags=NO_21CM)
+    assert np.array_equal(m2, 2 * m1)
+    Ka = rng.integers(1, 4096, size=(N, F, T)).astype(np.float32)
+    Kb = rng.integers(1, 4096, size=(N, F, T)).astype(np.float32)
+    ma = orc.model(Ka, freqs, 230.0, 0.0, th, flags=NO_21CM)
+    mb = orc.model(Kb, freqs, 230.0, 0.0, th, flags=NO_21CM)
+    mab = orc.model(Ka + Kb, freqs, 230.0, 0.0, th, flags=NO_21CM)
+    assert np.allclose(mab, ma + mb, rtol=1e-14, atol=0)
+
+
+def pin_permutation(orc):
+    """Relabelling the regions (K and beta permuted together) leaves M and
+    lnL unchanged up to the rounding of the reordered region sum."""
+    rng = _rng(17)
+    N, F, T = 6, 11, 4
+    K, freqs = _rand_problem(rng, N, F, T)
+    th = _rand_theta(rng, N, 4)
+    D = rng.normal(200.0, 50.0, size=(F, T))
+    perm = rng.permutation(N)
+    Kp = np.ascontiguousarray(K[perm])
+    thp = th.copy()
+    thp[:, :N] = th[:, perm]
+    a = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+    b = orc.loglike(Kp, freqs, D, 230.0, 2.725, thp)
+    assert np.allclose(a, b, rtol=1e-12, atol=0), (a, b)
+    ma = orc.model(K, freqs, 230.0, 2.725, th[0])
+    mb = orc.model(Kp, freqs, 230.0, 2.725, thp[0])
+    assert np.allclose(ma, mb, rtol=1e-14, atol=0)
+    # a permutation that is not applied to beta must change the model
+    thq = th[0].copy()
+    mc = orc.model(Kp, freqs, 230.0, 2.725, thq)
+    assert not np.allclose(ma, mc, rtol=1e-6)
+
+
+def pin_nesting(orc):
+    """Strict nesting (Sec. 4): splitting region j into two regions with
+    K/2 each (exact in FP32) and the same spectral index leaves M unchanged
+    up to rounding, for every j."""
+    rng = _rng(19)
+    N, F, T = 4, 13, 3
+    K, freqs = _rand_problem(rng, N, F, T)
+    th = _rand_theta(rng, N, 1)[0]
+    m0 = orc.model(K, freqs, 230.0, 2.725, th)
+    for j in range(N):
+        Ks = np.concatenate([K[:j], K[j:j + 1] * np.float32(0.5),
+                             K[j:j + 1] * np.float32(0.5), K[j + 1:]])
+        ths = np.concatenate([th[:j], [th[j], th[j]], th[j + 1:]])
+        m1 = orc.model(np.ascontiguousarray(Ks), freqs, 230.0, 2.725, ths)
+        assert np.allclose(m1, m0, rtol=2e-15, atol=0), j
+
+
+def pin_gaussian_library(orc):
+    """Eq. likelihood is the textbook Gaussian: lnL equals the sum of
+    scipy.stats.norm.logpdf(D, M, sigma), with M taken value by value from
+    the 50-digit model."""
+    rng = _rng(23)
+    N, F, T = 3, 6, 4
+    K, freqs = _rand_problem(rng, N, F, T)
+    th = _rand_theta(rng, N, 2)
+    th[:, -1] = [0.7, 2.5]
+    D = rng.normal(100.0, 20.0, size=(F, T))
+    got = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+    for b in range(2):
+        mm = mp_model(K, freqs, 230.0, 2.725, th[b])
+        M = np.array([[float(mm[f][t]) for t in range(T)] for f in range(F)])
+        ref = math.fsum(stats.norm.logpdf(D, M, th[b, -1]).ravel())
+        assert _relerr(got[b], ref) <= 1e-11, (b, got[b], ref)
+
+
+def pin_noise_free(orc):
+    """D = M(theta*) exactly: chi-square is zero, so
+    lnL(theta*) = -FT/2 ln(2 pi sigma^2) in closed form; with
+    D = M(theta*) + delta, lnL = -FT delta^2/(2 sigma^2) - FT/2 ln(2 pi sigma^2)."""
+    rng = _rng(29)
+    N, F, T = 5, 17, 6
+    K, freqs = _rand_problem(rng, N, F, T)
+    th = _rand_theta(rng, N, 1)[0]
+    th[-1] = 0.025
+    D = orc.model(K, freqs, 230.0, 2.725, th)
+    got = orc.loglike(K, freqs, D, 230.0, 2.725, th[None])[0]
+    n = F * T
+    ref = -0.5 * n * float(mp.log(2 * mp.pi * mp.mpf("0.025") ** 2))
+    assert _relerr(got, ref) <= 1e-14, (got, ref)
+    delta = 0.01
+    got2 = orc.loglike(K, freqs, D + delta, 230.0, 2.725, th[None])[0]
+    ref2 = -n * delta ** 2 / (2 * 0.025 ** 2) + ref
+    assert _relerr(got2, ref2) <= 1e-9, (got2, ref2)
+
+
+def pin_invalid_rows(orc):
+    """Rows with sigma <= 0, w <= 0 or a non-finite entry give -inf; the
+    other rows of the same batch are unaffected; without the 21-cm term
+    the width is not a parameter."""
+    rng = _rng(31)
+    N, F, T = 2, 5, 2
+    K, freqs = _rand_problem(rng, N, F, T)
+    D = rng.normal(50.0, 5.0, size=(F, T))
+    th = _rand_theta(rng, N, 6)
+    th[1, -1] = 0.0
+    th[2, N + 2] = -1.0
+    th[3, 0] = np.nan
+    th[4, N] = np.inf
+    got = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+    assert np.isfinite(got[0]) and np.isfinite(got[5])
+    assert np.all(got[1:5] == -np.inf), got
+    ok = orc.loglike(K, freqs, D, 230.0, 2.725, th[[0, 5]])
+    assert np.array_equal(ok, got[[0, 5]])
+    th2 = np.array([[2.5, 2.6, 0.1]])
+    assert np.isfinite(orc.loglike(K, freqs, D, 230.0, 2.725, th2, flags=NO_21CM)[0])
+
+
+def pin_batch_rows(orc):
+    """Rows are independent: permuting the batch permutes the output
+    exactly, and one row alone equals the same row inside a batch."""
+    rng = _rng(37)
+    N, F, T = 3, 8, 3
+    K, freqs = _rand_problem(rng, N, F, T)
+    D = rng.normal(80.0, 10.0, size=(F, T))
+    th = _rand_theta(rng, N, 9)
+    a = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+    p = rng.permutation(9)
+    b = orc.loglike(K, freqs, D, 230.0, 2.725, th[p])
+    assert np.array_equal(a[p], b)
+    c = orc.loglike(K, freqs, D, 230.0, 2.725, th[4:5], threads=1)
+    assert c[0] == a[4]
+
+
+ALL_PINS = [pin_brute_force, pin_n1_closed_form, pin_unit_power,
+            pin_t21_profile, pin_linearity, pin_permutation, pin_nesting,
+            pin_gaussian_library, pin_noise_free, pin_invalid_rows,
+            pin_batch_rows]

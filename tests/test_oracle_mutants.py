@@ -1,0 +1,60 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check
+that the pin suite catches every one of them.
+
+Each mutant is one textual edit of oracle/fgl_oracle.c: a dropped term, a
+flipped sign, a wrong index, a transposed operand, a lost factor.  The
+edited copy is compiled into a temporary directory; the real oracle is not
+touched.
+"""
+import os
+
+import pytest
+
+import oracle
+from tests import pins
+
+MUTANTS = {
+    "beta_sign": ("powv[i] = pow(ratio, -beta[i]);", "powv[i] = pow(ratio, beta[i]);"),
+    "ratio_inverted": ("double ratio = nu / nu_ref;", "double ratio = nu_ref / nu;"),
+    "power_in_float": ("powv[i] = pow(ratio, -beta[i]);",
+                       "powv[i] = (float)pow(ratio, -beta[i]);"),
+    "dropped_last_region": ("for (int i = 0; i < N; ++i) {                 /* ascending i */",
+                            "for (int i = 0; i < N - 1; ++i) {"),
+    "K_transposed": ("K + ((size_t)i * F + f) * T", "K + ((size_t)f * N + i) * T"),
+    "K_time_index": ("row[t] += (double)Ki[t] * powv[i];",
+                     "row[t] += (double)Ki[0] * powv[i];"),
+    "dropped_tcmb": ("row[t] = row[t] + t_cmb + sig21;", "row[t] = row[t] + sig21;"),
+    "t21_sign": ("sig21 = A * exp(", "sig21 = -A * exp("),
+    "t21_width": ("(2.0 * w * w)", "(w * w)"),
+    "t21_exp_sign": ("exp(-(dv * dv)", "exp((dv * dv)"),
+    "dropped_t21": ("row[t] = row[t] + t_cmb + sig21;", "row[t] = row[t] + t_cmb;"),
+    "sigma_not_squared": ("double s2 = sigma * sigma;", "double s2 = sigma;"),
+    "chi2_half_lost": ("return -0.5 * (chi2.s + chi2.c) / s2",
+                       "return -1.0 * (chi2.s + chi2.c) / s2"),
+    "dropped_normalisation": ("- 0.5 * n * log(2.0 * M_PI * s2);", ";"),
+    "normalisation_not_2pi": ("log(2.0 * M_PI * s2)", "log(M_PI * s2)"),
+    "residual_shifted": ("double r = D[k] - m[k];",
+                         "double r = D[k] - m[k == 0 ? 0 : k - 1];"),
+    "compensation_sign": ("a->c += (a->s - t) + x;", "a->c += (a->s - t) - x;"),
+    "invalid_not_checked": ("if (!(sigma > 0.0)) return 0;", ""),
+    "width_not_checked": ("if (!(w > 0.0)) return 0;", ""),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique/absent"
+    mpath = os.path.join(tmp_path, "mutant.c")
+    with open(mpath, "w") as fh:
+        fh.write(src.replace(old, new))
+    so = oracle.build(mpath, os.path.join(tmp_path, "libmutant.so"))
+    orc = oracle.Oracle(so)
+    caught = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(orc)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"no pin caught the planted mistake {name}"
