@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched foreground log-likelihood on one MI355X.
+
+One step = one call of the whole path (row preparation, the fused
+power-law / contraction / FP64 residual kernel, the fixed-order finalize)
+over one batch of B parameter rows already resident in HBM.  The headline
+workload is N=32 regions, F=301 channels, T=96 time bins, B=16384 rows,
+mixed precision; the plain FP32 and FP64 forms are timed the same way on
+the same rows, the serving mix is run briefly for its p50/p99 latency, and
+the FP64 CPU oracle is timed on a bounded sample on the host cores.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
+EXP_FLOPS = 20               # FP64 flops counted per power-law value
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", type=int, default=2, choices=[0, 1, 2, 4])
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--serve-seconds", type=float, default=3.0)
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--tune", action="store_true", help="autotune tiles before timing")
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_prec(fgl, m, th, out, prec, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        m.loglike_device(th, out, prec)
+    torch.cuda.synchronize()
+    m.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.loglike_device(th, out, prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, n = m.kernel_time()
+    m.kernel_timing(False)
+    B = th.shape[0]
+    ms = (t1 - t0) * 1e3 / steps
+    return {"evals_per_s": B * steps / (t1 - t0), "ms_per_step": ms,
+            "kernel_ms": kms / max(n, 1), "launches": n}
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM bytes per launch of the likelihood kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel."""
+    path = os.path.join(ROOT, "profiles", "k_mixed_N32_F301_T96_B16384_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def serving_leg(fgl, seconds, log_every=1.0):
+    import workload
+    clients = workload.serving_clients(64, n_requests=64)
+    models = [fgl.Model.from_workload(c.work) for c in clients]
+    srv = fgl.Server(budget_bytes=0, max_inflight=8)
+    rng = np.random.Generator(np.random.PCG64(31))
+    state = []
+    now = time.perf_counter()
+    for c in clients:
+        state.append({"next": now + rng.exponential(2e-3), "ticket": None, "k": 0})
+    lat, rows = [], 0
+    t_start = time.perf_counter()
+    t_end = t_start + seconds
+    next_log = t_start + log_every
+    while True:
+        now = time.perf_counter()
+        if now >= next_log:
+            log(f"serving: {len(lat)} requests done")
+            next_log += log_every
+        busy = False
+        for c, st, m in zip(clients, state, models):
+            if st["ticket"] is not None:
+                busy = True
+                r = srv.poll(st["ticket"])
+                if r is not None:
+                    out, us = r
+                    lat.append(us)
+                    rows += out.size
+                    st["ticket"] = None
+                    st["next"] = now + rng.exponential(2e-3)
+            elif now < t_end and now >= st["next"]:
+                B = c.batches[st["k"] % len(c.batches)]
+                st["ticket"] = srv.submit(m, c.work.theta[:B], "mixed")
+                st["k"] += 1
+                busy = True
+        if now >= t_end and not busy:
+            break
+        time.sleep(20e-6)
+    wall = time.perf_counter() - t_start
+    srv.close()
+    for m in models:
+        m.close()
+    lat = np.array(lat)
+    return {"clients": len(clients), "requests": int(lat.size),
+            "p50_ms": float(np.percentile(lat, 50)) / 1e3,
+            "p99_ms": float(np.percentile(lat, 99)) / 1e3,
+            "evals_per_s": rows / wall, "seconds": wall, "max_inflight": 8}
+
+
+def cpu_leg(w, gpu_out, seconds):
+    import oracle
+    orc = oracle.load()
+    cores = orc.max_threads()
+    n = min(w.B, 256)
+    t0 = time.perf_counter()
+    ref = orc.loglike_w(w, w.theta[:n])
+    dt = time.perf_counter() - t0
+    target = int(n * seconds / max(dt, 1e-6))
+    n2 = int(min(w.B, max(n, target)))
+    if n2 > n:
+        t0 = time.perf_counter()
+        ref = orc.loglike_w(w, w.theta[:n2])
+        dt = time.perf_counter() - t0
+        n = n2
+    d = np.abs(gpu_out[:n] - ref)
+    tol = 1e-6 * np.abs(ref) + 1e-3
+    return ({"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+             "sample": f"first {n} of the {w.B} rows, all host threads",
+             "seconds": dt},
+            {"rows": n, "max_abs_dlogL": float(d.max()),
+             "max_dlogL_over_tol": float((d / tol).max()),
+             "within_tol": bool(np.all(d <= tol))})
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                                   "--gpus N with N > 1 is not supported",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    import workload
+    from paper_2603_13196_amd import fgl
+    torch.cuda.set_device(0)
+    w = workload.config(a.workload)
+    log(f"workload {w.name}: N={w.N} F={w.F} T={w.T} B={w.B}")
+    m = fgl.Model.from_workload(w)
+    th = torch.from_numpy(w.theta).cuda()
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    if a.tune:
+        for prec in ("mixed", "fp32", "fp64"):
+            m.tune(w.B, prec)
+    res = {}
+    for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
+        res[prec] = time_prec(fgl, m, th, out, prec, a.steps, a.warmup)
+        if prec == "mixed":
+            gpu_out = out.cpu().numpy().copy()
+        log(f"{prec}: {res[prec]['evals_per_s']:.4e} evals/s, "
+            f"{res[prec]['ms_per_step']:.4f} ms/step, kernel {res[prec]['kernel_ms']:.4f} ms")
+    mix = res["mixed"]
+    # roofline of the likelihood kernel: FP64 work the method needs per
+    # evaluation (residual and chi-square: 3 F T; power laws: N F values at
+    # EXP_FLOPS each) over the kernel's average launch time
+    flops = w.B * (3.0 * w.F * w.T + EXP_FLOPS * w.N * w.F)
+    achieved = flops / (mix["kernel_ms"] * 1e-3) / 1e12
+    src = open(os.path.join(ROOT, "paper_2603_13196_amd", "csrc", "fgl_kernels.hip"), "rb").read()
+    traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+    line = {
+        "metric": "logL evals/s at N=32,F=301,T=96 (mixed vs plain); serve p50/p99 latency",
+        "value": mix["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": mix["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8-mfma+f64", "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "B": w.B,
+                   "precision": "mixed", "tile": list(m.tile(w.B, "mixed"))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic, "kernel": "k_mixed",
+                     "kernel_ms": mix["kernel_ms"]},
+    }
+    if "fp32" in res:
+        line["plain_fp32"] = {"value": res["fp32"]["evals_per_s"], "ms_per_step": res["fp32"]["ms_per_step"],
+                              "kernel_ms": res["fp32"]["kernel_ms"]}
+        line["plain_fp64"] = {"value": res["fp64"]["evals_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
+                              "kernel_ms": res["fp64"]["kernel_ms"]}
+        line["mixed_over_fp32"] = mix["evals_per_s"] / res["fp32"]["evals_per_s"]
+    m.close()
+    if not a.no_serve:
+        log("serving leg")
+        line["serving"] = serving_leg(fgl, a.serve_seconds)
+    if not a.no_cpu:
+        log("cpu baseline leg")
+        cb, par = cpu_leg(w, gpu_out, a.cpu_seconds)
+        line["cpu_baseline"] = cb
+        line["parity_vs_oracle"] = par
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * fgl.h -- C-ABI of the batched Gaussian log-likelihood of the region-based
+ * global-21-cm foreground model (Tutt et al., "Optimising Foreground
+ * Modelling for Global 21cm Cosmology with GPU-Accelerated Nested
+ * Sampling"), on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Sec. 2.2, Eq. fast_forward_model with the amplitude masks
+ * collapsed to alpha = 1 as the paper fits spectral-index masks only;
+ * Sec. 2.1, Eq. t21model; Sec. 2.3.1, Eq. likelihood): for every parameter
+ * row b,
+ *
+ *   M[b,nu,t] = sum_i K[i,nu,t] (nu/nu_ref)^(-beta_bi) + T_CMB
+ *               + A_b exp(-(nu - nu21_b)^2 / (2 w_b^2))
+ *   lnL_b     = -1/2 sum_{nu,t} [ ln(2 pi sigma_b^2) + (D[nu,t] - M[b,nu,t])^2 / sigma_b^2 ]
+ *
+ * K[i,nu,t] are the chromatic response functions of the regions
+ * (Eq. chromatic_function), precomputed by the caller; D is the observed
+ * antenna temperature on the channel-time grid.
+ *
+ * Parameter rows (theta) are FP64, row-major [B][P]:
+ *   [beta_0 .. beta_{N-1}, A (K, signed), nu21 (MHz), w = sigma_21 (MHz), sigma (K)]
+ * with P = N + 4; with FGL_NO_21CM the row is [beta_0 .. beta_{N-1}, sigma],
+ * P = N + 1.  (Table priors lists these parameters; sigma is linear.)
+ *
+ * Row validity: a row with a non-finite entry, sigma <= 0, w <= 0 (with the
+ * 21-cm term) or |beta_i| > 64 yields lnL = -inf.  This does not fail the
+ * call.
+ *
+ * Precision modes:
+ *   FGL_PREC_MIXED  the region sum as exact 8-bit integer slices of the
+ *                   powers and of K on the matrix cores (int32 sums), the
+ *                   residual D - M and the chi-square in FP64.  Agrees with
+ *                   an FP64 evaluation within |dlnL| <= 1e-6 |lnL| + 1e-3.
+ *   FGL_PREC_FP32   the model in FP32, residual and chi-square in FP64.
+ *   FGL_PREC_FP64   everything in FP64.
+ *
+ * Errors: every call returns an FGL_* status; fgl_last_error() gives a
+ * message for the calling thread's last failure.  Nothing is ever printed.
+ *
+ * Determinism: the same model, rows and mode give bitwise-identical
+ * results, whatever else runs on the device at the same time.
+ *
+ * Threads: calls on different models may run concurrently.  Calls on one
+ * model are serialised by the library (host-pointer entry points) or must be
+ * ordered by the caller's stream (device entry point).
+ */
+#ifndef FGL_H
+#define FGL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fgl_model fgl_model;   /* opaque, library-owned */
+typedef struct fgl_server fgl_server; /* opaque, library-owned */
+
+enum {
+  FGL_OK = 0,
+  FGL_EINVAL = -1,  /* bad argument (the message says which) */
+  FGL_ENOMEM = -2,  /* device or host allocation failed */
+  FGL_EBUSY = -3,   /* object still has requests in flight */
+  FGL_EDEVICE = -4, /* HIP runtime error */
+  FGL_EAGAIN = -5   /* not yet: retry later (serving admission) */
+};
+
+enum { FGL_PREC_MIXED = 0, FGL_PREC_FP32 = 1, FGL_PREC_FP64 = 2 };
+
+#define FGL_NO_21CM 1u /* model without the 21-cm term: P = N + 1 */
+
+/*
+ * Create a model: the fixed inputs of the likelihood (Sec. 2.2 precomputes
+ * K once per observation; Eq. likelihood's D is fixed per fit).
+ *   K      host, FP32 [N][F][T], row-major; finite.
+ *   freqs  host, FP64 [F], channel frequencies in MHz, finite, > 0, with
+ *          2^-8 <= freqs/nu_ref <= 2^8.
+ *   data   host, FP64 [F][T], antenna temperature D in K, finite.
+ *   nu_ref reference frequency of the power laws (MHz, > 0).
+ *   N      regions, 1..128;  F channels >= 1;  T time bins >= 1.
+ *   t_cmb  CMB temperature added to the model (K), finite.
+ *   flags  0 or FGL_NO_21CM.
+ * The library copies everything to the device and re-lays it out for its
+ * kernels; the caller may free its arrays on return.  *out receives the
+ * model, owned by the library until fgl_model_destroy.
+ * Returns FGL_OK, FGL_EINVAL, FGL_ENOMEM or FGL_EDEVICE.
+ */
+int fgl_model_create(const float* K, const double* freqs, const double* data,
+                     double nu_ref, int N, int F, int T, double t_cmb,
+                     unsigned flags, fgl_model** out);
+
+/* Parameters per row (N + 4, or N + 1 with FGL_NO_21CM); -1 for NULL. */
+int fgl_model_nparams(const fgl_model* m);
+
+/*
+ * lnL for B rows (Eq. likelihood).
+ *   theta  host, FP64 [B][P] (layout above), read during the call only.
+ *   B      rows, >= 0 (B = 0 is a no-op).
+ *   out    host, FP64 [B], written on success.
+ *   prec   FGL_PREC_MIXED, FGL_PREC_FP32 or FGL_PREC_FP64.
+ * Synchronous: returns when out is written.  Returns FGL_OK, FGL_EINVAL,
+ * FGL_ENOMEM, FGL_EBUSY (model being destroyed) or FGL_EDEVICE.
+ */
+int fgl_loglike_batch(fgl_model* m, const double* theta, int B,
+                      double* out_logL, int prec);
+
+/*
+ * Same as fgl_loglike_batch with device memory, enqueued on a caller stream.
+ *   d_theta  device, FP64 [B][P];  d_out  device, FP64 [B].
+ *   hip_stream  hipStream_t (NULL = the legacy default stream).
+ * Asynchronous: returns after enqueueing; d_out is valid once the stream
+ * reaches this point.  d_theta must stay valid until then.  The model's
+ * per-stream workspace is reused by the next call on the same stream.
+ */
+int fgl_loglike_batch_device(fgl_model* m, const double* d_theta, int B,
+                             double* d_out, int prec, void* hip_stream);
+
+/*
+ * Tile configuration used for (model, B, prec): waves per workgroup and
+ * channels per workgroup, as chosen by the autotuner (measuring on first use
+ * when FGL_TUNE=1 or fgl_tune was called).  Returns FGL_OK.
+ */
+int fgl_get_tile(fgl_model* m, int B, int prec, int* waves, int* chans);
+
+/* Measure the candidate tiles for (model, B, prec) now and keep the
+ * fastest for later calls.  Synchronous; uses the device. */
+int fgl_tune(fgl_model* m, int B, int prec);
+
+/* Device bytes held by the model (its resident inputs, not workspaces). */
+size_t fgl_model_bytes(const fgl_model* m);
+
+/*
+ * Kernel timing (instrumentation for benchmarks and roofline reports).
+ * fgl_kernel_timing(m, 1) resets the counters and, from then on, records a
+ * HIP event pair around the likelihood kernel of every call on m, on the
+ * stream that kernel runs on (graph replay is bypassed meanwhile);
+ * fgl_kernel_timing(m, 0) stops recording.  fgl_kernel_time waits for the
+ * recorded kernels and returns their summed duration (ms) and count.
+ */
+int fgl_kernel_timing(fgl_model* m, int enable);
+int fgl_kernel_time(fgl_model* m, double* total_ms, int64_t* launches);
+
+/* Destroy a model.  Returns FGL_EBUSY, freeing nothing, while a call or a
+ * served request on it is in flight; never blocks. */
+int fgl_model_destroy(fgl_model* m);
+
+/*
+ * Serving (continuous batching of likelihood requests from many concurrent
+ * samplers, Sec. 3.1.2: each nested-sampling iteration submits the rows of
+ * its parallel slice chains).
+ *   hbm_budget_bytes  device bytes the server may keep resident for the
+ *                     models of admitted requests (0 = no limit).
+ *   max_inflight      requests on the device at once (>= 1).
+ * A request is admitted when its model is resident or can be made resident
+ * within the budget (idle models are evicted least-recently-used first) and
+ * a slot is free; otherwise it waits in arrival order.  Admitted requests
+ * run on several streams so that their work overlaps on the device.
+ */
+int fgl_serve_create(size_t hbm_budget_bytes, int max_inflight,
+                     fgl_server** out);
+
+/*
+ * Submit B rows of theta (host) for model m; out_logL (host, [B]) is
+ * written before the request is reported done.  theta and out_logL must
+ * stay valid until fgl_serve_poll reports done.  *ticket identifies the
+ * request.  Returns FGL_OK, FGL_EINVAL, or FGL_EAGAIN when the model alone
+ * exceeds the budget.
+ */
+int fgl_serve_submit(fgl_server* s, fgl_model* m, const double* theta, int B,
+                     double* out_logL, int prec, uint64_t* ticket);
+
+/*
+ * Poll a ticket: *done = 1 when out_logL is written (then *latency_us is the
+ * submit-to-completion time), else 0.  A done ticket is retired by the poll
+ * that reports it; polling it again returns FGL_EINVAL.  A request that
+ * failed on the device reports done with its status as the return value.
+ */
+int fgl_serve_poll(fgl_server* s, uint64_t ticket, int* done,
+                   double* latency_us);
+
+/* Block until every submitted request is done (completions stay pollable). */
+int fgl_serve_drain(fgl_server* s);
+
+/* Destroy the server: FGL_EBUSY while requests are pending or in flight. */
+int fgl_serve_destroy(fgl_server* s);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* fgl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGL_H */

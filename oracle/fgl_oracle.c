@@ -24,8 +24,11 @@
  * noise level of Eq. likelihood; sigma is linear, in K).  With flag bit 0
  * (no 21-cm term) the row is [beta_0 .. beta_{N-1}, sigma].
  *
- * A row with sigma <= 0, w <= 0 or any non-finite entry gets lnL = -inf
- * (the paper does not define these; they have zero prior mass).
+ * A row with sigma <= 0, w <= 0, any non-finite entry, or a spectral index
+ * outside [-64, 64] gets lnL = -inf.  The paper does not define these rows;
+ * they have zero prior mass (its spectral-index prior spans 2.458-3.146), and
+ * the index bound keeps every power of a frequency ratio within 2^+-8 inside
+ * the double range.
  *
  * All arithmetic is IEEE double.  Powers use pow(); the region sum runs in
  * ascending i; the chi-square is summed over (nu, t) in row-major order with
@@ -57,6 +60,8 @@ static int row_valid(const double *th, int P, int N, unsigned flags)
 {
     for (int k = 0; k < P; ++k)
         if (!isfinite(th[k])) return 0;
+    for (int i = 0; i < N; ++i)
+        if (fabs(th[i]) > 64.0) return 0;
     double sigma = th[P - 1];
     if (!(sigma > 0.0)) return 0;
     if (!(flags & ORACLE_NO_21CM)) {

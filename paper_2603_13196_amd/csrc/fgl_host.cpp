@@ -1,0 +1,785 @@
+// Host side of the C-ABI: model residency, per-stream workspaces, tile
+// choice and tuning, hipGraph replay of the per-call launch sequence.
+#include "fgl_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+
+namespace fgl {
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_err;
+
+int set_err(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_err(hipError_t e, const char* what) {
+  return set_err(e == hipErrorOutOfMemory ? FGL_ENOMEM : FGL_EDEVICE,
+                 "%s: %s", what, hipGetErrorString(e));
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// live models (so that a server can drop the workspaces of its streams)
+
+static std::mutex g_models_mu;
+static std::vector<Model*> g_models;
+
+static void register_model(Model* m) {
+  std::lock_guard<std::mutex> g(g_models_mu);
+  g_models.push_back(m);
+}
+
+static void unregister_model(Model* m) {
+  std::lock_guard<std::mutex> g(g_models_mu);
+  g_models.erase(std::remove(g_models.begin(), g_models.end(), m), g_models.end());
+}
+
+// ---------------------------------------------------------------------------
+// device check
+
+static int check_device(int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_err(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_err(FGL_EDEVICE, "device %d is %s; this library is built for gfx950",
+                   dev, prop.gcnArchName);
+  *dev_out = dev;
+  return FGL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-side layouts (built once per model)
+
+// Balanced base-256 digits of a signed integer q with q + 0x808080 < 2^31:
+// byte 3 of the result is the most significant digit, every byte read as
+// int8 is a digit, and q = sum_L digit_L 2^(8(3-L)) with L = 3 - byte index.
+static inline uint32_t digits4(int32_t q) {
+  return ((uint32_t)q + 0x808080u) ^ 0x808080u;
+}
+
+static void build_layouts(Model* m, const float* K, const double* freqs,
+                          const double* data) {
+  const int N = m->N, F = m->F, T = m->T;
+  const int TT = m->dm.TT, TT16 = m->dm.TT16, KC = m->dm.KC;
+  const int NP2 = m->dm.NP2, NQ = m->dm.NQ;
+  auto Kat = [&](int i, int f, int t) -> float {
+    return K[((size_t)i * F + f) * T + t];
+  };
+  // mixed digits [F][4][KC][TT][64][16] and per-channel exponents: K at
+  // channel f is scaled by 2^(31 - eK) (|K| < 2^eK), rounded, and cut into
+  // four balanced digits whose top digit must stay within [-127, 127]; if
+  // rounding reaches 128 the channel uses eK + 1.
+  m->h_kd.assign((size_t)F * 4 * KC * TT * 1024, 0);
+  m->h_eK.assign(F, 0);
+  for (int f = 0; f < F; ++f) {
+    float mx = 0.0f;
+    for (int i = 0; i < N; ++i)
+      for (int t = 0; t < T; ++t) mx = std::max(mx, std::fabs(Kat(i, f, t)));
+    int ek = 0;
+    if (mx > 0.0f) std::frexp((double)mx, &ek);   // mx < 2^ek
+    for (;; ++ek) {
+      const double q = std::nearbyint(std::ldexp((double)mx, 31 - ek));
+      if (q + (double)0x808080 < 2147483648.0) break;   // top digit <= 127
+    }
+    m->h_eK[f] = ek;
+    int8_t* base = m->h_kd.data() + (size_t)f * 4 * KC * TT * 1024;
+    for (int kc = 0; kc < KC; ++kc)
+      for (int tt = 0; tt < TT; ++tt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int j = 0; j < 16; ++j) {
+            const int i = kc * 32 + (lane >> 5) * 16 + j;
+            const int t = tt * 32 + (lane & 31);
+            uint32_t d = 0x00000000u;
+            if (i < N && t < T) {
+              const double v = std::ldexp((double)Kat(i, f, t), 31 - ek);
+              d = digits4((int32_t)std::nearbyint(v));
+            }
+            for (int L = 0; L < 4; ++L) {
+              const int8_t dig = (int8_t)(uint8_t)(d >> (8 * (3 - L)));
+              base[(((size_t)L * KC + kc) * TT + tt) * 1024 + lane * 16 + j] = dig;
+            }
+          }
+  }
+  // FP32 A operands [F][NP2][TT][64]: lane -> (t = tt*32 + lane%32,
+  // i = 2k + lane/32); region N is the constant column (1 for t < T)
+  m->h_k32.assign((size_t)F * NP2 * TT * 64, 0.0f);
+  for (int f = 0; f < F; ++f)
+    for (int k = 0; k < NP2; ++k)
+      for (int tt = 0; tt < TT; ++tt)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = 2 * k + (lane >> 5), t = tt * 32 + (lane & 31);
+          float v = 0.0f;
+          if (t < T) v = i < N ? Kat(i, f, t) : (i == N ? 1.0f : 0.0f);
+          m->h_k32[(((size_t)f * NP2 + k) * TT + tt) * 64 + lane] = v;
+        }
+  // FP64 A operands (exact FP32 values) [F][NQ][TT16][64]: lane ->
+  // (t = tt*16 + lane%16, i = 4k + lane/16)
+  m->h_k64.assign((size_t)F * NQ * TT16 * 64, 0.0f);
+  for (int f = 0; f < F; ++f)
+    for (int k = 0; k < NQ; ++k)
+      for (int tt = 0; tt < TT16; ++tt)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = 4 * k + (lane >> 4), t = tt * 16 + (lane & 15);
+          float v = 0.0f;
+          if (t < T) v = i < N ? Kat(i, f, t) : (i == N ? 1.0f : 0.0f);
+          m->h_k64[(((size_t)f * NQ + k) * TT16 + tt) * 64 + lane] = v;
+        }
+  // per-channel constants
+  m->h_nl64.resize(F);
+  m->h_nl2.resize(F);
+  m->h_nu.assign(freqs, freqs + F);
+  for (int f = 0; f < F; ++f) {
+    const double l2 = std::log2(freqs[f] / m->nu_ref);
+    m->h_nl2[f] = -l2;
+    m->h_nl64[f] = -64.0 * l2;
+  }
+  // data [F][TT*32], zero padded in t
+  m->h_D.assign((size_t)F * TT * 32, 0.0);
+  for (int f = 0; f < F; ++f)
+    for (int t = 0; t < T; ++t) m->h_D[(size_t)f * TT * 32 + t] = data[(size_t)f * T + t];
+  // exponent tables: Q 2^((k - kTabLo)/64) with Q = 2^39 - 2^33, then
+  // 2^(m/64) / (1 - 2^-6) (the unit of the level-0 digit product)
+  const long double Q = 549755813888.0L - 8589934592.0L;
+  m->h_tab.resize(kTabSize + kFracSize);
+  for (int k = 0; k < kTabSize; ++k)
+    m->h_tab[k] = (double)(Q * std::exp2((long double)(k - kTabLo) / 64.0L));
+  for (int k = 0; k < kFracSize; ++k)
+    m->h_tab[kTabSize + k] = (double)(std::exp2((long double)k / 64.0L) / (1.0L - 1.0L / 64.0L));
+  const long double c1 = std::log(2.0L) / 64.0L;
+  m->dm.c1 = (double)c1;
+  m->dm.c2 = (double)(c1 * c1 / 2.0L);
+  m->dm.c3 = (double)(c1 * c1 * c1 / 6.0L);
+  m->dm.c4 = (double)(c1 * c1 * c1 * c1 / 24.0L);
+}
+
+// ---------------------------------------------------------------------------
+// residency
+
+template <typename T>
+static hipError_t upload(T** dptr, const std::vector<T>& h) {
+  const size_t bytes = std::max<size_t>(h.size() * sizeof(T), 16);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dptr), bytes);
+  if (e != hipSuccess) return e;
+  if (!h.empty()) e = hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+size_t resident_bytes(const Model* m) {
+  return m->h_kd.size() + m->h_eK.size() * 4 + m->h_k32.size() * 4 +
+         m->h_k64.size() * 4 + (m->h_nl64.size() + m->h_nl2.size() + m->h_nu.size()) * 8 +
+         m->h_D.size() * 8 + m->h_tab.size() * 8;
+}
+
+int make_resident(Model* m) {
+  if (m->resident) return FGL_OK;
+  hipError_t e = hipSetDevice(m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  int8_t* kd = nullptr;
+  int32_t* eK = nullptr;
+  float *k32 = nullptr, *k64 = nullptr;
+  double *nl64 = nullptr, *nl2 = nullptr, *nu = nullptr, *D = nullptr, *tab = nullptr;
+  if ((e = upload(&kd, m->h_kd)) != hipSuccess || (e = upload(&eK, m->h_eK)) != hipSuccess ||
+      (e = upload(&k32, m->h_k32)) != hipSuccess || (e = upload(&k64, m->h_k64)) != hipSuccess ||
+      (e = upload(&nl64, m->h_nl64)) != hipSuccess || (e = upload(&nl2, m->h_nl2)) != hipSuccess ||
+      (e = upload(&nu, m->h_nu)) != hipSuccess || (e = upload(&D, m->h_D)) != hipSuccess ||
+      (e = upload(&tab, m->h_tab)) != hipSuccess) {
+    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+    return hip_err(e, "uploading model");
+  }
+  m->dm.kd = kd;
+  m->dm.eK = eK;
+  m->dm.k32 = k32;
+  m->dm.k64 = k64;
+  m->dm.nl64 = nl64;
+  m->dm.nl2 = nl2;
+  m->dm.nu = nu;
+  m->dm.D = D;
+  m->dm.tab = tab;
+  m->resident = true;
+  return FGL_OK;
+}
+
+void evict(Model* m) {
+  if (!m->resident) return;
+  (void)hipSetDevice(m->dev);
+  // device-pointer calls return before their kernels finish
+  (void)hipDeviceSynchronize();
+  const void* ps[] = {m->dm.kd, m->dm.eK, m->dm.k32, m->dm.k64, m->dm.nl64,
+                      m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab};
+  for (const void* p : ps)
+    if (p) (void)hipFree(const_cast<void*>(p));
+  m->dm.kd = nullptr;
+  m->dm.eK = nullptr;
+  m->dm.k32 = m->dm.k64 = nullptr;
+  m->dm.nl64 = m->dm.nl2 = m->dm.nu = m->dm.D = m->dm.tab = nullptr;
+  m->resident = false;
+  // graphs captured against the old buffers are stale
+  for (auto& kv : m->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  }
+  m->graphs.clear();
+}
+
+// ---------------------------------------------------------------------------
+// workspaces
+
+static void free_work(WorkBuf& wb) {
+  if (wb.w.betaT) (void)hipFree(wb.w.betaT);
+  if (wb.w.rows) (void)hipFree(wb.w.rows);
+  if (wb.w.partial) (void)hipFree(wb.w.partial);
+  if (wb.d_theta) (void)hipFree(wb.d_theta);
+  if (wb.d_out) (void)hipFree(wb.d_out);
+  if (wb.h_theta) (void)hipHostFree(wb.h_theta);
+  if (wb.h_out) (void)hipHostFree(wb.h_out);
+  wb = WorkBuf();
+}
+
+static int padded_rows(int B) { return std::max(256, (B + 255) / 256 * 256); }
+
+// Free the workspaces every live model keeps for stream s (the stream is
+// about to be destroyed).
+void drop_stream_work(hipStream_t s) {
+  (void)hipStreamSynchronize(s);
+  std::lock_guard<std::mutex> g(g_models_mu);
+  for (Model* m : g_models) {
+    std::lock_guard<std::mutex> lk(m->mu);
+    auto it = m->work.find(s);
+    if (it != m->work.end()) {
+      free_work(it->second);
+      m->work.erase(it);
+    }
+  }
+}
+
+int ensure_work(Model* m, WorkBuf& wb, int B, int ngroups, bool host_io) {
+  const int Bpad = padded_rows(B);
+  const int betaRows = m->dm.KC * 32;
+  const bool grow_rows = Bpad > wb.cap_rows;
+  const bool grow_groups = grow_rows || ngroups > wb.w.ngroup_cap;
+  const bool grow_io = host_io && (grow_rows || !wb.h_theta);
+  if (!grow_rows && !grow_groups && !grow_io) {
+    wb.w.B = B;
+    wb.w.Bpad = Bpad;
+    return FGL_OK;
+  }
+  // drop graphs that captured the old pointers
+  for (auto& kv : m->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  m->graphs.clear();
+  const int rows = std::max(padded_rows(bucket_of(B)), wb.cap_rows);
+  const int groups = std::max(ngroups, wb.w.ngroup_cap);
+  WorkBuf nw;
+  hipError_t e;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&nw.w.betaT), (size_t)betaRows * rows * 8)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&nw.w.rows), (size_t)rows * sizeof(RowParams))) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&nw.w.partial), (size_t)groups * rows * 8)) != hipSuccess) {
+    free_work(nw);
+    return hip_err(e, "allocating workspace");
+  }
+  if (host_io || wb.h_theta) {
+    const size_t tb = (size_t)rows * m->P * 8, ob = (size_t)rows * 8;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&nw.d_theta), tb)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&nw.d_out), ob)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&nw.h_theta), tb, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&nw.h_out), ob, hipHostMallocDefault)) != hipSuccess) {
+      free_work(nw);
+      return hip_err(e, "allocating staging buffers");
+    }
+  }
+  // the old buffers may still be read by work queued on this stream
+  if (wb.stream_synced_free) {
+    free_work(wb);
+  } else {
+    m->retired.push_back(wb);
+    wb = WorkBuf();
+  }
+  nw.cap_rows = rows;
+  nw.w.ngroup_cap = groups;
+  nw.w.B = B;
+  nw.w.Bpad = Bpad;
+  nw.stream_synced_free = wb.stream_synced_free;
+  wb = nw;
+  return FGL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+
+Kind kind_of(int prec) {
+  return prec == FGL_PREC_FP32 ? kFP32 : (prec == FGL_PREC_FP64 ? kFP64 : kMixed);
+}
+
+// Largest wave count whose kernel fits in registers without spilling.
+static int max_waves(Kind k, const DevModel& d) {
+  if (k == kMixed) return d.KC <= 2 ? 8 : 4;
+  if (k == kFP32) return d.NP2 <= 48 ? 8 : 4;
+  return 8;
+}
+
+// Channels of one reduction group: fixed per (model, precision).  Up to four
+// channels, as many as fit in the LDS budget of a 4-wave workgroup.
+int group_of(Kind k, const DevModel& d) {
+  for (int g = 4; g >= 1; --g) {
+    Tile t{4, g, g};
+    if (lds_bytes(k, d, t) <= 76 * 1024) return g;
+  }
+  Tile t{4, 1, 1};
+  return lds_bytes(k, d, t) <= max_lds_bytes() ? 1 : 0;
+}
+
+// Candidate tiles for the tuner: waves in {4, 8} (within register limits),
+// channels per workgroup a multiple of the group fitting in LDS.
+std::vector<Tile> candidates(Kind k, const DevModel& d) {
+  std::vector<Tile> out;
+  const int G = group_of(k, d);
+  if (G == 0) return out;
+  for (int w : {4, 8}) {
+    if (w > max_waves(k, d)) continue;
+    for (int mult = 1; mult <= 8; ++mult) {
+      Tile t{w, G * mult, G};
+      if (lds_bytes(k, d, t) > max_lds_bytes()) break;
+      if (mult <= 2 || mult == 4 || mult == 8) out.push_back(t);
+    }
+  }
+  return out;
+}
+
+// Heuristic tile when no measurement is cached: as many waves as registers
+// allow, and the largest channel block that keeps >= 2 workgroups per CU
+// resident and >= 1024 workgroups in flight.
+Tile default_tile(Kind k, const DevModel& d, int B) {
+  const int G = group_of(k, d);
+  const int W = max_waves(k, d);
+  Tile best{W, G, G};
+  const int cols = cols_per_wave(k) * W;
+  const int nb = padded_rows(B) / cols;
+  for (int mult = 1; mult <= 8; ++mult) {
+    Tile t{W, G * mult, G};
+    if (lds_bytes(k, d, t) > 80 * 1024) break;
+    const int blocks = nb * ((d.F + t.fc - 1) / t.fc);
+    if (mult > 1 && blocks < 1024) break;
+    best = t;
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// one call: prep -> main -> finalize on stream s
+
+int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const double* d_theta,
+            int B, double* d_out, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_prep(m->dm, d_theta, B, wb.w, m->dm.KC * 32, s)) != hipSuccess)
+    return hip_err(e, "prep kernel");
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (m->timing) {
+    if (!m->ev_free.empty()) {
+      ev = m->ev_free.back();
+      m->ev_free.pop_back();
+    } else if ((e = hipEventCreate(&ev.first)) != hipSuccess ||
+               (e = hipEventCreate(&ev.second)) != hipSuccess) {
+      return hip_err(e, "hipEventCreate");
+    }
+    if ((e = hipEventRecord(ev.first, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
+  }
+  if ((e = launch_main(k, m->dm, wb.w, tile, s)) != hipSuccess)
+    return hip_err(e, "likelihood kernel");
+  if (m->timing) {
+    if ((e = hipEventRecord(ev.second, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
+    m->ev_used.push_back(ev);
+  }
+  if ((e = launch_finalize(k, m->dm, wb.w, tile, d_out, s)) != hipSuccess)
+    return hip_err(e, "finalize kernel");
+  return FGL_OK;
+}
+
+Tile tile_for(Model* m, Kind k, int B) {
+  const uint64_t key = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
+  auto it = m->tiles.find(key);
+  if (it != m->tiles.end()) return it->second;
+  return default_tile(k, m->dm, B);
+}
+
+int bucket_of(int B) {
+  int b = 256;
+  while (b < B) b *= 2;
+  return b;
+}
+
+// Time every candidate tile on the rows already staged in wb (device theta)
+// and remember the fastest for this (precision, B bucket).
+int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
+         double* d_out, hipStream_t s) {
+  std::vector<Tile> cand = candidates(k, m->dm);
+  if (cand.empty()) return set_err(FGL_EINVAL, "no tile fits this model");
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_err(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_err(e, "hipEventCreate");
+  }
+  float best_ms = std::numeric_limits<float>::max();
+  Tile best = cand[0];
+  int rc = FGL_OK;
+  for (const Tile& t : cand) {
+    rc = ensure_work(m, wb, B, n_groups(m->dm, t), false);
+    if (rc != FGL_OK) break;
+    rc = enqueue(m, k, t, wb, d_theta, B, d_out, s);  // warm-up
+    if (rc != FGL_OK) break;
+    (void)hipEventRecord(e0, s);
+    const int reps = 3;
+    for (int r = 0; r < reps && rc == FGL_OK; ++r) rc = enqueue(m, k, t, wb, d_theta, B, d_out, s);
+    (void)hipEventRecord(e1, s);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+      rc = hip_err(e, "tuning run");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == FGL_OK) {
+    const uint64_t key = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
+    m->tiles[key] = best;
+  }
+  return rc;
+}
+
+}  // namespace fgl
+
+// ===========================================================================
+// C-ABI
+
+using namespace fgl;
+
+extern "C" {
+
+const char* fgl_last_error(void) { return last_error(); }
+
+int fgl_model_create(const float* K, const double* freqs, const double* data,
+                     double nu_ref, int N, int F, int T, double t_cmb,
+                     unsigned flags, fgl_model** out) {
+  if (!out) return set_err(FGL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!K || !freqs || !data) return set_err(FGL_EINVAL, "K, freqs and data must be non-NULL");
+  if (N < 1 || N > kMixedMaxN) return set_err(FGL_EINVAL, "N=%d outside 1..%d", N, kMixedMaxN);
+  if (F < 1 || T < 1) return set_err(FGL_EINVAL, "F=%d and T=%d must be >= 1", F, T);
+  if (flags & ~FGL_NO_21CM) return set_err(FGL_EINVAL, "unknown flags 0x%x", flags);
+  if (!(nu_ref > 0.0) || !std::isfinite(nu_ref)) return set_err(FGL_EINVAL, "nu_ref must be finite and > 0");
+  if (!std::isfinite(t_cmb)) return set_err(FGL_EINVAL, "t_cmb must be finite");
+  for (int f = 0; f < F; ++f) {
+    const double r = freqs[f] / nu_ref;
+    if (!std::isfinite(freqs[f]) || !(freqs[f] > 0.0) || r < 1.0 / 256.0 || r > 256.0)
+      return set_err(FGL_EINVAL, "freqs[%d]=%g: need finite, > 0, within 2^-8..2^8 of nu_ref", f, freqs[f]);
+  }
+  for (size_t k = 0; k < (size_t)N * F * T; ++k)
+    if (!std::isfinite(K[k])) return set_err(FGL_EINVAL, "K[%zu] is not finite", k);
+  for (size_t k = 0; k < (size_t)F * T; ++k)
+    if (!std::isfinite(data[k])) return set_err(FGL_EINVAL, "data[%zu] is not finite", k);
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != FGL_OK) return rc;
+
+  Model* m = new (std::nothrow) Model();
+  if (!m) return set_err(FGL_ENOMEM, "host allocation");
+  m->dev = dev;
+  m->N = N;
+  m->F = F;
+  m->T = T;
+  m->P = (flags & FGL_NO_21CM) ? N + 1 : N + 4;
+  m->nu_ref = nu_ref;
+  m->t_cmb = t_cmb;
+  m->flags = flags;
+  DevModel& d = m->dm;
+  d.N = N;
+  d.F = F;
+  d.T = T;
+  d.P = m->P;
+  d.TT = (T + 31) / 32;
+  d.TT16 = (T + 15) / 16;
+  d.KC = (N + 31) / 32;
+  d.NP2 = (N + 1 + 1) / 2;
+  d.NQ = (N + 1 + 3) / 4;
+  d.t_cmb = t_cmb;
+  d.flags = flags;
+  for (Kind k : {kMixed, kFP32, kFP64}) {
+    if (group_of(k, d) == 0) {
+      delete m;
+      return set_err(FGL_EINVAL, "T=%d with N=%d does not fit one channel in LDS", T, N);
+    }
+  }
+  try {
+    build_layouts(m, K, freqs, data);
+  } catch (const std::bad_alloc&) {
+    delete m;
+    return set_err(FGL_ENOMEM, "host allocation for layouts");
+  }
+  hipError_t e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_err(e, "hipStreamCreate");
+  }
+  rc = make_resident(m);
+  if (rc != FGL_OK) {
+    (void)hipStreamDestroy(m->stream);
+    delete m;
+    return rc;
+  }
+  const char* tune_env = std::getenv("FGL_TUNE");
+  m->autotune = tune_env && tune_env[0] == '1';
+  const char* graph_env = std::getenv("FGL_NO_GRAPH");
+  m->use_graphs = !(graph_env && graph_env[0] == '1');
+  register_model(m);
+  *out = reinterpret_cast<fgl_model*>(m);
+  return FGL_OK;
+}
+
+int fgl_model_nparams(const fgl_model* mh) {
+  return mh ? reinterpret_cast<const Model*>(mh)->P : -1;
+}
+
+size_t fgl_model_bytes(const fgl_model* mh) {
+  return mh ? resident_bytes(reinterpret_cast<const Model*>(mh)) : 0;
+}
+
+static int check_call(Model* m, int B, int prec) {
+  if (!m) return set_err(FGL_EINVAL, "model is NULL");
+  if (B < 0) return set_err(FGL_EINVAL, "B=%d < 0", B);
+  if (prec != FGL_PREC_MIXED && prec != FGL_PREC_FP32 && prec != FGL_PREC_FP64)
+    return set_err(FGL_EINVAL, "unknown precision %d", prec);
+  if (m->dying.load()) return set_err(FGL_EBUSY, "model is being destroyed");
+  return FGL_OK;
+}
+
+int fgl_loglike_batch(fgl_model* mh, const double* theta, int B, double* out, int prec) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_call(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  if (B == 0) return FGL_OK;
+  if (!theta || !out) return set_err(FGL_EINVAL, "theta and out must be non-NULL");
+  InflightGuard guard(m);
+  std::lock_guard<std::mutex> lk(m->mu);
+  hipError_t e = hipSetDevice(m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  if ((rc = make_resident(m)) != FGL_OK) return rc;
+  const Kind k = kind_of(prec);
+  hipStream_t s = m->stream;
+  WorkBuf& wb = m->work[s];
+  wb.stream_synced_free = true;   // this stream is synchronised after every call
+  Tile tile = tile_for(m, k, B);
+  if ((rc = ensure_work(m, wb, B, n_groups(m->dm, tile), true)) != FGL_OK) return rc;
+  const size_t tb = (size_t)B * m->P * 8;
+  std::memcpy(wb.h_theta, theta, tb);
+  const uint64_t tkey = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
+  if (m->autotune && !m->tiles.count(tkey)) {
+    if ((e = hipMemcpyAsync(wb.d_theta, wb.h_theta, tb, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return hip_err(e, "copy theta");
+    if ((rc = tune(m, k, wb, wb.d_theta, B, wb.d_out, s)) != FGL_OK) return rc;
+    tile = tile_for(m, k, B);
+    if ((rc = ensure_work(m, wb, B, n_groups(m->dm, tile), true)) != FGL_OK) return rc;
+    std::memcpy(wb.h_theta, theta, tb);
+  }
+  // graph replay for a (precision, B, tile) seen before; eager otherwise
+  const GraphKey gk{k, B, tile.waves, tile.fc};
+  auto it = m->graphs.find(gk);
+  const bool graphs = m->use_graphs && !m->timing;
+  if (graphs && it != m->graphs.end() && it->second.exec) {
+    if ((e = hipGraphLaunch(it->second.exec, s)) != hipSuccess) return hip_err(e, "hipGraphLaunch");
+  } else {
+    const bool capture = graphs && it != m->graphs.end();  // second sighting
+    hipGraph_t graph = nullptr;
+    if (capture && (e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_err(e, "hipStreamBeginCapture");
+    rc = FGL_OK;
+    if ((e = hipMemcpyAsync(wb.d_theta, wb.h_theta, tb, hipMemcpyHostToDevice, s)) != hipSuccess)
+      rc = hip_err(e, "copy theta");
+    if (rc == FGL_OK) rc = enqueue(m, k, tile, wb, wb.d_theta, B, wb.d_out, s);
+    if (rc == FGL_OK && (e = hipMemcpyAsync(wb.h_out, wb.d_out, (size_t)B * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      rc = hip_err(e, "copy out");
+    if (capture) {
+      hipError_t ee = hipStreamEndCapture(s, &graph);
+      if (rc == FGL_OK && ee != hipSuccess) rc = hip_err(ee, "hipStreamEndCapture");
+      if (rc == FGL_OK) {
+        hipGraphExec_t exec = nullptr;
+        if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+          rc = hip_err(e, "hipGraphInstantiate");
+        else if ((e = hipGraphLaunch(exec, s)) != hipSuccess)
+          rc = hip_err(e, "hipGraphLaunch");
+        m->graphs[gk].exec = exec;
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != FGL_OK) return rc;
+    } else {
+      if (rc != FGL_OK) return rc;
+      m->graphs[gk];   // remember the sighting
+    }
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+  std::memcpy(out, wb.h_out, (size_t)B * 8);
+  return FGL_OK;
+}
+
+int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
+                             double* d_out, int prec, void* hip_stream) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_call(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  if (B == 0) return FGL_OK;
+  if (!d_theta || !d_out) return set_err(FGL_EINVAL, "d_theta and d_out must be non-NULL");
+  InflightGuard guard(m);
+  std::lock_guard<std::mutex> lk(m->mu);
+  hipError_t e = hipSetDevice(m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  if ((rc = make_resident(m)) != FGL_OK) return rc;
+  const Kind k = kind_of(prec);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  WorkBuf& wb = m->work[s];
+  const uint64_t tkey = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
+  if (m->autotune && !m->tiles.count(tkey)) {
+    if ((rc = tune(m, k, wb, d_theta, B, d_out, s)) != FGL_OK) return rc;
+  }
+  const Tile tile = tile_for(m, k, B);
+  if ((rc = ensure_work(m, wb, B, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
+  return enqueue(m, k, tile, wb, d_theta, B, d_out, s);
+}
+
+int fgl_get_tile(fgl_model* mh, int B, int prec, int* waves, int* chans) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_call(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  const Tile t = tile_for(m, kind_of(prec), std::max(B, 1));
+  if (waves) *waves = t.waves;
+  if (chans) *chans = t.fc;
+  return FGL_OK;
+}
+
+int fgl_tune(fgl_model* mh, int B, int prec) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_call(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  if (B < 1) return set_err(FGL_EINVAL, "B must be >= 1 to tune");
+  InflightGuard guard(m);
+  std::lock_guard<std::mutex> lk(m->mu);
+  hipError_t e = hipSetDevice(m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  if ((rc = make_resident(m)) != FGL_OK) return rc;
+  hipStream_t s = m->stream;
+  WorkBuf& wb = m->work[s];
+  wb.stream_synced_free = true;
+  if ((rc = ensure_work(m, wb, B, n_groups(m->dm, default_tile(kind_of(prec), m->dm, B)), true)) != FGL_OK)
+    return rc;
+  // tune on prior-like rows: beta = 2.75, A = -0.1, nu0 = 100, w = 15, sigma = 0.025
+  for (int b = 0; b < B; ++b) {
+    double* row = wb.h_theta + (size_t)b * m->P;
+    for (int i = 0; i < m->N; ++i) row[i] = 2.4 + 0.7 * ((b * 7 + i * 13) % 17) / 16.0;
+    if (!(m->flags & FGL_NO_21CM)) {
+      row[m->N] = -0.1;
+      row[m->N + 1] = 100.0;
+      row[m->N + 2] = 15.0;
+    }
+    row[m->P - 1] = 0.025;
+  }
+  if ((e = hipMemcpyAsync(wb.d_theta, wb.h_theta, (size_t)B * m->P * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_err(e, "copy theta");
+  rc = tune(m, kind_of(prec), wb, wb.d_theta, B, wb.d_out, s);
+  if (rc != FGL_OK) return rc;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+  return FGL_OK;
+}
+
+int fgl_kernel_timing(fgl_model* mh, int enable) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  if (!m) return set_err(FGL_EINVAL, "model is NULL");
+  std::lock_guard<std::mutex> lk(m->mu);
+  for (auto& ev : m->ev_used) {
+    (void)hipEventSynchronize(ev.second);
+    m->ev_free.push_back(ev);
+  }
+  m->ev_used.clear();
+  m->timing = enable != 0;
+  return FGL_OK;
+}
+
+int fgl_kernel_time(fgl_model* mh, double* total_ms, int64_t* launches) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  if (!m || !total_ms || !launches) return set_err(FGL_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(m->mu);
+  double tot = 0.0;
+  for (auto& ev : m->ev_used) {
+    hipError_t e = hipEventSynchronize(ev.second);
+    if (e != hipSuccess) return hip_err(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, ev.first, ev.second)) != hipSuccess)
+      return hip_err(e, "hipEventElapsedTime");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)m->ev_used.size();
+  return FGL_OK;
+}
+
+int fgl_model_destroy(fgl_model* mh) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  if (!m) return set_err(FGL_EINVAL, "model is NULL");
+  if (m->inflight.load() != 0 || m->served.load() != 0)
+    return set_err(FGL_EBUSY, "model has %d calls and %d served requests in flight",
+                   m->inflight.load(), m->served.load());
+  bool expected = false;
+  if (!m->dying.compare_exchange_strong(expected, true))
+    return set_err(FGL_EBUSY, "model is already being destroyed");
+  if (m->inflight.load() != 0 || m->served.load() != 0) {
+    m->dying.store(false);
+    return set_err(FGL_EBUSY, "model became busy");
+  }
+  unregister_model(m);
+  serve_forget_model(m);
+  (void)hipSetDevice(m->dev);
+  // work may still be queued on caller streams (device-pointer calls)
+  (void)hipDeviceSynchronize();
+  for (auto& kv : m->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  m->graphs.clear();
+  for (auto& kv : m->work) free_work(kv.second);
+  for (auto& wb : m->retired) free_work(wb);
+  for (auto* v : {&m->ev_used, &m->ev_free})
+    for (auto& ev : *v) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  evict(m);
+  (void)hipStreamDestroy(m->stream);
+  delete m;
+  return FGL_OK;
+}
+
+}  // extern "C"

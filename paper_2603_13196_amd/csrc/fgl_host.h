@@ -1,0 +1,98 @@
+// Host-side model object shared by the C-ABI (fgl_host.cpp) and the serving
+// loop (fgl_serve.cpp).  Internal; the public interface is include/fgl.h.
+#pragma once
+#include "../../include/fgl.h"
+#include "fgl_internal.h"
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace fgl {
+
+// Workspace bound to one stream of one model.
+struct WorkBuf {
+  Work w{};
+  int cap_rows = 0;
+  double* d_theta = nullptr;   // staging for host-pointer calls
+  double* d_out = nullptr;
+  double* h_theta = nullptr;   // pinned
+  double* h_out = nullptr;     // pinned
+  bool stream_synced_free = false;  // old buffers may be freed at once
+};
+
+struct GraphKey {
+  int kind, B, waves, fc;
+  bool operator<(const GraphKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (B != o.B) return B < o.B;
+    if (waves != o.waves) return waves < o.waves;
+    return fc < o.fc;
+  }
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+};
+
+struct Model {
+  int dev = 0;
+  int N = 0, F = 0, T = 0, P = 0;
+  double nu_ref = 0.0, t_cmb = 0.0;
+  unsigned flags = 0;
+  DevModel dm{};
+  bool resident = false;
+  bool autotune = false;
+  bool use_graphs = true;
+  hipStream_t stream = nullptr;
+  std::mutex mu;                        // serialises calls on this model
+  std::atomic<int> inflight{0};         // synchronous calls in progress
+  std::atomic<int> served{0};           // serving requests not yet done
+  std::atomic<bool> dying{false};
+  std::map<hipStream_t, WorkBuf> work;  // per-stream workspaces
+  std::vector<WorkBuf> retired;         // outgrown workspaces (freed at destroy)
+  std::map<GraphKey, GraphEntry> graphs;
+  std::unordered_map<uint64_t, Tile> tiles;  // tuned tiles per (kind, B bucket)
+  // host copies of the device layouts (re-uploaded after an eviction)
+  std::vector<int8_t> h_kd;
+  std::vector<int32_t> h_eK;
+  std::vector<float> h_k32, h_k64;
+  std::vector<double> h_nl64, h_nl2, h_nu, h_D, h_tab;
+  // serving bookkeeping
+  uint64_t last_use = 0;
+  // kernel timing (fgl_kernel_timing)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+};
+
+struct InflightGuard {
+  Model* m;
+  explicit InflightGuard(Model* mm) : m(mm) { m->inflight.fetch_add(1); }
+  ~InflightGuard() { m->inflight.fetch_sub(1); }
+};
+
+int set_err(int code, const char* fmt, ...);
+int hip_err(hipError_t e, const char* what);
+const char* last_error();
+
+size_t resident_bytes(const Model* m);
+int make_resident(Model* m);
+void evict(Model* m);
+int ensure_work(Model* m, WorkBuf& wb, int B, int ngroups, bool host_io);
+Kind kind_of(int prec);
+int group_of(Kind k, const DevModel& d);
+std::vector<Tile> candidates(Kind k, const DevModel& d);
+Tile default_tile(Kind k, const DevModel& d, int B);
+Tile tile_for(Model* m, Kind k, int B);
+int bucket_of(int B);
+int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb,
+            const double* d_theta, int B, double* d_out, hipStream_t s);
+int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
+         double* d_out, hipStream_t s);
+void drop_stream_work(hipStream_t s);   // fgl_host.cpp
+void serve_forget_model(Model* m);      // fgl_serve.cpp
+
+}  // namespace fgl

@@ -1,0 +1,92 @@
+// Internal interface between the host library (fgl_host.cpp) and the device
+// kernels (fgl_kernels.hip).  Not part of the public C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fgl {
+
+// Exponent tables of the mixed kernel: tab[k] = Q 2^((k - kTabLo)/64) for
+// k in [0, kTabSize), Q = 2^39 - 2^33 (forty octaves below the row maximum
+// down to the maximum itself), then frac[m] = 2^(m/64) / (1 - 2^-6) for
+// m in [0, 64) at tab[kTabSize + m].
+constexpr int kTabLo = 2560;
+constexpr int kTabSize = 2562;
+constexpr int kFracSize = 64;
+// Level sums are kept in two int32 accumulators (see fgl_kernels.hip);
+// their range bounds the region count of the mixed kernel.
+constexpr int kMixedMaxN = 128;
+
+// Per-row parameters written by the prep kernel (one 64-byte record per row).
+struct RowParams {
+  double bmin, bmax;   // extreme spectral indices of the row
+  double A, nu0;       // 21-cm amplitude (K) and centre (MHz)
+  double inv_w;        // 1 / width (1/MHz)
+  double sigma;        // noise level (K)
+  double t21;          // 1.0 with the 21-cm term, 0.0 without
+  int32_t valid;       // 0: invalid row -> logL = -inf
+  int32_t pad;
+};
+
+// Kernel families behind one entry point.
+enum Kind { kMixed = 0, kFP32 = 1, kFP64 = 2 };
+
+// Tile configuration of one launch (chosen by the tuner).
+// The channel sum of a row is cut into reduction groups of `group`
+// consecutive channels; the workgroup of a row tile stages `fc` channels
+// (a multiple of `group`) and writes one partial per group.  The group size
+// is fixed per (model, precision), so results never depend on the tuned
+// waves/fc.
+struct Tile {
+  int waves;   // waves per workgroup: 4 or 8
+  int fc;      // frequency channels staged per workgroup
+  int group;   // channels per reduction group
+};
+
+// Device-side model (all pointers are device memory owned by the model).
+struct DevModel {
+  int N, F, T, P;
+  int TT;            // 32-row time tiles (mixed, FP32)
+  int TT16;          // 16-row time tiles (FP64)
+  int KC;            // 32-region chunks (mixed)
+  int NP2;           // region pairs incl. the constant column (FP32)
+  int NQ;            // region quads incl. the constant column (FP64)
+  double t_cmb;
+  unsigned flags;
+  const int8_t* kd;      // mixed digits [F][4][KC][TT][64][16]
+  const int32_t* eK;     // [F] per-channel exponent of the digits
+  const float* k32;      // FP32 A-operands [F][NP2][TT][64]
+  const float* k64;      // FP64 A-operands, as exact FP32 [F][NQ][TT16][64]
+  const double* nl64;    // [F] -64 log2(nu/nu_ref)
+  const double* nl2;     // [F] -log2(nu/nu_ref)
+  const double* nu;      // [F] MHz
+  const double* D;       // [F][TT*32] data, zero padded in t
+  const double* tab;     // [kTabSize + kFracSize] exponent tables
+  double c1, c2, c3, c4; // Taylor coefficients of 2^(r/64)
+};
+
+// Per-call workspace (device memory owned by the model, per stream).
+struct Work {
+  int B, Bpad;           // rows and rows padded to the widest b-tile
+  double* betaT;         // [KC*32 rounded][Bpad] sanitised spectral indices
+  RowParams* rows;       // [Bpad]
+  double* partial;       // [ngroups][Bpad]
+  int ngroup_cap;        // capacity of partial in groups
+};
+
+// Launchers (fgl_kernels.hip).  All enqueue on `s`; none synchronises.
+hipError_t launch_prep(const DevModel& m, const double* theta, int B,
+                       const Work& w, int betaRows, hipStream_t s);
+hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
+                       const Tile& tile, hipStream_t s);
+hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
+                           const Tile& tile, double* out, hipStream_t s);
+
+// Shape helpers shared by host and launcher.
+int lds_bytes(Kind k, const DevModel& m, const Tile& t);
+int cols_per_wave(Kind k);
+int n_chunks(const DevModel& m, const Tile& t);   // workgroups along nu
+int n_groups(const DevModel& m, const Tile& t);   // partials per row
+int max_lds_bytes();
+
+}  // namespace fgl

@@ -1,0 +1,615 @@
+// Device kernels of the batched foreground log-likelihood, for CDNA4 (gfx950).
+//
+// Computed quantity (Tutt et al., Eqs. fast_forward_model, t21model and
+// likelihood): for each parameter row b,
+//   M[b,nu,t] = sum_i K[i,nu,t] (nu/nu_ref)^(-beta_bi) + T_CMB
+//               + A_b exp(-(nu - nu0_b)^2 / (2 w_b^2))
+//   lnL_b     = -sum_{nu,t} [ (D - M)^2 / (2 sigma_b^2) + ln(2 pi sigma_b^2)/2 ]
+//
+// Every kernel works in the transposed orientation M^T = K^T (T x N) P (N x B)
+// per channel: MFMA rows are time bins, MFMA columns are parameter rows.  A
+// wave owns one tile of parameter rows (its MFMA columns) for a range of
+// channels, so each lane holds exactly one row b and all per-row constants
+// are per-lane scalars; the time bins of a lane sit in its accumulator
+// registers and the data D[nu, t] for them are broadcast reads from LDS.
+//
+// The workgroup stages the chromatic responses of a block of channels (and
+// the data of those channels) in LDS once; its waves then run independently
+// over the channels.  Each workgroup writes one chi-square partial per row
+// and per reduction group of channels; a finalize kernel sums the partials
+// of a row in channel order.  The group size is fixed per model, so results
+// are bitwise reproducible, independent of the tuned tile and of what else
+// runs on the device.
+//
+// Three arithmetic forms share that skeleton:
+//   k_mixed: exact integer slicing.  The powers are computed in FP64,
+//            rounded to 39-bit fixed point relative to the row's largest
+//            power at the channel and cut into five signed 8-bit digits; K
+//            is cut into four digits once, at model creation.  The fourteen
+//            digit products of significance 0..4 run as
+//            v_mfma_i32_32x32x32_i8 with exact int32 sums in three
+//            accumulators; the constant term T_CMB + A g enters through the
+//            level-combining shift-adds, and D - M and the chi-square run in
+//            FP64.
+//   k_fp32:  the model in FP32 (v_mfma_f32_32x32x2_f32, FP32 powers),
+//            residual and chi-square in FP64.
+//   k_fp64:  the model in FP64 (v_mfma_f64_16x16x4_f64, FP64 powers).
+#include "fgl_internal.h"
+
+#include <math.h>
+
+#include <mutex>
+#include <set>
+
+namespace fgl {
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// shared helpers
+
+// Workgroup id -> (row tile, channel chunk).  Consecutive workgroup ids go
+// to different XCDs round-robin; the remap gives every XCD a contiguous run
+// of (chunk, tile) pairs so that the workgroups reading one chunk of K mostly
+// share one XCD's L2.
+__device__ inline void map_block(int nb, int nc, int& bt, int& ch) {
+  const int total = nb * nc;
+  const int id = blockIdx.x;
+  const int xcd = id & 7, k = id >> 3;
+  const int q = total >> 3, rem = total & 7;
+  const int L = xcd * q + (xcd < rem ? xcd : rem) + k;
+  ch = L / nb;
+  bt = L - ch * nb;
+}
+
+// Cooperative 16-byte copy global -> LDS (bytes is a multiple of 16).
+__device__ inline void stage(void* dst, const void* src, int bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const int n = bytes >> 4;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) d[k] = s[k];
+}
+
+// 4x4 byte transpose: out[L] gathers byte (3-L) of v0..v3 (byte k of out[L]
+// comes from v_k).  Eight v_perm_b32.
+__device__ inline void transpose4(uint32_t v0, uint32_t v1, uint32_t v2,
+                                  uint32_t v3, uint32_t out[4]) {
+  const uint32_t a = __builtin_amdgcn_perm(v1, v0, 0x05010400u);
+  const uint32_t b = __builtin_amdgcn_perm(v1, v0, 0x07030602u);
+  const uint32_t c = __builtin_amdgcn_perm(v3, v2, 0x05010400u);
+  const uint32_t d = __builtin_amdgcn_perm(v3, v2, 0x07030602u);
+  out[3] = __builtin_amdgcn_perm(c, a, 0x05040100u);  // byte 0 of each
+  out[2] = __builtin_amdgcn_perm(c, a, 0x07060302u);  // byte 1
+  out[1] = __builtin_amdgcn_perm(d, b, 0x05040100u);  // byte 2
+  out[0] = __builtin_amdgcn_perm(d, b, 0x07060302u);  // byte 3
+}
+
+// exp(-z^2/2) in FP32 for the 21-cm profile; its error (~1e-7 relative)
+// is far below what the likelihood can resolve.
+__device__ inline double gauss21(double nu, const RowParams& rp) {
+  const float z = (float)((nu - rp.nu0) * rp.inv_w);
+  return (double)__builtin_amdgcn_exp2f(-0.7213475204444817f * z * z);
+}
+
+// ---------------------------------------------------------------------------
+// mixed: exact int8 slices on MFMA
+//
+// Digits.  At channel nu a row's powers are normalised by 2^(ymax/64), the
+// row's largest power rounded up to 1/64 octave (ymax from the extreme
+// spectral index), so x_i = P_i / 2^(ymax/64) lies in (0, 1].  Each x_i is
+// rounded to q_i = round(x_i Q), Q = 2^39 - 2^33, and written as five
+// balanced base-256 digits d0..d4 (d0 in [0, 127], the others in
+// [-128, 127]).  One FP64 fma produces all five: t = x Q + (2^52 + 2^31 +
+// 2^23 + 2^15 + 2^7) is an integer-valued double whose low word holds the
+// four low digits offset by 128 and whose high word's low byte holds d0.
+// K at channel nu is scaled by 2^(31 - eK(nu)) and cut into four digits
+// e0..e3 (e0 in [-127, 127]) once, at model creation.
+//
+// Products.  The fourteen digit products of significance p + q <= 4 run on
+// v_mfma_i32_32x32x32_i8; their int32 sums are exact.  Three accumulators
+// hold them: acc0 = S0 2^8 + S1, acc1 = S2 2^8 + S3, acc2 = S4 (S_l is the
+// sum of the products of significance l); the constant T_CMB + A g of the
+// row enters acc0 and acc1 through the shift-adds that combine levels.
+// Dropped products (significance >= 5) are below 2^-40 of the leading
+// term; the power-law rounding is below 2^-40 of the row's largest power.
+
+template <int W, int KC>
+__global__ __launch_bounds__(W * 64) void k_mixed(DevModel m, Work w, int fc, int G,
+                                                  int nb, int nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int bt, ch;
+  map_block(nb, nc, bt, ch);
+  const int TT = m.TT;
+  const int f0 = ch * fc;
+  const int fn = min(fc, m.F - f0);
+  const int kbytes = 4 * KC * TT * 1024;
+  unsigned char* s_kd = smem;
+  double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kbytes);
+  double* s_tab = s_D + (size_t)fc * TT * 32;
+  stage(s_kd, m.kd + (size_t)f0 * kbytes, fn * kbytes);
+  stage(s_D, m.D + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
+  stage(s_tab, m.tab, (kTabSize + kFracSize) * 8);
+  __syncthreads();
+  const double* s_frac = s_tab + kTabSize;
+
+  const int g = lane >> 5;
+  const int b = bt * (W * 32) + wave * 32 + (lane & 31);
+  const RowParams rp = w.rows[b];
+  double beta[KC][16];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      beta[kc][j] = w.betaT[(size_t)(kc * 32 + g * 16 + j) * w.Bpad + b];
+
+  const double MAGIC = 0x1.8p52;                        // rint via the low word
+  const double DIGITS = 0x1.0p52 + (double)0x80808080u;  // digit offsets
+  double acc_a = 0.0, acc_b = 0.0;
+  for (int f = 0; f < fn; ++f) {
+    const int fi = f0 + f;
+    const double nl = m.nl64[fi];
+    const int ek = m.eK[fi];
+    // row constants at this channel: normalisation, level units, constant term
+    const double c = m.t_cmb + rp.A * gauss21(m.nu[fi], rp);
+    const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
+    double ymax = ceil(bext * nl);
+    int ey = (int)floor(ymax * (1.0 / 64.0));
+    double u0 = ldexp(s_frac[(int)(ymax - 64.0 * ey)], ey + ek - 14);
+    int ec;
+    frexp(c / u0 * 256.0, &ec);          // |c| / unit of acc0 < 2^ec
+    if (ec > 29) {                        // constant term dominates: coarser digits
+      ymax += 64.0 * (ec - 29);
+      ey += ec - 29;
+      u0 = ldexp(u0, ec - 29);
+    }
+    const double s0 = u0 * 0x1.0p-8, s1 = u0 * 0x1.0p-24, s2 = u0 * 0x1.0p-32;
+    const double c0f = rint(c / s0);
+    const int c0 = (int)c0f;
+    const int c1 = (int)rint(fma(-c0f, s0, c) / s1);
+
+    // power-law digits: the MFMA B operands of this lane (row b, 16 regions
+    // per 32-region chunk), five significance levels
+    i32x4 Bop[KC][5];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      uint32_t lo[16], hi[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double y = fma(beta[kc][j], nl, -ymax);    // 64 log2(x), <= 0
+        y = fmax(y, -(double)kTabLo);
+        const double t = y + MAGIC;
+        const int jj = (int)(uint32_t)__double_as_longlong(t);
+        const double r = y - (t - MAGIC);          // |r| <= 1/2
+        const double T2 = s_tab[jj + kTabLo];      // Q 2^(jj/64)
+        double p = fma(r, m.c4, m.c3);
+        p = fma(r, p, m.c2);
+        p = fma(r, p, m.c1);
+        p = fma(r, p, 1.0);                        // 2^(r/64)
+        const double q = fma(T2, p, DIGITS);       // 2^52 + q + offsets
+        const unsigned long long bits = __double_as_longlong(q);
+        lo[j] = (uint32_t)bits ^ 0x80808080u;      // digits d4 d3 d2 d1
+        hi[j] = (uint32_t)(bits >> 32);            // low byte: d0
+      }
+#pragma unroll
+      for (int m4 = 0; m4 < 4; ++m4) {
+        uint32_t o[4];
+        transpose4(lo[4 * m4], lo[4 * m4 + 1], lo[4 * m4 + 2], lo[4 * m4 + 3], o);
+        // o[L] holds byte (3 - L) of the low words: d(L+1)
+#pragma unroll
+        for (int L = 0; L < 4; ++L) Bop[kc][L + 1][m4] = (int32_t)o[L];
+        const uint32_t h01 = __builtin_amdgcn_perm(hi[4 * m4 + 1], hi[4 * m4], 0x0c0c0400u);
+        const uint32_t h23 = __builtin_amdgcn_perm(hi[4 * m4 + 3], hi[4 * m4 + 2], 0x0c0c0400u);
+        Bop[kc][0][m4] = (int32_t)(h01 | (h23 << 16));
+      }
+    }
+
+    const unsigned char* kf = s_kd + (size_t)f * kbytes + lane * 16;
+    const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
+    for (int tt = 0; tt < TT; ++tt) {
+      i32x4 A[4][KC];
+#pragma unroll
+      for (int L = 0; L < 4; ++L)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+          A[L][kc] = *reinterpret_cast<const i32x4*>(
+              kf + ((L * KC + kc) * TT + tt) * 1024);
+      i32x16 a0 = {}, a1 = {}, a2 = {};
+#define MF(acc, q, p) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[q][kc], Bop[kc][p], acc, 0, 0, 0)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        MF(a0, 0, 0);                                      // level 0
+        MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);          // level 2
+        MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);  // level 4
+      }
+      a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)c0);
+      a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)c1);
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        MF(a0, 0, 1); MF(a0, 1, 0);                        // level 1
+        MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);  // level 3
+      }
+#undef MF
+      const double* Dt = Df + tt * 32;
+      double Dv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Dv[j] = Dt[(j >> 2) * 8 + (j & 3)];
+      const bool ragged = (tt == TT - 1) && (m.T & 31);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double r = fma(-s0, (double)a0[j], Dv[j]);
+        r = fma(-s1, (double)a1[j], r);
+        r = fma(-s2, (double)a2[j], r);
+        if (ragged) {
+          const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
+          r = t < m.T ? r : 0.0;
+        }
+        if (j & 1) acc_b = fma(r, r, acc_b);
+        else acc_a = fma(r, r, acc_a);
+      }
+    }
+    // one partial per reduction group of G channels (f0 is a multiple of G)
+    if ((f + 1) % G == 0 || f == fn - 1) {
+      double acc = acc_a + acc_b;
+      acc += __shfl_xor(acc, 32);
+      if (g == 0) w.partial[(size_t)((f0 + f) / G) * w.Bpad + b] = acc;
+      acc_a = 0.0;
+      acc_b = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plain FP32 model (FP64 residual and chi-square)
+
+template <int W, int NPB>
+__global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int G,
+                                                 int nb, int nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int bt, ch;
+  map_block(nb, nc, bt, ch);
+  const int TT = m.TT, NP2 = m.NP2, N = m.N;
+  const int f0 = ch * fc;
+  const int fn = min(fc, m.F - f0);
+  const int kfl = NP2 * TT * 64;            // floats per channel
+  float* s_k = reinterpret_cast<float*>(smem);
+  double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kfl * 4);
+  stage(s_k, m.k32 + (size_t)f0 * kfl, fn * kfl * 4);
+  stage(s_D, m.D + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
+  __syncthreads();
+
+  const int g = lane >> 5;
+  const int b = bt * (W * 32) + wave * 32 + (lane & 31);
+  const RowParams rp = w.rows[b];
+  float betaf[NPB];
+#pragma unroll
+  for (int k = 0; k < NPB; ++k) {
+    const int i = 2 * k + g;
+    betaf[k] = (k < NP2 && i < N) ? (float)w.betaT[(size_t)i * w.Bpad + b] : 0.0f;
+  }
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int f = 0; f < fn; ++f) {
+    const int fi = f0 + f;
+    const float nl = (float)m.nl2[fi];
+    const float c = (float)(m.t_cmb + rp.A * gauss21(m.nu[fi], rp));
+    float Bp[NPB];
+#pragma unroll
+    for (int k = 0; k < NPB; ++k) {
+      const int i = 2 * k + g;
+      const float p = __builtin_amdgcn_exp2f(betaf[k] * nl);
+      Bp[k] = i < N ? p : (i == N ? c : 0.0f);
+    }
+    const float* kf = s_k + (size_t)f * kfl + lane;
+    const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
+    for (int tt = 0; tt < TT; ++tt) {
+      f32x16 a = {};
+#pragma unroll
+      for (int k = 0; k < NPB; ++k)
+        if (k < NP2)
+          a = __builtin_amdgcn_mfma_f32_32x32x2f32(kf[(k * TT + tt) * 64], Bp[k], a, 0, 0, 0);
+      const double* Dt = Df + tt * 32;
+      const bool ragged = (tt == TT - 1) && (m.T & 31);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double r = Dt[(j >> 2) * 8 + (j & 3)] - (double)a[j];
+        if (ragged) {
+          const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
+          r = t < m.T ? r : 0.0;
+        }
+        if (j & 1) acc1 = fma(r, r, acc1);
+        else acc0 = fma(r, r, acc0);
+      }
+    }
+    // one partial per reduction group of G channels (f0 is a multiple of G)
+    if ((f + 1) % G == 0 || f == fn - 1) {
+      double acc = acc0 + acc1;
+      acc += __shfl_xor(acc, 32);
+      if (g == 0) w.partial[(size_t)((f0 + f) / G) * w.Bpad + b] = acc;
+      acc0 = 0.0;
+      acc1 = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plain FP64 model
+
+template <int W, int NQB>
+__global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int G,
+                                                 int nb, int nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int bt, ch;
+  map_block(nb, nc, bt, ch);
+  const int TT16 = m.TT16, NQ = m.NQ, N = m.N;
+  const int f0 = ch * fc;
+  const int fn = min(fc, m.F - f0);
+  const int kdl = NQ * TT16 * 64;           // values per channel
+  float* s_k = reinterpret_cast<float*>(smem);
+  double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kdl * 4);
+  stage(s_k, m.k64 + (size_t)f0 * kdl, fn * kdl * 4);
+  stage(s_D, m.D + (size_t)f0 * m.TT * 32, fn * m.TT * 32 * 8);
+  __syncthreads();
+
+  const int g = lane >> 4;                  // 0..3
+  const int b = bt * (W * 16) + wave * 16 + (lane & 15);
+  const RowParams rp = w.rows[b];
+  double beta[NQB];
+#pragma unroll
+  for (int k = 0; k < NQB; ++k) {
+    const int i = 4 * k + g;
+    beta[k] = (k < NQ && i < N) ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
+  }
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int f = 0; f < fn; ++f) {
+    const int fi = f0 + f;
+    const double nl = m.nl2[fi];
+    const double z = (m.nu[fi] - rp.nu0) * rp.inv_w;
+    const double c = m.t_cmb + rp.A * exp(-0.5 * z * z);
+    double Bp[NQB];
+#pragma unroll
+    for (int k = 0; k < NQB; ++k) {
+      const int i = 4 * k + g;
+      const double p = exp2(beta[k] * nl);
+      Bp[k] = i < N ? p : (i == N ? c : 0.0);
+    }
+    const float* kf = s_k + (size_t)f * kdl + lane;
+    // 16x16 FP64 MFMA output: register j of lane l holds row l/16 + 4 j
+    const double* Df = s_D + (size_t)f * m.TT * 32 + g;
+    for (int tt = 0; tt < TT16; ++tt) {
+      f64x4 a = {};
+#pragma unroll
+      for (int k = 0; k < NQB; ++k)
+        if (k < NQ)
+          a = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kf[(k * TT16 + tt) * 64], Bp[k], a, 0, 0, 0);
+      const double* Dt = Df + tt * 16;
+      const bool ragged = (tt == TT16 - 1) && (m.T & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double r = Dt[4 * j] - a[j];
+        if (ragged) {
+          const int t = tt * 16 + g + 4 * j;
+          r = t < m.T ? r : 0.0;
+        }
+        if (j & 1) acc1 = fma(r, r, acc1);
+        else acc0 = fma(r, r, acc0);
+      }
+    }
+    if ((f + 1) % G == 0 || f == fn - 1) {
+      double acc = acc0 + acc1;
+      acc += __shfl_xor(acc, 16);
+      acc += __shfl_xor(acc, 32);
+      if (g == 0) w.partial[(size_t)((f0 + f) / G) * w.Bpad + b] = acc;
+      acc0 = 0.0;
+      acc1 = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row preparation and finalize
+
+// One thread per padded row: validate, sanitise, transpose the spectral
+// indices to [i][b] and record the row constants.  Invalid rows are given
+// harmless values (their result is overwritten with -inf at finalize).
+__global__ void k_prep(const double* __restrict__ theta, int B, int Bpad,
+                       int N, int P, unsigned flags, int betaRows,
+                       double* __restrict__ betaT, RowParams* __restrict__ rows) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= Bpad) return;
+  const bool no21 = flags & 1u;
+  RowParams rp;
+  rp.valid = 0;
+  rp.pad = 0;
+  rp.A = 0.0;
+  rp.nu0 = 0.0;
+  rp.inv_w = 1.0;
+  rp.sigma = 1.0;
+  rp.t21 = no21 ? 0.0 : 1.0;
+  bool ok = b < B;
+  const double* th = theta + (size_t)b * P;
+  if (ok) {
+    for (int k = 0; k < P; ++k) ok = ok && isfinite(th[k]);
+    for (int i = 0; i < N; ++i) ok = ok && fabs(th[i]) <= 64.0;
+    ok = ok && th[P - 1] > 0.0;
+    if (!no21) ok = ok && th[N + 2] > 0.0;
+  }
+  double bmin = 0.0, bmax = 0.0;
+  if (ok) {
+    bmin = bmax = N > 0 ? th[0] : 0.0;
+    for (int i = 1; i < N; ++i) {
+      bmin = fmin(bmin, th[i]);
+      bmax = fmax(bmax, th[i]);
+    }
+    rp.valid = 1;
+    rp.sigma = th[P - 1];
+    if (!no21) {
+      rp.A = th[N];
+      rp.nu0 = th[N + 1];
+      rp.inv_w = 1.0 / th[N + 2];
+    }
+  }
+  rp.bmin = bmin;
+  rp.bmax = bmax;
+  for (int i = 0; i < betaRows; ++i)
+    betaT[(size_t)i * Bpad + b] = (ok && i < N) ? th[i] : bmin;
+  rows[b] = rp;
+}
+
+// lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2), with chi2_b the
+// sum of the row's group partials in channel order.
+__global__ void k_finalize(const double* __restrict__ partial, int ngroup,
+                           int Bpad, const RowParams* __restrict__ rows,
+                           int B, double nFT, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const RowParams rp = rows[b];
+  if (!rp.valid) {
+    out[b] = -INFINITY;
+    return;
+  }
+  double s = 0.0;
+  for (int c = 0; c < ngroup; ++c) s += partial[(size_t)c * Bpad + b];
+  const double s2 = rp.sigma * rp.sigma;
+  out[b] = -0.5 * s / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+int cols_per_wave(Kind k) { return k == kFP64 ? 16 : 32; }
+
+int max_lds_bytes() { return 160 * 1024; }
+
+int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
+  const int d = t.fc * m.TT * 32 * 8;
+  switch (k) {
+    case kMixed: return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + kFracSize) * 8;
+    case kFP32: return t.fc * m.NP2 * m.TT * 64 * 4 + d;
+    default: return t.fc * m.NQ * m.TT16 * 64 * 4 + d;
+  }
+}
+
+int n_chunks(const DevModel& m, const Tile& t) { return (m.F + t.fc - 1) / t.fc; }
+
+int n_groups(const DevModel& m, const Tile& t) {
+  return (m.F + t.group - 1) / t.group;
+}
+
+namespace {
+
+std::mutex g_attr_mu;
+std::set<const void*> g_attr_done;
+
+// Launch with dynamic LDS.  The LDS limit of a kernel is raised once per
+// process, on its first (never captured) launch.
+template <typename KernelT>
+hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
+              const DevModel& m, const Work& w, int fc, int G, int nb, int nc) {
+  const void* fp = reinterpret_cast<const void*>(kern);
+  {
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    if (!g_attr_done.count(fp)) {
+      hipError_t e = hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         max_lds_bytes());
+      if (e != hipSuccess) return e;
+      g_attr_done.insert(fp);
+    }
+  }
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, s, m, w, fc, G, nb, nc);
+  return hipGetLastError();
+}
+
+template <int W>
+hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
+                   int nc, int lds, hipStream_t s) {
+  const int blocks = nb * nc, th = W * 64;
+  switch (m.KC) {
+    case 1: return go(k_mixed<W, 1>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_mixed<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 3: return go(k_mixed<W, 3>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_mixed<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int W>
+hipError_t fp32_w(const DevModel& m, const Work& w, int fc, int G, int nb,
+                  int nc, int lds, hipStream_t s) {
+  const int blocks = nb * nc, th = W * 64;
+  const int n = m.NP2;
+  if (n <= 4) return go(k_fp32<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 8) return go(k_fp32<W, 8>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 12) return go(k_fp32<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 17) return go(k_fp32<W, 17>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 24) return go(k_fp32<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 33) return go(k_fp32<W, 33>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 48) return go(k_fp32<W, 48>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 65) return go(k_fp32<W, 65>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  return hipErrorInvalidValue;
+}
+
+template <int W>
+hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
+                  int nc, int lds, hipStream_t s) {
+  const int blocks = nb * nc, th = W * 64;
+  const int n = m.NQ;
+  if (n <= 2) return go(k_fp64<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 4) return go(k_fp64<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 6) return go(k_fp64<W, 6>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 9) return go(k_fp64<W, 9>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 12) return go(k_fp64<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 17) return go(k_fp64<W, 17>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 24) return go(k_fp64<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  if (n <= 33) return go(k_fp64<W, 33>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_prep(const DevModel& m, const double* theta, int B,
+                       const Work& w, int betaRows, hipStream_t s) {
+  const int threads = 256;
+  const int blocks = (w.Bpad + threads - 1) / threads;
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(threads), 0, s, theta, B,
+                     w.Bpad, m.N, m.P, m.flags, betaRows, w.betaT, w.rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
+                       const Tile& tile, hipStream_t s) {
+  const int cols = cols_per_wave(k) * tile.waves;
+  const int nb = w.Bpad / cols;
+  const int nc = n_chunks(m, tile);
+  const int lds = lds_bytes(k, m, tile);
+  if (w.Bpad % cols != 0 || n_groups(m, tile) > w.ngroup_cap ||
+      tile.group < 1 || tile.fc % tile.group != 0 || lds > max_lds_bytes())
+    return hipErrorInvalidValue;
+  if (k == kMixed) {
+    return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
+                           : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
+  } else if (k == kFP32) {
+    return tile.waves == 8 ? fp32_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
+                           : fp32_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
+  }
+  return tile.waves == 8 ? fp64_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
+                         : fp64_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
+}
+
+hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
+                           const Tile& tile, double* out, hipStream_t s) {
+  (void)k;
+  const int threads = 256;
+  const int blocks = (w.B + threads - 1) / threads;
+  hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, s, w.partial,
+                     n_groups(m, tile), w.Bpad, w.rows, w.B,
+                     (double)m.F * (double)m.T, out);
+  return hipGetLastError();
+}
+
+}  // namespace fgl

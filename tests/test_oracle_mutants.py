@@ -38,6 +38,8 @@ MUTANTS = {
     "compensation_sign": ("a->c += (a->s - t) + x;", "a->c += (a->s - t) - x;"),
     "invalid_not_checked": ("if (!(sigma > 0.0)) return 0;", ""),
     "width_not_checked": ("if (!(w > 0.0)) return 0;", ""),
+    "beta_bound_not_checked": ("if (fabs(th[i]) > 64.0) return 0;",
+                               "if (fabs(th[i]) > 1e300) return 0;"),
 }
 
 

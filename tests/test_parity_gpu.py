@@ -1,0 +1,238 @@
+"""GPU parity: the HIP library (through the C-ABI) against the FP64 oracle.
+
+Small workloads are compared row by row on every row; the full-size
+workloads run in the launch configuration the benchmark times and are
+compared on sampled rows.  Every case names its workload before it runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from tests.gpu_util import check, lib, say
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ("mixed", "fp32", "fp64")
+
+
+@pytest.fixture(scope="module")
+def fgl():
+    return lib()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def _model(fgl, w):
+    return fgl.Model(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_small_configs_all_rows(fgl, orc, k):
+    """Workloads 0 (N=4, F=151, T=1) and 1 (N=16, F=151, T=20): every row of
+    the prior batch and of a 1024-row posterior shell."""
+    for kind in ("prior", "shell"):
+        w = workload.config(k) if kind == "prior" else workload.posterior_shell(k)
+        say(f"workload {k} {kind}: N={w.N} F={w.F} T={w.T} B={w.B}")
+        ref = orc.loglike_w(w)
+        m = _model(fgl, w)
+        for prec in PRECS:
+            got = m.loglike(w.theta, prec)
+            if prec == "fp32" and kind == "shell":
+                d = np.abs(got - ref)
+                say(f"  fp32 shell (reported, not asserted): max|d|={d.max():.3e}")
+                continue
+            check(got, ref, prec, f"cfg{k}/{kind}", w.theta, w.F * w.T)
+        m.close()
+
+
+def test_headline_shape_reduced_batch(fgl, orc):
+    """N=32, F=301, T=96 (the headline shape): 1024 prior rows and the
+    1024-row posterior shell, every row."""
+    wp = workload.config(2, B=1024)
+    ws = workload.posterior_shell(2, 1024)
+    say(f"workload 2 reduced: N={wp.N} F={wp.F} T={wp.T}")
+    m = _model(fgl, wp)
+    for w, kind in ((wp, "prior"), (ws, "shell")):
+        ref = orc.loglike_w(w)
+        check(m.loglike(w.theta, "mixed"), ref, "mixed", f"cfg2/{kind}")
+        check(m.loglike(w.theta, "fp64"), ref, "fp64", f"cfg2/{kind}", w.theta, w.F * w.T)
+        got32 = m.loglike(w.theta, "fp32")
+        d = np.abs(got32 - ref)
+        say(f"  fp32 {kind}: max|d|={d.max():.3e} "
+            f"max|d|/mixed-tol={(d / (1e-6 * np.abs(ref) + 1e-3)).max():.3e}")
+    m.close()
+
+
+def test_headline_full_batch_sampled(fgl, orc):
+    """Full N=32, F=301, T=96, B=16384 call (the benchmark's launch), with
+    the oracle on 512 sampled rows, plus a full posterior shell."""
+    w = workload.config(2)
+    say(f"workload 2 full: B={w.B}")
+    m = _model(fgl, w)
+    rng = np.random.Generator(np.random.PCG64(5))
+    idx = np.sort(rng.choice(w.B, 512, replace=False))
+    ref = orc.loglike_w(w, w.theta[idx])
+    for prec in ("mixed", "fp64"):
+        got = m.loglike(w.theta, prec)
+        check(got[idx], ref, prec, "cfg2/full-sampled", w.theta[idx], w.F * w.T)
+    m.close()
+
+
+def test_large_config_subsample(fgl, orc):
+    """N=64, F=401, T=240, B=65536: full launch, oracle on 256 rows."""
+    w = workload.config(4)
+    say(f"workload 4: N={w.N} F={w.F} T={w.T} B={w.B}")
+    m = _model(fgl, w)
+    rng = np.random.Generator(np.random.PCG64(9))
+    idx = np.sort(rng.choice(w.B, 256, replace=False))
+    ref = orc.loglike_w(w, w.theta[idx])
+    got = m.loglike(w.theta, "mixed")
+    check(got[idx], ref, "mixed", "cfg4/sampled")
+    sh = workload.posterior_shell(4, 256)
+    check(m.loglike(sh.theta, "mixed"), orc.loglike_w(sh), "mixed", "cfg4/shell")
+    m.close()
+
+
+@pytest.mark.parametrize("N,F,T,B", [
+    (1, 7, 1, 1), (3, 5, 2, 257), (31, 13, 31, 300), (32, 9, 32, 64),
+    (33, 11, 33, 100), (64, 6, 65, 70), (100, 5, 17, 40), (128, 3, 40, 33),
+    (7, 1, 96, 512), (12, 40, 130, 129)])
+def test_shapes_and_ragged_tails(fgl, orc, N, F, T, B):
+    """Region chunks (N over 32), ragged time tiles, ragged batches, a single
+    channel, a single row, with chromatic K and mixed prior/shell rows."""
+    freqs = np.linspace(55.0, 190.0, F) if F > 1 else np.array([123.0])
+    w = workload.make(N, freqs, T, B, 1000 + N * 7 + T, chroma=0.05, batch="mixed")
+    say(f"shape N={N} F={F} T={T} B={B}")
+    ref = orc.loglike_w(w)
+    m = _model(fgl, w)
+    for prec in PRECS:
+        got = m.loglike(w.theta, prec)
+        if prec == "fp32":
+            half = B // 2      # prior half only
+            check(got[:half], ref[:half], prec, f"N{N}F{F}T{T}B{B}")
+        else:
+            check(got, ref, prec, f"N{N}F{F}T{T}B{B}", w.theta, w.F * w.T)
+    m.close()
+
+
+def test_edge_rows_and_values(fgl, orc):
+    """Invalid rows give -inf; signed and tiny K, a channel at nu_ref, a
+    large 21-cm amplitude, beta at the +-64 limit, nu near 2^+-8 nu_ref."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    N, T = 5, 7
+    freqs = np.array([1.0, 50.0, 230.0, 231.0, 5000.0, 58000.0])
+    F = freqs.size
+    K = rng.normal(0.0, 3.0, size=(N, F, T)).astype(np.float32)
+    K[1] *= np.float32(1e-6)
+    D = rng.normal(20.0, 5.0, size=(F, T))
+    th = np.zeros((12, N + 4))
+    th[:, :N] = rng.uniform(-2.0, 4.0, size=(12, N))
+    th[:, N:] = [-0.1, 120.0, 15.0, 0.5]
+    th[1, N + 3] = 0.0          # sigma = 0
+    th[2, N + 2] = -3.0         # w < 0
+    th[3, 2] = np.nan
+    th[4, 0] = 65.0             # beyond the beta limit
+    th[5, N] = np.inf
+    th[6, 0] = 4.5              # steep spectrum across 2^+-8 of nu_ref
+    th[6, 1] = -2.5
+    th[7, N] = 1e6              # huge 21-cm amplitude
+    th[8, N + 2] = 1e-3         # very narrow profile
+    th[9, :N] = 0.0             # unit powers
+    th[10, N + 3] = 1e3         # broad noise
+    m = fgl.Model(K, freqs, D, 230.0, 2.725)
+    ref = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+    say(f"edge rows: ref={ref}")
+    assert np.all(ref[1:6] == -np.inf)
+    for prec in ("mixed", "fp64"):
+        check(m.loglike(th, prec), ref, prec, "edge", th, F * T)
+    got32 = m.loglike(th, "fp32")
+    assert np.all(got32[1:6] == -np.inf)
+    m.close()
+    # spectral indices at the +-64 validity limit on a narrow band
+    f2 = np.linspace(200.0, 260.0, 9)
+    K2 = rng.lognormal(1.0, 0.5, size=(3, 9, 4)).astype(np.float32)
+    D2 = rng.normal(30.0, 3.0, size=(9, 4))
+    th2 = np.array([[64.0, -64.0, 0.5, -0.1, 220.0, 10.0, 2.0],
+                    [-64.0, 64.0, 63.9, 0.0, 210.0, 5.0, 1.0],
+                    [64.0000001, 1.0, 1.0, 0.0, 210.0, 5.0, 1.0]])
+    m2 = fgl.Model(K2, f2, D2, 230.0, 2.725)
+    ref2 = orc.loglike(K2, f2, D2, 230.0, 2.725, th2)
+    assert np.all(np.isfinite(ref2[:2])) and ref2[2] == -np.inf
+    for prec in ("mixed", "fp64"):
+        check(m2.loglike(th2, prec), ref2, prec, "beta-limit", th2, 9 * 4)
+    m2.close()
+
+
+def test_no_21cm_flag(fgl, orc):
+    w = workload.config(1, B=512)
+    th = np.concatenate([w.theta[:, :w.N], w.theta[:, -1:]], axis=1)
+    m = fgl.Model(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, flags=fgl.FGL_NO_21CM)
+    assert m.P == w.N + 1
+    ref = orc.loglike(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, th, flags=1)
+    check(m.loglike(th, "mixed"), ref, "mixed", "no21")
+    check(m.loglike(th, "fp64"), ref, "fp64", "no21", th, w.F * w.T)
+    m.close()
+
+
+def test_determinism_and_row_independence(fgl):
+    """Bitwise: repeated calls (eager, then graph capture, then replays with
+    other work in between), one row alone vs inside a large batch, batch
+    permutation, and tuned vs default tiles."""
+    w = workload.config(2, B=4096, batch="mixed")
+    m = _model(fgl, w)
+    other = _model(fgl, workload.config(1, B=64))
+    for prec in PRECS:
+        say(f"determinism {prec}")
+        a = m.loglike(w.theta, prec)
+        for rep in range(4):
+            other.loglike(workload.config(1, B=64).theta, prec)
+            b = m.loglike(w.theta, prec)
+            assert np.array_equal(a, b), (prec, rep)
+        one = m.loglike(w.theta[123:124], prec)
+        assert one[0] == a[123]
+        p = np.random.Generator(np.random.PCG64(3)).permutation(w.B)
+        assert np.array_equal(m.loglike(w.theta[p], prec), a[p])
+        m.tune(w.B, prec)
+        assert np.array_equal(m.loglike(w.theta, prec), a), f"{prec}: tile changed bits"
+    m.close()
+    other.close()
+
+
+def test_device_entry_point_matches_host(fgl):
+    import torch
+    w = workload.config(2, B=2048, batch="mixed")
+    m = _model(fgl, w)
+    th = torch.from_numpy(w.theta).to("cuda")
+    for prec in PRECS:
+        out = m.loglike_device(th, prec=prec)
+        torch.cuda.synchronize()
+        host = m.loglike(w.theta, prec)
+        assert np.array_equal(out.cpu().numpy(), host), prec
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = m.loglike_device(th, prec="mixed", stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), m.loglike(w.theta, "mixed"))
+    m.close()
+
+
+def test_errors_and_zero_rows(fgl):
+    w = workload.config(0, B=8)
+    m = _model(fgl, w)
+    assert m.loglike(np.zeros((0, m.P))).shape == (0,)
+    with pytest.raises(fgl.FGLError) as e:
+        fgl.fgl_loglike_batch(m.handle, w.theta, 8, np.empty(8), 7)
+    assert e.value.code == fgl.FGL_EINVAL
+    with pytest.raises(fgl.FGLError):
+        fgl.Model(w.K, -w.freqs, w.data)
+    with pytest.raises(fgl.FGLError):
+        fgl.Model(w.K, w.freqs, w.data, nu_ref=0.0)
+    bad = w.K.copy()
+    bad[0, 0, 0] = np.nan
+    with pytest.raises(fgl.FGLError):
+        fgl.Model(bad, w.freqs, w.data)
+    m.close()
