@@ -41,6 +41,9 @@ def parse():
     p.add_argument("--serve-seconds", type=float, default=3.0)
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--tune", action="store_true", help="autotune tiles before timing")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="only run a 256 MiB device-to-device copy three times "
+                        "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
 
 
@@ -166,6 +169,14 @@ def main():
     import workload
     from paper_2603_13196_amd import fgl
     torch.cuda.set_device(0)
+    if a.calib_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": src.numel() * 8, "copies": 3}))
+        return
     w = workload.config(a.workload)
     log(f"workload {w.name}: N={w.N} F={w.F} T={w.T} B={w.B}")
     m = fgl.Model.from_workload(w)
@@ -196,7 +207,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8-mfma+f64", "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "B": w.B,
-                   "precision": "mixed", "tile": list(m.tile(w.B, "mixed"))},
+                   "precision": "mixed", "tile": dict(zip(("waves", "chans", "occupancy"), m.tile(w.B, "mixed")))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "kernel": "k_mixed",

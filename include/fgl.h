@@ -117,15 +117,23 @@ int fgl_loglike_batch_device(fgl_model* m, const double* d_theta, int B,
                              double* d_out, int prec, void* hip_stream);
 
 /*
- * Tile configuration used for (model, B, prec): waves per workgroup and
- * channels per workgroup, as chosen by the autotuner (measuring on first use
- * when FGL_TUNE=1 or fgl_tune was called).  Returns FGL_OK.
+ * Tile configuration used for (model, B, prec): waves per workgroup,
+ * channels per workgroup and the waves per SIMD the kernel variant is
+ * compiled for, as chosen by the autotuner (measuring on first use when
+ * FGL_TUNE=1 or fgl_tune was called).  Any output pointer may be NULL.
+ * The tile never changes results.  Returns FGL_OK.
  */
-int fgl_get_tile(fgl_model* m, int B, int prec, int* waves, int* chans);
+int fgl_get_tile(fgl_model* m, int B, int prec, int* waves, int* chans,
+                 int* occupancy);
 
 /* Measure the candidate tiles for (model, B, prec) now and keep the
  * fastest for later calls.  Synchronous; uses the device. */
 int fgl_tune(fgl_model* m, int B, int prec);
+
+/* Force the tile for (model, B's size class, prec); FGL_EINVAL unless it is
+ * one of the tuner's candidates for this model.  Results are unchanged. */
+int fgl_set_tile(fgl_model* m, int B, int prec, int waves, int chans,
+                 int occupancy);
 
 /* Device bytes held by the model (its resident inputs, not workspaces). */
 size_t fgl_model_bytes(const fgl_model* m);

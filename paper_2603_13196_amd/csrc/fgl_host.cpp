@@ -161,11 +161,14 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
   // exponent tables: Q 2^((k - kTabLo)/64) with Q = 2^39 - 2^33, then
   // 2^(m/64) / (1 - 2^-6) (the unit of the level-0 digit product)
   const long double Q = 549755813888.0L - 8589934592.0L;
-  m->h_tab.resize(kTabSize + kFracSize);
+  m->h_tab.resize(kTabSize + 2 * kFracSize);
   for (int k = 0; k < kTabSize; ++k)
     m->h_tab[k] = (double)(Q * std::exp2((long double)(k - kTabLo) / 64.0L));
-  for (int k = 0; k < kFracSize; ++k)
-    m->h_tab[kTabSize + k] = (double)(std::exp2((long double)k / 64.0L) / (1.0L - 1.0L / 64.0L));
+  for (int k = 0; k < kFracSize; ++k) {
+    const long double u = std::exp2((long double)k / 64.0L) / (1.0L - 1.0L / 64.0L);
+    m->h_tab[kTabSize + k] = (double)u;
+    m->h_tab[kTabSize + kFracSize + k] = (double)(1.0L / u);
+  }
   const long double c1 = std::log(2.0L) / 64.0L;
   m->dm.c1 = (double)c1;
   m->dm.c2 = (double)(c1 * c1 / 2.0L);
@@ -343,10 +346,10 @@ static int max_waves(Kind k, const DevModel& d) {
 // channels, as many as fit in the LDS budget of a 4-wave workgroup.
 int group_of(Kind k, const DevModel& d) {
   for (int g = 4; g >= 1; --g) {
-    Tile t{4, g, g};
+    Tile t{4, g, g, 2};
     if (lds_bytes(k, d, t) <= 76 * 1024) return g;
   }
-  Tile t{4, 1, 1};
+  Tile t{4, 1, 1, 2};
   return lds_bytes(k, d, t) <= max_lds_bytes() ? 1 : 0;
 }
 
@@ -359,7 +362,7 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
   for (int w : {4, 8}) {
     if (w > max_waves(k, d)) continue;
     for (int mult = 1; mult <= 8; ++mult) {
-      Tile t{w, G * mult, G};
+      Tile t{w, G * mult, G, 2};
       if (lds_bytes(k, d, t) > max_lds_bytes()) break;
       if (mult <= 2 || mult == 4 || mult == 8) out.push_back(t);
     }
@@ -373,11 +376,11 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
 Tile default_tile(Kind k, const DevModel& d, int B) {
   const int G = group_of(k, d);
   const int W = max_waves(k, d);
-  Tile best{W, G, G};
+  Tile best{W, G, G, 2};
   const int cols = cols_per_wave(k) * W;
   const int nb = padded_rows(B) / cols;
   for (int mult = 1; mult <= 8; ++mult) {
-    Tile t{W, G * mult, G};
+    Tile t{W, G * mult, G, 2};
     if (lds_bytes(k, d, t) > 80 * 1024) break;
     const int blocks = nb * ((d.F + t.fc - 1) / t.fc);
     if (mult > 1 && blocks < 1024) break;
@@ -609,7 +612,7 @@ int fgl_loglike_batch(fgl_model* mh, const double* theta, int B, double* out, in
     std::memcpy(wb.h_theta, theta, tb);
   }
   // graph replay for a (precision, B, tile) seen before; eager otherwise
-  const GraphKey gk{k, B, tile.waves, tile.fc};
+  const GraphKey gk{k, B, tile.waves, tile.fc, tile.occ};
   auto it = m->graphs.find(gk);
   const bool graphs = m->use_graphs && !m->timing;
   if (graphs && it != m->graphs.end() && it->second.exec) {
@@ -672,7 +675,7 @@ int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
   return enqueue(m, k, tile, wb, d_theta, B, d_out, s);
 }
 
-int fgl_get_tile(fgl_model* mh, int B, int prec, int* waves, int* chans) {
+int fgl_get_tile(fgl_model* mh, int B, int prec, int* waves, int* chans, int* occupancy) {
   Model* m = reinterpret_cast<Model*>(mh);
   int rc = check_call(m, B, prec);
   if (rc != FGL_OK) return rc;
@@ -680,7 +683,25 @@ int fgl_get_tile(fgl_model* mh, int B, int prec, int* waves, int* chans) {
   const Tile t = tile_for(m, kind_of(prec), std::max(B, 1));
   if (waves) *waves = t.waves;
   if (chans) *chans = t.fc;
+  if (occupancy) *occupancy = t.occ;
   return FGL_OK;
+}
+
+int fgl_set_tile(fgl_model* mh, int B, int prec, int waves, int chans, int occupancy) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_call(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  const Kind k = kind_of(prec);
+  for (const Tile& t : candidates(k, m->dm)) {
+    if (t.waves == waves && t.fc == chans && t.occ == occupancy) {
+      const uint64_t key = ((uint64_t)k << 32) | (uint32_t)bucket_of(std::max(B, 1));
+      m->tiles[key] = t;
+      return FGL_OK;
+    }
+  }
+  return set_err(FGL_EINVAL, "tile (waves=%d, chans=%d, occupancy=%d) is not a candidate for "
+                 "this model and precision", waves, chans, occupancy);
 }
 
 int fgl_tune(fgl_model* mh, int B, int prec) {

@@ -25,12 +25,13 @@ struct WorkBuf {
 };
 
 struct GraphKey {
-  int kind, B, waves, fc;
+  int kind, B, waves, fc, occ;
   bool operator<(const GraphKey& o) const {
     if (kind != o.kind) return kind < o.kind;
     if (B != o.B) return B < o.B;
     if (waves != o.waves) return waves < o.waves;
-    return fc < o.fc;
+    if (fc != o.fc) return fc < o.fc;
+    return occ < o.occ;
   }
 };
 

@@ -9,7 +9,8 @@ namespace fgl {
 // Exponent tables of the mixed kernel: tab[k] = Q 2^((k - kTabLo)/64) for
 // k in [0, kTabSize), Q = 2^39 - 2^33 (forty octaves below the row maximum
 // down to the maximum itself), then frac[m] = 2^(m/64) / (1 - 2^-6) for
-// m in [0, 64) at tab[kTabSize + m].
+// m in [0, 64) at tab[kTabSize + m], then 1 / frac[m] at
+// tab[kTabSize + kFracSize + m].
 constexpr int kTabLo = 2560;
 constexpr int kTabSize = 2562;
 constexpr int kFracSize = 64;
@@ -41,6 +42,7 @@ struct Tile {
   int waves;   // waves per workgroup: 4 or 8
   int fc;      // frequency channels staged per workgroup
   int group;   // channels per reduction group
+  int occ;     // mixed kernel: waves per SIMD compiled for (2, or 3 with 4 waves)
 };
 
 // Device-side model (all pointers are device memory owned by the model).

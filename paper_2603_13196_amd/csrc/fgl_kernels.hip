@@ -117,8 +117,11 @@ __device__ inline double gauss21(double nu, const RowParams& rp) {
 // Dropped products (significance >= 5) are below 2^-40 of the leading
 // term; the power-law rounding is below 2^-40 of the row's largest power.
 
-template <int W, int KC>
-__global__ __launch_bounds__(W * 64) void k_mixed(DevModel m, Work w, int fc, int G,
+// OCC is the number of waves per SIMD the kernel is compiled for (register
+// budget 512 / OCC).
+template <int W, int KC, int OCC>
+__global__ __launch_bounds__(W * 64)
+__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
                                                   int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -133,9 +136,11 @@ __global__ __launch_bounds__(W * 64) void k_mixed(DevModel m, Work w, int fc, in
   double* s_tab = s_D + (size_t)fc * TT * 32;
   stage(s_kd, m.kd + (size_t)f0 * kbytes, fn * kbytes);
   stage(s_D, m.D + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
-  stage(s_tab, m.tab, (kTabSize + kFracSize) * 8);
+  stage(s_tab, m.tab, (kTabSize + 2 * kFracSize) * 8);
   __syncthreads();
-  const double* s_frac = s_tab + kTabSize;
+  const double* s_tab0 = s_tab + kTabLo;            // s_tab0[jj], jj in [-kTabLo, 0]
+  const double* s_frac = s_tab + kTabSize;          // unit of the level-0 product
+  const double* s_ifrac = s_frac + kFracSize;       // its reciprocal
 
   const int g = lane >> 5;
   const int b = bt * (W * 32) + wave * 32 + (lane & 31);
@@ -158,19 +163,23 @@ __global__ __launch_bounds__(W * 64) void k_mixed(DevModel m, Work w, int fc, in
     const double c = m.t_cmb + rp.A * gauss21(m.nu[fi], rp);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
     double ymax = ceil(bext * nl);
-    int ey = (int)floor(ymax * (1.0 / 64.0));
-    double u0 = ldexp(s_frac[(int)(ymax - 64.0 * ey)], ey + ek - 14);
+    const int ey = (int)floor(ymax * (1.0 / 64.0));
+    const int fm = (int)(ymax - 64.0 * ey);
+    int eu = ey + ek - 14;
+    double ic = c * ldexp(s_ifrac[fm], 8 - eu);   // ~ c / unit of acc0
     int ec;
-    frexp(c / u0 * 256.0, &ec);          // |c| / unit of acc0 < 2^ec
-    if (ec > 29) {                        // constant term dominates: coarser digits
-      ymax += 64.0 * (ec - 29);
-      ey += ec - 29;
-      u0 = ldexp(u0, ec - 29);
+    frexp(ic, &ec);                               // |ic| < 2^ec
+    if (ec > 29) {                                // constant term dominates:
+      ymax += 64.0 * (ec - 29);                   // coarser power-law digits
+      eu += ec - 29;
+      ic = ldexp(ic, 29 - ec);
     }
+    const double u0 = ldexp(s_frac[fm], eu);
     const double s0 = u0 * 0x1.0p-8, s1 = u0 * 0x1.0p-24, s2 = u0 * 0x1.0p-32;
-    const double c0f = rint(c / s0);
+    const double c0f = rint(ic);
     const int c0 = (int)c0f;
-    const int c1 = (int)rint(fma(-c0f, s0, c) / s1);
+    // exact remainder (fma), then to level-3 units; c1 in [-2^15, 2^15]
+    const int c1 = (int)rint(fma(-c0f, s0, c) * ldexp(s_ifrac[fm], 24 - eu));
 
     // power-law digits: the MFMA B operands of this lane (row b, 16 regions
     // per 32-region chunk), five significance levels
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(W * 64) void k_mixed(DevModel m, Work w, int fc, in
         const double t = y + MAGIC;
         const int jj = (int)(uint32_t)__double_as_longlong(t);
         const double r = y - (t - MAGIC);          // |r| <= 1/2
-        const double T2 = s_tab[jj + kTabLo];      // Q 2^(jj/64)
+        const double T2 = s_tab0[jj];              // Q 2^(jj/64)
         double p = fma(r, m.c4, m.c3);
         p = fma(r, p, m.c2);
         p = fma(r, p, m.c1);
@@ -208,49 +217,72 @@ __global__ __launch_bounds__(W * 64) void k_mixed(DevModel m, Work w, int fc, in
       }
     }
 
+    // A wave finishes one time tile before the next; the other waves of its
+    // SIMD overlap their vector work with its matrix work.
     const unsigned char* kf = s_kd + (size_t)f * kbytes + lane * 16;
     const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
-    for (int tt = 0; tt < TT; ++tt) {
-      i32x4 A[4][KC];
+    auto load_A = [&](int tt, i32x4 (&A)[4][KC]) {
 #pragma unroll
       for (int L = 0; L < 4; ++L)
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
-          A[L][kc] = *reinterpret_cast<const i32x4*>(
-              kf + ((L * KC + kc) * TT + tt) * 1024);
-      i32x16 a0 = {}, a1 = {}, a2 = {};
+          A[L][kc] = *reinterpret_cast<const i32x4*>(kf + ((L * KC + kc) * TT + tt) * 1024);
+    };
 #define MF(acc, q, p) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[q][kc], Bop[kc][p], acc, 0, 0, 0)
+    // levels 0, 2 and 4 (no dependence on a shift)
+    auto part1 = [&](const i32x4 (&A)[4][KC], i32x16& a0, i32x16& a1, i32x16& a2) {
+      a0 = i32x16{};
+      a1 = i32x16{};
+      a2 = i32x16{};
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
-        MF(a0, 0, 0);                                      // level 0
-        MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);          // level 2
-        MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);  // level 4
+        MF(a0, 0, 0);
+        MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);
+        MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);
       }
+    };
+    // shift-adds (with the constant term), then levels 1 and 3
+    auto part2 = [&](const i32x4 (&A)[4][KC], i32x16& a0, i32x16& a1) {
       a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)c0);
       a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)c1);
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
-        MF(a0, 0, 1); MF(a0, 1, 0);                        // level 1
-        MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);  // level 3
+        MF(a0, 0, 1); MF(a0, 1, 0);
+        MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);
       }
+    };
 #undef MF
+    auto epi = [&](int tt, const i32x16& a0, const i32x16& a1, const i32x16& a2) {
       const double* Dt = Df + tt * 32;
-      double Dv[16];
+      if (tt == TT - 1 && (m.T & 31)) {           // ragged last tile (uniform)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) Dv[j] = Dt[(j >> 2) * 8 + (j & 3)];
-      const bool ragged = (tt == TT - 1) && (m.T & 31);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        double r = fma(-s0, (double)a0[j], Dv[j]);
-        r = fma(-s1, (double)a1[j], r);
-        r = fma(-s2, (double)a2[j], r);
-        if (ragged) {
+        for (int j = 0; j < 16; ++j) {
+          double r = fma(-s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
+          r = fma(-s1, (double)a1[j], r);
+          r = fma(-s2, (double)a2[j], r);
           const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
           r = t < m.T ? r : 0.0;
+          if (j & 1) acc_b = fma(r, r, acc_b);
+          else acc_a = fma(r, r, acc_a);
         }
-        if (j & 1) acc_b = fma(r, r, acc_b);
-        else acc_a = fma(r, r, acc_a);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double r = fma(-s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
+          r = fma(-s1, (double)a1[j], r);
+          r = fma(-s2, (double)a2[j], r);
+          if (j & 1) acc_b = fma(r, r, acc_b);
+          else acc_a = fma(r, r, acc_a);
+        }
       }
+    };
+    for (int tt = 0; tt < TT; ++tt) {
+      i32x4 A[4][KC];
+      i32x16 x0, x1, x2;
+      load_A(tt, A);
+      part1(A, x0, x1, x2);
+      part2(A, x0, x1);
+      epi(tt, x0, x1, x2);
     }
     // one partial per reduction group of G channels (f0 is a multiple of G)
     if ((f + 1) % G == 0 || f == fn - 1) {
@@ -414,69 +446,99 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 // ---------------------------------------------------------------------------
 // row preparation and finalize
 
-// One thread per padded row: validate, sanitise, transpose the spectral
-// indices to [i][b] and record the row constants.  Invalid rows are given
-// harmless values (their result is overwritten with -inf at finalize).
-__global__ void k_prep(const double* __restrict__ theta, int B, int Bpad,
-                       int N, int P, unsigned flags, int betaRows,
-                       double* __restrict__ betaT, RowParams* __restrict__ rows) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= Bpad) return;
+// Row preparation: validate, sanitise, transpose the spectral indices to
+// [i][b] and record the row constants.  A block of 256 threads takes 64
+// rows: the rows are read coalesced into LDS, one thread per row derives
+// the row record, and all threads write the transposed indices coalesced.
+// Invalid rows are given harmless values (finalize writes -inf for them).
+constexpr int kPrepRows = 64;
+
+__global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, int B, int Bpad,
+                                              int N, int P, unsigned flags, int betaRows,
+                                              double* __restrict__ betaT,
+                                              RowParams* __restrict__ rows) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* s_th = reinterpret_cast<double*>(smem);                 // [64][P]
+  double* s_fill = s_th + (size_t)kPrepRows * P;                 // [64] bmin or 0
+  int* s_ok = reinterpret_cast<int*>(s_fill + kPrepRows);        // [64]
+  const int b0 = blockIdx.x * kPrepRows;
+  const int nrow = max(0, min(kPrepRows, B - b0));
+  for (int k = threadIdx.x; k < nrow * P; k += blockDim.x)
+    s_th[k] = theta[(size_t)b0 * P + k];
+  __syncthreads();
   const bool no21 = flags & 1u;
-  RowParams rp;
-  rp.valid = 0;
-  rp.pad = 0;
-  rp.A = 0.0;
-  rp.nu0 = 0.0;
-  rp.inv_w = 1.0;
-  rp.sigma = 1.0;
-  rp.t21 = no21 ? 0.0 : 1.0;
-  bool ok = b < B;
-  const double* th = theta + (size_t)b * P;
-  if (ok) {
-    for (int k = 0; k < P; ++k) ok = ok && isfinite(th[k]);
-    for (int i = 0; i < N; ++i) ok = ok && fabs(th[i]) <= 64.0;
-    ok = ok && th[P - 1] > 0.0;
-    if (!no21) ok = ok && th[N + 2] > 0.0;
-  }
-  double bmin = 0.0, bmax = 0.0;
-  if (ok) {
-    bmin = bmax = N > 0 ? th[0] : 0.0;
-    for (int i = 1; i < N; ++i) {
-      bmin = fmin(bmin, th[i]);
-      bmax = fmax(bmax, th[i]);
+  if (threadIdx.x < kPrepRows) {
+    const int r = threadIdx.x;
+    const double* th = s_th + (size_t)r * P;
+    bool ok = r < nrow;
+    if (ok) {
+      for (int k = 0; k < P; ++k) ok = ok && isfinite(th[k]);
+      for (int i = 0; i < N; ++i) ok = ok && fabs(th[i]) <= 64.0;
+      ok = ok && th[P - 1] > 0.0;
+      if (!no21) ok = ok && th[N + 2] > 0.0;
     }
-    rp.valid = 1;
-    rp.sigma = th[P - 1];
-    if (!no21) {
-      rp.A = th[N];
-      rp.nu0 = th[N + 1];
-      rp.inv_w = 1.0 / th[N + 2];
+    RowParams rp;
+    rp.valid = ok ? 1 : 0;
+    rp.pad = 0;
+    rp.A = 0.0;
+    rp.nu0 = 0.0;
+    rp.inv_w = 1.0;
+    rp.sigma = 1.0;
+    rp.t21 = no21 ? 0.0 : 1.0;
+    double bmin = 0.0, bmax = 0.0;
+    if (ok) {
+      bmin = bmax = th[0];
+      for (int i = 1; i < N; ++i) {
+        bmin = fmin(bmin, th[i]);
+        bmax = fmax(bmax, th[i]);
+      }
+      rp.sigma = th[P - 1];
+      if (!no21) {
+        rp.A = th[N];
+        rp.nu0 = th[N + 1];
+        rp.inv_w = 1.0 / th[N + 2];
+      }
     }
+    rp.bmin = bmin;
+    rp.bmax = bmax;
+    s_fill[r] = bmin;
+    s_ok[r] = ok ? 1 : 0;
+    if (b0 + r < Bpad) rows[b0 + r] = rp;
   }
-  rp.bmin = bmin;
-  rp.bmax = bmax;
-  for (int i = 0; i < betaRows; ++i)
-    betaT[(size_t)i * Bpad + b] = (ok && i < N) ? th[i] : bmin;
-  rows[b] = rp;
+  __syncthreads();
+  // betaT[i][b]: beta_i for valid rows and i < N, the row's minimum otherwise
+  for (int k = threadIdx.x; k < betaRows * kPrepRows; k += blockDim.x) {
+    const int i = k / kPrepRows, r = k - i * kPrepRows;
+    if (b0 + r >= Bpad) continue;
+    const double v = (s_ok[r] && i < N) ? s_th[(size_t)r * P + i] : s_fill[r];
+    betaT[(size_t)i * Bpad + b0 + r] = v;
+  }
 }
 
-// lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2), with chi2_b the
-// sum of the row's group partials in channel order.
-__global__ void k_finalize(const double* __restrict__ partial, int ngroup,
-                           int Bpad, const RowParams* __restrict__ rows,
-                           int B, double nFT, double* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2).  Sixteen
+// threads per row: thread s sums the partials of groups s, s+16, ... in
+// order, then a fixed xor-shuffle tree adds the sixteen sums, so the
+// result does not depend on timing.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int ngroup,
+                                                  int Bpad, const RowParams* __restrict__ rows,
+                                                  int B, double nFT, double* __restrict__ out) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = gid >> 4, s = gid & 15;
+  double acc = 0.0;
+  if (b < B)
+    for (int c = s; c < ngroup; c += 16) acc += partial[(size_t)c * Bpad + b];
+  acc += __shfl_xor(acc, 8);
+  acc += __shfl_xor(acc, 4);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 1);
+  if (b >= B || s != 0) return;
   const RowParams rp = rows[b];
   if (!rp.valid) {
     out[b] = -INFINITY;
     return;
   }
-  double s = 0.0;
-  for (int c = 0; c < ngroup; ++c) s += partial[(size_t)c * Bpad + b];
   const double s2 = rp.sigma * rp.sigma;
-  out[b] = -0.5 * s / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
+  out[b] = -0.5 * acc / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,7 +551,7 @@ int max_lds_bytes() { return 160 * 1024; }
 int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
   const int d = t.fc * m.TT * 32 * 8;
   switch (k) {
-    case kMixed: return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + kFracSize) * 8;
+    case kMixed: return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + 2 * kFracSize) * 8;
     case kFP32: return t.fc * m.NP2 * m.TT * 64 * 4 + d;
     default: return t.fc * m.NQ * m.TT16 * 64 * 4 + d;
   }
@@ -506,34 +568,37 @@ namespace {
 std::mutex g_attr_mu;
 std::set<const void*> g_attr_done;
 
-// Launch with dynamic LDS.  The LDS limit of a kernel is raised once per
-// process, on its first (never captured) launch.
+// Raise a kernel's dynamic-LDS limit once per process.  The first launch of
+// every kernel is eager (graphs capture only repeated calls), so this never
+// runs during stream capture.
+hipError_t allow_lds(const void* fp) {
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  if (g_attr_done.count(fp)) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     max_lds_bytes());
+  if (e == hipSuccess) g_attr_done.insert(fp);
+  return e;
+}
+
+// Launch with dynamic LDS.
 template <typename KernelT>
 hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
               const DevModel& m, const Work& w, int fc, int G, int nb, int nc) {
-  const void* fp = reinterpret_cast<const void*>(kern);
-  {
-    std::lock_guard<std::mutex> lk(g_attr_mu);
-    if (!g_attr_done.count(fp)) {
-      hipError_t e = hipFuncSetAttribute(fp, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         max_lds_bytes());
-      if (e != hipSuccess) return e;
-      g_attr_done.insert(fp);
-    }
-  }
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(kern));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, s, m, w, fc, G, nb, nc);
   return hipGetLastError();
 }
 
-template <int W>
+template <int W, int OCC>
 hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                    int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
   switch (m.KC) {
-    case 1: return go(k_mixed<W, 1>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_mixed<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 3: return go(k_mixed<W, 3>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_mixed<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go(k_mixed<W, 1, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_mixed<W, 2, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 3: return go(k_mixed<W, 3, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_mixed<W, 4, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -574,9 +639,11 @@ hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
 
 hipError_t launch_prep(const DevModel& m, const double* theta, int B,
                        const Work& w, int betaRows, hipStream_t s) {
-  const int threads = 256;
-  const int blocks = (w.Bpad + threads - 1) / threads;
-  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(threads), 0, s, theta, B,
+  const int blocks = (w.Bpad + kPrepRows - 1) / kPrepRows;
+  const int lds = kPrepRows * (m.P + 1) * 8 + kPrepRows * 4;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_prep));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), lds, s, theta, B,
                      w.Bpad, m.N, m.P, m.flags, betaRows, w.betaT, w.rows);
   return hipGetLastError();
 }
@@ -591,8 +658,8 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
       tile.group < 1 || tile.fc % tile.group != 0 || lds > max_lds_bytes())
     return hipErrorInvalidValue;
   if (k == kMixed) {
-    return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
-                           : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
+    return tile.waves == 8 ? mixed_w<8, 2>(m, w, tile.fc, tile.group, nb, nc, lds, s)
+                           : mixed_w<4, 2>(m, w, tile.fc, tile.group, nb, nc, lds, s);
   } else if (k == kFP32) {
     return tile.waves == 8 ? fp32_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
                            : fp32_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
@@ -605,7 +672,7 @@ hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
                            const Tile& tile, double* out, hipStream_t s) {
   (void)k;
   const int threads = 256;
-  const int blocks = (w.B + threads - 1) / threads;
+  const int blocks = (w.B * 16 + threads - 1) / threads;
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, s, w.partial,
                      n_groups(m, tile), w.Bpad, w.rows, w.B,
                      (double)m.F * (double)m.T, out);

@@ -60,8 +60,11 @@ _SIGS = {
     "fgl_loglike_batch_device": ([_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp],
                                  ctypes.c_int),
     "fgl_get_tile": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                      ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                     ctypes.c_int),
     "fgl_tune": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "fgl_set_tile": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                      ctypes.c_int], ctypes.c_int),
     "fgl_model_bytes": ([_vp], ctypes.c_size_t),
     "fgl_model_destroy": ([_vp], ctypes.c_int),
     "fgl_kernel_timing": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -201,11 +204,16 @@ class Model:
     def tune(self, B: int, prec="mixed"):
         _check(_lib.fgl_tune(self.handle, int(B), _prec(prec)))
 
+    def set_tile(self, B: int, prec, waves: int, chans: int, occupancy: int = 2):
+        _check(_lib.fgl_set_tile(self.handle, int(B), _prec(prec), int(waves), int(chans),
+                                 int(occupancy)))
+
     def tile(self, B: int, prec="mixed"):
-        w, c = ctypes.c_int(), ctypes.c_int()
+        """(waves per workgroup, channels per workgroup, waves per SIMD)."""
+        w, c, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(_lib.fgl_get_tile(self.handle, int(B), _prec(prec), ctypes.byref(w),
-                                 ctypes.byref(c)))
-        return w.value, c.value
+                                 ctypes.byref(c), ctypes.byref(p)))
+        return w.value, c.value, p.value
 
     def kernel_timing(self, enable: bool = True):
         _check(_lib.fgl_kernel_timing(self.handle, int(bool(enable))))
