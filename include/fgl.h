@@ -28,9 +28,16 @@
  *
  * Precision modes:
  *   FGL_PREC_MIXED  the region sum as exact 8-bit integer slices of the
- *                   powers and of K on the matrix cores (int32 sums), the
- *                   residual D - M and the chi-square in FP64.  Agrees with
- *                   an FP64 evaluation within |dlnL| <= 1e-6 |lnL| + 1e-3.
+ *                   powers and of the model's matrix on the matrix cores
+ *                   (int32 sums), the residual and the chi-square in FP64.
+ *                   Agrees with an FP64 evaluation within
+ *                   |dlnL| <= 1e-6 |lnL| + 1e-3.  Two forms give that same
+ *                   quantity (fgl_mixed_form): the direct form evaluates
+ *                   M on the T time bins; the projected form, used when
+ *                   T >= N + 1, N <= 96 and it needs fewer 32-row tiles,
+ *                   evaluates the time sum of each channel exactly in an
+ *                   orthonormal basis of the channel's centred responses
+ *                   (N + 1 rows instead of T).
  *   FGL_PREC_FP32   the model in FP32, residual and chi-square in FP64.
  *   FGL_PREC_FP64   everything in FP64.
  *
@@ -68,7 +75,11 @@ enum {
 
 enum { FGL_PREC_MIXED = 0, FGL_PREC_FP32 = 1, FGL_PREC_FP64 = 2 };
 
-#define FGL_NO_21CM 1u /* model without the 21-cm term: P = N + 1 */
+#define FGL_NO_21CM 1u      /* model without the 21-cm term: P = N + 1 */
+#define FGL_MIXED_DIRECT 2u /* mixed precision: always use the direct form */
+
+/* Forms of the mixed-precision evaluation (fgl_mixed_form). */
+enum { FGL_FORM_DIRECT = 0, FGL_FORM_PROJECTED = 1 };
 
 /*
  * Create a model: the fixed inputs of the likelihood (Sec. 2.2 precomputes
@@ -80,7 +91,8 @@ enum { FGL_PREC_MIXED = 0, FGL_PREC_FP32 = 1, FGL_PREC_FP64 = 2 };
  *   nu_ref reference frequency of the power laws (MHz, > 0).
  *   N      regions, 1..128;  F channels >= 1;  T time bins >= 1.
  *   t_cmb  CMB temperature added to the model (K), finite.
- *   flags  0 or FGL_NO_21CM.
+ *   flags  0, or FGL_NO_21CM and/or FGL_MIXED_DIRECT (keep the direct form
+ *          of the mixed evaluation even where the projected one is shorter).
  * The library copies everything to the device and re-lays it out for its
  * kernels; the caller may free its arrays on return.  *out receives the
  * model, owned by the library until fgl_model_destroy.
@@ -92,6 +104,10 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
 
 /* Parameters per row (N + 4, or N + 1 with FGL_NO_21CM); -1 for NULL. */
 int fgl_model_nparams(const fgl_model* m);
+
+/* Form of the model's mixed-precision evaluation: FGL_FORM_DIRECT or
+ * FGL_FORM_PROJECTED (fixed at creation); FGL_EINVAL for NULL. */
+int fgl_mixed_form(const fgl_model* m);
 
 /*
  * lnL for B rows (Eq. likelihood).

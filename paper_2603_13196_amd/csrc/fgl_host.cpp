@@ -78,6 +78,8 @@ static inline uint32_t digits4(int32_t q) {
   return ((uint32_t)q + 0x808080u) ^ 0x808080u;
 }
 
+static void build_projected(Model* m, const float* K, const double* data);
+
 static void build_layouts(Model* m, const float* K, const double* freqs,
                           const double* data) {
   const int N = m->N, F = m->F, T = m->T;
@@ -174,6 +176,113 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
   m->dm.c2 = (double)(c1 * c1 / 2.0L);
   m->dm.c3 = (double)(c1 * c1 * c1 / 6.0L);
   m->dm.c4 = (double)(c1 * c1 * c1 * c1 / 24.0L);
+  if (m->dm.proj) build_projected(m, K, data);
+}
+
+// Projected form of the mixed kernel.  Per channel, with Kbar_i and Dbar
+// the time means and K~, D~ the centred series (T x N and T), a Householder
+// QR K~ = Q R in long double gives the N x N upper-triangular R and
+// z = Q^T D~.  The matrix rows are [sqrt(T) Kbar ; R] (the last row of R is
+// left out and stored in pk when N is a multiple of 32), the targets are
+// [(row 0 is formed per parameter row) ; z_0 .. z_{N-1}], and the constant
+// sum_{k >= N} z_k^2 over all channels is chi0.
+static inline void digits6(long long q, int8_t out[6]) {
+  // balanced base-256 digits, out[0] most significant: the low five bytes
+  // of q + 0x8080808080 are digit + 128, the rest is the top digit
+  const long long u = q + 0x8080808080LL;
+  for (int L = 1; L < 6; ++L)
+    out[L] = (int8_t)((uint8_t)((u >> (8 * (5 - L))) & 0xff) ^ 0x80);
+  out[0] = (int8_t)(u >> 40);
+}
+
+static void build_projected(Model* m, const float* K, const double* data) {
+  const int N = m->N, F = m->F, T = m->T;
+  DevModel& d = m->dm;
+  const int KC = d.KC, RT = d.RT;
+  const int rows = d.peel ? N : N + 1;              // rows in MFMA tiles
+  const long double sT = std::sqrt((long double)T);
+  m->h_rd.assign((size_t)F * kProjDigits * KC * RT * 1024, 0);
+  m->h_eR.assign(F, 0);
+  m->h_tg.assign((size_t)F * RT * 32, 0.0);
+  m->h_dbar.assign(F, 0.0);
+  m->h_pk.assign((size_t)F * 2, 0.0);
+  long double chi0 = 0.0L;
+  std::vector<long double> A((size_t)N * T), z(T), mat((size_t)rows * N);
+  for (int f = 0; f < F; ++f) {
+    // centred columns, column-major: A[i*T + t]
+    for (int i = 0; i < N; ++i) {
+      long double s = 0.0L;
+      const float* Ki = K + ((size_t)i * F + f) * T;
+      for (int t = 0; t < T; ++t) s += Ki[t];
+      const long double mean = s / T;
+      mat[i] = sT * mean;                            // row 0: sqrt(T) Kbar
+      for (int t = 0; t < T; ++t) A[(size_t)i * T + t] = (long double)Ki[t] - mean;
+    }
+    long double sd = 0.0L;
+    const double* Df = data + (size_t)f * T;
+    for (int t = 0; t < T; ++t) sd += Df[t];
+    const long double dmean = sd / T;
+    for (int t = 0; t < T; ++t) z[t] = (long double)Df[t] - dmean;
+    // Householder QR of the T x N centred block (T >= N + 1)
+    for (int j = 0; j < N; ++j) {
+      long double* a = &A[(size_t)j * T];
+      long double nrm = 0.0L;
+      for (int t = j; t < T; ++t) nrm += a[t] * a[t];
+      nrm = std::sqrt(nrm);
+      if (nrm == 0.0L) continue;                     // column already in span
+      const long double alpha = a[j] > 0.0L ? -nrm : nrm;
+      // v = a[j:] - alpha e_j, stored in place; v^T v = 2 nrm (nrm + |a_j|)
+      const long double vj = a[j] - alpha;
+      const long double vtv = 2.0L * nrm * (nrm + std::fabs(a[j]));
+      a[j] = vj;
+      auto reflect = [&](long double* x) {
+        long double s = 0.0L;
+        for (int t = j; t < T; ++t) s += a[t] * x[t];
+        const long double k = 2.0L * s / vtv;
+        for (int t = j; t < T; ++t) x[t] -= k * a[t];
+      };
+      for (int k = j + 1; k < N; ++k) reflect(&A[(size_t)k * T]);
+      reflect(z.data());
+      a[j] = alpha;                                  // R[j][j]
+      for (int t = j + 1; t < T; ++t) a[t] = 0.0L;
+    }
+    // rows 1.. of the matrix: R[k][i] = A[i*T + k] for i >= k
+    for (int k = 0; k + 1 < rows; ++k)
+      for (int i = 0; i < N; ++i) mat[(size_t)(k + 1) * N + i] = i >= k ? A[(size_t)i * T + k] : 0.0L;
+    long double e2 = 0.0L;
+    for (int t = N; t < T; ++t) e2 += z[t] * z[t];
+    chi0 += e2;
+    if (d.peel) {
+      m->h_pk[2 * f] = (double)A[(size_t)(N - 1) * T + (N - 1)];
+      m->h_pk[2 * f + 1] = (double)z[N - 1];
+    }
+    m->h_dbar[f] = (double)(sT * dmean);
+    for (int k = 1; k < rows; ++k) m->h_tg[(size_t)f * RT * 32 + k] = (double)z[k - 1];
+    // per-channel fixed point and digits [kProjDigits][KC][RT][64][16]
+    long double mx = 0.0L;
+    for (size_t k = 0; k < (size_t)rows * N; ++k) mx = std::max(mx, std::fabs(mat[k]));
+    int er = 0;
+    if (mx > 0.0L) std::frexp((double)mx, &er);
+    if (mx > 0.0L && std::ldexp((long double)1.0L, er) <= mx) ++er;   // mx < 2^er
+    m->h_eR[f] = er;
+    int8_t* base = m->h_rd.data() + (size_t)f * kProjDigits * KC * RT * 1024;
+    for (int kc = 0; kc < KC; ++kc)
+      for (int rt = 0; rt < RT; ++rt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int j = 0; j < 16; ++j) {
+            const int i = kc * 32 + (lane >> 5) * 16 + j;
+            const int k = rt * 32 + (lane & 31);
+            int8_t dg[6] = {0, 0, 0, 0, 0, 0};
+            if (i < N && k < rows) {
+              const long double v = std::ldexp(mat[(size_t)k * N + i], kProjBits - er);
+              digits6(std::llrint(v), dg);
+            }
+            for (int L = 0; L < kProjDigits; ++L)
+              base[(((size_t)L * KC + kc) * RT + rt) * 1024 + lane * 16 + j] = dg[L];
+          }
+  }
+  d.chi0 = (double)chi0;
+  d.sqrtT = (double)sT;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,27 +300,36 @@ static hipError_t upload(T** dptr, const std::vector<T>& h) {
 size_t resident_bytes(const Model* m) {
   return m->h_kd.size() + m->h_eK.size() * 4 + m->h_k32.size() * 4 +
          m->h_k64.size() * 4 + (m->h_nl64.size() + m->h_nl2.size() + m->h_nu.size()) * 8 +
-         m->h_D.size() * 8 + m->h_tab.size() * 8;
+         m->h_D.size() * 8 + m->h_tab.size() * 8 + m->h_rd.size() + m->h_eR.size() * 4 +
+         (m->h_tg.size() + m->h_dbar.size() + m->h_pk.size()) * 8;
 }
 
 int make_resident(Model* m) {
   if (m->resident) return FGL_OK;
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
-  int8_t* kd = nullptr;
-  int32_t* eK = nullptr;
+  int8_t *kd = nullptr, *rd = nullptr;
+  int32_t *eK = nullptr, *eR = nullptr;
   float *k32 = nullptr, *k64 = nullptr;
   double *nl64 = nullptr, *nl2 = nullptr, *nu = nullptr, *D = nullptr, *tab = nullptr;
+  double *tg = nullptr, *dbar = nullptr, *pk = nullptr;
   if ((e = upload(&kd, m->h_kd)) != hipSuccess || (e = upload(&eK, m->h_eK)) != hipSuccess ||
       (e = upload(&k32, m->h_k32)) != hipSuccess || (e = upload(&k64, m->h_k64)) != hipSuccess ||
       (e = upload(&nl64, m->h_nl64)) != hipSuccess || (e = upload(&nl2, m->h_nl2)) != hipSuccess ||
       (e = upload(&nu, m->h_nu)) != hipSuccess || (e = upload(&D, m->h_D)) != hipSuccess ||
-      (e = upload(&tab, m->h_tab)) != hipSuccess) {
-    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab};
+      (e = upload(&tab, m->h_tab)) != hipSuccess || (e = upload(&rd, m->h_rd)) != hipSuccess ||
+      (e = upload(&eR, m->h_eR)) != hipSuccess || (e = upload(&tg, m->h_tg)) != hipSuccess ||
+      (e = upload(&dbar, m->h_dbar)) != hipSuccess || (e = upload(&pk, m->h_pk)) != hipSuccess) {
+    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk};
     for (void* p : ps)
       if (p) (void)hipFree(p);
     return hip_err(e, "uploading model");
   }
+  m->dm.rd = rd;
+  m->dm.eR = eR;
+  m->dm.tg = tg;
+  m->dm.dbar = dbar;
+  m->dm.pk = pk;
   m->dm.kd = kd;
   m->dm.eK = eK;
   m->dm.k32 = k32;
@@ -231,9 +349,13 @@ void evict(Model* m) {
   // device-pointer calls return before their kernels finish
   (void)hipDeviceSynchronize();
   const void* ps[] = {m->dm.kd, m->dm.eK, m->dm.k32, m->dm.k64, m->dm.nl64,
-                      m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab};
+                      m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab, m->dm.rd,
+                      m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
+  m->dm.rd = nullptr;
+  m->dm.eR = nullptr;
+  m->dm.tg = m->dm.dbar = m->dm.pk = nullptr;
   m->dm.kd = nullptr;
   m->dm.eK = nullptr;
   m->dm.k32 = m->dm.k64 = nullptr;
@@ -496,7 +618,7 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
   if (!K || !freqs || !data) return set_err(FGL_EINVAL, "K, freqs and data must be non-NULL");
   if (N < 1 || N > kMixedMaxN) return set_err(FGL_EINVAL, "N=%d outside 1..%d", N, kMixedMaxN);
   if (F < 1 || T < 1) return set_err(FGL_EINVAL, "F=%d and T=%d must be >= 1", F, T);
-  if (flags & ~FGL_NO_21CM) return set_err(FGL_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(FGL_NO_21CM | FGL_MIXED_DIRECT)) return set_err(FGL_EINVAL, "unknown flags 0x%x", flags);
   if (!(nu_ref > 0.0) || !std::isfinite(nu_ref)) return set_err(FGL_EINVAL, "nu_ref must be finite and > 0");
   if (!std::isfinite(t_cmb)) return set_err(FGL_EINVAL, "t_cmb must be finite");
   for (int f = 0; f < F; ++f) {
@@ -534,6 +656,17 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
   d.NQ = (N + 1 + 3) / 4;
   d.t_cmb = t_cmb;
   d.flags = flags;
+  // the projected form when its N + 1 rows take fewer 32-row tiles than T
+  d.proj = d.RT = d.peel = 0;
+  if (!(flags & FGL_MIXED_DIRECT) && N <= kProjMaxN && T >= N + 1) {
+    const int peel = N % 32 == 0 ? 1 : 0;
+    const int RT = (N + 1 - peel + 31) / 32;
+    if (RT < d.TT) {
+      d.proj = 1;
+      d.RT = RT;
+      d.peel = peel;
+    }
+  }
   for (Kind k : {kMixed, kFP32, kFP64}) {
     if (group_of(k, d) == 0) {
       delete m;
@@ -673,6 +806,12 @@ int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
   const Tile tile = tile_for(m, k, B);
   if ((rc = ensure_work(m, wb, B, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
   return enqueue(m, k, tile, wb, d_theta, B, d_out, s);
+}
+
+int fgl_mixed_form(const fgl_model* mh) {
+  if (!mh) return set_err(FGL_EINVAL, "model is NULL");
+  const Model* m = reinterpret_cast<const Model*>(mh);
+  return m->dm.proj ? FGL_FORM_PROJECTED : FGL_FORM_DIRECT;
 }
 
 int fgl_get_tile(fgl_model* mh, int B, int prec, int* waves, int* chans, int* occupancy) {

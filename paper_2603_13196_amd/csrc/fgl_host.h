@@ -62,6 +62,9 @@ struct Model {
   std::vector<int32_t> h_eK;
   std::vector<float> h_k32, h_k64;
   std::vector<double> h_nl64, h_nl2, h_nu, h_D, h_tab;
+  std::vector<int8_t> h_rd;                  // projected form (empty if unused)
+  std::vector<int32_t> h_eR;
+  std::vector<double> h_tg, h_dbar, h_pk;
   // serving bookkeeping
   uint64_t last_use = 0;
   // kernel timing (fgl_kernel_timing)

@@ -14,9 +14,16 @@ namespace fgl {
 constexpr int kTabLo = 2560;
 constexpr int kTabSize = 2562;
 constexpr int kFracSize = 64;
-// Level sums are kept in two int32 accumulators (see fgl_kernels.hip);
-// their range bounds the region count of the mixed kernel.
+// Level sums are kept in int32 accumulators (see fgl_kernels.hip); their
+// range bounds the region count of the mixed kernel: 128 for the direct
+// form, 96 for the projected form (which carries one more level).
 constexpr int kMixedMaxN = 128;
+constexpr int kProjMaxN = 96;
+// Digits of the projected-form matrix and its fixed-point scale: entries
+// are scaled by 2^(kProjBits - eR(nu)) (|entry| < 2^eR) and cut into
+// kProjDigits balanced base-256 digits.
+constexpr int kProjDigits = 6;
+constexpr int kProjBits = 46;
 
 // Per-row parameters written by the prep kernel (one 64-byte record per row).
 struct RowParams {
@@ -42,7 +49,7 @@ struct Tile {
   int waves;   // waves per workgroup: 4 or 8
   int fc;      // frequency channels staged per workgroup
   int group;   // channels per reduction group
-  int occ;     // mixed kernel: waves per SIMD compiled for (2, or 3 with 4 waves)
+  int occ;     // waves per SIMD the kernel is compiled for (2)
 };
 
 // Device-side model (all pointers are device memory owned by the model).
@@ -65,6 +72,19 @@ struct DevModel {
   const double* D;       // [F][TT*32] data, zero padded in t
   const double* tab;     // [kTabSize + kFracSize] exponent tables
   double c1, c2, c3, c4; // Taylor coefficients of 2^(r/64)
+  // projected form of the mixed kernel (proj = 1): per channel, the rows
+  // [sqrt(T) mean_t K ; R] where K~^T = Q R is the QR factorisation of the
+  // time-centred responses, and targets [sqrt(T) mean_t D ; (Q^T D~)_0..]
+  int proj;              // 1: the mixed kernel runs the projected form
+  int RT;                // 32-row tiles of the projected matrix
+  int peel;              // 1: the last row of R (one entry) is done in FP64
+  double sqrtT;
+  double chi0;           // sum over channels of the data's out-of-span part
+  const int8_t* rd;      // digits [F][kProjDigits][KC][RT][64][16]
+  const int32_t* eR;     // [F] per-channel exponent of the digits
+  const double* tg;      // [F][RT*32] targets (row 0 is per parameter row)
+  const double* dbar;    // [F] sqrt(T) mean_t D
+  const double* pk;      // [F][2] peeled diagonal entry and its target
 };
 
 // Per-call workspace (device memory owned by the model, per stream).

@@ -24,13 +24,12 @@
 // Three arithmetic forms share that skeleton:
 //   k_mixed: exact integer slicing.  The powers are computed in FP64,
 //            rounded to 39-bit fixed point relative to the row's largest
-//            power at the channel and cut into five signed 8-bit digits; K
-//            is cut into four digits once, at model creation.  The fourteen
-//            digit products of significance 0..4 run as
+//            power at the channel and cut into five signed 8-bit digits; the
+//            matrix rows (K itself, or an orthonormal projection of it with
+//            N + 1 rows when that is shorter than T) are cut into digits once,
+//            at model creation.  The digit products run as
 //            v_mfma_i32_32x32x32_i8 with exact int32 sums in three
-//            accumulators; the constant term T_CMB + A g enters through the
-//            level-combining shift-adds, and D - M and the chi-square run in
-//            FP64.
+//            accumulators, and the residual and the chi-square run in FP64.
 //   k_fp32:  the model in FP32 (v_mfma_f32_32x32x2_f32, FP32 powers),
 //            residual and chi-square in FP64.
 //   k_fp64:  the model in FP64 (v_mfma_f64_16x16x4_f64, FP64 powers).
@@ -106,36 +105,54 @@ __device__ inline double gauss21(double nu, const RowParams& rp) {
 // [-128, 127]).  One FP64 fma produces all five: t = x Q + (2^52 + 2^31 +
 // 2^23 + 2^15 + 2^7) is an integer-valued double whose low word holds the
 // four low digits offset by 128 and whose high word's low byte holds d0.
-// K at channel nu is scaled by 2^(31 - eK(nu)) and cut into four digits
-// e0..e3 (e0 in [-127, 127]) once, at model creation.
 //
-// Products.  The fourteen digit products of significance p + q <= 4 run on
-// v_mfma_i32_32x32x32_i8; their int32 sums are exact.  Three accumulators
-// hold them: acc0 = S0 2^8 + S1, acc1 = S2 2^8 + S3, acc2 = S4 (S_l is the
-// sum of the products of significance l); the constant T_CMB + A g of the
-// row enters acc0 and acc1 through the shift-adds that combine levels.
-// Dropped products (significance >= 5) are below 2^-40 of the leading
-// term; the power-law rounding is below 2^-40 of the row's largest power.
+// Two forms share the power-law code and the digit products.
+//
+// Direct form (the model on the time grid).  The MFMA rows are time bins:
+// K at channel nu is scaled by 2^(31 - eK(nu)) and cut into four digits
+// e0..e3 (e0 in [-127, 127]) once, at model creation.  The fourteen digit
+// products of significance p + q <= 4 run on v_mfma_i32_32x32x32_i8; their
+// int32 sums are exact.  Three accumulators hold them: acc0 = S0 2^8 + S1,
+// acc1 = S2 2^8 + S3, acc2 = S4 (S_l is the sum of the products of
+// significance l); the constant T_CMB + A g of the row enters acc0 and acc1
+// through the shift-adds that combine levels.  Dropped products
+// (significance >= 5) are below 2^-40 of the leading term; the power-law
+// rounding is below 2^-40 of the row's largest power.
+//
+// Projected form (the residual in an orthonormal basis of each channel).
+// With Kbar, Dbar the time means at channel nu and K~, D~ the centred
+// series, the time sum of (D - M)^2 splits exactly into
+//   T (Dbar - c - Kbar.P)^2 + |D~ - K~^T P|^2,
+// and with the QR factorisation K~^T = Q R (R upper triangular, N x N) the
+// second term is |Q^T D~ - R P|^2 over the first N coordinates plus the
+// data's part outside the span of K~, a constant per model.  The MFMA rows
+// are then the N + 1 rows [sqrt(T) Kbar ; R] instead of T time bins, and the
+// residual of each row is its target [sqrt(T) (Dbar - c) ; (Q^T D~)_k]
+// minus the row's product with P.  R is not exact in a few digits, so its
+// rows are cut into six digits (46-bit fixed point per channel) and the
+// twenty products of significance <= 5 run, in three accumulators
+// S0 2^8 + S1, S2 2^8 + S3, S4 2^8 + S5.  When N is a multiple of 32 the
+// last row of R (a single diagonal entry) is evaluated in FP64 from the
+// same rounded power, so the MFMA rows fill whole tiles.
 
-// OCC is the number of waves per SIMD the kernel is compiled for (register
-// budget 512 / OCC).
-template <int W, int KC, int OCC>
+template <int W, int KC, bool PROJ>
 __global__ __launch_bounds__(W * 64)
-__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
-                                                  int nb, int nc) {
+__attribute__((amdgpu_waves_per_eu(2, 2))) void k_mixed(DevModel m, Work w, int fc, int G,
+                                                int nb, int nc) {
+  constexpr int ND = PROJ ? kProjDigits : 4;       // digits of the matrix rows
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
   map_block(nb, nc, bt, ch);
-  const int TT = m.TT;
+  const int TT = PROJ ? m.RT : m.TT;               // 32-row tiles
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
-  const int kbytes = 4 * KC * TT * 1024;
+  const int kbytes = ND * KC * TT * 1024;
   unsigned char* s_kd = smem;
   double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kbytes);
   double* s_tab = s_D + (size_t)fc * TT * 32;
-  stage(s_kd, m.kd + (size_t)f0 * kbytes, fn * kbytes);
-  stage(s_D, m.D + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
+  stage(s_kd, (PROJ ? m.rd : m.kd) + (size_t)f0 * kbytes, fn * kbytes);
+  stage(s_D, (PROJ ? m.tg : m.D) + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
   stage(s_tab, m.tab, (kTabSize + 2 * kFracSize) * 8);
   __syncthreads();
   const double* s_tab0 = s_tab + kTabLo;            // s_tab0[jj], jj in [-kTabLo, 0]
@@ -158,32 +175,45 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   for (int f = 0; f < fn; ++f) {
     const int fi = f0 + f;
     const double nl = m.nl64[fi];
-    const int ek = m.eK[fi];
+    const int ek = PROJ ? m.eR[fi] : m.eK[fi];
     // row constants at this channel: normalisation, level units, constant term
     const double c = m.t_cmb + rp.A * gauss21(m.nu[fi], rp);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
     double ymax = ceil(bext * nl);
     const int ey = (int)floor(ymax * (1.0 / 64.0));
     const int fm = (int)(ymax - 64.0 * ey);
-    int eu = ey + ek - 14;
-    double ic = c * ldexp(s_ifrac[fm], 8 - eu);   // ~ c / unit of acc0
-    int ec;
-    frexp(ic, &ec);                               // |ic| < 2^ec
-    if (ec > 29) {                                // constant term dominates:
-      ymax += 64.0 * (ec - 29);                   // coarser power-law digits
-      eu += ec - 29;
-      ic = ldexp(ic, 29 - ec);
+    double s0, s1, s2, t0 = 0.0;
+    int c0 = 0, c1 = 0;
+    if constexpr (PROJ) {
+      const double u = ldexp(s_frac[fm], ey + ek + 72 - kProjBits - 39);
+      s0 = u * 0x1.0p-8;
+      s1 = u * 0x1.0p-24;
+      s2 = u * 0x1.0p-40;
+      t0 = m.dbar[fi] - m.sqrtT * c;               // target of the mean row
+    } else {
+      int eu = ey + ek - 14;
+      double ic = c * ldexp(s_ifrac[fm], 8 - eu);   // ~ c / unit of acc0
+      int ec;
+      frexp(ic, &ec);                               // |ic| < 2^ec
+      if (ec > 29) {                                // constant term dominates:
+        ymax += 64.0 * (ec - 29);                   // coarser power-law digits
+        eu += ec - 29;
+        ic = ldexp(ic, 29 - ec);
+      }
+      const double u0 = ldexp(s_frac[fm], eu);
+      s0 = u0 * 0x1.0p-8;
+      s1 = u0 * 0x1.0p-24;
+      s2 = u0 * 0x1.0p-32;
+      const double c0f = rint(ic);
+      c0 = (int)c0f;
+      // exact remainder (fma), then to level-3 units; c1 in [-2^15, 2^15]
+      c1 = (int)rint(fma(-c0f, s0, c) * ldexp(s_ifrac[fm], 24 - eu));
     }
-    const double u0 = ldexp(s_frac[fm], eu);
-    const double s0 = u0 * 0x1.0p-8, s1 = u0 * 0x1.0p-24, s2 = u0 * 0x1.0p-32;
-    const double c0f = rint(ic);
-    const int c0 = (int)c0f;
-    // exact remainder (fma), then to level-3 units; c1 in [-2^15, 2^15]
-    const int c1 = (int)rint(fma(-c0f, s0, c) * ldexp(s_ifrac[fm], 24 - eu));
 
     // power-law digits: the MFMA B operands of this lane (row b, 16 regions
     // per 32-region chunk), five significance levels
     i32x4 Bop[KC][5];
+    double qlast = 0.0;                              // rounded power, last region
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       uint32_t lo[16], hi[16];
@@ -200,6 +230,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
         p = fma(r, p, m.c1);
         p = fma(r, p, 1.0);                        // 2^(r/64)
         const double q = fma(T2, p, DIGITS);       // 2^52 + q + offsets
+        if (PROJ && kc == KC - 1 && j == 15) qlast = q - DIGITS;
         const unsigned long long bits = __double_as_longlong(q);
         lo[j] = (uint32_t)bits ^ 0x80808080u;      // digits d4 d3 d2 d1
         hi[j] = (uint32_t)(bits >> 32);            // low byte: d0
@@ -217,20 +248,20 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       }
     }
 
-    // A wave finishes one time tile before the next; the other waves of its
+    // A wave finishes one row tile before the next; the other waves of its
     // SIMD overlap their vector work with its matrix work.
     const unsigned char* kf = s_kd + (size_t)f * kbytes + lane * 16;
     const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
-    auto load_A = [&](int tt, i32x4 (&A)[4][KC]) {
+    auto load_A = [&](int tt, i32x4 (&A)[ND][KC]) {
 #pragma unroll
-      for (int L = 0; L < 4; ++L)
+      for (int L = 0; L < ND; ++L)
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
           A[L][kc] = *reinterpret_cast<const i32x4*>(kf + ((L * KC + kc) * TT + tt) * 1024);
     };
 #define MF(acc, q, p) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[q][kc], Bop[kc][p], acc, 0, 0, 0)
     // levels 0, 2 and 4 (no dependence on a shift)
-    auto part1 = [&](const i32x4 (&A)[4][KC], i32x16& a0, i32x16& a1, i32x16& a2) {
+    auto part1 = [&](const i32x4 (&A)[ND][KC], i32x16& a0, i32x16& a1, i32x16& a2) {
       a0 = i32x16{};
       a1 = i32x16{};
       a2 = i32x16{};
@@ -239,22 +270,33 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
         MF(a0, 0, 0);
         MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);
         MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);
+        if constexpr (PROJ) MF(a2, 4, 0);
       }
     };
-    // shift-adds (with the constant term), then levels 1 and 3
-    auto part2 = [&](const i32x4 (&A)[4][KC], i32x16& a0, i32x16& a1) {
-      a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)c0);
-      a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)c1);
+    // shift-adds (direct form: with the constant term), then levels 1, 3
+    // (and 5 in the projected form)
+    auto part2 = [&](const i32x4 (&A)[ND][KC], i32x16& a0, i32x16& a1, i32x16& a2) {
+      if constexpr (PROJ) {
+        a0 = (i32x16)((u32x16)a0 << 8u);
+        a1 = (i32x16)((u32x16)a1 << 8u);
+        a2 = (i32x16)((u32x16)a2 << 8u);
+      } else {
+        a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)c0);
+        a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)c1);
+      }
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         MF(a0, 0, 1); MF(a0, 1, 0);
         MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);
+        if constexpr (PROJ) {
+          MF(a2, 1, 4); MF(a2, 2, 3); MF(a2, 3, 2); MF(a2, 4, 1); MF(a2, 5, 0);
+        }
       }
     };
 #undef MF
     auto epi = [&](int tt, const i32x16& a0, const i32x16& a1, const i32x16& a2) {
       const double* Dt = Df + tt * 32;
-      if (tt == TT - 1 && (m.T & 31)) {           // ragged last tile (uniform)
+      if (!PROJ && tt == TT - 1 && (m.T & 31)) {   // ragged last tile (uniform)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           double r = fma(-s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
@@ -268,7 +310,11 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       } else {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          double r = fma(-s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
+          double d = Dt[(j >> 2) * 8 + (j & 3)];
+          // projected form: row 0 (element 0 of the first tile in lanes
+          // 0..31) is the mean row, whose target depends on the row b
+          if (PROJ && j == 0) d = (tt == 0 && g == 0) ? t0 : d;
+          double r = fma(-s0, (double)a0[j], d);
           r = fma(-s1, (double)a1[j], r);
           r = fma(-s2, (double)a2[j], r);
           if (j & 1) acc_b = fma(r, r, acc_b);
@@ -277,12 +323,21 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       }
     };
     for (int tt = 0; tt < TT; ++tt) {
-      i32x4 A[4][KC];
+      i32x4 A[ND][KC];
       i32x16 x0, x1, x2;
       load_A(tt, A);
       part1(A, x0, x1, x2);
-      part2(A, x0, x1);
+      part2(A, x0, x1, x2);
       epi(tt, x0, x1, x2);
+    }
+    if constexpr (PROJ) {
+      // peeled last row of R: R[N-1][N-1] P_{N-1}, P from the same rounding
+      // (region N - 1 = 32 KC - 1 is element 15 of the last chunk, g = 1)
+      if (m.peel) {
+        const double v = ldexp(s_frac[fm], ey - 39) * m.pk[2 * fi];
+        const double r = fma(-v, qlast, m.pk[2 * fi + 1]);
+        acc_a = fma(r, g ? r : 0.0, acc_a);
+      }
     }
     // one partial per reduction group of G channels (f0 is a multiple of G)
     if ((f + 1) % G == 0 || f == fn - 1) {
@@ -515,13 +570,16 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
   }
 }
 
-// lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2).  Sixteen
+// lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2), with chi2_b
+// the sum of the row's partials plus chi0 (a per-model constant of the
+// projected form, 0 otherwise).  Sixteen
 // threads per row: thread s sums the partials of groups s, s+16, ... in
 // order, then a fixed xor-shuffle tree adds the sixteen sums, so the
 // result does not depend on timing.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int ngroup,
                                                   int Bpad, const RowParams* __restrict__ rows,
-                                                  int B, double nFT, double* __restrict__ out) {
+                                                  int B, double nFT, double chi0,
+                                                  double* __restrict__ out) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = gid >> 4, s = gid & 15;
   double acc = 0.0;
@@ -538,7 +596,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     return;
   }
   const double s2 = rp.sigma * rp.sigma;
-  out[b] = -0.5 * acc / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
+  out[b] = -0.5 * (acc + chi0) / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,7 +609,11 @@ int max_lds_bytes() { return 160 * 1024; }
 int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
   const int d = t.fc * m.TT * 32 * 8;
   switch (k) {
-    case kMixed: return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + 2 * kFracSize) * 8;
+    case kMixed:
+      if (m.proj)
+        return t.fc * (kProjDigits * m.KC * m.RT * 1024 + m.RT * 32 * 8) +
+               (kTabSize + 2 * kFracSize) * 8;
+      return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + 2 * kFracSize) * 8;
     case kFP32: return t.fc * m.NP2 * m.TT * 64 * 4 + d;
     default: return t.fc * m.NQ * m.TT16 * 64 * 4 + d;
   }
@@ -590,15 +652,23 @@ hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
   return hipGetLastError();
 }
 
-template <int W, int OCC>
+template <int W>
 hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                    int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
+  if (m.proj) {
+    switch (m.KC) {
+      case 1: return go(k_mixed<W, 1, true>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 2: return go(k_mixed<W, 2, true>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 3: return go(k_mixed<W, 3, true>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (m.KC) {
-    case 1: return go(k_mixed<W, 1, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_mixed<W, 2, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 3: return go(k_mixed<W, 3, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_mixed<W, 4, OCC>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go(k_mixed<W, 1, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_mixed<W, 2, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 3: return go(k_mixed<W, 3, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_mixed<W, 4, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -658,8 +728,8 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
       tile.group < 1 || tile.fc % tile.group != 0 || lds > max_lds_bytes())
     return hipErrorInvalidValue;
   if (k == kMixed) {
-    return tile.waves == 8 ? mixed_w<8, 2>(m, w, tile.fc, tile.group, nb, nc, lds, s)
-                           : mixed_w<4, 2>(m, w, tile.fc, tile.group, nb, nc, lds, s);
+    return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
+                           : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
   } else if (k == kFP32) {
     return tile.waves == 8 ? fp32_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
                            : fp32_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
@@ -670,12 +740,12 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
 
 hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
                            const Tile& tile, double* out, hipStream_t s) {
-  (void)k;
   const int threads = 256;
   const int blocks = (w.B * 16 + threads - 1) / threads;
+  const double chi0 = (k == kMixed && m.proj) ? m.chi0 : 0.0;
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, s, w.partial,
                      n_groups(m, tile), w.Bpad, w.rows, w.B,
-                     (double)m.F * (double)m.T, out);
+                     (double)m.F * (double)m.T, chi0, out);
   return hipGetLastError();
 }
 

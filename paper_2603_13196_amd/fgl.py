@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(HERE, "libfgl.so")
 FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EBUSY, FGL_EDEVICE, FGL_EAGAIN = 0, -1, -2, -3, -4, -5
 FGL_PREC_MIXED, FGL_PREC_FP32, FGL_PREC_FP64 = 0, 1, 2
 FGL_NO_21CM = 1
+FGL_MIXED_DIRECT = 2
+FGL_FORM_DIRECT, FGL_FORM_PROJECTED = 0, 1
 PREC = {"mixed": FGL_PREC_MIXED, "fp32": FGL_PREC_FP32, "fp64": FGL_PREC_FP64}
 _NAMES = {FGL_EINVAL: "EINVAL", FGL_ENOMEM: "ENOMEM", FGL_EBUSY: "EBUSY",
           FGL_EDEVICE: "EDEVICE", FGL_EAGAIN: "EAGAIN"}
@@ -56,6 +58,7 @@ _SIGS = {
                           ctypes.c_int, ctypes.c_double, ctypes.c_uint,
                           ctypes.POINTER(_vp)], ctypes.c_int),
     "fgl_model_nparams": ([_vp], ctypes.c_int),
+    "fgl_mixed_form": ([_vp], ctypes.c_int),
     "fgl_loglike_batch": ([_vp, _dp, ctypes.c_int, _dp, ctypes.c_int], ctypes.c_int),
     "fgl_loglike_batch_device": ([_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp],
                                  ctypes.c_int),
@@ -178,8 +181,13 @@ class Model:
         self.P = _lib.fgl_model_nparams(self.handle)
 
     @classmethod
-    def from_workload(cls, w) -> "Model":
-        return cls(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb)
+    def from_workload(cls, w, flags: int = 0) -> "Model":
+        return cls(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, flags)
+
+    @property
+    def form(self) -> str:
+        """'direct' or 'projected': the form of the mixed evaluation."""
+        return "projected" if _lib.fgl_mixed_form(self.handle) == FGL_FORM_PROJECTED else "direct"
 
     def loglike(self, theta, prec="mixed") -> np.ndarray:
         th = _f64(theta).reshape(-1, self.P)

@@ -26,8 +26,22 @@ def orc():
     return oracle.load()
 
 
-def _model(fgl, w):
-    return fgl.Model(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb)
+def _model(fgl, w, flags=0):
+    return fgl.Model(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, flags)
+
+
+def _mixed_forms(fgl, w, theta, ref, label, expect=None):
+    """The mixed evaluation in both of its forms (the library's choice and
+    the direct form forced by FGL_MIXED_DIRECT) against the oracle."""
+    for flags in (0, fgl.FGL_MIXED_DIRECT):
+        m = _model(fgl, w, flags)
+        form = m.form
+        if flags:
+            assert form == "direct"
+        elif expect is not None:
+            assert form == expect, (label, form)
+        check(m.loglike(theta, "mixed"), ref, "mixed", f"{label}/{form}")
+        m.close()
 
 
 @pytest.mark.parametrize("k", [0, 1])
@@ -58,7 +72,7 @@ def test_headline_shape_reduced_batch(fgl, orc):
     m = _model(fgl, wp)
     for w, kind in ((wp, "prior"), (ws, "shell")):
         ref = orc.loglike_w(w)
-        check(m.loglike(w.theta, "mixed"), ref, "mixed", f"cfg2/{kind}")
+        _mixed_forms(fgl, w, w.theta, ref, f"cfg2/{kind}", expect="projected")
         check(m.loglike(w.theta, "fp64"), ref, "fp64", f"cfg2/{kind}", w.theta, w.F * w.T)
         got32 = m.loglike(w.theta, "fp32")
         d = np.abs(got32 - ref)
@@ -90,26 +104,36 @@ def test_large_config_subsample(fgl, orc):
     rng = np.random.Generator(np.random.PCG64(9))
     idx = np.sort(rng.choice(w.B, 256, replace=False))
     ref = orc.loglike_w(w, w.theta[idx])
+    assert m.form == "projected"
     got = m.loglike(w.theta, "mixed")
     check(got[idx], ref, "mixed", "cfg4/sampled")
-    sh = workload.posterior_shell(4, 256)
-    check(m.loglike(sh.theta, "mixed"), orc.loglike_w(sh), "mixed", "cfg4/shell")
     m.close()
+    md = _model(fgl, w, fgl.FGL_MIXED_DIRECT)
+    check(md.loglike(w.theta, "mixed")[idx], ref, "mixed", "cfg4/sampled/direct")
+    md.close()
+    sh = workload.posterior_shell(4, 256)
+    _mixed_forms(fgl, sh, sh.theta, orc.loglike_w(sh), "cfg4/shell", expect="projected")
 
 
 @pytest.mark.parametrize("N,F,T,B", [
     (1, 7, 1, 1), (3, 5, 2, 257), (31, 13, 31, 300), (32, 9, 32, 64),
     (33, 11, 33, 100), (64, 6, 65, 70), (100, 5, 17, 40), (128, 3, 40, 33),
-    (7, 1, 96, 512), (12, 40, 130, 129)])
+    (7, 1, 96, 512), (12, 40, 130, 129), (32, 6, 40, 100), (32, 5, 33, 64),
+    (40, 9, 96, 200), (70, 4, 100, 50), (96, 3, 130, 40), (1, 3, 50, 65)])
 def test_shapes_and_ragged_tails(fgl, orc, N, F, T, B):
     """Region chunks (N over 32), ragged time tiles, ragged batches, a single
-    channel, a single row, with chromatic K and mixed prior/shell rows."""
+    channel, a single row, with chromatic K and mixed prior/shell rows; the
+    mixed evaluation in both forms wherever the projected one applies
+    (T >= N + 1 with fewer row tiles; with and without the peeled row)."""
     freqs = np.linspace(55.0, 190.0, F) if F > 1 else np.array([123.0])
     w = workload.make(N, freqs, T, B, 1000 + N * 7 + T, chroma=0.05, batch="mixed")
     say(f"shape N={N} F={F} T={T} B={B}")
     ref = orc.loglike_w(w)
+    proj = T >= N + 1 and N <= 96 and (N + 1 - (N % 32 == 0) + 31) // 32 < (T + 31) // 32
+    _mixed_forms(fgl, w, w.theta, ref, f"N{N}F{F}T{T}B{B}",
+                 expect="projected" if proj else "direct")
     m = _model(fgl, w)
-    for prec in PRECS:
+    for prec in ("fp32", "fp64"):
         got = m.loglike(w.theta, prec)
         if prec == "fp32":
             half = B // 2      # prior half only
@@ -167,11 +191,63 @@ def test_edge_rows_and_values(fgl, orc):
     m2.close()
 
 
-def test_no_21cm_flag(fgl, orc):
-    w = workload.config(1, B=512)
+def test_edge_rows_projected_form(fgl, orc):
+    """The projected form on degenerate responses: a region with K = 0, two
+    identical regions (rank-deficient), a region constant in time (zero
+    after centring), data constant in time, T = N + 1, and the invalid and
+    extreme rows of the direct-form edge test."""
+    rng = np.random.Generator(np.random.PCG64(78))
+    for N, T in ((6, 40), (32, 33), (33, 96)):
+        F = 7
+        freqs = np.linspace(60.0, 180.0, F)
+        K = rng.lognormal(2.0, 0.5, size=(N, F, T)).astype(np.float32)
+        K[1] = 0.0
+        K[3] = K[2]
+        K[4] = K[4, :, :1]
+        D = rng.normal(200.0, 5.0, size=(F, T))
+        D[2] = 123.0
+        th = np.zeros((10, N + 4))
+        th[:, :N] = rng.uniform(1.5, 3.5, size=(10, N))
+        th[:, N:] = [-0.1, 120.0, 15.0, 0.05]
+        th[1, N + 3] = 0.0
+        th[2, 3] = np.nan
+        th[3, 0] = -64.0
+        th[4, N] = 1e6
+        th[5, :N] = 0.0
+        th[6, N + 3] = 1e-6
+        m = fgl.Model(K, freqs, D, 230.0, 2.725)
+        say(f"projected edge N={N} T={T}: form={m.form}")
+        assert m.form == "projected"
+        ref = orc.loglike(K, freqs, D, 230.0, 2.725, th)
+        check(m.loglike(th, "mixed"), ref, "mixed", f"proj-edge N{N}T{T}")
+        m.close()
+
+
+def test_nesting_projected_form(fgl, orc):
+    """Strict nesting through the projected form: splitting a region into
+    two halves with the same spectral index leaves lnL unchanged (the split
+    model is rank-deficient)."""
+    w = workload.make(8, np.linspace(50.0, 200.0, 31), 48, 256, 4242, chroma=0.05, batch="mixed")
+    K2 = np.concatenate([w.K[:3], w.K[3:4] * np.float32(0.5), w.K[3:4] * np.float32(0.5), w.K[4:]])
+    th2 = np.concatenate([w.theta[:, :4], w.theta[:, 3:4], w.theta[:, 4:]], axis=1)
+    ref = orc.loglike_w(w)
+    m1 = _model(fgl, w)
+    m2 = fgl.Model(K2, w.freqs, w.data, w.nu_ref, w.t_cmb)
+    assert m1.form == m2.form == "projected"
+    a, b = m1.loglike(w.theta, "mixed"), m2.loglike(th2, "mixed")
+    check(a, ref, "mixed", "nest/original")
+    check(b, ref, "mixed", "nest/split")
+    m1.close()
+    m2.close()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_no_21cm_flag(fgl, orc, k):
+    w = workload.config(k, B=512)
     th = np.concatenate([w.theta[:, :w.N], w.theta[:, -1:]], axis=1)
     m = fgl.Model(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, flags=fgl.FGL_NO_21CM)
     assert m.P == w.N + 1
+    say(f"no21 workload {k}: form={m.form}")
     ref = orc.loglike(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, th, flags=1)
     check(m.loglike(th, "mixed"), ref, "mixed", "no21")
     check(m.loglike(th, "fp64"), ref, "fp64", "no21", th, w.F * w.T)
