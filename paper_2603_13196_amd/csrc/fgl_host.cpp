@@ -493,17 +493,21 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
 }
 
 // Heuristic tile when no measurement is cached: as many waves as registers
-// allow, and the largest channel block that keeps >= 2 workgroups per CU
-// resident and >= 1024 workgroups in flight.
+// allow, and the largest channel block whose LDS still lets the workgroups
+// that registers allow on a CU be resident (the mixed kernel runs two waves
+// per SIMD, so eight waves per CU; the plain kernels are given two
+// workgroups per CU), with >= 1024 workgroups in flight.
 Tile default_tile(Kind k, const DevModel& d, int B) {
   const int G = group_of(k, d);
   const int W = max_waves(k, d);
   Tile best{W, G, G, 2};
   const int cols = cols_per_wave(k) * W;
   const int nb = padded_rows(B) / cols;
-  for (int mult = 1; mult <= 8; ++mult) {
+  const int per_cu = k == kMixed ? std::max(1, 8 / W) : 2;
+  const int lds_cap = max_lds_bytes() / per_cu;
+  for (int mult = 1; mult <= 8; mult *= 2) {
     Tile t{W, G * mult, G, 2};
-    if (lds_bytes(k, d, t) > 80 * 1024) break;
+    if (lds_bytes(k, d, t) > lds_cap) break;
     const int blocks = nb * ((d.F + t.fc - 1) / t.fc);
     if (mult > 1 && blocks < 1024) break;
     best = t;

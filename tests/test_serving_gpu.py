@@ -1,0 +1,187 @@
+"""GPU serving: continuous batching through the C-ABI (fgl_serve_*).
+
+A served result must not depend on what else runs with it: each request's
+output is compared bitwise with the same rows evaluated alone through
+fgl_loglike_batch, and sampled rows with the oracle.  Admission by HBM
+budget with eviction, a model larger than the budget, a host-forced
+failure, destroying a busy model or server, and the argument errors are
+exercised from the host; no case makes a kernel fail.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from tests.gpu_util import check, lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fgl():
+    return lib()
+
+
+def _wait(srv, tickets, timeout_s=120.0):
+    """Poll until every ticket is done; returns {ticket: out or FGLError}."""
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < len(tickets):
+        for t in tickets:
+            if t in got:
+                continue
+            try:
+                r = srv.poll(t)
+            except Exception as e:          # a failed request reports done
+                got[t] = e
+                continue
+            if r is not None:
+                got[t] = r[0]
+        assert time.time() < t_end, f"{len(tickets) - len(got)} requests never completed"
+        time.sleep(1e-4)
+    return got
+
+
+def _requests(clients, per_client, seed):
+    """(client index, rows, precision) for every request, interleaved."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    precs = ("mixed", "mixed", "fp64", "fp32")
+    reqs = []
+    for k in range(per_client):
+        for ci, c in enumerate(clients):
+            B = c.batches[k % len(c.batches)]
+            rows = np.sort(rng.choice(c.work.B, size=B, replace=False))
+            reqs.append((ci, rows, precs[(ci + k) % len(precs)]))
+    return reqs
+
+
+def _run_mix(fgl, clients, models, reqs, budget, inflight):
+    srv = fgl.Server(budget_bytes=budget, max_inflight=inflight)
+    tickets = [srv.submit(models[ci], clients[ci].work.theta[rows], prec)
+               for ci, rows, prec in reqs]
+    got = _wait(srv, tickets)
+    srv.drain()
+    srv.close()
+    return [got[t] for t in tickets]
+
+
+def test_mix_equals_alone(fgl):
+    """Twelve clients of the serving mix (N 4..40, T 1..96, F 151/301, both
+    forms of the mixed evaluation), three requests each with mixed, FP64 and
+    FP32 rows, two slots so that requests queue and merge: every served
+    result is bitwise the result of the same rows alone."""
+    clients = workload.serving_clients(12, n_requests=3, min_B=1, max_B=3000)
+    models = [fgl.Model.from_workload(c.work) for c in clients]
+    say("forms: " + " ".join(f"N{c.work.N}T{c.work.T}:{m.form}" for c, m in zip(clients, models)))
+    reqs = _requests(clients, 3, seed=11)
+    served = _run_mix(fgl, clients, models, reqs, budget=0, inflight=2)
+    orc = oracle.load()
+    for (ci, rows, prec), out in zip(reqs, served):
+        assert not isinstance(out, Exception), out
+        alone = models[ci].loglike(clients[ci].work.theta[rows], prec)
+        assert np.array_equal(out, alone), (ci, prec, rows.size)
+    # sampled rows of the mixed requests against the oracle
+    for (ci, rows, prec), out in zip(reqs[:12], served[:12]):
+        if prec != "mixed":
+            continue
+        w = clients[ci].work
+        sub = rows[:16]
+        ref = orc.loglike_w(w, w.theta[sub])
+        check(out[:16], ref, "mixed", f"served client {ci}")
+    for m in models:
+        m.close()
+
+
+def test_budget_admission_and_eviction(fgl):
+    """An HBM budget of about two models for six: requests wait for room,
+    idle models are evicted and re-uploaded, results are unchanged."""
+    clients = workload.serving_clients(6, n_requests=2, seed=99, min_B=64, max_B=2048)
+    models = [fgl.Model.from_workload(c.work) for c in clients]
+    sizes = sorted(m.nbytes for m in models)
+    budget = sizes[-1] + sizes[-2]
+    say(f"model bytes {sizes}, budget {budget}")
+    reqs = _requests(clients, 2, seed=12)
+    served = _run_mix(fgl, clients, models, reqs, budget=budget, inflight=3)
+    for (ci, rows, prec), out in zip(reqs, served):
+        assert not isinstance(out, Exception), out
+        alone = models[ci].loglike(clients[ci].work.theta[rows], prec)
+        assert np.array_equal(out, alone), (ci, prec)
+    # a model larger than the whole budget is refused at submission
+    srv = fgl.Server(budget_bytes=sizes[0] // 2, max_inflight=1)
+    bi = max(range(len(models)), key=lambda i: models[i].nbytes)
+    with pytest.raises(fgl.FGLError) as e:
+        srv.submit(models[bi], clients[bi].work.theta[:1])
+    assert e.value.code == fgl.FGL_EAGAIN
+    srv.close()
+    for m in models:
+        m.close()
+
+
+def test_forced_failure_is_reported(fgl, monkeypatch):
+    """The request named by FGL_SERVE_FAIL_TICKET fails from the host; the
+    others complete normally."""
+    monkeypatch.setenv("FGL_SERVE_FAIL_TICKET", "3")
+    w = workload.config(1, B=1024)
+    m = fgl.Model.from_workload(w)
+    srv = fgl.Server(max_inflight=2)
+    tickets = [srv.submit(m, w.theta[k * 100:(k + 1) * 100]) for k in range(6)]
+    got = _wait(srv, tickets)
+    for k, t in enumerate(tickets):
+        if t == 3:
+            assert isinstance(got[t], fgl.FGLError) and got[t].code == fgl.FGL_EDEVICE
+        else:
+            assert np.array_equal(got[t], m.loglike(w.theta[k * 100:(k + 1) * 100]))
+    srv.close()
+    m.close()
+
+
+def test_destroy_while_busy(fgl):
+    """fgl_model_destroy and fgl_serve_destroy return FGL_EBUSY, freeing
+    nothing, while requests on them are queued or running; after a drain
+    both succeed and completions stay pollable until then."""
+    wl = workload.config(4, B=65536)
+    blocker = fgl.Model.from_workload(wl)
+    ws = workload.config(0, B=256)
+    small = fgl.Model.from_workload(ws)
+    srv = fgl.Server(max_inflight=1)
+    # one slot: the small model's request waits behind the large launches
+    tb = [srv.submit(blocker, wl.theta) for _ in range(4)]
+    ts = srv.submit(small, ws.theta)
+    rc = fgl._lib.fgl_model_destroy(small.handle)
+    assert rc == fgl.FGL_EBUSY, rc
+    rc = fgl._lib.fgl_serve_destroy(srv.handle)
+    assert rc == fgl.FGL_EBUSY, rc
+    srv.drain()
+    got = _wait(srv, tb + [ts])
+    assert np.array_equal(got[ts], small.loglike(ws.theta))
+    srv.close()
+    small.close()
+    blocker.close()
+
+
+def test_serving_argument_errors(fgl):
+    w = workload.config(0, B=8)
+    m = fgl.Model.from_workload(w)
+    with pytest.raises(fgl.FGLError):
+        fgl.Server(max_inflight=0)
+    srv = fgl.Server(max_inflight=1)
+    with pytest.raises(fgl.FGLError) as e:
+        fgl.fgl_serve_submit(srv.handle, m.handle, w.theta, 0, np.empty(1), "mixed")
+    assert e.value.code == fgl.FGL_EINVAL
+    with pytest.raises(fgl.FGLError) as e:
+        fgl.fgl_serve_submit(srv.handle, m.handle, w.theta, 8, np.empty(8), 9)
+    assert e.value.code == fgl.FGL_EINVAL
+    with pytest.raises(fgl.FGLError) as e:
+        fgl.fgl_serve_poll(srv.handle, 12345)
+    assert e.value.code == fgl.FGL_EINVAL
+    t = srv.submit(m, w.theta)
+    got = _wait(srv, [t])
+    assert np.array_equal(got[t], m.loglike(w.theta))
+    with pytest.raises(fgl.FGLError):       # retired by the poll that reported it
+        fgl.fgl_serve_poll(srv.handle, t)
+    srv.close()
+    m.close()
+    assert os.environ.get("FGL_SERVE_FAIL_TICKET") is None
