@@ -73,15 +73,23 @@ def time_prec(fgl, m, th, out, prec, steps, warmup):
 
 def traffic_from_profiles(kernel_src_hash):
     """HBM bytes per launch of the likelihood kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel."""
-    path = os.path.join(ROOT, "profiles", "k_mixed_N32_F301_T96_B16384_traffic.json")
+    rocprofv3 counter summary (lines "key: value"), if it was taken on the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_mixed_N32_F301_T96_B16384_traffic.txt")
     try:
-        d = json.load(open(path))
-    except (OSError, ValueError):
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("#", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    except OSError:
         return None
-    if d.get("kernel_source_sha256") != kernel_src_hash:
+    if kv.get("kernel_source_sha256") != kernel_src_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def serving_leg(fgl, seconds, log_every=1.0):
@@ -192,6 +200,15 @@ def main():
             gpu_out = out.cpu().numpy().copy()
         log(f"{prec}: {res[prec]['evals_per_s']:.4e} evals/s, "
             f"{res[prec]['ms_per_step']:.4f} ms/step, kernel {res[prec]['kernel_ms']:.4f} ms")
+    form = m.form
+    if not a.no_plain and form == "projected":
+        # the same mixed evaluation in its direct form, for comparison
+        md = fgl.Model.from_workload(w, fgl.FGL_MIXED_DIRECT)
+        if a.tune:
+            md.tune(w.B, "mixed")
+        res["mixed_direct"] = time_prec(fgl, md, th, out, "mixed", a.steps, a.warmup)
+        md.close()
+        log(f"mixed (direct form): {res['mixed_direct']['evals_per_s']:.4e} evals/s")
     mix = res["mixed"]
     # roofline of the likelihood kernel: FP64 work the method needs per
     # evaluation (residual and chi-square: 3 F T; power laws: N F values at
@@ -207,7 +224,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8-mfma+f64", "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "B": w.B,
-                   "precision": "mixed", "tile": dict(zip(("waves", "chans", "occupancy"), m.tile(w.B, "mixed")))},
+                   "precision": "mixed", "form": form,
+                   "tile": dict(zip(("waves", "chans", "occupancy"), m.tile(w.B, "mixed")))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "kernel": "k_mixed",
@@ -219,6 +237,10 @@ def main():
         line["plain_fp64"] = {"value": res["fp64"]["evals_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
                               "kernel_ms": res["fp64"]["kernel_ms"]}
         line["mixed_over_fp32"] = mix["evals_per_s"] / res["fp32"]["evals_per_s"]
+    if "mixed_direct" in res:
+        line["mixed_direct_form"] = {"value": res["mixed_direct"]["evals_per_s"],
+                                     "ms_per_step": res["mixed_direct"]["ms_per_step"],
+                                     "kernel_ms": res["mixed_direct"]["kernel_ms"]}
     m.close()
     if not a.no_serve:
         log("serving leg")

@@ -53,16 +53,18 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Workgroup id -> (row tile, channel chunk).  Consecutive workgroup ids go
 // to different XCDs round-robin; the remap gives every XCD a contiguous run
-// of (chunk, tile) pairs so that the workgroups reading one chunk of K mostly
-// share one XCD's L2.
+// of row tiles, channel chunk fastest, so an XCD reads only its own rows'
+// spectral indices and row records (which then stay in its L2 across all
+// channel chunks) while the chunks of K, shared by all XCDs, are read once
+// per XCD.
 __device__ inline void map_block(int nb, int nc, int& bt, int& ch) {
   const int total = nb * nc;
   const int id = blockIdx.x;
   const int xcd = id & 7, k = id >> 3;
   const int q = total >> 3, rem = total & 7;
   const int L = xcd * q + (xcd < rem ? xcd : rem) + k;
-  ch = L / nb;
-  bt = L - ch * nb;
+  bt = L / nc;
+  ch = L - bt * nc;
 }
 
 // Cooperative 16-byte copy global -> LDS (bytes is a multiple of 16).
