@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
+PRECS = ("mixed", "fp32", "fp64")
 EXP_FLOPS = 20               # FP64 flops counted per power-law value
 
 
@@ -40,7 +41,8 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--serve-seconds", type=float, default=3.0)
     p.add_argument("--cpu-seconds", type=float, default=10.0)
-    p.add_argument("--tune", action="store_true", help="autotune tiles before timing")
+    p.add_argument("--no-tune", action="store_true",
+                   help="time the default tiles instead of the autotuned ones")
     p.add_argument("--calib-copy", action="store_true",
                    help="only run a 256 MiB device-to-device copy three times "
                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -190,8 +192,8 @@ def main():
     m = fgl.Model.from_workload(w)
     th = torch.from_numpy(w.theta).cuda()
     out = torch.empty(w.B, dtype=torch.float64, device="cuda")
-    if a.tune:
-        for prec in ("mixed", "fp32", "fp64"):
+    if not a.no_tune:
+        for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
             m.tune(w.B, prec)
     res = {}
     for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
@@ -204,7 +206,7 @@ def main():
     if not a.no_plain and form == "projected":
         # the same mixed evaluation in its direct form, for comparison
         md = fgl.Model.from_workload(w, fgl.FGL_MIXED_DIRECT)
-        if a.tune:
+        if not a.no_tune:
             md.tune(w.B, "mixed")
         res["mixed_direct"] = time_prec(fgl, md, th, out, "mixed", a.steps, a.warmup)
         md.close()
@@ -217,6 +219,7 @@ def main():
     achieved = flops / (mix["kernel_ms"] * 1e-3) / 1e12
     src = open(os.path.join(ROOT, "paper_2603_13196_amd", "csrc", "fgl_kernels.hip"), "rb").read()
     traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+    tiles = {p: dict(zip(("waves", "chans", "occupancy"), m.tile(w.B, p))) for p in res if p in PRECS}
     line = {
         "metric": "logL evals/s at N=32,F=301,T=96 (mixed vs plain); serve p50/p99 latency",
         "value": mix["evals_per_s"], "unit": "evals/s", "n_gpus": 1,
@@ -224,8 +227,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8-mfma+f64", "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "B": w.B,
-                   "precision": "mixed", "form": form,
-                   "tile": dict(zip(("waves", "chans", "occupancy"), m.tile(w.B, "mixed")))},
+                   "precision": "mixed", "form": form, "tiles": tiles,
+                   "tuned": not a.no_tune},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "kernel": "k_mixed",

@@ -124,27 +124,25 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
           }
   }
   // FP32 A operands [F][NP2][TT][64]: lane -> (t = tt*32 + lane%32,
-  // i = 2k + lane/32); region N is the constant column (1 for t < T)
+  // i = 2k + lane/32); regions >= N and times >= T are zero
   m->h_k32.assign((size_t)F * NP2 * TT * 64, 0.0f);
   for (int f = 0; f < F; ++f)
     for (int k = 0; k < NP2; ++k)
       for (int tt = 0; tt < TT; ++tt)
         for (int lane = 0; lane < 64; ++lane) {
           const int i = 2 * k + (lane >> 5), t = tt * 32 + (lane & 31);
-          float v = 0.0f;
-          if (t < T) v = i < N ? Kat(i, f, t) : (i == N ? 1.0f : 0.0f);
+          const float v = (t < T && i < N) ? Kat(i, f, t) : 0.0f;
           m->h_k32[(((size_t)f * NP2 + k) * TT + tt) * 64 + lane] = v;
         }
   // FP64 A operands (exact FP32 values) [F][NQ][TT16][64]: lane ->
-  // (t = tt*16 + lane%16, i = 4k + lane/16)
+  // (t = tt*16 + lane%16, i = 4k + lane/16); regions >= N are zero
   m->h_k64.assign((size_t)F * NQ * TT16 * 64, 0.0f);
   for (int f = 0; f < F; ++f)
     for (int k = 0; k < NQ; ++k)
       for (int tt = 0; tt < TT16; ++tt)
         for (int lane = 0; lane < 64; ++lane) {
           const int i = 4 * k + (lane >> 4), t = tt * 16 + (lane & 15);
-          float v = 0.0f;
-          if (t < T) v = i < N ? Kat(i, f, t) : (i == N ? 1.0f : 0.0f);
+          const float v = (t < T && i < N) ? Kat(i, f, t) : 0.0f;
           m->h_k64[(((size_t)f * NQ + k) * TT16 + tt) * 64 + lane] = v;
         }
   // per-channel constants
@@ -460,7 +458,7 @@ Kind kind_of(int prec) {
 // Largest wave count whose kernel fits in registers without spilling.
 static int max_waves(Kind k, const DevModel& d) {
   if (k == kMixed) return d.KC <= 2 ? 8 : 4;
-  if (k == kFP32) return d.NP2 <= 48 ? 8 : 4;
+  if (k == kFP32) return 8;
   return 8;
 }
 
@@ -656,8 +654,8 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
   d.TT = (T + 31) / 32;
   d.TT16 = (T + 15) / 16;
   d.KC = (N + 31) / 32;
-  d.NP2 = (N + 1 + 1) / 2;
-  d.NQ = (N + 1 + 3) / 4;
+  d.NP2 = fp32_slots(N);
+  d.NQ = fp64_slots(N);
   d.t_cmb = t_cmb;
   d.flags = flags;
   // the projected form when its N + 1 rows take fewer 32-row tiles than T

@@ -36,6 +36,21 @@ struct RowParams {
   int32_t pad;
 };
 
+// Compiled operand slot counts of the plain kernels: region pairs (FP32) and
+// region quads (FP64), rounded up; padded regions have K = 0.
+inline int fp32_slots(int N) {
+  const int n = (N + 1) / 2;
+  for (int s : {2, 4, 8, 12, 16, 24, 32, 48, 64})
+    if (n <= s) return s;
+  return 0;
+}
+inline int fp64_slots(int N) {
+  const int n = (N + 3) / 4;
+  for (int s : {1, 2, 4, 6, 8, 12, 16, 24, 32})
+    if (n <= s) return s;
+  return 0;
+}
+
 // Kernel families behind one entry point.
 enum Kind { kMixed = 0, kFP32 = 1, kFP64 = 2 };
 
@@ -58,13 +73,13 @@ struct DevModel {
   int TT;            // 32-row time tiles (mixed, FP32)
   int TT16;          // 16-row time tiles (FP64)
   int KC;            // 32-region chunks (mixed)
-  int NP2;           // region pairs incl. the constant column (FP32)
-  int NQ;            // region quads incl. the constant column (FP64)
+  int NP2;           // region pairs, rounded up to a compiled size (FP32)
+  int NQ;            // region quads, rounded up to a compiled size (FP64)
   double t_cmb;
   unsigned flags;
   const int8_t* kd;      // mixed digits [F][4][KC][TT][64][16]
   const int32_t* eK;     // [F] per-channel exponent of the digits
-  const float* k32;      // FP32 A-operands [F][NP2][TT][64]
+  const float* k32;      // FP32 A-operands [F][NP2][TT][64], zero-padded regions
   const float* k64;      // FP64 A-operands, as exact FP32 [F][NQ][TT16][64]
   const double* nl64;    // [F] -64 log2(nu/nu_ref)
   const double* nl2;     // [F] -log2(nu/nu_ref)

@@ -354,6 +354,11 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mixed(DevModel m, Work w, int 
 
 // ---------------------------------------------------------------------------
 // plain FP32 model (FP64 residual and chi-square)
+//
+// The region sum runs as v_mfma_f32_32x32x2_f32 over NPB region pairs (the
+// model's pair count rounded up to a compiled size; padded regions have
+// K = 0 and unit powers).  The constant T_CMB + A g is added to the FP32 sum
+// in the epilogue, then D - M and the chi-square run in FP64.
 
 template <int W, int NPB>
 __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int G,
@@ -362,10 +367,10 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
   map_block(nb, nc, bt, ch);
-  const int TT = m.TT, NP2 = m.NP2, N = m.N;
+  const int TT = m.TT, N = m.N;
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
-  const int kfl = NP2 * TT * 64;            // floats per channel
+  const int kfl = NPB * TT * 64;            // floats per channel
   float* s_k = reinterpret_cast<float*>(smem);
   double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kfl * 4);
   stage(s_k, m.k32 + (size_t)f0 * kfl, fn * kfl * 4);
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
 #pragma unroll
   for (int k = 0; k < NPB; ++k) {
     const int i = 2 * k + g;
-    betaf[k] = (k < NP2 && i < N) ? (float)w.betaT[(size_t)i * w.Bpad + b] : 0.0f;
+    betaf[k] = i < N ? (float)w.betaT[(size_t)i * w.Bpad + b] : 0.0f;
   }
   double acc0 = 0.0, acc1 = 0.0;
   for (int f = 0; f < fn; ++f) {
@@ -388,24 +393,22 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
     const float c = (float)(m.t_cmb + rp.A * gauss21(m.nu[fi], rp));
     float Bp[NPB];
 #pragma unroll
-    for (int k = 0; k < NPB; ++k) {
-      const int i = 2 * k + g;
-      const float p = __builtin_amdgcn_exp2f(betaf[k] * nl);
-      Bp[k] = i < N ? p : (i == N ? c : 0.0f);
-    }
+    for (int k = 0; k < NPB; ++k) Bp[k] = __builtin_amdgcn_exp2f(betaf[k] * nl);
     const float* kf = s_k + (size_t)f * kfl + lane;
     const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
     for (int tt = 0; tt < TT; ++tt) {
+      float Ak[NPB];
+#pragma unroll
+      for (int k = 0; k < NPB; ++k) Ak[k] = kf[(k * TT + tt) * 64];
       f32x16 a = {};
 #pragma unroll
       for (int k = 0; k < NPB; ++k)
-        if (k < NP2)
-          a = __builtin_amdgcn_mfma_f32_32x32x2f32(kf[(k * TT + tt) * 64], Bp[k], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_32x32x2f32(Ak[k], Bp[k], a, 0, 0, 0);
       const double* Dt = Df + tt * 32;
       const bool ragged = (tt == TT - 1) && (m.T & 31);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double r = Dt[(j >> 2) * 8 + (j & 3)] - (double)a[j];
+        double r = Dt[(j >> 2) * 8 + (j & 3)] - (double)(a[j] + c);
         if (ragged) {
           const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
           r = t < m.T ? r : 0.0;
@@ -427,6 +430,10 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
 
 // ---------------------------------------------------------------------------
 // plain FP64 model
+//
+// v_mfma_f64_16x16x4_f64 over NQB region quads (padded as above; K staged as
+// its exact FP32 values and widened in registers), the constant term added in
+// the FP64 epilogue.
 
 template <int W, int NQB>
 __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int G,
@@ -435,10 +442,10 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
   map_block(nb, nc, bt, ch);
-  const int TT16 = m.TT16, NQ = m.NQ, N = m.N;
+  const int TT16 = m.TT16, N = m.N;
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
-  const int kdl = NQ * TT16 * 64;           // values per channel
+  const int kdl = NQB * TT16 * 64;          // values per channel
   float* s_k = reinterpret_cast<float*>(smem);
   double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kdl * 4);
   stage(s_k, m.k64 + (size_t)f0 * kdl, fn * kdl * 4);
@@ -452,7 +459,7 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 #pragma unroll
   for (int k = 0; k < NQB; ++k) {
     const int i = 4 * k + g;
-    beta[k] = (k < NQ && i < N) ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
+    beta[k] = i < N ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
   }
   double acc0 = 0.0, acc1 = 0.0;
   for (int f = 0; f < fn; ++f) {
@@ -462,25 +469,23 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
     const double c = m.t_cmb + rp.A * exp(-0.5 * z * z);
     double Bp[NQB];
 #pragma unroll
-    for (int k = 0; k < NQB; ++k) {
-      const int i = 4 * k + g;
-      const double p = exp2(beta[k] * nl);
-      Bp[k] = i < N ? p : (i == N ? c : 0.0);
-    }
+    for (int k = 0; k < NQB; ++k) Bp[k] = exp2(beta[k] * nl);
     const float* kf = s_k + (size_t)f * kdl + lane;
     // 16x16 FP64 MFMA output: register j of lane l holds row l/16 + 4 j
     const double* Df = s_D + (size_t)f * m.TT * 32 + g;
     for (int tt = 0; tt < TT16; ++tt) {
+      float Ak[NQB];
+#pragma unroll
+      for (int k = 0; k < NQB; ++k) Ak[k] = kf[(k * TT16 + tt) * 64];
       f64x4 a = {};
 #pragma unroll
       for (int k = 0; k < NQB; ++k)
-        if (k < NQ)
-          a = __builtin_amdgcn_mfma_f64_16x16x4f64((double)kf[(k * TT16 + tt) * 64], Bp[k], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Ak[k], Bp[k], a, 0, 0, 0);
       const double* Dt = Df + tt * 16;
       const bool ragged = (tt == TT16 - 1) && (m.T & 15);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        double r = Dt[4 * j] - a[j];
+        double r = (Dt[4 * j] - c) - a[j];
         if (ragged) {
           const int t = tt * 16 + g + 4 * j;
           r = t < m.T ? r : 0.0;
@@ -679,32 +684,36 @@ template <int W>
 hipError_t fp32_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
-  const int n = m.NP2;
-  if (n <= 4) return go(k_fp32<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 8) return go(k_fp32<W, 8>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 12) return go(k_fp32<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 17) return go(k_fp32<W, 17>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 24) return go(k_fp32<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 33) return go(k_fp32<W, 33>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 48) return go(k_fp32<W, 48>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 65) return go(k_fp32<W, 65>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  return hipErrorInvalidValue;
+  switch (m.NP2) {
+    case 2: return go(k_fp32<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_fp32<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_fp32<W, 8>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_fp32<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_fp32<W, 16>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_fp32<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 32: return go(k_fp32<W, 32>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 48: return go(k_fp32<W, 48>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 64: return go(k_fp32<W, 64>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int W>
 hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
-  const int n = m.NQ;
-  if (n <= 2) return go(k_fp64<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 4) return go(k_fp64<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 6) return go(k_fp64<W, 6>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 9) return go(k_fp64<W, 9>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 12) return go(k_fp64<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 17) return go(k_fp64<W, 17>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 24) return go(k_fp64<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  if (n <= 33) return go(k_fp64<W, 33>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-  return hipErrorInvalidValue;
+  switch (m.NQ) {
+    case 1: return go(k_fp64<W, 1>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_fp64<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_fp64<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 6: return go(k_fp64<W, 6>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_fp64<W, 8>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_fp64<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_fp64<W, 16>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_fp64<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 32: return go(k_fp64<W, 32>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
