@@ -474,40 +474,48 @@ int group_of(Kind k, const DevModel& d) {
 }
 
 // Candidate tiles for the tuner: waves in {4, 8} (within register limits),
-// channels per workgroup a multiple of the group fitting in LDS.
+// channels per workgroup a multiple of the group fitting in LDS, and for the
+// projected mixed kernel with one region chunk also the variant compiled for
+// three waves per SIMD (with the LDS of the workgroups that then share a CU).
 std::vector<Tile> candidates(Kind k, const DevModel& d) {
   std::vector<Tile> out;
   const int G = group_of(k, d);
   if (G == 0) return out;
+  const bool occ3 = k == kMixed && d.proj && d.KC == 1;
   for (int w : {4, 8}) {
     if (w > max_waves(k, d)) continue;
-    for (int mult = 1; mult <= 8; ++mult) {
-      Tile t{w, G * mult, G, 2};
-      if (lds_bytes(k, d, t) > max_lds_bytes()) break;
-      if (mult <= 2 || mult == 4 || mult == 8) out.push_back(t);
+    for (int occ = 2; occ <= (occ3 ? 3 : 2); ++occ) {
+      const int per_cu = occ == 3 ? std::max(1, 12 / w) : 1;
+      for (int mult = 1; mult <= 8; ++mult) {
+        Tile t{w, G * mult, G, occ};
+        if (lds_bytes(k, d, t) * per_cu > max_lds_bytes()) break;
+        if (mult <= 2 || mult == 4 || mult == 8) out.push_back(t);
+      }
     }
   }
   return out;
 }
 
 // Heuristic tile when no measurement is cached: as many waves as registers
-// allow, and the largest channel block whose LDS still lets the workgroups
-// that registers allow on a CU be resident (the mixed kernel runs two waves
-// per SIMD, so eight waves per CU; the plain kernels are given two
-// workgroups per CU), with >= 1024 workgroups in flight.
+// allow (the projected mixed kernel with one region chunk in its
+// three-waves-per-SIMD variant), and the largest channel block whose LDS
+// still lets the workgroups that registers allow on a CU be resident (the
+// mixed kernel's 8-wave workgroups run one per CU; the plain kernels are
+// given two workgroups per CU), with >= 2048 workgroups in flight.
 Tile default_tile(Kind k, const DevModel& d, int B) {
   const int G = group_of(k, d);
   const int W = max_waves(k, d);
-  Tile best{W, G, G, 2};
+  const int occ = (k == kMixed && d.proj && d.KC == 1) ? 3 : 2;
+  Tile best{W, G, G, occ};
   const int cols = cols_per_wave(k) * W;
   const int nb = padded_rows(B) / cols;
-  const int per_cu = k == kMixed ? std::max(1, 8 / W) : 2;
+  const int per_cu = k == kMixed ? std::max(1, 4 * occ / W) : 2;   // workgroups per CU
   const int lds_cap = max_lds_bytes() / per_cu;
   for (int mult = 1; mult <= 8; mult *= 2) {
-    Tile t{W, G * mult, G, 2};
+    Tile t{W, G * mult, G, occ};
     if (lds_bytes(k, d, t) > lds_cap) break;
     const int blocks = nb * ((d.F + t.fc - 1) / t.fc);
-    if (mult > 1 && blocks < 1024) break;
+    if (mult > 1 && blocks < 2048) break;
     best = t;
   }
   return best;

@@ -38,6 +38,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <type_traits>
 #include <set>
 
 namespace fgl {
@@ -137,10 +138,12 @@ __device__ inline double gauss21(double nu, const RowParams& rp) {
 // last row of R (a single diagonal entry) is evaluated in FP64 from the
 // same rounded power, so the MFMA rows fill whole tiles.
 
-template <int W, int KC, bool PROJ>
+// OCC: waves per SIMD the register allocation targets (2, or 3 for the
+// projected form with one region chunk, which fits in 168 registers).
+template <int W, int KC, bool PROJ, int OCC>
 __global__ __launch_bounds__(W * 64)
-__attribute__((amdgpu_waves_per_eu(2, 2))) void k_mixed(DevModel m, Work w, int fc, int G,
-                                                int nb, int nc) {
+__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
+                                                    int nb, int nc) {
   constexpr int ND = PROJ ? kProjDigits : 4;       // digits of the matrix rows
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -213,16 +216,22 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mixed(DevModel m, Work w, int 
     }
 
     // power-law digits: the MFMA B operands of this lane (row b, 16 regions
-    // per 32-region chunk), five significance levels
+    // per 32-region chunk), five significance levels.  Exponents below the
+    // table (x < 2^-40, digits all zero) are clamped to its end; the clamp
+    // is skipped when no lane of the wave can reach it at this channel.
+    const double ylow = (nl > 0.0 ? rp.bmin : rp.bmax) * nl - ymax;
+    const bool clamp = __builtin_amdgcn_ballot_w64(ylow < -(double)kTabLo) != 0;
     i32x4 Bop[KC][5];
     double qlast = 0.0;                              // rounded power, last region
+    auto digits = [&](auto clamp_c) {
+    constexpr bool CL = decltype(clamp_c)::value;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       uint32_t lo[16], hi[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         double y = fma(beta[kc][j], nl, -ymax);    // 64 log2(x), <= 0
-        y = fmax(y, -(double)kTabLo);
+        if (CL) y = fmax(y, -(double)kTabLo);
         const double t = y + MAGIC;
         const int jj = (int)(uint32_t)__double_as_longlong(t);
         const double r = y - (t - MAGIC);          // |r| <= 1/2
@@ -249,6 +258,11 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mixed(DevModel m, Work w, int 
         Bop[kc][0][m4] = (int32_t)(h01 | (h23 << 16));
       }
     }
+    };
+    if (clamp)
+      digits(std::true_type{});
+    else
+      digits(std::false_type{});
 
     // A wave finishes one row tile before the next; the other waves of its
     // SIMD overlap their vector work with its matrix work.
@@ -661,21 +675,23 @@ hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
 
 template <int W>
 hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
-                   int nc, int lds, hipStream_t s) {
+                   int nc, int occ, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
   if (m.proj) {
     switch (m.KC) {
-      case 1: return go(k_mixed<W, 1, true>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 2: return go(k_mixed<W, 2, true>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 3: return go(k_mixed<W, 3, true>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 1:
+        return occ == 3 ? go(k_mixed<W, 1, true, 3>, blocks, th, lds, s, m, w, fc, G, nb, nc)
+                        : go(k_mixed<W, 1, true, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 2: return go(k_mixed<W, 2, true, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 3: return go(k_mixed<W, 3, true, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
       default: return hipErrorInvalidValue;
     }
   }
   switch (m.KC) {
-    case 1: return go(k_mixed<W, 1, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_mixed<W, 2, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 3: return go(k_mixed<W, 3, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_mixed<W, 4, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go(k_mixed<W, 1, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_mixed<W, 2, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 3: return go(k_mixed<W, 3, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_mixed<W, 4, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -739,8 +755,8 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
       tile.group < 1 || tile.fc % tile.group != 0 || lds > max_lds_bytes())
     return hipErrorInvalidValue;
   if (k == kMixed) {
-    return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
-                           : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
+    return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s)
+                           : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s);
   } else if (k == kFP32) {
     return tile.waves == 8 ? fp32_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
                            : fp32_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);
