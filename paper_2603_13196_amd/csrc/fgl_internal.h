@@ -14,6 +14,7 @@ namespace fgl {
 constexpr int kTabLo = 2560;
 constexpr int kTabSize = 2562;
 constexpr int kFracSize = 64;
+constexpr int kTabBytes = (kTabSize + 2 * kFracSize) * 8;   // a multiple of 16
 // Level sums are kept in int32 accumulators (see fgl_kernels.hip); their
 // range bounds the region count of the mixed kernel: 128 for the direct
 // form, 96 for the projected form (which carries one more level).

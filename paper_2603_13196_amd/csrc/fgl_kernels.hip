@@ -153,12 +153,14 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
   const int kbytes = ND * KC * TT * 1024;
-  unsigned char* s_kd = smem;
-  double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kbytes);
-  double* s_tab = s_D + (size_t)fc * TT * 32;
+  // LDS: the exponent tables at offset 0 (so a table byte offset is an LDS
+  // address), then the channels' matrix digits and data
+  double* s_tab = reinterpret_cast<double*>(smem);
+  unsigned char* s_kd = smem + kTabBytes;
+  double* s_D = reinterpret_cast<double*>(s_kd + (size_t)fc * kbytes);
+  stage(s_tab, m.tab, kTabBytes);
   stage(s_kd, (PROJ ? m.rd : m.kd) + (size_t)f0 * kbytes, fn * kbytes);
   stage(s_D, (PROJ ? m.tg : m.D) + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
-  stage(s_tab, m.tab, (kTabSize + 2 * kFracSize) * 8);
   __syncthreads();
   const double* s_tab0 = s_tab + kTabLo;            // s_tab0[jj], jj in [-kTabLo, 0]
   const double* s_frac = s_tab + kTabSize;          // unit of the level-0 product
@@ -177,12 +179,21 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   const double MAGIC = 0x1.8p52;                        // rint via the low word
   const double DIGITS = 0x1.0p52 + (double)0x80808080u;  // digit offsets
   double acc_a = 0.0, acc_b = 0.0;
+  // per-channel scalars, fetched one channel ahead
+  double nl_n = m.nl64[f0], nu_n = m.nu[f0];
+  int ek_n = PROJ ? m.eR[f0] : m.eK[f0];
   for (int f = 0; f < fn; ++f) {
     const int fi = f0 + f;
-    const double nl = m.nl64[fi];
-    const int ek = PROJ ? m.eR[fi] : m.eK[fi];
+    const double nl = nl_n, nuf = nu_n;
+    const int ek = ek_n;
+    {
+      const int fx = min(fi + 1, m.F - 1);
+      nl_n = m.nl64[fx];
+      nu_n = m.nu[fx];
+      ek_n = PROJ ? m.eR[fx] : m.eK[fx];
+    }
     // row constants at this channel: normalisation, level units, constant term
-    const double c = m.t_cmb + rp.A * gauss21(m.nu[fi], rp);
+    const double c = m.t_cmb + rp.A * gauss21(nuf, rp);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
     double ymax = ceil(bext * nl);
     const int ey = (int)floor(ymax * (1.0 / 64.0));
