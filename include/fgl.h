@@ -209,6 +209,36 @@ int fgl_serve_drain(fgl_server* s);
 /* Destroy the server: FGL_EBUSY while requests are pending or in flight. */
 int fgl_serve_destroy(fgl_server* s);
 
+/*
+ * Slice-sampling chains on the device (the replacement step of batched
+ * nested sampling, Sec. 3.1.2 and Sec. 3.1.3).  Sampler coordinates are the
+ * parameter row with its last entry (sigma) replaced by log sigma; the prior
+ * is uniform over the box [lo, hi] in those coordinates.
+ *
+ * fgl_chains_create: an engine for model m with room for max_chains chains;
+ *   lo, hi host [P] (finite, lo < hi), copied; seed keys the chains' Philox
+ *   random streams.  The model cannot be destroyed while the engine exists
+ *   (fgl_model_destroy returns FGL_EBUSY).
+ * fgl_chains_run: n chains start at x0 (host [n][P], inside the box) with
+ *   lnL l0 (host [n]) and each takes `steps` hit-and-run slice steps under
+ *   lnL > lstar, directions drawn in the geometry of chol (host [P][P],
+ *   row-major lower-triangular factor of the live points' covariance), the
+ *   likelihood evaluated in precision prec.  x_out, l_out (host [n][P], [n])
+ *   receive the end points and their lnL; *evals (optional) the number of
+ *   in-box proposals evaluated, *rounds (optional) the batched rounds run.
+ *   Synchronous.  FGL_EAGAIN if chains did not finish within a generous
+ *   bound of rounds (a likelihood that is nowhere above lstar near a start).
+ * fgl_chains_destroy: releases the engine.
+ */
+typedef struct fgl_chains fgl_chains;  /* opaque, library-owned */
+int fgl_chains_create(fgl_model* m, int max_chains, const double* lo,
+                      const double* hi, uint64_t seed, fgl_chains** out);
+int fgl_chains_run(fgl_chains* c, const double* x0, const double* l0, int n,
+                   double lstar, const double* chol, int steps, int prec,
+                   double* x_out, double* l_out, int64_t* evals,
+                   int64_t* rounds);
+int fgl_chains_destroy(fgl_chains* c);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* fgl_last_error(void);
 

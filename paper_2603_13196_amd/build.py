@@ -1,7 +1,7 @@
 """Build the HIP library ``libfgl.so`` in-tree for gfx950 with hipcc.
 
 Usage: ``python -m paper_2603_13196_amd.build`` (or ``build()`` from Python).
-The three translation units compile in parallel and are linked into one
+The translation units compile in parallel and are linked into one
 shared library next to this file.
 """
 from __future__ import annotations
@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfgl.so")
-SOURCES = ["fgl_kernels.hip", "fgl_host.cpp", "fgl_serve.cpp"]
+SOURCES = ["fgl_kernels.hip", "fgl_host.cpp", "fgl_serve.cpp", "fgl_chains.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in device code.

@@ -79,6 +79,12 @@ _SIGS = {
                        ctypes.c_int),
     "fgl_serve_drain": ([_vp], ctypes.c_int),
     "fgl_serve_destroy": ([_vp], ctypes.c_int),
+    "fgl_chains_create": ([_vp, ctypes.c_int, _dp, _dp, ctypes.c_uint64, ctypes.POINTER(_vp)],
+                          ctypes.c_int),
+    "fgl_chains_run": ([_vp, _dp, _dp, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int,
+                        ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_int64),
+                        ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "fgl_chains_destroy": ([_vp], ctypes.c_int),
     "fgl_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -283,3 +289,48 @@ class Server:
         if self.handle is not None:
             fgl_serve_destroy(self.handle)
             self.handle = None
+
+
+class Chains:
+    """Slice-sampling chains on the device for a resident model
+    (fgl_chains_*): the replacement step of batched nested sampling."""
+
+    def __init__(self, model: Model, max_chains: int, lo, hi, seed: int = 0):
+        lo, hi = _f64(lo), _f64(hi)
+        if lo.size != model.P or hi.size != model.P:
+            raise ValueError("lo and hi need one entry per parameter")
+        h = _vp()
+        _check(_lib.fgl_chains_create(model.handle, int(max_chains), lo.ctypes.data_as(_dp),
+                                      hi.ctypes.data_as(_dp), ctypes.c_uint64(seed),
+                                      ctypes.byref(h)))
+        self.handle = h
+        self.model = model
+        self.P = model.P
+
+    def run(self, x0, l0, lstar: float, chol, steps: int, prec="mixed"):
+        """(x [n, P], lnL [n], in-box evaluations, rounds) after `steps` slice
+        steps of each chain from x0 under lnL > lstar."""
+        x0 = _f64(x0).reshape(-1, self.P)
+        l0 = _f64(l0)
+        chol = _f64(chol).reshape(self.P, self.P)
+        n = x0.shape[0]
+        x = np.empty_like(x0)
+        lx = np.empty(n)
+        ev, rounds = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.fgl_chains_run(self.handle, x0.ctypes.data_as(_dp), l0.ctypes.data_as(_dp),
+                                   n, float(lstar), chol.ctypes.data_as(_dp), int(steps),
+                                   _prec(prec), x.ctypes.data_as(_dp), lx.ctypes.data_as(_dp),
+                                   ctypes.byref(ev), ctypes.byref(rounds)))
+        return x, lx, ev.value, rounds.value
+
+    def close(self):
+        if self.handle is not None:
+            _check(_lib.fgl_chains_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle is not None:
+                _lib.fgl_chains_destroy(self.handle)
+        except Exception:
+            pass
