@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--serve-seconds", type=float, default=3.0)
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--no-sampler", action="store_true",
+                   help="skip the nested-sampling run (10 regions, T = 1, benchmark settings)")
     p.add_argument("--no-tune", action="store_true",
                    help="time the default tiles instead of the autotuned ones")
     p.add_argument("--calib-copy", action="store_true",
@@ -141,6 +143,36 @@ def serving_leg(fgl, seconds, log_every=1.0):
             "p50_ms": float(np.percentile(lat, 50)) / 1e3,
             "p99_ms": float(np.percentile(lat, 99)) / 1e3,
             "evals_per_s": rows / wall, "seconds": wall, "max_inflight": 8}
+
+
+def sampler_leg(fgl, regions=10, T=1):
+    """One nested-sampling run with the slice chains on the device, at the
+    paper's benchmark hyperparameters (n_live = 25 d, num_inner_steps = 5 d,
+    num_delete = n_live / 5) on a synthetic model with `regions` regions."""
+    import math
+    import workload
+    from paper_2603_13196_amd import sampler as ns
+    w = workload.make(regions, workload.freq_grid(50.0, 200.0, 1.0), T, 8, 1234 + regions + T,
+                      batch="prior")
+    m = fgl.Model.from_workload(w)
+    lo, hi = ns.foreground_box(w.N)
+    d = lo.size
+    n_live, inner = 25 * d, 5 * d
+    b = n_live // 5
+    ch = ns.gpu_chains(m, lo, hi, b, "mixed", seed=1)
+    t0 = time.perf_counter()
+    r = ns.nested_slice_sampling(ns.model_loglike(m, "mixed"), lo, hi, n_live=n_live,
+                                 num_delete=b, num_inner_steps=inner, seed=2, chains=ch)
+    dt = time.perf_counter() - t0
+    zt = np.concatenate([w.truth[:-1], [math.log(w.truth[-1])]])[None, :]
+    l_truth = float(m.loglike(ns.to_theta(zt), "mixed")[0])
+    ch.engine.close()
+    m.close()
+    return {"model": f"N{regions}_F{w.F}_T{T}", "d": d, "n_live": n_live, "num_delete": b,
+            "num_inner_steps": inner, "seconds": dt, "iterations": r.iterations,
+            "likelihood_evals": r.n_like, "evals_per_s": r.n_like / dt,
+            "logz": r.logz, "logz_err": r.logz_err,
+            "max_lnL_found": float(r.dead_logl.max()), "lnL_at_truth": l_truth}
 
 
 def cpu_leg(w, gpu_out, seconds):
@@ -248,6 +280,9 @@ def main():
     if not a.no_serve:
         log("serving leg")
         line["serving"] = serving_leg(fgl, a.serve_seconds)
+    if not a.no_sampler:
+        log("nested sampling leg")
+        line["nested_sampling"] = sampler_leg(fgl)
     if not a.no_cpu:
         log("cpu baseline leg")
         cb, par = cpu_leg(w, gpu_out, a.cpu_seconds)

@@ -106,12 +106,15 @@ __device__ void new_step(const ChainState& s, int i) {
   const int P = s.P;
   double* d = s.dir + (size_t)i * P;
   double nrm = 0.0;
+  // the direction needs randomness, not precision: the Box-Muller pairs are
+  // formed with the FP32 hardware transcendentals
   for (int k = 0; k < P; k += 2) {
     double u0, u1;
     uniform2(s, i, u0, u1);
-    const double rad = sqrt(-2.0 * log(1.0 - u0));     // 1 - u0 in (0, 1]
-    const double ang = 6.283185307179586 * u1;
-    const double z0 = rad * cos(ang), z1 = rad * sin(ang);
+    const float v = (float)(1.0 - u0);                  // in (0, 1]
+    const float rad = __builtin_sqrtf(-2.0f * __logf(v));
+    const float ang = 6.2831853f * (float)u1;
+    const double z0 = (double)(rad * __cosf(ang)), z1 = (double)(rad * __sinf(ang));
     d[k] = z0;
     nrm += z0 * z0;
     if (k + 1 < P) {
