@@ -48,6 +48,17 @@ class Oracle:
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_uint, dp, dp]
         lib.oracle_model.restype = ctypes.c_int
+        lib.oracle_loglike_masks.argtypes = [fp, dp, dp, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_uint, dp,
+                                             ctypes.c_int, dp, ctypes.c_int]
+        lib.oracle_loglike_masks.restype = ctypes.c_int
+        lib.oracle_model_masks.argtypes = [fp, dp, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_uint, dp, dp]
+        lib.oracle_model_masks.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         self._lib = lib
 
@@ -86,13 +97,51 @@ class Oracle:
             flags, th.ctypes.data_as(dp), m.ctypes.data_as(dp))
         return m if rc == 0 else None
 
+    def loglike_masks(self, K, freqs, data, nu_ref, t_cmb, theta,
+                      flags: int = 0, threads: int = 0) -> np.ndarray:
+        """Amplitude masks crossed with spectral-index masks:
+        K [n_alpha, n_beta, F, T]; rows [beta.., alpha.., A, nu21, w, sigma]."""
+        K = np.ascontiguousarray(K, dtype=np.float32)
+        freqs, data, theta = self._f64(freqs), self._f64(data), self._f64(theta)
+        NA, NB, F, T = K.shape
+        theta = theta.reshape(-1, theta.shape[-1])
+        B = theta.shape[0]
+        out = np.empty(B, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = self._lib.oracle_loglike_masks(
+            K.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            freqs.ctypes.data_as(dp), data.ctypes.data_as(dp),
+            float(nu_ref), float(t_cmb), NA, NB, F, T, flags,
+            theta.ctypes.data_as(dp), B, out.ctypes.data_as(dp), int(threads))
+        if rc != 0:
+            raise RuntimeError(f"oracle_loglike_masks failed ({rc})")
+        return out
+
+    def model_masks(self, K, freqs, nu_ref, t_cmb, theta_row,
+                    flags: int = 0) -> Optional[np.ndarray]:
+        K = np.ascontiguousarray(K, dtype=np.float32)
+        freqs, th = self._f64(freqs), self._f64(theta_row)
+        NA, NB, F, T = K.shape
+        m = np.empty((F, T), dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = self._lib.oracle_model_masks(
+            K.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            freqs.ctypes.data_as(dp), float(nu_ref), float(t_cmb), NA, NB, F, T,
+            flags, th.ctypes.data_as(dp), m.ctypes.data_as(dp))
+        return m if rc == 0 else None
+
     def max_threads(self) -> int:
         return int(self._lib.oracle_max_threads())
 
     # convenience on a workload object
     def loglike_w(self, w, theta=None, threads: int = 0) -> np.ndarray:
-        return self.loglike(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb,
-                            w.theta if theta is None else theta,
+        th = w.theta if theta is None else theta
+        na = getattr(w, "n_alpha", 0)
+        if na:
+            K4 = w.K.reshape(na, w.N // na, w.F, w.T)
+            return self.loglike_masks(K4, w.freqs, w.data, w.nu_ref, w.t_cmb,
+                                      th, threads=threads)
+        return self.loglike(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, th,
                             threads=threads)
 
 

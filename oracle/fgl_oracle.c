@@ -11,28 +11,37 @@
  * What it computes, for every parameter row b (Tutt et al.):
  *
  *   g(nu)      = exp(-(nu - nu21)^2 / (2 w^2))               Eq. t21model
- *   T_FG       = sum_i K[i,nu,t] (nu/nu_ref)^(-beta_i) + T_CMB
- *                                        Eq. fast_forward_model, with the
- *                amplitude masks collapsed to one (alpha = 1), as the paper
- *                fits spectral-index masks only (end of Sec. 2.2)
+ *   T_FG       = sum_i sum_j alpha_i K[i,j,nu,t] (nu/nu_ref)^(-beta_j) + T_CMB
+ *                                                  Eq. fast_forward_model
  *   M(nu,t)    = T_FG(nu,t) + A g(nu)          definition after Eq. likelihood
  *   lnL        = -1/2 sum_{nu,t} [ ln(2 pi sigma^2) + (D - M)^2 / sigma^2 ]
  *                                                            Eq. likelihood
  *
- * Parameter row layout: [beta_0 .. beta_{N-1}, A, nu21, w, sigma]
- * (the region indices, the three 21-cm parameters of Eq. t21model and the
- * noise level of Eq. likelihood; sigma is linear, in K).  With flag bit 0
- * (no 21-cm term) the row is [beta_0 .. beta_{N-1}, sigma].
+ * Two parameterisations of the masks (Sec. 2.2):
  *
- * A row with sigma <= 0, w <= 0, any non-finite entry, or a spectral index
- * outside [-64, 64] gets lnL = -inf.  The paper does not define these rows;
- * they have zero prior mass (its spectral-index prior spans 2.458-3.146), and
- * the index bound keeps every power of a frequency ratio within 2^+-8 inside
- * the double range.
+ *  - spectral-index masks only (the paper's fits, end of Sec. 2.2): one
+ *    amplitude mask with alpha = 1, K[j,nu,t] for j < N, and the row
+ *    [beta_0 .. beta_{N-1}, A, nu21, w, sigma];
+ *  - n_alpha amplitude masks crossed with n_beta spectral-index masks:
+ *    K[i,j,nu,t] at K + ((i n_beta + j) F + nu) T, and the row
+ *    [beta_0 .. beta_{n_beta-1}, alpha_0 .. alpha_{n_alpha-1}, A, nu21, w,
+ *    sigma].
+ *
+ * The three 21-cm parameters are those of Eq. t21model and sigma is the
+ * noise level of Eq. likelihood (linear, in K).  With flag bit 0 (no 21-cm
+ * term) they are left out and the row ends with sigma alone.
+ *
+ * A row with sigma <= 0, w <= 0, any non-finite entry, a spectral index
+ * outside [-64, 64] or an amplitude scale outside [2^-32, 2^32] gets
+ * lnL = -inf.  The paper does not define these rows; they have zero prior
+ * mass (its spectral-index prior spans 2.458-3.146; alpha is a gain
+ * correction near one), and the bounds keep every term inside the double
+ * range.
  *
  * All arithmetic is IEEE double.  Powers use pow(); the region sum runs in
- * ascending i; the chi-square is summed over (nu, t) in row-major order with
- * Neumaier's compensated summation.
+ * ascending (i, j), each term formed as (alpha_i K) times the power; the
+ * chi-square is summed over (nu, t) in row-major order with Neumaier's
+ * compensated summation.
  */
 #include <math.h>
 #include <stddef.h>
@@ -56,49 +65,65 @@ static void nm_add(neumaier_t *a, double x)
     a->s = t;
 }
 
-static int row_valid(const double *th, int P, int N, unsigned flags)
+/* Parameter count of a row. */
+static int n_params(int NA, int NB, unsigned flags)
+{
+    return NB + NA + ((flags & ORACLE_NO_21CM) ? 1 : 4);
+}
+
+static int row_valid(const double *th, int P, int NA, int NB, unsigned flags)
 {
     for (int k = 0; k < P; ++k)
         if (!isfinite(th[k])) return 0;
-    for (int i = 0; i < N; ++i)
-        if (fabs(th[i]) > 64.0) return 0;
+    for (int j = 0; j < NB; ++j)
+        if (fabs(th[j]) > 64.0) return 0;
+    for (int i = 0; i < NA; ++i) {
+        double a = th[NB + i];
+        if (!(a >= 0x1p-32 && a <= 0x1p32)) return 0;
+    }
     double sigma = th[P - 1];
     if (!(sigma > 0.0)) return 0;
     if (!(flags & ORACLE_NO_21CM)) {
-        double w = th[N + 2];
+        double w = th[P - 2];
         if (!(w > 0.0)) return 0;
     }
     return 1;
 }
 
-/* Model M(nu, t) of one parameter row into m[F*T].  Returns 0, or -1 when
- * the row is invalid (m is then left untouched). */
-int oracle_model(const float *K, const double *freqs, double nu_ref,
-                 double t_cmb, int N, int F, int T, unsigned flags,
-                 const double *theta_row, double *m)
+/* Model M(nu, t) of one parameter row into m[F*T], with NA amplitude masks
+ * (NA = 0: none, alpha = 1) and NB spectral-index masks.  Returns 0, or -1
+ * when the row is invalid (m is then left untouched). */
+int oracle_model_masks(const float *K, const double *freqs, double nu_ref,
+                       double t_cmb, int NA, int NB, int F, int T,
+                       unsigned flags, const double *theta_row, double *m)
 {
-    int P = (flags & ORACLE_NO_21CM) ? N + 1 : N + 4;
-    if (!row_valid(theta_row, P, N, flags)) return -1;
-    const double *beta = theta_row;
-    double *powv = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    int P = n_params(NA, NB, flags);
+    if (!row_valid(theta_row, P, NA, NB, flags)) return -1;
+    const double *beta = theta_row;              /* beta_j, j < NB */
+    const double *alpha = theta_row + NB;        /* alpha_i, i < NA */
+    int n_amp = NA > 0 ? NA : 1;                 /* amplitude masks */
+    double *powv = (double *)malloc(sizeof(double) * (size_t)(NB > 0 ? NB : 1));
     if (!powv) return -2;
     for (int f = 0; f < F; ++f) {
         double nu = freqs[f];
         double ratio = nu / nu_ref;
-        for (int i = 0; i < N; ++i)
-            powv[i] = pow(ratio, -beta[i]);          /* (nu/nu_ref)^(-beta_i) */
+        for (int j = 0; j < NB; ++j)
+            powv[j] = pow(ratio, -beta[j]);          /* (nu/nu_ref)^(-beta_j) */
         double sig21 = 0.0;
         if (!(flags & ORACLE_NO_21CM)) {
-            double A = theta_row[N], nu21 = theta_row[N + 1], w = theta_row[N + 2];
+            double A = theta_row[P - 4], nu21 = theta_row[P - 3], w = theta_row[P - 2];
             double dv = nu - nu21;
             sig21 = A * exp(-(dv * dv) / (2.0 * w * w));
         }
         double *row = m + (size_t)f * T;
         for (int t = 0; t < T; ++t) row[t] = 0.0;
-        for (int i = 0; i < N; ++i) {                 /* ascending i */
-            const float *Ki = K + ((size_t)i * F + f) * T;
-            for (int t = 0; t < T; ++t)
-                row[t] += (double)Ki[t] * powv[i];
+        for (int i = 0; i < n_amp; ++i) {             /* ascending (i, j) */
+            double a = NA > 0 ? alpha[i] : 1.0;
+            for (int j = 0; j < NB; ++j) {
+                const float *Kij = K + (((size_t)i * NB + j) * F + f) * T;
+                for (int t = 0; t < T; ++t)
+                    row[t] += (a * (double)Kij[t]) * powv[j];
+            }
         }
         for (int t = 0; t < T; ++t)
             row[t] = row[t] + t_cmb + sig21;
@@ -107,14 +132,24 @@ int oracle_model(const float *K, const double *freqs, double nu_ref,
     return 0;
 }
 
+/* The spectral-index-only model: N masks, alpha = 1. */
+int oracle_model(const float *K, const double *freqs, double nu_ref,
+                 double t_cmb, int N, int F, int T, unsigned flags,
+                 const double *theta_row, double *m)
+{
+    return oracle_model_masks(K, freqs, nu_ref, t_cmb, 0, N, F, T, flags,
+                              theta_row, m);
+}
+
 /* lnL of one row, given the data D[F*T]; scratch m[F*T]. */
 static double loglike_row(const float *K, const double *freqs,
                           const double *D, double nu_ref, double t_cmb,
-                          int N, int F, int T, unsigned flags,
+                          int NA, int NB, int F, int T, unsigned flags,
                           const double *theta_row, double *m)
 {
-    int P = (flags & ORACLE_NO_21CM) ? N + 1 : N + 4;
-    if (oracle_model(K, freqs, nu_ref, t_cmb, N, F, T, flags, theta_row, m) != 0)
+    int P = n_params(NA, NB, flags);
+    if (oracle_model_masks(K, freqs, nu_ref, t_cmb, NA, NB, F, T, flags,
+                           theta_row, m) != 0)
         return -INFINITY;
     double sigma = theta_row[P - 1];
     neumaier_t chi2 = {0.0, 0.0};
@@ -127,15 +162,16 @@ static double loglike_row(const float *K, const double *freqs,
     return -0.5 * (chi2.s + chi2.c) / s2 - 0.5 * n * log(2.0 * M_PI * s2);
 }
 
-/* lnL for B rows of theta[B][P] into out[B].  nthreads <= 0 uses the
- * OpenMP default; 1 runs serially.  Returns 0, or -1 on bad sizes. */
-int oracle_loglike(const float *K, const double *freqs, const double *D,
-                   double nu_ref, double t_cmb, int N, int F, int T,
-                   unsigned flags, const double *theta, int B, double *out,
-                   int nthreads)
+/* lnL for B rows of theta[B][P] into out[B] (masks as in
+ * oracle_model_masks).  nthreads <= 0 uses the OpenMP default; 1 runs
+ * serially.  Returns 0, or -1 on bad sizes. */
+int oracle_loglike_masks(const float *K, const double *freqs, const double *D,
+                         double nu_ref, double t_cmb, int NA, int NB, int F,
+                         int T, unsigned flags, const double *theta, int B,
+                         double *out, int nthreads)
 {
-    if (N < 0 || F <= 0 || T <= 0 || B < 0) return -1;
-    int P = (flags & ORACLE_NO_21CM) ? N + 1 : N + 4;
+    if (NA < 0 || NB < 0 || F <= 0 || T <= 0 || B < 0) return -1;
+    int P = n_params(NA, NB, flags);
     int fail = 0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -151,12 +187,22 @@ int oracle_loglike(const float *K, const double *freqs, const double *D,
         } else {
 #pragma omp for schedule(dynamic, 4)
             for (int b = 0; b < B; ++b)
-                out[b] = loglike_row(K, freqs, D, nu_ref, t_cmb, N, F, T,
+                out[b] = loglike_row(K, freqs, D, nu_ref, t_cmb, NA, NB, F, T,
                                      flags, theta + (size_t)b * P, m);
             free(m);
         }
     }
     return fail ? -2 : 0;
+}
+
+/* The spectral-index-only likelihood: N masks, alpha = 1. */
+int oracle_loglike(const float *K, const double *freqs, const double *D,
+                   double nu_ref, double t_cmb, int N, int F, int T,
+                   unsigned flags, const double *theta, int B, double *out,
+                   int nthreads)
+{
+    return oracle_loglike_masks(K, freqs, D, nu_ref, t_cmb, 0, N, F, T, flags,
+                                theta, B, out, nthreads);
 }
 
 /* Number of OpenMP threads a parallel region would use (1 without OpenMP). */

@@ -300,7 +300,160 @@ def pin_batch_rows(orc):
     assert c[0] == a[4]
 
 
+# ---------------------------------------------------------------------------
+# amplitude masks crossed with spectral-index masks (Eq. fast_forward_model
+# with n_alpha > 0): K [n_alpha, n_beta, F, T], rows
+# [beta_0.., alpha_0.., A, nu21, w, sigma]
+
+def _rand_theta_masks(rng, NA, NB, B=1, alo=0.5, ahi=2.0):
+    th = np.empty((B, NB + NA + 4))
+    th[:, :NB] = rng.uniform(2.0, 3.5, size=(B, NB))
+    th[:, NB:NB + NA] = rng.uniform(alo, ahi, size=(B, NA))
+    th[:, NB + NA] = rng.uniform(-0.5, 0.0, size=B)
+    th[:, NB + NA + 1] = rng.uniform(50, 200, size=B)
+    th[:, NB + NA + 2] = rng.uniform(5, 40, size=B)
+    th[:, NB + NA + 3] = np.exp(rng.uniform(math.log(1e-3), math.log(0.1), size=B))
+    return th
+
+
+def mp_model_masks(K4, freqs, nu_ref, t_cmb, th):
+    """50-digit evaluation of Eq. fast_forward_model with both mask sets,
+    plus Eq. t21model."""
+    NA, NB, F, T = K4.shape
+    beta = [mp.mpf(float(b)) for b in th[:NB]]
+    alpha = [mp.mpf(float(a)) for a in th[NB:NB + NA]]
+    A, nu0, w = (mp.mpf(float(v)) for v in th[NB + NA:NB + NA + 3])
+    out = [[None] * T for _ in range(F)]
+    for f in range(F):
+        nu = mp.mpf(float(freqs[f]))
+        x = nu / mp.mpf(float(nu_ref))
+        p = [mp.power(x, -b) for b in beta]
+        s21 = A * mp.exp(-(nu - nu0) ** 2 / (2 * w * w))
+        for t in range(T):
+            acc = mp.mpf(0)
+            for i in range(NA):
+                for j in range(NB):
+                    acc += alpha[i] * mp.mpf(float(K4[i, j, f, t])) * p[j]
+            out[f][t] = acc + mp.mpf(float(t_cmb)) + s21
+    return out
+
+
+def pin_masks_brute_force(orc, seeds=range(5)):
+    """Tiny problems with 1-3 amplitude masks and 1-3 spectral-index masks
+    against 50-digit mpmath: lnL to 1e-13 and every model value to 1e-14
+    relative."""
+    for s in seeds:
+        rng = _rng(300 + s)
+        NA, NB = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+        F, T = int(rng.integers(1, 5)), int(rng.integers(1, 4))
+        K, freqs = _rand_problem(rng, NA * NB, F, T)
+        K4 = K.reshape(NA, NB, F, T)
+        th = _rand_theta_masks(rng, NA, NB, 3)
+        D = rng.normal(40.0, 10.0, size=(F, T))
+        got = orc.loglike_masks(K4, freqs, D, 230.0, 2.725, th)
+        for b in range(3):
+            mm = mp_model_masks(K4, freqs, 230.0, 2.725, th[b])
+            sig = mp.mpf(float(th[b, -1]))
+            chi2 = mp.mpf(0)
+            for f in range(F):
+                for t in range(T):
+                    r = mp.mpf(float(D[f, t])) - mm[f][t]
+                    chi2 += r * r
+            ref = -chi2 / (2 * sig * sig) - mp.mpf(F * T) / 2 * mp.log(2 * mp.pi * sig * sig)
+            assert _relerr(got[b], ref) <= 1e-13, (s, b, got[b], float(ref))
+            m = orc.model_masks(K4, freqs, 230.0, 2.725, th[b])
+            for f in range(F):
+                for t in range(T):
+                    assert _relerr(m[f, t], mm[f][t]) <= 1e-14, (s, f, t)
+
+
+def pin_masks_power_of_two_alpha(orc):
+    """With every alpha_i a power of two, alpha_i K_ij is exact in FP32, so
+    the crossed model equals, bit for bit, the spectral-index-only model
+    whose region (i, j) has response alpha_i K_ij and index beta_j."""
+    rng = _rng(41)
+    NA, NB, F, T = 3, 4, 9, 5
+    K, freqs = _rand_problem(rng, NA * NB, F, T)
+    K4 = K.reshape(NA, NB, F, T)
+    th = _rand_theta_masks(rng, NA, NB, 6)
+    th[:, NB:NB + NA] = 2.0 ** rng.integers(-3, 4, size=(6, NA))
+    D = rng.normal(150.0, 30.0, size=(F, T))
+    got = orc.loglike_masks(K4, freqs, D, 230.0, 2.725, th)
+    for b in range(6):
+        a = th[b, NB:NB + NA]
+        Kf = np.ascontiguousarray((K4 * a[:, None, None, None].astype(np.float32))
+                                  .reshape(NA * NB, F, T))
+        thf = np.concatenate([np.tile(th[b, :NB], NA), th[b, NB + NA:]])
+        ref = orc.loglike(Kf, freqs, D, 230.0, 2.725, thf[None])[0]
+        assert got[b] == ref, (b, got[b], ref)
+        assert np.array_equal(orc.model_masks(K4, freqs, 230.0, 2.725, th[b]),
+                              orc.model(Kf, freqs, 230.0, 2.725, thf))
+
+
+def pin_masks_unit_power(orc):
+    """beta = 0: every power is one, so M = sum_i alpha_i sum_j K_ij + T_CMB
+    (summed exactly with fsum, then rounded)."""
+    rng = _rng(43)
+    NA, NB, F, T = 3, 2, 6, 3
+    K, freqs = _rand_problem(rng, NA * NB, F, T)
+    K4 = K.reshape(NA, NB, F, T)
+    th = np.zeros(NB + NA + 1)
+    th[NB:NB + NA] = [0.75, 1.3, 2.2]
+    th[-1] = 0.1
+    m = orc.model_masks(K4, freqs, 230.0, 2.725, th, flags=NO_21CM)
+    for f in range(F):
+        for t in range(T):
+            terms = [th[NB + i] * float(K4[i, j, f, t]) for i in range(NA) for j in range(NB)]
+            s = math.fsum(terms) + 2.725
+            assert abs(m[f, t] - s) <= 4e-16 * s * NA * NB, (f, t, m[f, t], s)
+
+
+def pin_masks_nesting(orc):
+    """Strict nesting in both mask sets: splitting an amplitude mask into
+    two with K/2 each and the same alpha, or a spectral-index mask into two
+    with K/2 each and the same beta, leaves M unchanged up to rounding."""
+    rng = _rng(47)
+    NA, NB, F, T = 2, 3, 7, 2
+    K, freqs = _rand_problem(rng, NA * NB, F, T)
+    K4 = K.reshape(NA, NB, F, T)
+    th = _rand_theta_masks(rng, NA, NB, 1)[0]
+    beta, alpha, rest = th[:NB], th[NB:NB + NA], th[NB + NA:]
+    m0 = orc.model_masks(K4, freqs, 230.0, 2.725, th)
+    h = np.float32(0.5)
+    for i in range(NA):
+        Ks = np.concatenate([K4[:i], K4[i:i + 1] * h, K4[i:i + 1] * h, K4[i + 1:]])
+        ths = np.concatenate([beta, alpha[:i], [alpha[i], alpha[i]], alpha[i + 1:], rest])
+        m1 = orc.model_masks(np.ascontiguousarray(Ks), freqs, 230.0, 2.725, ths)
+        assert np.allclose(m1, m0, rtol=2e-15, atol=0), ("alpha", i)
+    for j in range(NB):
+        Ks = np.concatenate([K4[:, :j], K4[:, j:j + 1] * h, K4[:, j:j + 1] * h,
+                             K4[:, j + 1:]], axis=1)
+        ths = np.concatenate([beta[:j], [beta[j], beta[j]], beta[j + 1:], alpha, rest])
+        m1 = orc.model_masks(np.ascontiguousarray(Ks), freqs, 230.0, 2.725, ths)
+        assert np.allclose(m1, m0, rtol=2e-15, atol=0), ("beta", j)
+
+
+def pin_masks_invalid_alpha(orc):
+    """An amplitude scale outside [2^-32, 2^32] (zero and negative included)
+    makes the row -inf; the bounds themselves are valid."""
+    rng = _rng(53)
+    NA, NB, F, T = 2, 2, 4, 2
+    K, freqs = _rand_problem(rng, NA * NB, F, T)
+    K4 = K.reshape(NA, NB, F, T)
+    D = rng.normal(50.0, 5.0, size=(F, T))
+    th = _rand_theta_masks(rng, NA, NB, 7)
+    bad = [0.0, -1.0, 2.0 ** 33, 2.0 ** -33]
+    for r, v in enumerate(bad):
+        th[r + 1, NB + (r % NA)] = v
+    th[5, NB] = 2.0 ** 32
+    th[6, NB + 1] = 2.0 ** -32
+    got = orc.loglike_masks(K4, freqs, D, 230.0, 2.725, th)
+    assert np.all(got[1:5] == -np.inf), got
+    assert np.all(np.isfinite(got[[0, 5, 6]])), got
+
+
 ALL_PINS = [pin_brute_force, pin_n1_closed_form, pin_unit_power,
             pin_t21_profile, pin_linearity, pin_permutation, pin_nesting,
             pin_gaussian_library, pin_noise_free, pin_invalid_rows,
-            pin_batch_rows]
+            pin_batch_rows, pin_masks_brute_force, pin_masks_power_of_two_alpha,
+            pin_masks_unit_power, pin_masks_nesting, pin_masks_invalid_alpha]

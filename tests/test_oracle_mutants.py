@@ -14,15 +14,27 @@ import oracle
 from tests import pins
 
 MUTANTS = {
-    "beta_sign": ("powv[i] = pow(ratio, -beta[i]);", "powv[i] = pow(ratio, beta[i]);"),
+    "beta_sign": ("powv[j] = pow(ratio, -beta[j]);", "powv[j] = pow(ratio, beta[j]);"),
     "ratio_inverted": ("double ratio = nu / nu_ref;", "double ratio = nu_ref / nu;"),
-    "power_in_float": ("powv[i] = pow(ratio, -beta[i]);",
-                       "powv[i] = (float)pow(ratio, -beta[i]);"),
-    "dropped_last_region": ("for (int i = 0; i < N; ++i) {                 /* ascending i */",
-                            "for (int i = 0; i < N - 1; ++i) {"),
-    "K_transposed": ("K + ((size_t)i * F + f) * T", "K + ((size_t)f * N + i) * T"),
-    "K_time_index": ("row[t] += (double)Ki[t] * powv[i];",
-                     "row[t] += (double)Ki[0] * powv[i];"),
+    "power_in_float": ("powv[j] = pow(ratio, -beta[j]);",
+                       "powv[j] = (float)pow(ratio, -beta[j]);"),
+    "dropped_last_region": ("for (int j = 0; j < NB; ++j) {\n                const float",
+                            "for (int j = 0; j < NB - 1; ++j) {\n                const float"),
+    "K_transposed": ("K + (((size_t)i * NB + j) * F + f) * T",
+                     "K + (((size_t)f * NB + j) * n_amp + i) * T"),
+    "K_time_index": ("row[t] += (a * (double)Kij[t]) * powv[j];",
+                     "row[t] += (a * (double)Kij[0]) * powv[j];"),
+    # amplitude masks
+    "alpha_dropped": ("double a = NA > 0 ? alpha[i] : 1.0;", "double a = 1.0;"),
+    "alpha_index_j": ("double a = NA > 0 ? alpha[i] : 1.0;",
+                      "double a = NA > 0 ? alpha[(i + 1) % NA] : 1.0;"),
+    "alpha_squared": ("row[t] += (a * (double)Kij[t]) * powv[j];",
+                      "row[t] += (a * a * (double)Kij[t]) * powv[j];"),
+    "alpha_row_offset": ("const double *alpha = theta_row + NB;",
+                         "const double *alpha = theta_row + NB - 1;"),
+    "region_index_swapped": ("K + (((size_t)i * NB + j) * F + f) * T",
+                             "K + (((size_t)j * n_amp + i) * F + f) * T"),
+    "alpha_not_checked": ("if (!(a >= 0x1p-32 && a <= 0x1p32)) return 0;", ""),
     "dropped_tcmb": ("row[t] = row[t] + t_cmb + sig21;", "row[t] = row[t] + sig21;"),
     "t21_sign": ("sig21 = A * exp(", "sig21 = -A * exp("),
     "t21_width": ("(2.0 * w * w)", "(w * w)"),
@@ -38,8 +50,8 @@ MUTANTS = {
     "compensation_sign": ("a->c += (a->s - t) + x;", "a->c += (a->s - t) - x;"),
     "invalid_not_checked": ("if (!(sigma > 0.0)) return 0;", ""),
     "width_not_checked": ("if (!(w > 0.0)) return 0;", ""),
-    "beta_bound_not_checked": ("if (fabs(th[i]) > 64.0) return 0;",
-                               "if (fabs(th[i]) > 1e300) return 0;"),
+    "beta_bound_not_checked": ("if (fabs(th[j]) > 64.0) return 0;",
+                               "if (fabs(th[j]) > 1e300) return 0;"),
 }
 
 
