@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-sampler", action="store_true",
                    help="skip the nested-sampling run (10 regions, T = 1, benchmark settings)")
+    p.add_argument("--no-masks", action="store_true",
+                   help="skip the crossed-mask model (2 amplitude x 16 index masks)")
     p.add_argument("--no-tune", action="store_true",
                    help="time the default tiles instead of the autotuned ones")
     p.add_argument("--calib-copy", action="store_true",
@@ -175,6 +177,33 @@ def sampler_leg(fgl, regions=10, T=1):
             "max_lnL_found": float(r.dead_logl.max()), "lnL_at_truth": l_truth}
 
 
+def masks_leg(fgl, steps, warmup, tune):
+    """The crossed-mask model (amplitude masks x spectral-index masks,
+    Eq. fast_forward_model with alpha) at the headline shape: 2 x 16 masks,
+    F=301, T=96, B=16384, each precision timed like the headline."""
+    import torch
+    import workload
+    w = workload.masks_config()
+    m = fgl.Model.from_workload(w)
+    th = torch.from_numpy(w.theta).cuda()
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    res = {"workload": w.name, "n_alpha": w.n_alpha, "n_beta": w.N // w.n_alpha,
+           "P": w.P, "form": m.form}
+    for prec in PRECS:
+        if tune:
+            m.tune(w.B, prec)
+        r = time_prec(fgl, m, th, out, prec, steps, warmup)
+        res[prec] = {"value": r["evals_per_s"], "ms_per_step": r["ms_per_step"],
+                     "kernel_ms": r["kernel_ms"],
+                     "tile": dict(zip(("waves", "chans", "occupancy"), m.tile(w.B, prec)))}
+        log(f"masks {prec}: {r['evals_per_s']:.4e} evals/s, kernel {r['kernel_ms']:.4f} ms")
+    flops = w.B * (3.0 * w.F * w.T + EXP_FLOPS * w.N * w.F)
+    res["roofline_frac"] = flops / (res["mixed"]["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+    res["mixed_over_fp32"] = res["mixed"]["value"] / res["fp32"]["value"]
+    m.close()
+    return res
+
+
 def cpu_leg(w, gpu_out, seconds):
     import oracle
     orc = oracle.load()
@@ -277,6 +306,9 @@ def main():
                                      "ms_per_step": res["mixed_direct"]["ms_per_step"],
                                      "kernel_ms": res["mixed_direct"]["kernel_ms"]}
     m.close()
+    if not a.no_masks and not a.no_plain:
+        log("crossed-mask leg")
+        line["masks"] = masks_leg(fgl, a.steps, a.warmup, not a.no_tune)
     if not a.no_serve:
         log("serving leg")
         line["serving"] = serving_leg(fgl, a.serve_seconds)

@@ -102,7 +102,37 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
                      double nu_ref, int N, int F, int T, double t_cmb,
                      unsigned flags, fgl_model** out);
 
-/* Parameters per row (N + 4, or N + 1 with FGL_NO_21CM); -1 for NULL. */
+/*
+ * Create a model with amplitude masks crossed with spectral-index masks
+ * (Sec. 2.2, Eq. fast_forward_model with its amplitude scales; the paper
+ * fits spectral-index masks only and leaves amplitude masks to later work):
+ *
+ *   M[b,nu,t] = sum_i sum_j alpha_bi K[i,j,nu,t] (nu/nu_ref)^(-beta_bj)
+ *               + T_CMB + A_b exp(-(nu - nu21_b)^2 / (2 w_b^2))
+ *
+ *   K        host, FP32 [n_alpha][n_beta][F][T], row-major; finite.  Entry
+ *            (i, j) is the response of the overlap of amplitude mask i with
+ *            spectral-index mask j (Eq. chromatic_function); an empty
+ *            overlap has K = 0.
+ *   n_alpha  amplitude masks >= 1;  n_beta  spectral-index masks >= 1;
+ *            n_alpha * n_beta <= 128 regions.
+ *   The other arguments are those of fgl_model_create.
+ * Parameter rows: [beta_0 .. beta_{n_beta-1}, alpha_0 .. alpha_{n_alpha-1},
+ * A, nu21, w, sigma], P = n_beta + n_alpha + 4 (n_beta + n_alpha + 1 with
+ * FGL_NO_21CM).  A row with an amplitude scale outside [2^-32, 2^32] (zero
+ * and negative scales included: alpha is a gain correction) yields
+ * lnL = -inf, besides the rows described above.  Every other entry point,
+ * precision mode and accuracy statement applies unchanged; the projected
+ * form is chosen on N = n_alpha * n_beta.
+ * Returns FGL_OK, FGL_EINVAL, FGL_ENOMEM or FGL_EDEVICE.
+ */
+int fgl_model_create_masks(const float* K, const double* freqs,
+                           const double* data, double nu_ref, int n_alpha,
+                           int n_beta, int F, int T, double t_cmb,
+                           unsigned flags, fgl_model** out);
+
+/* Parameters per row (N + 4, or N + 1 with FGL_NO_21CM; with amplitude
+ * masks n_beta + n_alpha + 4 or + 1); -1 for NULL. */
 int fgl_model_nparams(const fgl_model* m);
 
 /* Form of the model's mixed-precision evaluation: FGL_FORM_DIRECT or

@@ -371,6 +371,7 @@ void evict(Model* m) {
 
 static void free_work(WorkBuf& wb) {
   if (wb.w.betaT) (void)hipFree(wb.w.betaT);
+  if (wb.w.offT) (void)hipFree(wb.w.offT);
   if (wb.w.rows) (void)hipFree(wb.w.rows);
   if (wb.w.partial) (void)hipFree(wb.w.partial);
   if (wb.d_theta) (void)hipFree(wb.d_theta);
@@ -417,6 +418,8 @@ int ensure_work(Model* m, WorkBuf& wb, int B, int ngroups, bool host_io) {
   WorkBuf nw;
   hipError_t e;
   if ((e = hipMalloc(reinterpret_cast<void**>(&nw.w.betaT), (size_t)betaRows * rows * 8)) != hipSuccess ||
+      (m->dm.NA > 0 &&
+       (e = hipMalloc(reinterpret_cast<void**>(&nw.w.offT), (size_t)betaRows * rows * 8)) != hipSuccess) ||
       (e = hipMalloc(reinterpret_cast<void**>(&nw.w.rows), (size_t)rows * sizeof(RowParams))) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void**>(&nw.w.partial), (size_t)groups * rows * 8)) != hipSuccess) {
     free_work(nw);
@@ -481,7 +484,7 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
   std::vector<Tile> out;
   const int G = group_of(k, d);
   if (G == 0) return out;
-  const bool occ3 = k == kMixed && d.proj && d.KC == 1;
+  const bool occ3 = k == kMixed && d.proj && d.KC == 1 && d.NA == 0;
   for (int w : {4, 8}) {
     if (w > max_waves(k, d)) continue;
     for (int occ = 2; occ <= (occ3 ? 3 : 2); ++occ) {
@@ -505,7 +508,7 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
 Tile default_tile(Kind k, const DevModel& d, int B) {
   const int G = group_of(k, d);
   const int W = max_waves(k, d);
-  const int occ = (k == kMixed && d.proj && d.KC == 1) ? 3 : 2;
+  const int occ = (k == kMixed && d.proj && d.KC == 1 && d.NA == 0) ? 3 : 2;
   Tile best{W, G, G, occ};
   const int cols = cols_per_wave(k) * W;
   const int nb = padded_rows(B) / cols;
@@ -620,13 +623,18 @@ extern "C" {
 
 const char* fgl_last_error(void) { return last_error(); }
 
-int fgl_model_create(const float* K, const double* freqs, const double* data,
-                     double nu_ref, int N, int F, int T, double t_cmb,
-                     unsigned flags, fgl_model** out) {
+// Model with NA amplitude masks (0: none, alpha = 1) and NB spectral-index
+// masks; the two C entry points below differ only in NA.
+static int create_model(const float* K, const double* freqs, const double* data,
+                        double nu_ref, int NA, int NB, int F, int T, double t_cmb,
+                        unsigned flags, fgl_model** out) {
   if (!out) return set_err(FGL_EINVAL, "out is NULL");
   *out = nullptr;
   if (!K || !freqs || !data) return set_err(FGL_EINVAL, "K, freqs and data must be non-NULL");
-  if (N < 1 || N > kMixedMaxN) return set_err(FGL_EINVAL, "N=%d outside 1..%d", N, kMixedMaxN);
+  if (NA < 0 || NB < 1 || (long)std::max(NA, 1) * NB > kMixedMaxN)
+    return set_err(FGL_EINVAL, "masks n_alpha=%d, n_beta=%d: need n_beta >= 1 and %d regions at most",
+                   NA, NB, kMixedMaxN);
+  const int N = std::max(NA, 1) * NB;
   if (F < 1 || T < 1) return set_err(FGL_EINVAL, "F=%d and T=%d must be >= 1", F, T);
   if (flags & ~(FGL_NO_21CM | FGL_MIXED_DIRECT)) return set_err(FGL_EINVAL, "unknown flags 0x%x", flags);
   if (!(nu_ref > 0.0) || !std::isfinite(nu_ref)) return set_err(FGL_EINVAL, "nu_ref must be finite and > 0");
@@ -650,12 +658,14 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
   m->N = N;
   m->F = F;
   m->T = T;
-  m->P = (flags & FGL_NO_21CM) ? N + 1 : N + 4;
+  m->P = NB + NA + ((flags & FGL_NO_21CM) ? 1 : 4);
   m->nu_ref = nu_ref;
   m->t_cmb = t_cmb;
   m->flags = flags;
   DevModel& d = m->dm;
   d.N = N;
+  d.NA = NA;
+  d.NB = NB;
   d.F = F;
   d.T = T;
   d.P = m->P;
@@ -707,6 +717,26 @@ int fgl_model_create(const float* K, const double* freqs, const double* data,
   register_model(m);
   *out = reinterpret_cast<fgl_model*>(m);
   return FGL_OK;
+}
+
+int fgl_model_create(const float* K, const double* freqs, const double* data,
+                     double nu_ref, int N, int F, int T, double t_cmb,
+                     unsigned flags, fgl_model** out) {
+  if (N < 1 || N > kMixedMaxN) {
+    if (out) *out = nullptr;
+    return set_err(FGL_EINVAL, "N=%d outside 1..%d", N, kMixedMaxN);
+  }
+  return create_model(K, freqs, data, nu_ref, 0, N, F, T, t_cmb, flags, out);
+}
+
+int fgl_model_create_masks(const float* K, const double* freqs, const double* data,
+                           double nu_ref, int n_alpha, int n_beta, int F, int T,
+                           double t_cmb, unsigned flags, fgl_model** out) {
+  if (n_alpha < 1) {
+    if (out) *out = nullptr;
+    return set_err(FGL_EINVAL, "n_alpha=%d: need at least one amplitude mask", n_alpha);
+  }
+  return create_model(K, freqs, data, nu_ref, n_alpha, n_beta, F, T, t_cmb, flags, out);
 }
 
 int fgl_model_nparams(const fgl_model* mh) {
@@ -871,11 +901,13 @@ int fgl_tune(fgl_model* mh, int B, int prec) {
   // tune on prior-like rows: beta = 2.75, A = -0.1, nu0 = 100, w = 15, sigma = 0.025
   for (int b = 0; b < B; ++b) {
     double* row = wb.h_theta + (size_t)b * m->P;
-    for (int i = 0; i < m->N; ++i) row[i] = 2.4 + 0.7 * ((b * 7 + i * 13) % 17) / 16.0;
+    const int NB = m->dm.NB, NA = m->dm.NA;
+    for (int j = 0; j < NB; ++j) row[j] = 2.4 + 0.7 * ((b * 7 + j * 13) % 17) / 16.0;
+    for (int i = 0; i < NA; ++i) row[NB + i] = 0.9 + 0.2 * ((b * 5 + i * 3) % 11) / 10.0;
     if (!(m->flags & FGL_NO_21CM)) {
-      row[m->N] = -0.1;
-      row[m->N + 1] = 100.0;
-      row[m->N + 2] = 15.0;
+      row[m->P - 4] = -0.1;
+      row[m->P - 3] = 100.0;
+      row[m->P - 2] = 15.0;
     }
     row[m->P - 1] = 0.025;
   }

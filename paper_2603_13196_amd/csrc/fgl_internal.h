@@ -26,9 +26,10 @@ constexpr int kProjMaxN = 96;
 constexpr int kProjDigits = 6;
 constexpr int kProjBits = 46;
 
-// Per-row parameters written by the prep kernel (one 64-byte record per row).
+// Per-row parameters written by the prep kernel (one 80-byte record per row).
 struct RowParams {
   double bmin, bmax;   // extreme spectral indices of the row
+  double omin, omax;   // extreme log2 amplitude scales (0 without amplitude masks)
   double A, nu0;       // 21-cm amplitude (K) and centre (MHz)
   double inv_w;        // 1 / width (1/MHz)
   double sigma;        // noise level (K)
@@ -71,6 +72,10 @@ struct Tile {
 // Device-side model (all pointers are device memory owned by the model).
 struct DevModel {
   int N, F, T, P;
+  // masks: NA amplitude masks (0: none, alpha = 1) crossed with NB
+  // spectral-index masks; region r = i NB + j has alpha_i and beta_j, and
+  // N = max(NA, 1) NB
+  int NA, NB;
   int TT;            // 32-row time tiles (mixed, FP32)
   int TT16;          // 16-row time tiles (FP64)
   int KC;            // 32-region chunks (mixed)
@@ -107,6 +112,7 @@ struct DevModel {
 struct Work {
   int B, Bpad;           // rows and rows padded to the widest b-tile
   double* betaT;         // [KC*32 rounded][Bpad] sanitised spectral indices
+  double* offT;          // [KC*32 rounded][Bpad] log2 alpha per region (NA > 0)
   RowParams* rows;       // [Bpad]
   double* partial;       // [ngroups][Bpad]
   int ngroup_cap;        // capacity of partial in groups

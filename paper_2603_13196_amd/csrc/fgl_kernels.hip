@@ -140,7 +140,7 @@ __device__ inline double gauss21(double nu, const RowParams& rp) {
 
 // OCC: waves per SIMD the register allocation targets (2, or 3 for the
 // projected form with one region chunk, which fits in 168 registers).
-template <int W, int KC, bool PROJ, int OCC>
+template <int W, int KC, bool PROJ, int OCC, bool AB>
 __global__ __launch_bounds__(W * 64)
 __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
                                                     int nb, int nc) {
@@ -170,11 +170,15 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   const int b = bt * (W * 32) + wave * 32 + (lane & 31);
   const RowParams rp = w.rows[b];
   double beta[KC][16];
+  double off[AB ? KC : 1][16];                     // 64 log2 alpha (AB)
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      beta[kc][j] = w.betaT[(size_t)(kc * 32 + g * 16 + j) * w.Bpad + b];
+    for (int j = 0; j < 16; ++j) {
+      const size_t at = (size_t)(kc * 32 + g * 16 + j) * w.Bpad + b;
+      beta[kc][j] = w.betaT[at];
+      if constexpr (AB) off[kc][j] = 64.0 * w.offT[at];
+    }
 
   const double MAGIC = 0x1.8p52;                        // rint via the low word
   const double DIGITS = 0x1.0p52 + (double)0x80808080u;  // digit offsets
@@ -195,7 +199,9 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     // row constants at this channel: normalisation, level units, constant term
     const double c = m.t_cmb + rp.A * gauss21(nuf, rp);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
-    double ymax = ceil(bext * nl);
+    // with amplitude masks the bound adds the row's largest 64 log2 alpha;
+    // fl is monotone, so no region's rounded exponent exceeds it
+    double ymax = AB ? ceil(fma(bext, nl, 64.0 * rp.omax)) : ceil(bext * nl);
     const int ey = (int)floor(ymax * (1.0 / 64.0));
     const int fm = (int)(ymax - 64.0 * ey);
     double s0, s1, s2, t0 = 0.0;
@@ -230,7 +236,8 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     // per 32-region chunk), five significance levels.  Exponents below the
     // table (x < 2^-40, digits all zero) are clamped to its end; the clamp
     // is skipped when no lane of the wave can reach it at this channel.
-    const double ylow = (nl > 0.0 ? rp.bmin : rp.bmax) * nl - ymax;
+    const double bfar = nl > 0.0 ? rp.bmin : rp.bmax;
+    const double ylow = (AB ? fma(bfar, nl, 64.0 * rp.omin) : bfar * nl) - ymax;
     const bool clamp = __builtin_amdgcn_ballot_w64(ylow < -(double)kTabLo) != 0;
     i32x4 Bop[KC][5];
     double qlast = 0.0;                              // rounded power, last region
@@ -241,7 +248,11 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       uint32_t lo[16], hi[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double y = fma(beta[kc][j], nl, -ymax);    // 64 log2(x), <= 0
+        double y;                                  // 64 log2(x), <= 0
+        if constexpr (AB)
+          y = fma(beta[kc][j], nl, off[kc][j]) - ymax;
+        else
+          y = fma(beta[kc][j], nl, -ymax);
         if (CL) y = fmax(y, -(double)kTabLo);
         const double t = y + MAGIC;
         const int jj = (int)(uint32_t)__double_as_longlong(t);
@@ -385,7 +396,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
 // K = 0 and unit powers).  The constant T_CMB + A g is added to the FP32 sum
 // in the epilogue, then D - M and the chi-square run in FP64.
 
-template <int W, int NPB>
+template <int W, int NPB, bool AB>
 __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int G,
                                                  int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -406,10 +417,12 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
   const int b = bt * (W * 32) + wave * 32 + (lane & 31);
   const RowParams rp = w.rows[b];
   float betaf[NPB];
+  float offf[AB ? NPB : 1];                   // log2 alpha (AB)
 #pragma unroll
   for (int k = 0; k < NPB; ++k) {
     const int i = 2 * k + g;
     betaf[k] = i < N ? (float)w.betaT[(size_t)i * w.Bpad + b] : 0.0f;
+    if constexpr (AB) offf[k] = i < N ? (float)w.offT[(size_t)i * w.Bpad + b] : 0.0f;
   }
   double acc0 = 0.0, acc1 = 0.0;
   for (int f = 0; f < fn; ++f) {
@@ -418,7 +431,8 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
     const float c = (float)(m.t_cmb + rp.A * gauss21(m.nu[fi], rp));
     float Bp[NPB];
 #pragma unroll
-    for (int k = 0; k < NPB; ++k) Bp[k] = __builtin_amdgcn_exp2f(betaf[k] * nl);
+    for (int k = 0; k < NPB; ++k)
+      Bp[k] = __builtin_amdgcn_exp2f(AB ? fmaf(betaf[k], nl, offf[k]) : betaf[k] * nl);
     const float* kf = s_k + (size_t)f * kfl + lane;
     const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
     for (int tt = 0; tt < TT; ++tt) {
@@ -460,7 +474,7 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
 // its exact FP32 values and widened in registers), the constant term added in
 // the FP64 epilogue.
 
-template <int W, int NQB>
+template <int W, int NQB, bool AB>
 __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int G,
                                                  int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -481,10 +495,12 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
   const int b = bt * (W * 16) + wave * 16 + (lane & 15);
   const RowParams rp = w.rows[b];
   double beta[NQB];
+  double off[AB ? NQB : 1];                   // log2 alpha (AB)
 #pragma unroll
   for (int k = 0; k < NQB; ++k) {
     const int i = 4 * k + g;
     beta[k] = i < N ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
+    if constexpr (AB) off[k] = i < N ? w.offT[(size_t)i * w.Bpad + b] : 0.0;
   }
   double acc0 = 0.0, acc1 = 0.0;
   for (int f = 0; f < fn; ++f) {
@@ -494,7 +510,7 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
     const double c = m.t_cmb + rp.A * exp(-0.5 * z * z);
     double Bp[NQB];
 #pragma unroll
-    for (int k = 0; k < NQB; ++k) Bp[k] = exp2(beta[k] * nl);
+    for (int k = 0; k < NQB; ++k) Bp[k] = exp2(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl);
     const float* kf = s_k + (size_t)f * kdl + lane;
     // 16x16 FP64 MFMA output: register j of lane l holds row l/16 + 4 j
     const double* Df = s_D + (size_t)f * m.TT * 32 + g;
@@ -533,21 +549,24 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 // ---------------------------------------------------------------------------
 // row preparation and finalize
 
-// Row preparation: validate, sanitise, transpose the spectral indices to
-// [i][b] and record the row constants.  A block of 256 threads takes 64
+// Row preparation: validate, sanitise, expand the spectral indices (and,
+// with amplitude masks, log2 of the amplitude scales) to one value per
+// region, transposed to [i][b], and record the row constants.  A block of 256 threads takes 64
 // rows: the rows are read coalesced into LDS, one thread per row derives
 // the row record, and all threads write the transposed indices coalesced.
 // Invalid rows are given harmless values (finalize writes -inf for them).
 constexpr int kPrepRows = 64;
 
 __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, int B, int Bpad,
-                                              int N, int P, unsigned flags, int betaRows,
-                                              double* __restrict__ betaT,
+                                              int N, int NA, int NB, int P, unsigned flags,
+                                              int betaRows, double* __restrict__ betaT,
+                                              double* __restrict__ offT,
                                               RowParams* __restrict__ rows) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* s_th = reinterpret_cast<double*>(smem);                 // [64][P]
   double* s_fill = s_th + (size_t)kPrepRows * P;                 // [64] bmin or 0
-  int* s_ok = reinterpret_cast<int*>(s_fill + kPrepRows);        // [64]
+  double* s_ofill = s_fill + kPrepRows;                          // [64] omin or 0
+  int* s_ok = reinterpret_cast<int*>(s_ofill + kPrepRows);       // [64]
   const int b0 = blockIdx.x * kPrepRows;
   const int nrow = max(0, min(kPrepRows, B - b0));
   for (int k = threadIdx.x; k < nrow * P; k += blockDim.x)
@@ -560,9 +579,10 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
     bool ok = r < nrow;
     if (ok) {
       for (int k = 0; k < P; ++k) ok = ok && isfinite(th[k]);
-      for (int i = 0; i < N; ++i) ok = ok && fabs(th[i]) <= 64.0;
+      for (int j = 0; j < NB; ++j) ok = ok && fabs(th[j]) <= 64.0;
+      for (int i = 0; i < NA; ++i) ok = ok && th[NB + i] >= 0x1p-32 && th[NB + i] <= 0x1p32;
       ok = ok && th[P - 1] > 0.0;
-      if (!no21) ok = ok && th[N + 2] > 0.0;
+      if (!no21) ok = ok && th[P - 2] > 0.0;
     }
     RowParams rp;
     rp.valid = ok ? 1 : 0;
@@ -572,33 +592,49 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
     rp.inv_w = 1.0;
     rp.sigma = 1.0;
     rp.t21 = no21 ? 0.0 : 1.0;
-    double bmin = 0.0, bmax = 0.0;
+    double bmin = 0.0, bmax = 0.0, omin = 0.0, omax = 0.0;
     if (ok) {
       bmin = bmax = th[0];
-      for (int i = 1; i < N; ++i) {
-        bmin = fmin(bmin, th[i]);
-        bmax = fmax(bmax, th[i]);
+      for (int j = 1; j < NB; ++j) {
+        bmin = fmin(bmin, th[j]);
+        bmax = fmax(bmax, th[j]);
+      }
+      if (NA > 0) {
+        omin = omax = log2(th[NB]);
+        for (int i = 1; i < NA; ++i) {
+          const double o = log2(th[NB + i]);
+          omin = fmin(omin, o);
+          omax = fmax(omax, o);
+        }
       }
       rp.sigma = th[P - 1];
       if (!no21) {
-        rp.A = th[N];
-        rp.nu0 = th[N + 1];
-        rp.inv_w = 1.0 / th[N + 2];
+        rp.A = th[P - 4];
+        rp.nu0 = th[P - 3];
+        rp.inv_w = 1.0 / th[P - 2];
       }
     }
     rp.bmin = bmin;
     rp.bmax = bmax;
+    rp.omin = omin;
+    rp.omax = omax;
     s_fill[r] = bmin;
+    s_ofill[r] = omin;
     s_ok[r] = ok ? 1 : 0;
     if (b0 + r < Bpad) rows[b0 + r] = rp;
   }
   __syncthreads();
-  // betaT[i][b]: beta_i for valid rows and i < N, the row's minimum otherwise
+  // betaT[i][b]: the index of region i's spectral-index mask for valid rows
+  // and i < N, the row's minimum otherwise; offT[i][b] likewise with log2 of
+  // the region's amplitude scale
   for (int k = threadIdx.x; k < betaRows * kPrepRows; k += blockDim.x) {
     const int i = k / kPrepRows, r = k - i * kPrepRows;
     if (b0 + r >= Bpad) continue;
-    const double v = (s_ok[r] && i < N) ? s_th[(size_t)r * P + i] : s_fill[r];
-    betaT[(size_t)i * Bpad + b0 + r] = v;
+    const bool real = s_ok[r] && i < N;
+    const int ia = i / NB, jb = i - ia * NB;
+    betaT[(size_t)i * Bpad + b0 + r] = real ? s_th[(size_t)r * P + jb] : s_fill[r];
+    if (NA > 0)
+      offT[(size_t)i * Bpad + b0 + r] = real ? log2(s_th[(size_t)r * P + NB + ia]) : s_ofill[r];
   }
 }
 
@@ -684,25 +720,53 @@ hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
   return hipGetLastError();
 }
 
-template <int W>
-hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
-                   int nc, int occ, int lds, hipStream_t s) {
+template <int W, bool AB>
+hipError_t mixed_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
+                    int nc, int occ, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
   if (m.proj) {
     switch (m.KC) {
       case 1:
-        return occ == 3 ? go(k_mixed<W, 1, true, 3>, blocks, th, lds, s, m, w, fc, G, nb, nc)
-                        : go(k_mixed<W, 1, true, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 2: return go(k_mixed<W, 2, true, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 3: return go(k_mixed<W, 3, true, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+        if constexpr (!AB)
+          if (occ == 3)
+            return go(k_mixed<W, 1, true, 3, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+        return go(k_mixed<W, 1, true, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 2: return go(k_mixed<W, 2, true, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 3: return go(k_mixed<W, 3, true, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
       default: return hipErrorInvalidValue;
     }
   }
   switch (m.KC) {
-    case 1: return go(k_mixed<W, 1, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_mixed<W, 2, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 3: return go(k_mixed<W, 3, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_mixed<W, 4, false, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go(k_mixed<W, 1, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_mixed<W, 2, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 3: return go(k_mixed<W, 3, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_mixed<W, 4, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int W>
+hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
+                   int nc, int occ, int lds, hipStream_t s) {
+  if (occ == 3 && m.NA > 0) return hipErrorInvalidValue;
+  return m.NA > 0 ? mixed_wa<W, true>(m, w, fc, G, nb, nc, occ, lds, s)
+                  : mixed_wa<W, false>(m, w, fc, G, nb, nc, occ, lds, s);
+}
+
+template <int W, bool AB>
+hipError_t fp32_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
+                   int nc, int lds, hipStream_t s) {
+  const int blocks = nb * nc, th = W * 64;
+  switch (m.NP2) {
+    case 2: return go(k_fp32<W, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_fp32<W, 4, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_fp32<W, 8, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_fp32<W, 12, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_fp32<W, 16, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_fp32<W, 24, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 32: return go(k_fp32<W, 32, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 48: return go(k_fp32<W, 48, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 64: return go(k_fp32<W, 64, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -710,17 +774,24 @@ hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
 template <int W>
 hipError_t fp32_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   int nc, int lds, hipStream_t s) {
+  return m.NA > 0 ? fp32_wa<W, true>(m, w, fc, G, nb, nc, lds, s)
+                  : fp32_wa<W, false>(m, w, fc, G, nb, nc, lds, s);
+}
+
+template <int W, bool AB>
+hipError_t fp64_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
+                   int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
-  switch (m.NP2) {
-    case 2: return go(k_fp32<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_fp32<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 8: return go(k_fp32<W, 8>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 12: return go(k_fp32<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 16: return go(k_fp32<W, 16>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 24: return go(k_fp32<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 32: return go(k_fp32<W, 32>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 48: return go(k_fp32<W, 48>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 64: return go(k_fp32<W, 64>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+  switch (m.NQ) {
+    case 1: return go(k_fp64<W, 1, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_fp64<W, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_fp64<W, 4, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 6: return go(k_fp64<W, 6, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_fp64<W, 8, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_fp64<W, 12, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_fp64<W, 16, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_fp64<W, 24, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 32: return go(k_fp64<W, 32, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -728,19 +799,8 @@ hipError_t fp32_w(const DevModel& m, const Work& w, int fc, int G, int nb,
 template <int W>
 hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   int nc, int lds, hipStream_t s) {
-  const int blocks = nb * nc, th = W * 64;
-  switch (m.NQ) {
-    case 1: return go(k_fp64<W, 1>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_fp64<W, 2>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_fp64<W, 4>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 6: return go(k_fp64<W, 6>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 8: return go(k_fp64<W, 8>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 12: return go(k_fp64<W, 12>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 16: return go(k_fp64<W, 16>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 24: return go(k_fp64<W, 24>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 32: return go(k_fp64<W, 32>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    default: return hipErrorInvalidValue;
-  }
+  return m.NA > 0 ? fp64_wa<W, true>(m, w, fc, G, nb, nc, lds, s)
+                  : fp64_wa<W, false>(m, w, fc, G, nb, nc, lds, s);
 }
 
 }  // namespace
@@ -748,11 +808,12 @@ hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
 hipError_t launch_prep(const DevModel& m, const double* theta, int B,
                        const Work& w, int betaRows, hipStream_t s) {
   const int blocks = (w.Bpad + kPrepRows - 1) / kPrepRows;
-  const int lds = kPrepRows * (m.P + 1) * 8 + kPrepRows * 4;
+  const int lds = kPrepRows * (m.P + 2) * 8 + kPrepRows * 4;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_prep));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), lds, s, theta, B,
-                     w.Bpad, m.N, m.P, m.flags, betaRows, w.betaT, w.rows);
+                     w.Bpad, m.N, m.NA, m.NB, m.P, m.flags, betaRows, w.betaT, w.offT,
+                     w.rows);
   return hipGetLastError();
 }
 

@@ -57,6 +57,9 @@ _SIGS = {
     "fgl_model_create": ([_fp, _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                           ctypes.c_int, ctypes.c_double, ctypes.c_uint,
                           ctypes.POINTER(_vp)], ctypes.c_int),
+    "fgl_model_create_masks": ([_fp, _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint,
+                                ctypes.POINTER(_vp)], ctypes.c_int),
     "fgl_model_nparams": ([_vp], ctypes.c_int),
     "fgl_mixed_form": ([_vp], ctypes.c_int),
     "fgl_loglike_batch": ([_vp, _dp, ctypes.c_int, _dp, ctypes.c_int], ctypes.c_int),
@@ -126,6 +129,20 @@ def fgl_model_create(K, freqs, data, nu_ref, N, F, T, t_cmb, flags=0):
     return h
 
 
+def fgl_model_create_masks(K, freqs, data, nu_ref, n_alpha, n_beta, F, T, t_cmb,
+                           flags=0):
+    """Amplitude masks crossed with spectral-index masks: K [n_alpha, n_beta,
+    F, T]; returns an opaque model handle; raises FGLError on failure."""
+    K = np.ascontiguousarray(K, dtype=np.float32)
+    freqs, data = _f64(freqs), _f64(data)
+    h = _vp()
+    _check(_lib.fgl_model_create_masks(K.ctypes.data_as(_fp), freqs.ctypes.data_as(_dp),
+                                       data.ctypes.data_as(_dp), float(nu_ref), int(n_alpha),
+                                       int(n_beta), int(F), int(T), float(t_cmb), int(flags),
+                                       ctypes.byref(h)))
+    return h
+
+
 def fgl_loglike_batch(model, theta, B, out, prec):
     return _check(_lib.fgl_loglike_batch(model, theta.ctypes.data_as(_dp), int(B),
                                          out.ctypes.data_as(_dp), _prec(prec)))
@@ -173,22 +190,39 @@ def fgl_serve_destroy(server):
 # --- convenience wrappers ------------------------------------------------------
 
 class Model:
-    """A resident model: K [N,F,T] (float32), freqs [F], data [F,T]."""
+    """A resident model: K [N,F,T] (float32), freqs [F], data [F,T].
+
+    With ``n_alpha`` > 0 the N = n_alpha * n_beta regions of K are amplitude
+    masks crossed with spectral-index masks, region i * n_beta + j (K may
+    also be given as [n_alpha, n_beta, F, T])."""
 
     def __init__(self, K, freqs, data, nu_ref: float = 230.0, t_cmb: float = 2.725,
-                 flags: int = 0):
+                 flags: int = 0, n_alpha: int = 0):
         K = np.ascontiguousarray(K, dtype=np.float32)
+        if K.ndim == 4:
+            if n_alpha not in (0, K.shape[0]):
+                raise ValueError("n_alpha disagrees with K's shape")
+            n_alpha = K.shape[0]
+            K = K.reshape(-1, K.shape[2], K.shape[3])
         if K.ndim != 3:
-            raise ValueError("K must be [N, F, T]")
+            raise ValueError("K must be [N, F, T] or [n_alpha, n_beta, F, T]")
         N, F, T = K.shape
         self.N, self.F, self.T = N, F, T
         self.flags = flags
-        self.handle = fgl_model_create(K, freqs, data, nu_ref, N, F, T, t_cmb, flags)
+        self.n_alpha = int(n_alpha)
+        if n_alpha:
+            if N % n_alpha:
+                raise ValueError("N is not a multiple of n_alpha")
+            self.handle = fgl_model_create_masks(K, freqs, data, nu_ref, n_alpha,
+                                                 N // n_alpha, F, T, t_cmb, flags)
+        else:
+            self.handle = fgl_model_create(K, freqs, data, nu_ref, N, F, T, t_cmb, flags)
         self.P = _lib.fgl_model_nparams(self.handle)
 
     @classmethod
     def from_workload(cls, w, flags: int = 0) -> "Model":
-        return cls(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, flags)
+        return cls(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, flags,
+                   n_alpha=getattr(w, "n_alpha", 0))
 
     @property
     def form(self) -> str:

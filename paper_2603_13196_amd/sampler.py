@@ -256,13 +256,17 @@ def nested_slice_sampling(loglike: Callable[[np.ndarray], np.ndarray],
 # --- the foreground model in sampler coordinates --------------------------------
 
 def foreground_box(N: int, no21: bool = False, beta=(2.0, 3.5), A=(-0.5, 0.0),
-                   nu0=(50.0, 200.0), w=(5.0, 40.0), sigma=(1e-3, 0.1)):
+                   nu0=(50.0, 200.0), w=(5.0, 40.0), sigma=(1e-3, 0.1),
+                   n_alpha: int = 0, alpha=(0.8, 1.2)):
     """Prior box of the foreground model's parameters in sampler coordinates:
     [beta_0..beta_{N-1}, A, nu21, w, log sigma] (log sigma: the log-uniform
     noise prior of Table priors), or [beta.., log sigma] without the 21-cm
-    term."""
-    lo = [beta[0]] * N + ([] if no21 else [A[0], nu0[0], w[0]]) + [math.log(sigma[0])]
-    hi = [beta[1]] * N + ([] if no21 else [A[1], nu0[1], w[1]]) + [math.log(sigma[1])]
+    term.  With n_alpha > 0 (amplitude masks crossed with N spectral-index
+    masks) the n_alpha uniform amplitude scales follow the indices."""
+    lo = ([beta[0]] * N + [alpha[0]] * n_alpha + ([] if no21 else [A[0], nu0[0], w[0]])
+          + [math.log(sigma[0])])
+    hi = ([beta[1]] * N + [alpha[1]] * n_alpha + ([] if no21 else [A[1], nu0[1], w[1]])
+          + [math.log(sigma[1])])
     return np.array(lo), np.array(hi)
 
 

@@ -59,6 +59,12 @@ def test_last_error_without_device_call(libpath):
         fgl.fgl_model_create([[[1.0]]], [100.0], [[1.0]], 230.0, 0, 1, 1, 2.725)
     assert e.value.code == fgl.FGL_EINVAL
     assert "N=0" in fgl.fgl_last_error()
+    K = [[[[1.0]]]]
+    for na, nb, what in ((0, 1, "n_alpha=0"), (1, 0, "n_beta=0"), (2, 65, "128 regions")):
+        with pytest.raises(fgl.FGLError) as e:
+            fgl.fgl_model_create_masks(K, [100.0], [[1.0]], 230.0, na, nb, 1, 1, 2.725)
+        assert e.value.code == fgl.FGL_EINVAL
+        assert what in fgl.fgl_last_error(), fgl.fgl_last_error()
 
 
 def test_binding_fails_loudly_without_library(tmp_path, libpath):

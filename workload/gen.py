@@ -54,6 +54,9 @@ PRIOR_A = (-0.5, 0.0)
 PRIOR_NU0 = (50.0, 200.0)
 PRIOR_W = (5.0, 40.0)
 PRIOR_LOGSIG = (math.log(1e-3), math.log(0.1))
+# amplitude scales of amplitude masks (Eq. fast_forward_model): the paper
+# gives no prior for them; they are gain corrections about one
+PRIOR_ALPHA = (0.8, 1.2)
 
 
 @dataclasses.dataclass
@@ -66,6 +69,11 @@ class Workload:
       data   float64 [F, T]     simulated antenna temperature (K)
       theta  float64 [B, N+4]   rows [beta_0..beta_{N-1}, A, nu0, w, sigma]
       truth  float64 [N+4]      parameters the data were simulated at
+
+    With n_alpha > 0 the N regions are n_alpha amplitude masks crossed with
+    n_beta = N / n_alpha spectral-index masks (region i * n_beta + j), and
+    rows are [beta_0..beta_{n_beta-1}, alpha_0..alpha_{n_alpha-1}, A, nu0,
+    w, sigma].
     """
     name: str
     K: np.ndarray
@@ -75,6 +83,7 @@ class Workload:
     truth: np.ndarray
     nu_ref: float = NU_REF
     t_cmb: float = T_CMB
+    n_alpha: int = 0
 
     @property
     def N(self) -> int:
@@ -221,6 +230,68 @@ CONFIG_NAMES = {
     2: "N32_F301_T96_B16384",
     4: "N64_F401_T240_B65536",
 }
+
+
+def make_masks(n_alpha: int, n_beta: int, freqs: np.ndarray, T: int, B: int,
+               seed: int, *, t_mod: float = 0.3, batch: str = "prior",
+               name: str = "masks", nu_ref: float = NU_REF,
+               t_cmb: float = T_CMB) -> Workload:
+    """Workload of the crossed-mask model: K for n_alpha * n_beta regions
+    (drawn as in ``make``), a truth with beta_j ~ U[2.45, 3.15] and
+    alpha_i ~ U[0.95, 1.05], data simulated with region responses
+    alpha_i K_ij, and a batch of B rows ('prior', 'shell' or 'mixed'); the
+    alpha prior is PRIOR_ALPHA and the shell jitter on alpha is 1e-4."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N = n_alpha * n_beta
+    K = _draw_K(rng, N, freqs, T, t_mod, 0.0)
+    beta_true = rng.uniform(2.45, 3.15, size=n_beta)
+    alpha_true = rng.uniform(0.95, 1.05, size=n_alpha)
+    a21, nu21, w21 = -0.15, 80.0, 15.0
+    K_eff = K.astype(np.float64) * np.repeat(alpha_true, n_beta)[:, None, None]
+    data = _simulate_sky(rng, K_eff, freqs, nu_ref, t_cmb,
+                         np.tile(beta_true, n_alpha), a21, nu21, w21, NOISE_K)
+    truth = np.concatenate([beta_true, alpha_true, [a21, nu21, w21, NOISE_K]])
+    nb, na = n_beta, n_alpha
+
+    def prior(n):
+        th = np.empty((n, nb + na + 4))
+        th[:, :nb] = rng.uniform(*PRIOR_BETA, size=(n, nb))
+        th[:, nb:nb + na] = rng.uniform(*PRIOR_ALPHA, size=(n, na))
+        th[:, nb + na] = rng.uniform(*PRIOR_A, size=n)
+        th[:, nb + na + 1] = rng.uniform(*PRIOR_NU0, size=n)
+        th[:, nb + na + 2] = rng.uniform(*PRIOR_W, size=n)
+        th[:, nb + na + 3] = np.exp(rng.uniform(*PRIOR_LOGSIG, size=n))
+        return th
+
+    def shell(n, n_exact=16):
+        th = np.repeat(truth[None, :], n, axis=0)
+        jit = np.concatenate([np.full(nb + na, 1e-4), [0.01, 1.0, 1.0]])
+        th[:, :-1] += rng.normal(0.0, 1.0, size=(n, nb + na + 3)) * jit[None, :]
+        th[:n_exact, :-1] = truth[None, :-1]
+        th[:, -1] = NOISE_K * rng.uniform(0.8, 1.25, size=n)
+        return th
+
+    if batch == "prior":
+        theta = prior(B)
+    elif batch == "shell":
+        theta = shell(B)
+    elif batch == "mixed":
+        theta = np.concatenate([prior(B // 2), shell(B - B // 2)])
+    else:
+        raise ValueError(f"unknown batch kind {batch!r}")
+    return Workload(name, K, np.ascontiguousarray(freqs), data,
+                    np.ascontiguousarray(theta), truth, nu_ref, t_cmb, n_alpha)
+
+
+# The crossed-mask counterpart of the headline workload: its 32 regions as
+# 2 amplitude masks x 16 spectral-index masks (N32, F301, T96, B16384).
+MASKS_NAME = "A2xB16_F301_T96_B16384"
+
+
+def masks_config(*, B: int = 16384, batch: str = "prior") -> Workload:
+    c = CONFIGS[2]
+    return make_masks(2, 16, freq_grid(*c["grid"]), c["T"], B, SEED_BASE + 5,
+                      t_mod=c["t_mod"], batch=batch, name=MASKS_NAME)
 
 
 def config(k: int, *, B: Optional[int] = None, batch: str = "prior",
