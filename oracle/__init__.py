@@ -59,6 +59,12 @@ class Oracle:
                                            ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_uint, dp, dp]
         lib.oracle_model_masks.restype = ctypes.c_int
+        lib.oracle_grad_batch_masks.argtypes = [fp, dp, dp, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_uint, dp,
+                                                ctypes.c_int, dp, dp, ctypes.c_int]
+        lib.oracle_grad_batch_masks.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         self._lib = lib
 
@@ -129,6 +135,37 @@ class Oracle:
             freqs.ctypes.data_as(dp), float(nu_ref), float(t_cmb), NA, NB, F, T,
             flags, th.ctypes.data_as(dp), m.ctypes.data_as(dp))
         return m if rc == 0 else None
+
+    def grad(self, K, freqs, data, nu_ref, t_cmb, theta, flags: int = 0,
+             n_alpha: int = 0, threads: int = 0):
+        """(lnL [B], d lnL / d theta [B, P]) of the spectral-index-only model
+        (K [N, F, T], n_alpha = 0) or of the crossed-mask model (K
+        [n_alpha, n_beta, F, T] or [n_alpha * n_beta, F, T])."""
+        K = np.ascontiguousarray(K, dtype=np.float32)
+        freqs, data, theta = self._f64(freqs), self._f64(data), self._f64(theta)
+        F, T = K.shape[-2], K.shape[-1]
+        N = int(np.prod(K.shape[:-2]))
+        NA = n_alpha if K.ndim == 3 else K.shape[0]
+        NB = N // max(NA, 1)
+        theta = theta.reshape(-1, theta.shape[-1])
+        B, P = theta.shape
+        out = np.empty(B, dtype=np.float64)
+        grad = np.empty((B, P), dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = self._lib.oracle_grad_batch_masks(
+            K.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            freqs.ctypes.data_as(dp), data.ctypes.data_as(dp),
+            float(nu_ref), float(t_cmb), NA, NB, F, T, flags,
+            theta.ctypes.data_as(dp), B, out.ctypes.data_as(dp),
+            grad.ctypes.data_as(dp), int(threads))
+        if rc != 0:
+            raise RuntimeError(f"oracle_grad_batch_masks failed ({rc})")
+        return out, grad
+
+    def grad_w(self, w, theta=None, threads: int = 0):
+        th = w.theta if theta is None else theta
+        return self.grad(w.K, w.freqs, w.data, w.nu_ref, w.t_cmb, th,
+                         n_alpha=getattr(w, "n_alpha", 0), threads=threads)
 
     def max_threads(self) -> int:
         return int(self._lib.oracle_max_threads())

@@ -205,6 +205,110 @@ int oracle_loglike(const float *K, const double *freqs, const double *D,
                                 theta, B, out, nthreads);
 }
 
+/* Gradient of lnL of one row with respect to the row's parameters, into
+ * g[P]; returns lnL (-inf for an invalid row, whose g is all NaN).  The
+ * chain rule through Eq. likelihood, Eq. fast_forward_model and
+ * Eq. t21model, with r = D - M and the sums over (nu, t):
+ *
+ *   dlnL/dtheta   = (1/sigma^2) sum r dM/dtheta       (theta other than sigma)
+ *   dM/dbeta_j    = -ln(nu/nu_ref) sum_i alpha_i K_ij (nu/nu_ref)^(-beta_j)
+ *   dM/dalpha_i   = sum_j K_ij (nu/nu_ref)^(-beta_j)
+ *   dM/dA         = g(nu)
+ *   dM/dnu21      = A g(nu) (nu - nu21) / w^2
+ *   dM/dw         = A g(nu) (nu - nu21)^2 / w^3
+ *   dlnL/dsigma   = chi2 / sigma^3 - F T / sigma
+ *
+ * Every sum over (nu, t) is compensated (Neumaier). */
+double oracle_grad_masks(const float *K, const double *freqs, const double *D,
+                         double nu_ref, double t_cmb, int NA, int NB, int F,
+                         int T, unsigned flags, const double *theta_row,
+                         double *g, double *m)
+{
+    int P = n_params(NA, NB, flags);
+    if (oracle_model_masks(K, freqs, nu_ref, t_cmb, NA, NB, F, T, flags,
+                           theta_row, m) != 0) {
+        for (int k = 0; k < P; ++k) g[k] = NAN;
+        return -INFINITY;
+    }
+    const double *beta = theta_row, *alpha = theta_row + NB;
+    int n_amp = NA > 0 ? NA : 1;
+    int no21 = (flags & ORACLE_NO_21CM) != 0;
+    double sigma = theta_row[P - 1];
+    neumaier_t *acc = (neumaier_t *)calloc((size_t)P, sizeof(neumaier_t));
+    if (!acc) return NAN;
+    neumaier_t chi2 = {0.0, 0.0};
+    for (int f = 0; f < F; ++f) {
+        double nu = freqs[f];
+        double lr = log(nu / nu_ref);
+        double dnu = 0.0, w = 1.0, A = 0.0, gnu = 0.0;
+        if (!no21) {
+            A = theta_row[P - 4];
+            double nu21 = theta_row[P - 3];
+            w = theta_row[P - 2];
+            dnu = nu - nu21;
+            gnu = exp(-(dnu * dnu) / (2.0 * (w * w)));
+        }
+        for (int t = 0; t < T; ++t) {
+            double r = D[(size_t)f * T + t] - m[(size_t)f * T + t];
+            nm_add(&chi2, r * r);
+            for (int i = 0; i < n_amp; ++i) {
+                double amp = NA > 0 ? alpha[i] : 1.0;
+                for (int j = 0; j < NB; ++j) {
+                    double kp = (double)K[(((size_t)i * NB + j) * F + f) * T + t]
+                                * pow(nu / nu_ref, -beta[j]);
+                    nm_add(&acc[j], r * (-lr * amp * kp));       /* beta_j */
+                    if (NA > 0) nm_add(&acc[NB + i], r * kp);  /* alpha_i */
+                }
+            }
+            if (!no21) {
+                nm_add(&acc[P - 4], r * gnu);
+                nm_add(&acc[P - 3], r * (A * gnu * dnu / (w * w)));
+                nm_add(&acc[P - 2], r * (A * gnu * dnu * dnu / (w * w * w)));
+            }
+        }
+    }
+    double var = sigma * sigma;
+    for (int k = 0; k < P - 1; ++k) g[k] = (acc[k].s + acc[k].c) / var;
+    double c2 = chi2.s + chi2.c;
+    double n = (double)F * (double)T;
+    g[P - 1] = c2 / (var * sigma) - n / sigma;
+    free(acc);
+    return -0.5 * c2 / var - 0.5 * n * log(2.0 * M_PI * var);
+}
+
+/* lnL and its gradient for B rows: out[B], grad[B][P]. */
+int oracle_grad_batch_masks(const float *K, const double *freqs,
+                            const double *D, double nu_ref, double t_cmb,
+                            int NA, int NB, int F, int T, unsigned flags,
+                            const double *theta, int B, double *out,
+                            double *grad, int nthreads)
+{
+    if (NA < 0 || NB < 0 || F <= 0 || T <= 0 || B < 0) return -1;
+    int P = n_params(NA, NB, flags);
+    int fail = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double *m = (double *)malloc(sizeof(double) * (size_t)F * T);
+        if (!m) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int b = 0; b < B; ++b)
+                out[b] = oracle_grad_masks(K, freqs, D, nu_ref, t_cmb, NA, NB, F, T,
+                                           flags, theta + (size_t)b * P,
+                                           grad + (size_t)b * P, m);
+            free(m);
+        }
+    }
+    return fail ? -2 : 0;
+}
+
 /* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
 int oracle_max_threads(void)
 {

@@ -452,8 +452,119 @@ def pin_masks_invalid_alpha(orc):
     assert np.all(np.isfinite(got[[0, 5, 6]])), got
 
 
+# ---------------------------------------------------------------------------
+# gradient of lnL with respect to the row's parameters
+
+def _mp_lnl_any(K4, freqs, D, nu_ref, t_cmb, th, NA):
+    """50-digit lnL of either model at a row given as mpf values."""
+    NAa, NB, F, T = K4.shape
+    beta = th[:NB]
+    alpha = th[NB:NB + NA] if NA else [mp.mpf(1)]
+    A, nu0, w, sig = th[-4], th[-3], th[-2], th[-1]
+    chi2 = mp.mpf(0)
+    for f in range(F):
+        nu = mp.mpf(float(freqs[f]))
+        x = nu / mp.mpf(float(nu_ref))
+        p = [mp.power(x, -b) for b in beta]
+        s21 = A * mp.exp(-(nu - nu0) ** 2 / (2 * w * w))
+        for t in range(T):
+            acc = mp.mpf(0)
+            for i in range(NAa):
+                for j in range(NB):
+                    acc += alpha[i] * mp.mpf(float(K4[i, j, f, t])) * p[j]
+            r = mp.mpf(float(D[f, t])) - (acc + mp.mpf(float(t_cmb)) + s21)
+            chi2 += r * r
+    return -chi2 / (2 * sig * sig) - mp.mpf(F * T) / 2 * mp.log(2 * mp.pi * sig * sig)
+
+
+def _mp_grad(K4, freqs, D, nu_ref, t_cmb, row, NA):
+    """Central differences of the 50-digit lnL with step 1e-18 (truncation
+    ~1e-36, rounding ~1e-32 relative): the gradient to ~25 digits."""
+    th = [mp.mpf(float(v)) for v in row]
+    h = mp.mpf("1e-18")
+    out = []
+    for k in range(len(th)):
+        tp = list(th)
+        tm = list(th)
+        tp[k] += h
+        tm[k] -= h
+        out.append((_mp_lnl_any(K4, freqs, D, nu_ref, t_cmb, tp, NA)
+                    - _mp_lnl_any(K4, freqs, D, nu_ref, t_cmb, tm, NA)) / (2 * h))
+    return out
+
+
+def pin_grad_brute_force(orc, seeds=range(4)):
+    """The oracle's analytic gradient against central differences of the
+    50-digit lnL, for spectral-index-only and crossed-mask problems, to
+    1e-11 relative to the largest gradient entry's magnitude scale (the
+    entries are sums of terms of both signs)."""
+    for s in seeds:
+        rng = _rng(500 + s)
+        NA = int(s % 2) * int(rng.integers(1, 3))          # 0 (index only) or 1-2
+        NB = int(rng.integers(1, 4))
+        F, T = int(rng.integers(2, 5)), int(rng.integers(1, 4))
+        N = max(NA, 1) * NB
+        K, freqs = _rand_problem(rng, N, F, T)
+        K4 = K.reshape(max(NA, 1), NB, F, T)
+        if NA:
+            th = _rand_theta_masks(rng, NA, NB, 2)
+        else:
+            th = _rand_theta(rng, NB, 2)
+        th[:, -1] = [0.3, 2.0]
+        D = rng.normal(60.0, 15.0, size=(F, T))
+        ll, g = orc.grad(K, freqs, D, 230.0, 2.725, th, n_alpha=NA)
+        ref_ll = orc.loglike_masks(K4, freqs, D, 230.0, 2.725, th) if NA else \
+            orc.loglike(K, freqs, D, 230.0, 2.725, th)
+        assert np.array_equal(ll, ref_ll), (s, ll, ref_ll)
+        for b in range(2):
+            ref = _mp_grad(K4, freqs, D, 230.0, 2.725, th[b], NA)
+            for k, rk in enumerate(ref):
+                assert abs(g[b, k] - float(rk)) <= 1e-11 * max(abs(float(rk)), 1e-6), \
+                    (s, b, k, g[b, k], float(rk))
+
+
+def pin_grad_noise_free(orc):
+    """D = M(theta) exactly (the oracle's own model values): every residual is
+    zero, so every derivative but sigma's vanishes exactly and
+    dlnL/dsigma = -F T / sigma."""
+    rng = _rng(59)
+    for NA, NB in ((0, 4), (2, 3)):
+        N = max(NA, 1) * NB
+        K, freqs = _rand_problem(rng, N, 9, 4)
+        K4 = K.reshape(max(NA, 1), NB, 9, 4)
+        th = (_rand_theta_masks(rng, NA, NB, 1) if NA else _rand_theta(rng, NB, 1))[0]
+        th[-1] = 0.025
+        D = orc.model_masks(K4, freqs, 230.0, 2.725, th) if NA else \
+            orc.model(K, freqs, 230.0, 2.725, th)
+        _, g = orc.grad(K, freqs, D, 230.0, 2.725, th[None], n_alpha=NA)
+        assert np.all(g[0, :-1] == 0.0), g
+        assert abs(g[0, -1] - (-36 / 0.025)) <= 1e-12 * 36 / 0.025, g[0, -1]
+
+
+def pin_grad_sigma_closed_form(orc):
+    """lnL(sigma) = -chi2/(2 sigma^2) - n ln sigma - (n/2) ln 2 pi with chi2
+    independent of sigma: chi2 recovered from lnL at two sigmas gives
+    dlnL/dsigma = chi2/sigma^3 - n/sigma, and the other entries do not
+    depend on sigma except through the factor 1/sigma^2."""
+    rng = _rng(61)
+    N, F, T = 3, 7, 5
+    K, freqs = _rand_problem(rng, N, F, T)
+    D = rng.normal(100.0, 10.0, size=(F, T))
+    th = _rand_theta(rng, N, 1)
+    th2 = th.copy()
+    th[0, -1], th2[0, -1] = 0.5, 1.5
+    l1, g1 = orc.grad(K, freqs, D, 230.0, 2.725, th)
+    l2, g2 = orc.grad(K, freqs, D, 230.0, 2.725, th2)
+    n = F * T
+    # l1 - l2 = -chi2/2 (1/0.25 - 1/2.25) - n ln(0.5/1.5)
+    chi2 = -(l1[0] - l2[0] + n * math.log(0.5 / 1.5)) / (0.5 * (4.0 - 1.0 / 2.25))
+    assert abs(g1[0, -1] - (chi2 / 0.125 - n / 0.5)) <= 1e-9 * chi2 / 0.125
+    assert np.allclose(g1[0, :-1] * 0.25, g2[0, :-1] * 2.25, rtol=1e-13, atol=0)
+
+
 ALL_PINS = [pin_brute_force, pin_n1_closed_form, pin_unit_power,
             pin_t21_profile, pin_linearity, pin_permutation, pin_nesting,
             pin_gaussian_library, pin_noise_free, pin_invalid_rows,
             pin_batch_rows, pin_masks_brute_force, pin_masks_power_of_two_alpha,
-            pin_masks_unit_power, pin_masks_nesting, pin_masks_invalid_alpha]
+            pin_masks_unit_power, pin_masks_nesting, pin_masks_invalid_alpha,
+            pin_grad_brute_force, pin_grad_noise_free, pin_grad_sigma_closed_form]

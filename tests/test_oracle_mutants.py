@@ -34,6 +34,25 @@ MUTANTS = {
                          "const double *alpha = theta_row + NB - 1;"),
     "region_index_swapped": ("K + (((size_t)i * NB + j) * F + f) * T",
                              "K + (((size_t)j * n_amp + i) * F + f) * T"),
+    # gradient
+    "grad_beta_sign": ("nm_add(&acc[j], r * (-lr * amp * kp));",
+                       "nm_add(&acc[j], r * (lr * amp * kp));"),
+    "grad_beta_no_alpha": ("nm_add(&acc[j], r * (-lr * amp * kp));",
+                           "nm_add(&acc[j], r * (-lr * kp));"),
+    "grad_alpha_times_alpha": ("if (NA > 0) nm_add(&acc[NB + i], r * kp);",
+                               "if (NA > 0) nm_add(&acc[NB + i], r * kp * amp);"),
+    "grad_nu21_sign": ("r * (A * gnu * dnu / (w * w))", "r * (-A * gnu * dnu / (w * w))"),
+    "grad_width_power": ("r * (A * gnu * dnu * dnu / (w * w * w))",
+                         "r * (A * gnu * dnu * dnu / (w * w))"),
+    "grad_amp_dropped_g": ("nm_add(&acc[P - 4], r * gnu);", "nm_add(&acc[P - 4], r);"),
+    "grad_sigma_cube": ("g[P - 1] = c2 / (var * sigma) - n / sigma;",
+                        "g[P - 1] = c2 / var - n / sigma;"),
+    "grad_sigma_count": ("g[P - 1] = c2 / (var * sigma) - n / sigma;",
+                         "g[P - 1] = c2 / (var * sigma) - 0.5 * n / sigma;"),
+    "grad_not_over_sigma2": ("g[k] = (acc[k].s + acc[k].c) / var;",
+                             "g[k] = (acc[k].s + acc[k].c) / sigma;"),
+    "grad_residual_sign": ("double r = D[(size_t)f * T + t] - m[(size_t)f * T + t];",
+                           "double r = m[(size_t)f * T + t] - D[(size_t)f * T + t];"),
     "alpha_not_checked": ("if (!(a >= 0x1p-32 && a <= 0x1p32)) return 0;", ""),
     "dropped_tcmb": ("row[t] = row[t] + t_cmb + sig21;", "row[t] = row[t] + sig21;"),
     "t21_sign": ("sig21 = A * exp(", "sig21 = -A * exp("),
