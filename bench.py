@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-sampler", action="store_true",
                    help="skip the nested-sampling run (10 regions, T = 1, benchmark settings)")
+    p.add_argument("--no-grad", action="store_true",
+                   help="skip the FP64 gradient leg")
     p.add_argument("--no-masks", action="store_true",
                    help="skip the crossed-mask model (2 amplitude x 16 index masks)")
     p.add_argument("--no-tune", action="store_true",
@@ -204,6 +206,30 @@ def masks_leg(fgl, steps, warmup, tune):
     return res
 
 
+def grad_leg(fgl, w, steps, warmup):
+    """lnL and its gradient (FP64) for the headline rows, timed like the
+    likelihood: grads/s and the gradient kernel's average time."""
+    import torch
+    m = fgl.Model.from_workload(w)
+    th = torch.from_numpy(w.theta).cuda()
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    grad = torch.empty((w.B, w.P), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        m.loglike_grad_device(th, out, grad)
+    torch.cuda.synchronize()
+    m.kernel_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.loglike_grad_device(th, out, grad)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, n = m.kernel_time()
+    m.kernel_timing(False)
+    m.close()
+    return {"value": w.B * steps / dt, "unit": "gradients/s", "ms_per_step": dt * 1e3 / steps,
+            "kernel_ms": kms / max(n, 1), "kernel": "k_grad64", "precision": "fp64"}
+
+
 def cpu_leg(w, gpu_out, seconds):
     import oracle
     orc = oracle.load()
@@ -306,6 +332,9 @@ def main():
                                      "ms_per_step": res["mixed_direct"]["ms_per_step"],
                                      "kernel_ms": res["mixed_direct"]["kernel_ms"]}
     m.close()
+    if not a.no_grad and not a.no_plain:
+        log("gradient leg")
+        line["gradient"] = grad_leg(fgl, w, a.steps, a.warmup)
     if not a.no_masks and not a.no_plain:
         log("crossed-mask leg")
         line["masks"] = masks_leg(fgl, a.steps, a.warmup, not a.no_tune)

@@ -163,6 +163,34 @@ int fgl_loglike_batch_device(fgl_model* m, const double* d_theta, int B,
                              double* d_out, int prec, void* hip_stream);
 
 /*
+ * lnL and its gradient d lnL / d theta for B rows (the chain rule through
+ * Eq. likelihood, Eq. fast_forward_model and Eq. t21model; the paper's
+ * pipeline is differentiable, Sec. 3).  Entries follow the row layout:
+ *   d/dbeta_j  = (1/sigma^2) sum_{nu,t} r (-ln(nu/nu_ref)) sum_i alpha_i K_ij P_j
+ *   d/dalpha_i = (1/sigma^2) sum_{nu,t} r sum_j K_ij P_j   (crossed masks)
+ *   d/dA, d/dnu21, d/dw through g(nu) = exp(-(nu-nu21)^2/(2 w^2))
+ *   d/dsigma   = chi2/sigma^3 - F T/sigma
+ * with r = D - M and P_j = (nu/nu_ref)^(-beta_j).
+ *   theta  host, FP64 [B][P], read during the call only.
+ *   out    host, FP64 [B]: lnL, as fgl_loglike_batch with FGL_PREC_FP64
+ *          up to rounding.
+ *   grad   host, FP64 [B][P].
+ *   prec   FGL_PREC_FP64 (the only mode with a gradient; others give
+ *          FGL_EINVAL).
+ * Invalid rows get lnL = -inf and a NaN gradient.  Synchronous.  Returns
+ * FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EBUSY or FGL_EDEVICE.
+ */
+int fgl_loglike_grad_batch(fgl_model* m, const double* theta, int B,
+                           double* out_logL, double* grad, int prec);
+
+/* Same with device memory (d_grad: FP64 [B][P]), enqueued on hip_stream as
+ * fgl_loglike_batch_device.  The kernel timing counters cover the gradient
+ * kernel of these calls too. */
+int fgl_loglike_grad_batch_device(fgl_model* m, const double* d_theta, int B,
+                                  double* d_out, double* d_grad, int prec,
+                                  void* hip_stream);
+
+/*
  * Tile configuration used for (model, B, prec): waves per workgroup,
  * channels per workgroup and the waves per SIMD the kernel variant is
  * compiled for, as chosen by the autotuner (measuring on first use when

@@ -378,6 +378,9 @@ static void free_work(WorkBuf& wb) {
   if (wb.d_out) (void)hipFree(wb.d_out);
   if (wb.h_theta) (void)hipHostFree(wb.h_theta);
   if (wb.h_out) (void)hipHostFree(wb.h_out);
+  if (wb.w.gpart) (void)hipFree(wb.w.gpart);
+  if (wb.d_grad) (void)hipFree(wb.d_grad);
+  if (wb.h_grad) (void)hipHostFree(wb.h_grad);
   wb = WorkBuf();
 }
 
@@ -551,6 +554,61 @@ int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const double* d_the
   }
   if ((e = launch_finalize(k, m->dm, wb.w, tile, d_out, s)) != hipSuccess)
     return hip_err(e, "finalize kernel");
+  return FGL_OK;
+}
+
+// Gradient partials for B rows (after ensure_work has set the row padding):
+// grow w.gpart, retiring the old buffer when queued work may still use it.
+static int ensure_gpart(Model* m, WorkBuf& wb, const GradShape& gs) {
+  const size_t need = (size_t)grad_slots(m->dm) * gs.chunks * wb.w.Bpad * 8;
+  if (wb.gpart_bytes >= need) return FGL_OK;
+  if (wb.w.gpart) {
+    if (wb.stream_synced_free) {
+      (void)hipFree(wb.w.gpart);
+    } else {
+      WorkBuf old;
+      old.w.gpart = wb.w.gpart;
+      m->retired.push_back(old);
+    }
+    wb.w.gpart = nullptr;
+    wb.gpart_bytes = 0;
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&wb.w.gpart), need);
+  if (e != hipSuccess) {
+    wb.w.gpart = nullptr;
+    return hip_err(e, "allocating gradient partials");
+  }
+  wb.gpart_bytes = need;
+  return FGL_OK;
+}
+
+// one gradient call: prep -> gradient kernel -> gradient finalize on stream s
+int enqueue_grad(Model* m, WorkBuf& wb, const double* d_theta, int B, double* d_out,
+                 double* d_grad, hipStream_t s) {
+  const GradShape gs = grad_shape(m->dm, wb.w.Bpad);
+  int rc = ensure_gpart(m, wb, gs);
+  if (rc != FGL_OK) return rc;
+  hipError_t e;
+  if ((e = launch_prep(m->dm, d_theta, B, wb.w, m->dm.KC * 32, s)) != hipSuccess)
+    return hip_err(e, "prep kernel");
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (m->timing) {
+    if (!m->ev_free.empty()) {
+      ev = m->ev_free.back();
+      m->ev_free.pop_back();
+    } else if ((e = hipEventCreate(&ev.first)) != hipSuccess ||
+               (e = hipEventCreate(&ev.second)) != hipSuccess) {
+      return hip_err(e, "hipEventCreate");
+    }
+    if ((e = hipEventRecord(ev.first, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
+  }
+  if ((e = launch_grad(m->dm, wb.w, gs, s)) != hipSuccess) return hip_err(e, "gradient kernel");
+  if (m->timing) {
+    if ((e = hipEventRecord(ev.second, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
+    m->ev_used.push_back(ev);
+  }
+  if ((e = launch_grad_finalize(m->dm, wb.w, gs, d_theta, d_out, d_grad, s)) != hipSuccess)
+    return hip_err(e, "gradient finalize");
   return FGL_OK;
 }
 
@@ -846,6 +904,80 @@ int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
   const Tile tile = tile_for(m, k, B);
   if ((rc = ensure_work(m, wb, B, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
   return enqueue(m, k, tile, wb, d_theta, B, d_out, s);
+}
+
+static int check_grad(Model* m, int B, int prec) {
+  int rc = check_call(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  if (prec != FGL_PREC_FP64)
+    return set_err(FGL_EINVAL, "gradients are evaluated in FP64 only (prec=%d)", prec);
+  return FGL_OK;
+}
+
+int fgl_loglike_grad_batch(fgl_model* mh, const double* theta, int B, double* out,
+                           double* grad, int prec) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_grad(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  if (B == 0) return FGL_OK;
+  if (!theta || !out || !grad) return set_err(FGL_EINVAL, "theta, out and grad must be non-NULL");
+  InflightGuard guard(m);
+  std::lock_guard<std::mutex> lk(m->mu);
+  hipError_t e = hipSetDevice(m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  if ((rc = make_resident(m)) != FGL_OK) return rc;
+  hipStream_t s = m->stream;
+  WorkBuf& wb = m->work[s];
+  wb.stream_synced_free = true;   // this stream is synchronised after every call
+  if ((rc = ensure_work(m, wb, B, 1, true)) != FGL_OK) return rc;
+  const size_t tb = (size_t)B * m->P * 8;
+  if (wb.grad_bytes < tb) {
+    if (wb.d_grad) (void)hipFree(wb.d_grad);
+    if (wb.h_grad) (void)hipHostFree(wb.h_grad);
+    wb.d_grad = wb.h_grad = nullptr;
+    wb.grad_bytes = 0;
+    const size_t cap = (size_t)wb.cap_rows * m->P * 8;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&wb.d_grad), cap)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&wb.h_grad), cap, hipHostMallocDefault)) != hipSuccess) {
+      if (wb.d_grad) (void)hipFree(wb.d_grad);
+      wb.d_grad = nullptr;
+      wb.h_grad = nullptr;
+      return hip_err(e, "allocating gradient staging");
+    }
+    wb.grad_bytes = cap;
+  }
+  std::memcpy(wb.h_theta, theta, tb);
+  if ((e = hipMemcpyAsync(wb.d_theta, wb.h_theta, tb, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_err(e, "copy theta");
+  if ((rc = enqueue_grad(m, wb, wb.d_theta, B, wb.d_out, wb.d_grad, s)) != FGL_OK) return rc;
+  if ((e = hipMemcpyAsync(wb.h_out, wb.d_out, (size_t)B * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_err(e, "copy out");
+  if ((e = hipMemcpyAsync(wb.h_grad, wb.d_grad, tb, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_err(e, "copy grad");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e, "hipStreamSynchronize");
+  std::memcpy(out, wb.h_out, (size_t)B * 8);
+  std::memcpy(grad, wb.h_grad, tb);
+  return FGL_OK;
+}
+
+int fgl_loglike_grad_batch_device(fgl_model* mh, const double* d_theta, int B,
+                                  double* d_out, double* d_grad, int prec,
+                                  void* hip_stream) {
+  Model* m = reinterpret_cast<Model*>(mh);
+  int rc = check_grad(m, B, prec);
+  if (rc != FGL_OK) return rc;
+  if (B == 0) return FGL_OK;
+  if (!d_theta || !d_out || !d_grad)
+    return set_err(FGL_EINVAL, "d_theta, d_out and d_grad must be non-NULL");
+  InflightGuard guard(m);
+  std::lock_guard<std::mutex> lk(m->mu);
+  hipError_t e = hipSetDevice(m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  if ((rc = make_resident(m)) != FGL_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  WorkBuf& wb = m->work[s];
+  if ((rc = ensure_work(m, wb, B, 1, false)) != FGL_OK) return rc;
+  return enqueue_grad(m, wb, d_theta, B, d_out, d_grad, s);
 }
 
 int fgl_mixed_form(const fgl_model* mh) {

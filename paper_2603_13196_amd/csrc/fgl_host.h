@@ -22,6 +22,10 @@ struct WorkBuf {
   double* h_theta = nullptr;   // pinned
   double* h_out = nullptr;     // pinned
   bool stream_synced_free = false;  // old buffers may be freed at once
+  size_t gpart_bytes = 0;      // capacity of w.gpart
+  double* d_grad = nullptr;    // gradient staging for host-pointer calls
+  double* h_grad = nullptr;    // pinned
+  size_t grad_bytes = 0;       // capacity of d_grad / h_grad
 };
 
 struct GraphKey {

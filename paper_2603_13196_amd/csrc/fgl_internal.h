@@ -116,7 +116,21 @@ struct Work {
   RowParams* rows;       // [Bpad]
   double* partial;       // [ngroups][Bpad]
   int ngroup_cap;        // capacity of partial in groups
+  double* gpart;         // gradient partials [chunks][grad_slots][Bpad]
 };
+
+// Gradient partials per (channel chunk, row): chi-square, the three 21-cm
+// sums, then per region sum_nu (-log2(nu/nu_ref)) c u and, with amplitude
+// masks, sum_nu c u (c: the region's coefficient, u: the region's row of
+// K times the residual).
+__host__ __device__ inline int grad_slots(const DevModel& m) { return 4 + m.N * (m.NA > 0 ? 2 : 1); }
+
+// Launch shape of the gradient kernel for B rows: 4-wave workgroups of 64
+// rows, `chunks` channel chunks of `per` channels, staged `fs` at a time.
+struct GradShape {
+  int nb, chunks, per, fs, lds;
+};
+GradShape grad_shape(const DevModel& m, int Bpad);
 
 // Launchers (fgl_kernels.hip).  All enqueue on `s`; none synchronises.
 hipError_t launch_prep(const DevModel& m, const double* theta, int B,
@@ -125,6 +139,13 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
                        const Tile& tile, hipStream_t s);
 hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
                            const Tile& tile, double* out, hipStream_t s);
+// Gradient (FP64): the kernel writes w.gpart, the finalize lnL and the
+// gradient rows.  w.gpart must hold grad_slots(m) * chunks * Bpad doubles.
+hipError_t launch_grad(const DevModel& m, const Work& w, const GradShape& g,
+                       hipStream_t s);
+hipError_t launch_grad_finalize(const DevModel& m, const Work& w, const GradShape& g,
+                                const double* theta, double* out, double* grad,
+                                hipStream_t s);
 
 // Shape helpers shared by host and launcher.
 int lds_bytes(Kind k, const DevModel& m, const Tile& t);

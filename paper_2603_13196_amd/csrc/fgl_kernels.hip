@@ -37,6 +37,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 #include <set>
@@ -547,6 +548,207 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 }
 
 // ---------------------------------------------------------------------------
+// gradient (FP64)
+//
+// d lnL / d theta by the chain rule through Eqs. likelihood,
+// fast_forward_model and t21model.  With r = D - M on the time grid and
+// c_i = alpha P_i the coefficient of region i at channel nu:
+//   d lnL / d beta  = (1/sigma^2) sum_nu (-ln(nu/nu_ref)) c_i u_i,
+//   d lnL / d alpha = (1/sigma^2) sum_nu P_i u_i,        u_i = sum_t K_i r,
+//   d lnL / d A     = (1/sigma^2) sum_nu g rho,          rho = sum_t r,
+//   d lnL / d nu21  = (A/(w^2 sigma^2)) sum_nu g (nu - nu21) rho,
+//   d lnL / d w     = (A/(w^3 sigma^2)) sum_nu g (nu - nu21)^2 rho,
+//   d lnL / d sigma = chi2/sigma^3 - F T/sigma.
+// The kernel runs the model of k_fp64 (same operands, same FP64 MFMA) and,
+// per 16-bin time tile, the transposed product u += K^T r on the same
+// matrix cores: the four residual registers of a lane are the B operands of
+// four v_mfma_f64_16x16x4_f64 whose K dimension is the lane group's time
+// bins, and the output rows land on the regions whose powers the lane
+// already holds (region 4q + g in register j = q mod 4 of group q / 4).  A
+// workgroup owns 64 rows for a chunk of channels, restaging K and D every
+// `fs` channels, and writes one set of partial sums per (chunk, row).
+
+template <int W, int NQB, bool AB>
+__global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, int fs,
+                                                   int nb, int nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NU = (NQB + 3) / 4;         // 16-region output groups
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int bt, ch;
+  map_block(nb, nc, bt, ch);
+  const int TT16 = m.TT16, N = m.N;
+  const int kdl = NQB * TT16 * 64;          // values per channel
+  float* s_k = reinterpret_cast<float*>(smem);
+  double* s_D = reinterpret_cast<double*>(smem + (size_t)fs * kdl * 4);
+  const int g = lane >> 4;                  // 0..3
+  const int b = bt * (W * 16) + wave * 16 + (lane & 15);
+  const RowParams rp = w.rows[b];
+  double beta[NQB];
+  double off[AB ? NQB : 1];
+#pragma unroll
+  for (int k = 0; k < NQB; ++k) {
+    const int i = 4 * k + g;
+    beta[k] = i < N ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
+    if constexpr (AB) off[k] = i < N ? w.offT[(size_t)i * w.Bpad + b] : 0.0;
+  }
+  double s1[NQB], s2[AB ? NQB : 1];
+#pragma unroll
+  for (int k = 0; k < NQB; ++k) {
+    s1[k] = 0.0;
+    if constexpr (AB) s2[k] = 0.0;
+  }
+  double chi_a = 0.0, chi_b = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
+  // the A operand of the transposed product: K[t][i] with t = 16 kt + 4 j + g
+  // and i = 16 it + (lane & 15), read from the forward layout
+  const int qsub = (lane & 15) >> 2;
+  const int tsub = g + 16 * (lane & 3);
+  const int c0 = ch * per, c1 = min(m.F, c0 + per);
+  for (int cs = c0; cs < c1; cs += fs) {
+    const int fn = min(fs, c1 - cs);
+    __syncthreads();                        // the previous stage is consumed
+    stage(s_k, m.k64 + (size_t)cs * kdl, fn * kdl * 4);
+    stage(s_D, m.D + (size_t)cs * m.TT * 32, fn * m.TT * 32 * 8);
+    __syncthreads();
+    for (int f = 0; f < fn; ++f) {
+      const int fi = cs + f;
+      const double nl = m.nl2[fi];
+      const double dnu = m.nu[fi] - rp.nu0;
+      const double z = dnu * rp.inv_w;
+      const double gg = exp(-0.5 * z * z);
+      const double c = m.t_cmb + rp.A * gg;
+      double Bp[NQB];
+#pragma unroll
+      for (int k = 0; k < NQB; ++k) Bp[k] = exp2(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl);
+      const float* kf = s_k + (size_t)f * kdl;
+      const double* Df = s_D + (size_t)f * m.TT * 32 + g;
+      f64x4 u[NU];
+#pragma unroll
+      for (int it = 0; it < NU; ++it) u[it] = f64x4{0.0, 0.0, 0.0, 0.0};
+      double rho = 0.0;
+      for (int tt = 0; tt < TT16; ++tt) {
+        float Ak[NQB];
+#pragma unroll
+        for (int k = 0; k < NQB; ++k) Ak[k] = kf[(k * TT16 + tt) * 64 + lane];
+        f64x4 a = {};
+#pragma unroll
+        for (int k = 0; k < NQB; ++k)
+          a = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Ak[k], Bp[k], a, 0, 0, 0);
+        const double* Dt = Df + tt * 16;
+        const bool ragged = (tt == TT16 - 1) && (m.T & 15);
+        double r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          r[j] = (Dt[4 * j] - c) - a[j];
+          if (ragged) {
+            const int t = tt * 16 + g + 4 * j;
+            r[j] = t < m.T ? r[j] : 0.0;
+          }
+          if (j & 1) chi_b = fma(r[j], r[j], chi_b);
+          else chi_a = fma(r[j], r[j], chi_a);
+          rho += r[j];
+        }
+#pragma unroll
+        for (int it = 0; it < NU; ++it) {
+          const int q = 4 * it + qsub;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const double at = q < NQB ? (double)kf[(q * TT16 + tt) * 64 + 4 * j + tsub] : 0.0;
+            u[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(at, r[j], u[it], 0, 0, 0);
+          }
+        }
+      }
+      // u[it][j] is region 16 it + 4 j + g = 4 q + g with q = 4 it + j
+#pragma unroll
+      for (int it = 0; it < NU; ++it)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int q = 4 * it + j;
+          if (q < NQB) {
+            const double cu = Bp[q] * u[it][j];
+            s1[q] = fma(nl, cu, s1[q]);
+            if constexpr (AB) s2[q] += cu;
+          }
+        }
+      const double grho = gg * rho;
+      h0 += grho;
+      h1 = fma(grho, dnu, h1);
+      h2 = fma(grho * dnu, dnu, h2);
+    }
+  }
+  // the lane groups hold disjoint time bins: chi-square and the 21-cm sums
+  // add over them; the region sums are per lane
+  double chi = chi_a + chi_b;
+  chi += __shfl_xor(chi, 16);
+  chi += __shfl_xor(chi, 32);
+  h0 += __shfl_xor(h0, 16);
+  h0 += __shfl_xor(h0, 32);
+  h1 += __shfl_xor(h1, 16);
+  h1 += __shfl_xor(h1, 32);
+  h2 += __shfl_xor(h2, 16);
+  h2 += __shfl_xor(h2, 32);
+  const int S = grad_slots(m);
+  double* gp = w.gpart + (size_t)ch * S * w.Bpad + b;
+  if (g == 0) {
+    gp[0] = chi;
+    gp[(size_t)1 * w.Bpad] = h0;
+    gp[(size_t)2 * w.Bpad] = h1;
+    gp[(size_t)3 * w.Bpad] = h2;
+  }
+#pragma unroll
+  for (int q = 0; q < NQB; ++q) {
+    const int i = 4 * q + g;
+    if (i < N) {
+      gp[(size_t)(4 + i) * w.Bpad] = s1[q];
+      if constexpr (AB) gp[(size_t)(4 + N + i) * w.Bpad] = s2[q];
+    }
+  }
+}
+
+// lnL and the gradient row from the chunk partials, one thread per row,
+// chunks summed in order.  Invalid rows get -inf and a NaN gradient.
+__global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, int chunks,
+                                                       const double* __restrict__ theta,
+                                                       double* __restrict__ out,
+                                                       double* __restrict__ grad) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= w.B) return;
+  const int S = grad_slots(m), P = m.P, N = m.N, NB = m.NB, NA = m.NA;
+  const size_t cs = (size_t)S * w.Bpad;
+  const double* gp = w.gpart + b;
+  double* gr = grad + (size_t)b * P;
+  const RowParams rp = w.rows[b];
+  if (!rp.valid) {
+    out[b] = -INFINITY;
+    for (int k = 0; k < P; ++k) gr[k] = NAN;
+    return;
+  }
+  auto sum = [&](int slot) {
+    double acc = 0.0;
+    for (int c = 0; c < chunks; ++c) acc += gp[c * cs + (size_t)slot * w.Bpad];
+    return acc;
+  };
+  const double s2 = rp.sigma * rp.sigma;
+  const double chi = sum(0);
+  const double nFT = (double)m.F * (double)m.T;
+  out[b] = -0.5 * chi / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
+  for (int k = 0; k < P; ++k) gr[k] = 0.0;
+  const double kb = M_LN2 / s2;             // d/d beta: -ln(nu/nu_ref) = ln2 nl2
+  for (int r = 0; r < N; ++r) {
+    const int ia = r / NB, jb = r - ia * NB;
+    gr[jb] += kb * sum(4 + r);
+    if (NA > 0) gr[NB + ia] += sum(4 + N + r);
+  }
+  for (int i = 0; i < NA; ++i) gr[NB + i] = gr[NB + i] / (theta[(size_t)b * P + NB + i] * s2);
+  if (!(m.flags & 1u)) {
+    const double iw = rp.inv_w;
+    gr[P - 4] = sum(1) / s2;
+    gr[P - 3] = rp.A * iw * iw * sum(2) / s2;
+    gr[P - 2] = rp.A * iw * iw * iw * sum(3) / s2;
+  }
+  gr[P - 1] = chi / (s2 * rp.sigma) - nFT / rp.sigma;
+}
+
+// ---------------------------------------------------------------------------
 // row preparation and finalize
 
 // Row preparation: validate, sanitise, expand the spectral indices (and,
@@ -845,6 +1047,61 @@ hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, s, w.partial,
                      n_groups(m, tile), w.Bpad, w.rows, w.B,
                      (double)m.F * (double)m.T, chi0, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gradient launchers
+
+namespace {
+
+template <bool AB>
+hipError_t grad_wa(const DevModel& m, const Work& w, const GradShape& gs, hipStream_t s) {
+  const int blocks = gs.nb * gs.chunks, th = 4 * 64;
+#define G64(Q)                                                                            \
+  case Q: {                                                                               \
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(k_grad64<4, Q, AB>));          \
+    if (e != hipSuccess) return e;                                                        \
+    hipLaunchKernelGGL((k_grad64<4, Q, AB>), dim3(blocks), dim3(th), gs.lds, s, m, w,     \
+                       gs.per, gs.fs, gs.nb, gs.chunks);                                  \
+    return hipGetLastError();                                                             \
+  }
+  switch (m.NQ) {
+    G64(1) G64(2) G64(4) G64(6) G64(8) G64(12) G64(16) G64(24) G64(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef G64
+}
+
+}  // namespace
+
+// 4-wave workgroups (64 rows); chunks of kGradChunk channels, fixed per
+// model so that a row's sums do not depend on the batch it came in; as many
+// channels staged at once as fit in 64 KB (at least one).
+constexpr int kGradChunk = 16;
+
+GradShape grad_shape(const DevModel& m, int Bpad) {
+  GradShape g;
+  g.nb = Bpad / 64;
+  const int per_ch = m.NQ * m.TT16 * 64 * 4 + m.TT * 32 * 8;
+  g.per = std::min(m.F, kGradChunk);
+  g.chunks = (m.F + g.per - 1) / g.per;
+  g.fs = std::max(1, std::min(g.per, (64 * 1024) / per_ch));
+  g.lds = g.fs * per_ch;
+  return g;
+}
+
+hipError_t launch_grad(const DevModel& m, const Work& w, const GradShape& g, hipStream_t s) {
+  if (w.Bpad % 64 != 0 || g.lds > max_lds_bytes() || !w.gpart) return hipErrorInvalidValue;
+  return m.NA > 0 ? grad_wa<true>(m, w, g, s) : grad_wa<false>(m, w, g, s);
+}
+
+hipError_t launch_grad_finalize(const DevModel& m, const Work& w, const GradShape& g,
+                                const double* theta, double* out, double* grad,
+                                hipStream_t s) {
+  const int blocks = (w.B + 255) / 256;
+  hipLaunchKernelGGL(k_grad_finalize, dim3(blocks), dim3(256), 0, s, m, w, g.chunks, theta,
+                     out, grad);
   return hipGetLastError();
 }
 

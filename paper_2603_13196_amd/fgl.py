@@ -65,6 +65,9 @@ _SIGS = {
     "fgl_loglike_batch": ([_vp, _dp, ctypes.c_int, _dp, ctypes.c_int], ctypes.c_int),
     "fgl_loglike_batch_device": ([_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp],
                                  ctypes.c_int),
+    "fgl_loglike_grad_batch": ([_vp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int], ctypes.c_int),
+    "fgl_loglike_grad_batch_device": ([_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp],
+                                      ctypes.c_int),
     "fgl_get_tile": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
                      ctypes.c_int),
@@ -153,6 +156,18 @@ def fgl_loglike_batch_device(model, d_theta: int, B, d_out: int, prec, stream: i
                                                 _prec(prec), _vp(stream)))
 
 
+def fgl_loglike_grad_batch(model, theta, B, out, grad, prec="fp64"):
+    return _check(_lib.fgl_loglike_grad_batch(model, theta.ctypes.data_as(_dp), int(B),
+                                              out.ctypes.data_as(_dp), grad.ctypes.data_as(_dp),
+                                              _prec(prec)))
+
+
+def fgl_loglike_grad_batch_device(model, d_theta: int, B, d_out: int, d_grad: int,
+                                  prec="fp64", stream: int = 0):
+    return _check(_lib.fgl_loglike_grad_batch_device(model, _vp(d_theta), int(B), _vp(d_out),
+                                                     _vp(d_grad), _prec(prec), _vp(stream)))
+
+
 def fgl_model_destroy(model):
     return _check(_lib.fgl_model_destroy(model))
 
@@ -234,6 +249,30 @@ class Model:
         out = np.empty(th.shape[0], dtype=np.float64)
         fgl_loglike_batch(self.handle, th, th.shape[0], out, prec)
         return out
+
+    def loglike_grad(self, theta, prec="fp64"):
+        """(lnL [B], d lnL / d theta [B, P]) for host rows (FP64)."""
+        th = _f64(theta).reshape(-1, self.P)
+        out = np.empty(th.shape[0], dtype=np.float64)
+        grad = np.empty_like(th)
+        fgl_loglike_grad_batch(self.handle, th, th.shape[0], out, grad, prec)
+        return out, grad
+
+    def loglike_grad_device(self, theta, out=None, grad=None, prec="fp64", stream=None):
+        """Device variant: theta a contiguous float64 CUDA tensor [B, P];
+        returns (out [B], grad [B, P]) torch tensors, enqueued on `stream`."""
+        import torch
+        if theta.dtype != torch.float64 or not theta.is_cuda or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous float64 device tensor")
+        B = theta.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=theta.device)
+        if grad is None:
+            grad = torch.empty((B, self.P), dtype=torch.float64, device=theta.device)
+        s = stream if stream is not None else torch.cuda.current_stream(theta.device)
+        fgl_loglike_grad_batch_device(self.handle, theta.data_ptr(), B, out.data_ptr(),
+                                      grad.data_ptr(), prec, s.cuda_stream)
+        return out, grad
 
     def loglike_device(self, theta, out=None, prec="mixed", stream=None):
         """theta: torch float64 CUDA tensor [B, P]; returns out (torch, [B]),
