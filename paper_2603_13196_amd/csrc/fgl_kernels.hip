@@ -704,16 +704,26 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
   }
 }
 
-// lnL and the gradient row from the chunk partials, one thread per row,
-// chunks summed in order.  Invalid rows get -inf and a NaN gradient.
-__global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, int chunks,
+// Sum the chunk partials of every (slot, row) in chunk order into the
+// first chunk's slab; one thread per (slot, row).
+__global__ __launch_bounds__(256) void k_grad_reduce(Work w, int S, int chunks) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)S * w.Bpad) return;
+  const size_t cs = (size_t)S * w.Bpad;
+  double acc = 0.0;
+  for (int c = 0; c < chunks; ++c) acc += w.gpart[c * cs + idx];
+  w.gpart[idx] = acc;
+}
+
+// lnL and the gradient row from the reduced sums, one thread per row.
+// Invalid rows get -inf and a NaN gradient.
+__global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w,
                                                        const double* __restrict__ theta,
                                                        double* __restrict__ out,
                                                        double* __restrict__ grad) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= w.B) return;
-  const int S = grad_slots(m), P = m.P, N = m.N, NB = m.NB, NA = m.NA;
-  const size_t cs = (size_t)S * w.Bpad;
+  const int P = m.P, N = m.N, NB = m.NB, NA = m.NA;
   const double* gp = w.gpart + b;
   double* gr = grad + (size_t)b * P;
   const RowParams rp = w.rows[b];
@@ -722,11 +732,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, int c
     for (int k = 0; k < P; ++k) gr[k] = NAN;
     return;
   }
-  auto sum = [&](int slot) {
-    double acc = 0.0;
-    for (int c = 0; c < chunks; ++c) acc += gp[c * cs + (size_t)slot * w.Bpad];
-    return acc;
-  };
+  auto sum = [&](int slot) { return gp[(size_t)slot * w.Bpad]; };
   const double s2 = rp.sigma * rp.sigma;
   const double chi = sum(0);
   const double nFT = (double)m.F * (double)m.T;
@@ -1099,9 +1105,14 @@ hipError_t launch_grad(const DevModel& m, const Work& w, const GradShape& g, hip
 hipError_t launch_grad_finalize(const DevModel& m, const Work& w, const GradShape& g,
                                 const double* theta, double* out, double* grad,
                                 hipStream_t s) {
+  const int S = grad_slots(m);
+  const size_t n = (size_t)S * w.Bpad;
+  hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, S,
+                     g.chunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int blocks = (w.B + 255) / 256;
-  hipLaunchKernelGGL(k_grad_finalize, dim3(blocks), dim3(256), 0, s, m, w, g.chunks, theta,
-                     out, grad);
+  hipLaunchKernelGGL(k_grad_finalize, dim3(blocks), dim3(256), 0, s, m, w, theta, out, grad);
   return hipGetLastError();
 }
 
