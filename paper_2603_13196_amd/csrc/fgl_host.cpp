@@ -204,6 +204,10 @@ static void build_projected(Model* m, const float* K, const double* data) {
   m->h_tg.assign((size_t)F * RT * 32, 0.0);
   m->h_dbar.assign(F, 0.0);
   m->h_pk.assign((size_t)F * 2, 0.0);
+  const int NQ = d.NQ, RT16 = (N + 1 + 15) / 16;
+  d.RT16 = RT16;
+  m->h_pa64.assign((size_t)F * NQ * RT16 * 64, 0.0);
+  m->h_pt64.assign((size_t)F * RT16 * 16, 0.0);
   long double chi0 = 0.0L;
   std::vector<long double> A((size_t)N * T), z(T), mat((size_t)rows * N);
   for (int f = 0; f < F; ++f) {
@@ -256,6 +260,20 @@ static void build_projected(Model* m, const float* K, const double* data) {
     }
     m->h_dbar[f] = (double)(sT * dmean);
     for (int k = 1; k < rows; ++k) m->h_tg[(size_t)f * RT * 32 + k] = (double)z[k - 1];
+    // FP64 operands of all N + 1 rows: row 0 sqrt(T) Kbar, row k >= 1 R[k-1]
+    auto full = [&](int k, int i) -> long double {
+      if (k == 0) return mat[i];
+      return i >= k - 1 ? A[(size_t)i * T + (k - 1)] : 0.0L;
+    };
+    for (int q = 0; q < NQ; ++q)
+      for (int tt = 0; tt < RT16; ++tt)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int k = tt * 16 + (lane & 15), i = 4 * q + (lane >> 4);
+          const double v = (k <= N && i < N) ? (double)full(k, i) : 0.0;
+          m->h_pa64[(((size_t)f * NQ + q) * RT16 + tt) * 64 + lane] = v;
+        }
+    m->h_pt64[(size_t)f * RT16 * 16] = (double)(sT * dmean);
+    for (int k = 1; k <= N; ++k) m->h_pt64[(size_t)f * RT16 * 16 + k] = (double)z[k - 1];
     // per-channel fixed point and digits [kProjDigits][KC][RT][64][16]
     long double mx = 0.0L;
     for (size_t k = 0; k < (size_t)rows * N; ++k) mx = std::max(mx, std::fabs(mat[k]));
@@ -299,7 +317,8 @@ size_t resident_bytes(const Model* m) {
   return m->h_kd.size() + m->h_eK.size() * 4 + m->h_k32.size() * 4 +
          m->h_k64.size() * 4 + (m->h_nl64.size() + m->h_nl2.size() + m->h_nu.size()) * 8 +
          m->h_D.size() * 8 + m->h_tab.size() * 8 + m->h_rd.size() + m->h_eR.size() * 4 +
-         (m->h_tg.size() + m->h_dbar.size() + m->h_pk.size()) * 8;
+         (m->h_tg.size() + m->h_dbar.size() + m->h_pk.size()) * 8 +
+         (m->h_pa64.size() + m->h_pt64.size()) * 8;
 }
 
 int make_resident(Model* m) {
@@ -310,15 +329,16 @@ int make_resident(Model* m) {
   int32_t *eK = nullptr, *eR = nullptr;
   float *k32 = nullptr, *k64 = nullptr;
   double *nl64 = nullptr, *nl2 = nullptr, *nu = nullptr, *D = nullptr, *tab = nullptr;
-  double *tg = nullptr, *dbar = nullptr, *pk = nullptr;
+  double *tg = nullptr, *dbar = nullptr, *pk = nullptr, *pa64 = nullptr, *pt64 = nullptr;
   if ((e = upload(&kd, m->h_kd)) != hipSuccess || (e = upload(&eK, m->h_eK)) != hipSuccess ||
+      (e = upload(&pa64, m->h_pa64)) != hipSuccess || (e = upload(&pt64, m->h_pt64)) != hipSuccess ||
       (e = upload(&k32, m->h_k32)) != hipSuccess || (e = upload(&k64, m->h_k64)) != hipSuccess ||
       (e = upload(&nl64, m->h_nl64)) != hipSuccess || (e = upload(&nl2, m->h_nl2)) != hipSuccess ||
       (e = upload(&nu, m->h_nu)) != hipSuccess || (e = upload(&D, m->h_D)) != hipSuccess ||
       (e = upload(&tab, m->h_tab)) != hipSuccess || (e = upload(&rd, m->h_rd)) != hipSuccess ||
       (e = upload(&eR, m->h_eR)) != hipSuccess || (e = upload(&tg, m->h_tg)) != hipSuccess ||
       (e = upload(&dbar, m->h_dbar)) != hipSuccess || (e = upload(&pk, m->h_pk)) != hipSuccess) {
-    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk};
+    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk, pa64, pt64};
     for (void* p : ps)
       if (p) (void)hipFree(p);
     return hip_err(e, "uploading model");
@@ -328,6 +348,8 @@ int make_resident(Model* m) {
   m->dm.tg = tg;
   m->dm.dbar = dbar;
   m->dm.pk = pk;
+  m->dm.pa64 = pa64;
+  m->dm.pt64 = pt64;
   m->dm.kd = kd;
   m->dm.eK = eK;
   m->dm.k32 = k32;
@@ -348,12 +370,12 @@ void evict(Model* m) {
   (void)hipDeviceSynchronize();
   const void* ps[] = {m->dm.kd, m->dm.eK, m->dm.k32, m->dm.k64, m->dm.nl64,
                       m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab, m->dm.rd,
-                      m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk};
+                      m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk, m->dm.pa64, m->dm.pt64};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
   m->dm.rd = nullptr;
   m->dm.eR = nullptr;
-  m->dm.tg = m->dm.dbar = m->dm.pk = nullptr;
+  m->dm.tg = m->dm.dbar = m->dm.pk = m->dm.pa64 = m->dm.pt64 = nullptr;
   m->dm.kd = nullptr;
   m->dm.eK = nullptr;
   m->dm.k32 = m->dm.k64 = nullptr;

@@ -69,6 +69,7 @@ struct Model {
   std::vector<int8_t> h_rd;                  // projected form (empty if unused)
   std::vector<int32_t> h_eR;
   std::vector<double> h_tg, h_dbar, h_pk;
+  std::vector<double> h_pa64, h_pt64;        // projected rows in FP64 (gradient)
   // serving bookkeeping
   uint64_t last_use = 0;
   // kernel timing (fgl_kernel_timing)

@@ -106,6 +106,11 @@ struct DevModel {
   const double* tg;      // [F][RT*32] targets (row 0 is per parameter row)
   const double* dbar;    // [F] sqrt(T) mean_t D
   const double* pk;      // [F][2] peeled diagonal entry and its target
+  // the same projected rows in FP64 for the gradient kernel: all N + 1 rows
+  // (nothing peeled) in 16-row tiles, as FP64 MFMA A operands
+  int RT16;              // 16-row tiles of the N + 1 rows
+  const double* pa64;    // [F][NQ][RT16][64]: lane -> (row 16 tt + lane%16, region 4 q + lane/16)
+  const double* pt64;    // [F][RT16*16] targets: row 0 sqrt(T) mean_t D, rows 1.. z
 };
 
 // Per-call workspace (device memory owned by the model, per stream).

@@ -568,18 +568,23 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 // workgroup owns 64 rows for a chunk of channels, restaging K and D every
 // `fs` channels, and writes one set of partial sums per (chunk, row).
 
-template <int W, int NQB, bool AB>
+template <int W, int NQB, bool AB, bool PROJ>
 __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, int fs,
                                                    int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
+  using AT = typename std::conditional<PROJ, double, float>::type;   // operand type
   constexpr int NU = (NQB + 3) / 4;         // 16-region output groups
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
   map_block(nb, nc, bt, ch);
-  const int TT16 = m.TT16, N = m.N;
-  const int kdl = NQB * TT16 * 64;          // values per channel
-  float* s_k = reinterpret_cast<float*>(smem);
-  double* s_D = reinterpret_cast<double*>(smem + (size_t)fs * kdl * 4);
+  const int TR = PROJ ? m.RT16 : m.TT16;    // 16-row tiles of the matrix
+  const int N = m.N;
+  const int kdl = NQB * TR * 64;            // operand values per channel
+  const int drow = PROJ ? m.RT16 * 16 : m.TT * 32;   // targets per channel
+  AT* s_k = reinterpret_cast<AT*>(smem);
+  double* s_D = reinterpret_cast<double*>(smem + (size_t)fs * kdl * sizeof(AT));
+  const AT* kg = PROJ ? reinterpret_cast<const AT*>(m.pa64) : reinterpret_cast<const AT*>(m.k64);
+  const double* dg = PROJ ? m.pt64 : m.D;
   const int g = lane >> 4;                  // 0..3
   const int b = bt * (W * 16) + wave * 16 + (lane & 15);
   const RowParams rp = w.rows[b];
@@ -598,16 +603,16 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
     if constexpr (AB) s2[k] = 0.0;
   }
   double chi_a = 0.0, chi_b = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
-  // the A operand of the transposed product: K[t][i] with t = 16 kt + 4 j + g
-  // and i = 16 it + (lane & 15), read from the forward layout
+  // the A operand of the transposed product: matrix row 16 tt + 4 j + g and
+  // region 16 it + (lane & 15), read from the forward layout
   const int qsub = (lane & 15) >> 2;
   const int tsub = g + 16 * (lane & 3);
   const int c0 = ch * per, c1 = min(m.F, c0 + per);
   for (int cs = c0; cs < c1; cs += fs) {
     const int fn = min(fs, c1 - cs);
     __syncthreads();                        // the previous stage is consumed
-    stage(s_k, m.k64 + (size_t)cs * kdl, fn * kdl * 4);
-    stage(s_D, m.D + (size_t)cs * m.TT * 32, fn * m.TT * 32 * 8);
+    stage(s_k, kg + (size_t)cs * kdl, fn * kdl * (int)sizeof(AT));
+    stage(s_D, dg + (size_t)cs * drow, fn * drow * 8);
     __syncthreads();
     for (int f = 0; f < fn; ++f) {
       const int fi = cs + f;
@@ -619,40 +624,55 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
       double Bp[NQB];
 #pragma unroll
       for (int k = 0; k < NQB; ++k) Bp[k] = exp2(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl);
-      const float* kf = s_k + (size_t)f * kdl;
-      const double* Df = s_D + (size_t)f * m.TT * 32 + g;
+      const AT* kf = s_k + (size_t)f * kdl;
+      const double* Df = s_D + (size_t)f * drow + g;
       f64x4 u[NU];
 #pragma unroll
       for (int it = 0; it < NU; ++it) u[it] = f64x4{0.0, 0.0, 0.0, 0.0};
       double rho = 0.0;
-      for (int tt = 0; tt < TT16; ++tt) {
-        float Ak[NQB];
+      for (int tt = 0; tt < TR; ++tt) {
+        AT Ak[NQB];
 #pragma unroll
-        for (int k = 0; k < NQB; ++k) Ak[k] = kf[(k * TT16 + tt) * 64 + lane];
+        for (int k = 0; k < NQB; ++k) Ak[k] = kf[(k * TR + tt) * 64 + lane];
         f64x4 a = {};
 #pragma unroll
         for (int k = 0; k < NQB; ++k)
           a = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Ak[k], Bp[k], a, 0, 0, 0);
         const double* Dt = Df + tt * 16;
-        const bool ragged = (tt == TT16 - 1) && (m.T & 15);
         double r[4];
+        if constexpr (PROJ) {
+          // targets; row 0 (tile 0, group 0, register 0) is the mean row,
+          // whose target sqrt(T) (Dbar - c) depends on the parameter row.
+          // Padded rows have zero operands and targets: their e is 0.
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          r[j] = (Dt[4 * j] - c) - a[j];
-          if (ragged) {
-            const int t = tt * 16 + g + 4 * j;
-            r[j] = t < m.T ? r[j] : 0.0;
+          for (int j = 0; j < 4; ++j) {
+            const bool mean_row = tt == 0 && g == 0 && j == 0;
+            const double tgt = mean_row ? fma(-m.sqrtT, c, Dt[0]) : Dt[4 * j];
+            r[j] = tgt - a[j];
+            if (j & 1) chi_b = fma(r[j], r[j], chi_b);
+            else chi_a = fma(r[j], r[j], chi_a);
+            if (mean_row) rho = m.sqrtT * r[j];   // sum_t r = sqrt(T) e_0
           }
-          if (j & 1) chi_b = fma(r[j], r[j], chi_b);
-          else chi_a = fma(r[j], r[j], chi_a);
-          rho += r[j];
+        } else {
+          const bool ragged = (tt == TR - 1) && (m.T & 15);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            r[j] = (Dt[4 * j] - c) - a[j];
+            if (ragged) {
+              const int t = tt * 16 + g + 4 * j;
+              r[j] = t < m.T ? r[j] : 0.0;
+            }
+            if (j & 1) chi_b = fma(r[j], r[j], chi_b);
+            else chi_a = fma(r[j], r[j], chi_a);
+            rho += r[j];
+          }
         }
 #pragma unroll
         for (int it = 0; it < NU; ++it) {
           const int q = 4 * it + qsub;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const double at = q < NQB ? (double)kf[(q * TT16 + tt) * 64 + 4 * j + tsub] : 0.0;
+            const double at = q < NQB ? (double)kf[(q * TR + tt) * 64 + 4 * j + tsub] : 0.0;
             u[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(at, r[j], u[it], 0, 0, 0);
           }
         }
@@ -675,7 +695,7 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
       h2 = fma(grho * dnu, dnu, h2);
     }
   }
-  // the lane groups hold disjoint time bins: chi-square and the 21-cm sums
+  // the lane groups hold disjoint matrix rows: chi-square and the 21-cm sums
   // add over them; the region sums are per lane
   double chi = chi_a + chi_b;
   chi += __shfl_xor(chi, 16);
@@ -717,7 +737,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(Work w, int S, int chunks) 
 
 // lnL and the gradient row from the reduced sums, one thread per row.
 // Invalid rows get -inf and a NaN gradient.
-__global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w,
+__global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, double chi0,
                                                        const double* __restrict__ theta,
                                                        double* __restrict__ out,
                                                        double* __restrict__ grad) {
@@ -734,7 +754,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w,
   }
   auto sum = [&](int slot) { return gp[(size_t)slot * w.Bpad]; };
   const double s2 = rp.sigma * rp.sigma;
-  const double chi = sum(0);
+  const double chi = sum(0) + chi0;
   const double nFT = (double)m.F * (double)m.T;
   out[b] = -0.5 * chi / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
   for (int k = 0; k < P; ++k) gr[k] = 0.0;
@@ -1061,15 +1081,15 @@ hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
 
 namespace {
 
-template <bool AB>
+template <bool AB, bool PROJ>
 hipError_t grad_wa(const DevModel& m, const Work& w, const GradShape& gs, hipStream_t s) {
   const int blocks = gs.nb * gs.chunks, th = 4 * 64;
 #define G64(Q)                                                                            \
   case Q: {                                                                               \
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(k_grad64<4, Q, AB>));          \
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(k_grad64<4, Q, AB, PROJ>));    \
     if (e != hipSuccess) return e;                                                        \
-    hipLaunchKernelGGL((k_grad64<4, Q, AB>), dim3(blocks), dim3(th), gs.lds, s, m, w,     \
-                       gs.per, gs.fs, gs.nb, gs.chunks);                                  \
+    hipLaunchKernelGGL((k_grad64<4, Q, AB, PROJ>), dim3(blocks), dim3(th), gs.lds, s, m,  \
+                       w, gs.per, gs.fs, gs.nb, gs.chunks);                               \
     return hipGetLastError();                                                             \
   }
   switch (m.NQ) {
@@ -1089,7 +1109,8 @@ constexpr int kGradChunk = 16;
 GradShape grad_shape(const DevModel& m, int Bpad) {
   GradShape g;
   g.nb = Bpad / 64;
-  const int per_ch = m.NQ * m.TT16 * 64 * 4 + m.TT * 32 * 8;
+  const int per_ch = m.proj ? m.NQ * m.RT16 * 64 * 8 + m.RT16 * 16 * 8
+                           : m.NQ * m.TT16 * 64 * 4 + m.TT * 32 * 8;
   g.per = std::min(m.F, kGradChunk);
   g.chunks = (m.F + g.per - 1) / g.per;
   g.fs = std::max(1, std::min(g.per, (64 * 1024) / per_ch));
@@ -1099,7 +1120,9 @@ GradShape grad_shape(const DevModel& m, int Bpad) {
 
 hipError_t launch_grad(const DevModel& m, const Work& w, const GradShape& g, hipStream_t s) {
   if (w.Bpad % 64 != 0 || g.lds > max_lds_bytes() || !w.gpart) return hipErrorInvalidValue;
-  return m.NA > 0 ? grad_wa<true>(m, w, g, s) : grad_wa<false>(m, w, g, s);
+  if (m.proj)
+    return m.NA > 0 ? grad_wa<true, true>(m, w, g, s) : grad_wa<false, true>(m, w, g, s);
+  return m.NA > 0 ? grad_wa<true, false>(m, w, g, s) : grad_wa<false, false>(m, w, g, s);
 }
 
 hipError_t launch_grad_finalize(const DevModel& m, const Work& w, const GradShape& g,
@@ -1112,7 +1135,9 @@ hipError_t launch_grad_finalize(const DevModel& m, const Work& w, const GradShap
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int blocks = (w.B + 255) / 256;
-  hipLaunchKernelGGL(k_grad_finalize, dim3(blocks), dim3(256), 0, s, m, w, theta, out, grad);
+  const double chi0 = m.proj ? m.chi0 : 0.0;
+  hipLaunchKernelGGL(k_grad_finalize, dim3(blocks), dim3(256), 0, s, m, w, chi0, theta, out,
+                     grad);
   return hipGetLastError();
 }
 

@@ -81,11 +81,13 @@ def _cases():
     f = lambda F: np.linspace(50.0, 200.0, F) if F > 1 else np.array([120.0])
     out = []
     for N, F, T, B in [(1, 5, 1, 7), (4, 151, 1, 64), (3, 9, 20, 100), (16, 13, 33, 70),
-                       (33, 5, 17, 40), (64, 4, 40, 33), (128, 3, 20, 20)]:
+                       (8, 11, 70, 50), (40, 5, 100, 30), (33, 5, 17, 40), (64, 4, 40, 33),
+                       (128, 3, 20, 20)]:
         out.append(("index", N, F, T, B,
                     lambda N=N, F=F, T=T, B=B: workload.make(N, f(F), T, B, 300 + N + T,
                                                              batch="mixed")))
-    for NA, NB, F, T, B in [(2, 3, 9, 20, 50), (3, 5, 6, 1, 40), (4, 32, 3, 20, 20)]:
+    for NA, NB, F, T, B in [(2, 3, 9, 20, 50), (3, 5, 6, 1, 40), (2, 16, 7, 96, 40),
+                            (4, 32, 3, 20, 20)]:
         out.append(("masks", NA * NB, F, T, B,
                     lambda NA=NA, NB=NB, F=F, T=T, B=B: workload.make_masks(
                         NA, NB, f(F), T, B, 400 + NA + NB, batch="mixed")))
@@ -96,13 +98,20 @@ def _cases():
 def test_grad_all_rows(fgl, orc, case):
     kind, N, F, T, B, make = case
     w = make()
-    say(f"gradient {kind} N={w.N} F={w.F} T={w.T} B={w.B} P={w.P}")
-    m = fgl.Model.from_workload(w)
-    ll, g = m.loglike_grad(w.theta)
     rl, rg = orc.grad_w(w)
-    check(ll, rl, "fp64", f"{kind}-N{N}", w.theta, w.F * w.T)
-    check_grad(g, rg, term_scale(orc, w, w.theta), f"{kind}-N{N}")
-    m.close()
+    scale = term_scale(orc, w, w.theta)
+    # the gradient sums over time in the model's form: the projected rows
+    # when the model has them, else the time grid (forced by the flag)
+    for flags in (0, fgl.FGL_MIXED_DIRECT):
+        m = fgl.Model.from_workload(w, flags)
+        form = m.form
+        say(f"gradient {kind} N={w.N} F={w.F} T={w.T} B={w.B} P={w.P} form={form}")
+        ll, g = m.loglike_grad(w.theta)
+        check(ll, rl, "fp64", f"{kind}-N{N}/{form}", w.theta, w.F * w.T)
+        check_grad(g, rg, scale, f"{kind}-N{N}/{form}")
+        m.close()
+        if form == "direct":
+            break
 
 
 def test_grad_headline_sampled(fgl, orc):
@@ -124,11 +133,14 @@ def test_grad_headline_sampled(fgl, orc):
     hl, hg = m.loglike_grad(w.theta[idx])
     assert np.array_equal(hl, out[idx]) and np.array_equal(hg, grad[idx])
     sh = workload.posterior_shell(2, 16)
-    sl, sg = m.loglike_grad(sh.theta)
     rl, rg = orc.grad_w(sh)
-    check(sl, rl, "fp64", "cfg2/grad-shell", sh.theta, sh.F * sh.T)
-    check_grad(sg, rg, term_scale(orc, sh, sh.theta), "cfg2/grad-shell")
-    m.close()
+    sc = term_scale(orc, sh, sh.theta)
+    assert m.form == "projected"
+    for mm in (m, fgl.Model.from_workload(sh, fgl.FGL_MIXED_DIRECT)):
+        sl, sg = mm.loglike_grad(sh.theta)
+        check(sl, rl, "fp64", f"cfg2/grad-shell/{mm.form}", sh.theta, sh.F * sh.T)
+        check_grad(sg, rg, sc, f"cfg2/grad-shell/{mm.form}")
+        mm.close()
 
 
 def test_grad_invalid_rows_and_errors(fgl, orc):
