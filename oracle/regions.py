@@ -32,7 +32,7 @@ Readings where the paper leaves details open:
   * region j is the half-open index interval [e_j, e_{j+1}); the last one is
     closed;
   * C^{-1}(c) is the smallest pixel spectral index whose C reaches c; the
-    mass of a region is the importance of its pixels;
+    mass of a region is the increase of C across it (its pixels' share);
   * ties in Algorithms 1 and 2 (equal widths or masses) go to the region
     with the lowest indices;
   * the horizon-aware weight does not depend on frequency; it is still
@@ -105,11 +105,14 @@ def cdf_inverse(xs, cs, c: float) -> float:
     return float(xs[min(k, xs.size - 1)])
 
 
-def region_mass(xs, w_sorted, a: float, b: float, last: bool) -> float:
-    """Importance of the pixels with a <= beta < b (<= b for the last region)."""
-    lo = np.searchsorted(xs, a, side="left")
-    hi = np.searchsorted(xs, b, side="right" if last else "left")
-    return float(np.sum(w_sorted[lo:hi]))
+def region_mass(xs, cs, a: float, b: float, last: bool) -> float:
+    """m_r = int_r dC: the increase of C over the pixels with a <= beta < b
+    (<= b for the last region)."""
+    lo = int(np.searchsorted(xs, a, side="left"))
+    hi = int(np.searchsorted(xs, b, side="right" if last else "left"))
+    top = float(cs[hi - 1]) if hi > 0 else 0.0
+    bottom = float(cs[lo - 1]) if lo > 0 else 0.0
+    return top - bottom
 
 
 def hierarchical(xs, cs, n_total: int) -> np.ndarray:
@@ -130,13 +133,13 @@ def hierarchical(xs, cs, n_total: int) -> np.ndarray:
     return np.array(edges)
 
 
-def recursive(xs, cs, n_total: int, weights_sorted) -> np.ndarray:
+def recursive(xs, cs, n_total: int) -> np.ndarray:
     """Alg. method2: start from [beta_min, beta_max]; repeatedly bisect, at
     its spectral-index midpoint, the region holding the most importance."""
     edges = [float(xs[0]), float(xs[-1])]
     while len(edges) - 1 < n_total:
         n = len(edges) - 1
-        masses = [region_mass(xs, weights_sorted, edges[j], edges[j + 1], j == n - 1)
+        masses = [region_mass(xs, cs, edges[j], edges[j + 1], j == n - 1)
                   for j in range(n)]
         j = int(np.argmax(masses))                  # first of the heaviest
         edges.insert(j + 1, 0.5 * (edges[j] + edges[j + 1]))
@@ -148,8 +151,7 @@ def partition(beta: np.ndarray, imp: np.ndarray, n_total: int, method: str) -> n
     if method == "hierarchical":
         return hierarchical(xs, cs, n_total)
     if method == "recursive":
-        order = np.argsort(beta.ravel(), kind="stable")
-        return recursive(xs, cs, n_total, imp.ravel()[order])
+        return recursive(xs, cs, n_total)
     raise ValueError(method)
 
 
