@@ -300,6 +300,78 @@ int fgl_chains_destroy(fgl_chains* c);
 /* Message of the calling thread's last failure ("" if none). */
 const char* fgl_last_error(void);
 
+/*
+ * Region construction and chromatic response functions (Sec. 4; Eq.
+ * chromatic_function), upstream of the likelihood: they produce the K a
+ * model is created from.
+ *
+ * The sky is an equirectangular grid of nlat rings (declination) by nlon
+ * columns (right ascension); pixel (r, c) has solid angle 4 pi omega[r].
+ * Sky-frame maps are indexed (ring, ra); the beam and horizon are fixed to
+ * the antenna and indexed (ring, hour angle).  At LST step t the sky pixel
+ * (r, c) sits at the antenna pixel (r, (c - s_t) mod nlon); shifts[t] = s_t.
+ */
+typedef struct fgl_sky fgl_sky;       /* opaque, library-owned */
+
+enum { FGL_WEIGHT_HORIZON = 0, FGL_WEIGHT_SKY = 1, FGL_WEIGHT_BEAM = 2 };
+enum { FGL_PARTITION_HIERARCHICAL = 0, FGL_PARTITION_RECURSIVE = 1 };
+
+/*
+ * Copy a sky to the device.
+ *   omega    host FP64 [nlat], pixel solid angle / (4 pi) of each ring, > 0.
+ *   t_ex     host FP64 [nlat][nlon], T_base - T_CMB at nu0 (K), sky frame.
+ *   beta     host FP64 [nlat][nlon], spectral index (Eq. spectralindexmap),
+ *            |beta| <= 64, sky frame.
+ *   beam     host FP32 [F][nlat][nlon], D(nu), antenna frame.
+ *   horizon  host uint8 [nlat][nlon], H (0 or non-zero), antenna frame.
+ *   freqs    host FP64 [F] (MHz, > 0); nu0 reference frequency (MHz, > 0);
+ *   t_cmb    CMB temperature (K).
+ * All inputs are copied; returns FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EDEVICE.
+ */
+int fgl_sky_create(int nlat, int nlon, int F, const double* omega,
+                   const double* t_ex, const double* beta, const float* beam,
+                   const uint8_t* horizon, const double* freqs, double nu0,
+                   double t_cmb, fgl_sky** out);
+
+/*
+ * Importance of every sky pixel for one of the three weightings of
+ * Sec. 4.2 (horizon: H; sky: T_sky H; beam: T_sky D H, with
+ * T_sky = t_ex (nu/nu0)^(-beta) + T_CMB, Eq. skyapproximation), each
+ * normalised to integrate to one over the sphere per (nu, t):
+ *   importance[q] = sum_{nu, t} omega(q) W(p_t(q), nu, t)   (host FP64
+ *   [nlat][nlon]), the per-pixel weights of Eq. weighted_cdf.
+ * shifts: host int32 [T], each in [0, nlon).  FGL_EINVAL when a weight
+ * integrates to zero at some (nu, t).  Synchronous.
+ */
+int fgl_sky_importance(fgl_sky* s, const int32_t* shifts, int T, int scheme,
+                       double* importance);
+
+/*
+ * Partition the spectral-index range on the importance-weighted CDF of n
+ * pixels (Eq. weighted_cdf) into n_regions regions by Alg. method1
+ * (FGL_PARTITION_HIERARCHICAL) or Alg. method2 (FGL_PARTITION_RECURSIVE).
+ * edges (host FP64 [n_regions + 1]) receives the non-decreasing edges; region
+ * j holds e_j <= beta < e_{j+1} (the last is closed).  C is the cumulative
+ * weight of the pixels in ascending beta (stable), divided by its total;
+ * C^{-1}(c) is the smallest pixel beta with C >= c; a region's mass is the
+ * increase of C across it; ties go to the lowest region.  Host only.
+ */
+int fgl_partition(const double* beta, const double* weight, int n,
+                  int n_regions, int method, double* edges);
+
+/*
+ * Chromatic response functions of the regions given by edges (Eq.
+ * chromatic_function, one amplitude mask):
+ *   K[j][nu][t] = sum_{q: region(q) = j} omega(q) t_ex(q) D(nu, p_t(q))
+ * in FP64 (host [n_regions][F][T]); pixels outside [e_0, e_N] belong to no
+ * region.  n_regions in 1..1024 (within one workgroup's LDS).  Synchronous;
+ * fgl_sky_kernel_ms then gives the correlation kernel's duration.
+ */
+int fgl_sky_chromatic(fgl_sky* s, const double* edges, int n_regions,
+                      const int32_t* shifts, int T, double* K);
+int fgl_sky_kernel_ms(const fgl_sky* s, double* ms);
+int fgl_sky_destroy(fgl_sky* s);
+
 #ifdef __cplusplus
 }
 #endif

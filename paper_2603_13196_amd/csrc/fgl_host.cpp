@@ -54,7 +54,7 @@ static void unregister_model(Model* m) {
 // ---------------------------------------------------------------------------
 // device check
 
-static int check_device(int* dev_out) {
+int check_device(int* dev_out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_err(e, "hipGetDevice");

@@ -86,6 +86,7 @@ struct InflightGuard {
 int set_err(int code, const char* fmt, ...);
 int hip_err(hipError_t e, const char* what);
 const char* last_error();
+int check_device(int* dev_out);   // current device, gfx950 required
 
 size_t resident_bytes(const Model* m);
 int make_resident(Model* m);

@@ -1,0 +1,543 @@
+// Region construction and chromatic response functions (Tutt et al.,
+// Sec. 4 and Eq. chromatic_function) on an equirectangular sky.
+//
+// Pixels are rings (declination) x columns (right ascension), with solid
+// angle omega[ring] (divided by 4 pi).  Sky-frame maps: t_ex = T_base -
+// T_CMB and the spectral index beta.  Antenna-frame maps (declination x hour
+// angle): the beam D(nu) and the horizon H.  At LST step t the sky pixel
+// (ring, ra) sits at the antenna pixel (ring, (ra - s_t) mod nlon).
+//
+// Every quantity here is a cyclic correlation along the columns of each
+// ring, summed over rings:
+//   Z(nu, t)  = sum_q omega a(q, nu) b(nu, p_t(q))        (normalisers)
+//   I(q)      = sum_{nu, t} omega a(q, nu) b(nu, p_t(q)) / Z(nu, t)
+//   K_j(nu, t) = sum_{q in region j} omega t_ex(q) D(nu, p_t(q))
+// with a = T_sky (Eq. skyapproximation) or 1 and b = D H, H or D by scheme.
+// k_sky_corr computes Z and K: one workgroup per (channel, ring chunk), one
+// thread per time step; a ring's b row, its pixels (sorted by region) and
+// their weights are staged in LDS, each thread sums its shifted products
+// region by region in a register and adds each region's sum to its own LDS
+// accumulator, so every sum has a fixed order.  k_sky_importance computes
+// I: one thread per pixel, looping over channels with the ring's b row and
+// 1/Z(nu, .) in LDS.  The partition (Algs. method1 and method2) is a short
+// sequential computation on the host.
+#include "fgl_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace fgl {
+
+namespace {
+
+constexpr int kRingChunk = 32;         // rings per k_sky_corr workgroup
+
+struct SkyDev {
+  int nlat, nlon, F;
+  double t_cmb;
+  const double* omega;   // [nlat]
+  const double* t_ex;    // [nlat][nlon]
+  const double* beta;    // [nlat][nlon]
+  const float* beam;     // [F][nlat][nlon]
+  const uint8_t* hor;    // [nlat][nlon]
+  const double* lr;      // [F] log2(nu / nu0)
+};
+
+enum Corr { kCorrK = 0, kCorrBeam = 1, kCorrSky = 2, kCorrHorizon = 3 };
+
+// b(nu, ring, ha) for a mode
+template <int MODE>
+__device__ inline double bval(const SkyDev& s, int f, int ring, int ha) {
+  const size_t px = (size_t)ring * s.nlon + ha;
+  if constexpr (MODE == kCorrK) return (double)s.beam[(size_t)f * s.nlat * s.nlon + px];
+  if constexpr (MODE == kCorrBeam)
+    return s.hor[px] ? (double)s.beam[(size_t)f * s.nlat * s.nlon + px] : 0.0;
+  return s.hor[px] ? 1.0 : 0.0;
+}
+
+// weight a(q, nu) of a sky pixel, omega included
+template <int MODE>
+__device__ inline double aval(const SkyDev& s, int f, int ring, int ra) {
+  const size_t px = (size_t)ring * s.nlon + ra;
+  if constexpr (MODE == kCorrK) return s.omega[ring] * s.t_ex[px];
+  if constexpr (MODE == kCorrHorizon) return s.omega[ring];
+  // Eq. skyapproximation
+  return s.omega[ring] * fma(s.t_ex[px], exp2(-s.beta[px] * s.lr[f]), s.t_cmb);
+}
+
+// partial[((chunk * NJ + j) * F + f) * T + t]: the sum over the chunk's
+// rings.  order[ring][k] lists the ring's columns by region, seg[ring][j]
+// the start of region j (seg[ring][NJ] = pixels in regions); without them
+// (Z) every pixel is region 0 in column order.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restrict__ shifts,
+                                                  int T, int t0, const int* __restrict__ order,
+                                                  const int* __restrict__ seg, int NJ,
+                                                  double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int f = blockIdx.x, chunk = blockIdx.y;
+  const int nlon = s.nlon;
+  double* s_acc = reinterpret_cast<double*>(smem);             // [blockDim][NJ]
+  double* s_a = s_acc + (size_t)blockDim.x * NJ;               // [nlon]
+  float* s_b = reinterpret_cast<float*>(s_a + nlon);            // [nlon]
+  int* s_idx = reinterpret_cast<int*>(s_b + nlon);             // [nlon]
+  int* s_seg = s_idx + nlon;                                   // [NJ + 1]
+  const int tl = threadIdx.x, t = t0 + tl;
+  const bool live = t < T;
+  const int sh = live ? shifts[t] : 0;
+  for (int j = 0; j < NJ; ++j) s_acc[(size_t)tl * NJ + j] = 0.0;
+  const int r0 = chunk * kRingChunk, r1 = min(s.nlat, r0 + kRingChunk);
+  for (int ring = r0; ring < r1; ++ring) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
+      const int ra = order ? order[(size_t)ring * nlon + k] : k;
+      s_idx[k] = ra;
+      s_a[k] = aval<MODE>(s, f, ring, ra);
+      s_b[k] = (float)bval<MODE>(s, f, ring, k);   // b values are FP32 or 0/1
+    }
+    for (int j = threadIdx.x; j <= NJ; j += blockDim.x)
+      s_seg[j] = seg ? seg[(size_t)ring * (NJ + 1) + j] : (j == 0 ? 0 : nlon);
+    __syncthreads();
+    if (!live) continue;
+    for (int j = 0; j < NJ; ++j) {
+      double acc = 0.0;
+      for (int k = s_seg[j]; k < s_seg[j + 1]; ++k) {
+        int ha = s_idx[k] - sh;
+        ha += ha < 0 ? nlon : 0;
+        acc = fma(s_a[k], (double)s_b[ha], acc);
+      }
+      s_acc[(size_t)tl * NJ + j] += acc;
+    }
+  }
+  if (!live) return;
+  for (int j = 0; j < NJ; ++j)
+    partial[(((size_t)chunk * NJ + j) * s.F + f) * T + t] = s_acc[(size_t)tl * NJ + j];
+}
+
+// out[i] = sum over chunks (in order) of partial[chunk * n + i]
+__global__ __launch_bounds__(256) void k_sky_reduce(const double* __restrict__ partial,
+                                                    int chunks, size_t n,
+                                                    double* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < chunks; ++c) acc += partial[(size_t)c * n + i];
+  out[i] = acc;
+}
+
+// I(ring, ra) = sum_nu a(q, nu) sum_t b(nu, ring, ra - s_t) / Z(nu, t); one
+// thread per column of one ring
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sky_importance(SkyDev s, const int* __restrict__ shifts,
+                                                        int T, const double* __restrict__ Z,
+                                                        double* __restrict__ imp) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ring = blockIdx.x;
+  const int nlon = s.nlon;
+  double* s_iz = reinterpret_cast<double*>(smem);   // [T]
+  int* s_sh = reinterpret_cast<int*>(s_iz + T);      // [T]
+  float* s_b = reinterpret_cast<float*>(s_sh + T + (T & 1));   // [nlon]
+  for (int t = threadIdx.x; t < T; t += blockDim.x) s_sh[t] = shifts[t];
+  for (int ra0 = 0; ra0 < nlon; ra0 += blockDim.x) {
+    const int ra = ra0 + threadIdx.x;
+    double total = 0.0;
+    for (int f = 0; f < s.F; ++f) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < T; t += blockDim.x) s_iz[t] = 1.0 / Z[(size_t)f * T + t];
+      for (int k = threadIdx.x; k < nlon; k += blockDim.x) s_b[k] = (float)bval<MODE>(s, f, ring, k);
+      __syncthreads();
+      if (ra < nlon) {
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) {
+          int ha = ra - s_sh[t];
+          ha += ha < 0 ? nlon : 0;
+          acc = fma((double)s_b[ha], s_iz[t], acc);
+        }
+        total = fma(aval<MODE>(s, f, ring, ra), acc, total);
+      }
+    }
+    if (ra < nlon) imp[(size_t)ring * nlon + ra] = total;
+  }
+}
+
+int corr_block(int T, int NJ, int nlon) {
+  int tb = std::min(256, (T + 63) / 64 * 64);
+  while (tb > 64 && (size_t)tb * NJ * 8 + (size_t)nlon * 16 + (NJ + 1) * 4 > 96 * 1024) tb -= 64;
+  return tb;
+}
+
+size_t corr_lds(int tb, int NJ, int nlon) {
+  return (size_t)tb * NJ * 8 + (size_t)nlon * 16 + (size_t)(NJ + 1) * 4;
+}
+
+struct Sky {
+  int dev = 0;
+  SkyDev d{};
+  double nu0 = 0.0;
+  hipStream_t stream = nullptr;
+  std::vector<double> h_beta;      // for the masks of a partition
+  double last_ms = 0.0;            // last k_sky_corr duration (chromatic)
+};
+
+template <typename KernelT>
+hipError_t set_lds(KernelT k) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// Z or K partial sums and their chunk reduction into out (device).
+template <int MODE>
+int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const int* d_seg, int NJ,
+             double* d_out, float* ms) {
+  const SkyDev& d = sk->d;
+  const int chunks = (d.nlat + kRingChunk - 1) / kRingChunk;
+  const size_t n = (size_t)NJ * d.F * T;
+  double* part = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&part), n * chunks * 8);
+  if (e != hipSuccess) return hip_err(e, "allocating partial sums");
+  const int tb = corr_block(T, NJ, d.nlon);
+  const size_t lds = corr_lds(tb, NJ, d.nlon);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, sk->stream);
+  }
+  if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {
+    for (int t0 = 0; t0 < T && e == hipSuccess; t0 += tb) {
+      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks), dim3(tb), lds, sk->stream, d,
+                         d_shifts, T, t0, d_order, d_seg, NJ, part);
+      e = hipGetLastError();
+    }
+  }
+  if (ms && e == hipSuccess) (void)hipEventRecord(e1, sk->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_sky_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, sk->stream,
+                       part, chunks, n, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(sk->stream);
+  if (ms && e == hipSuccess) (void)hipEventElapsedTime(ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(part);
+  return e == hipSuccess ? FGL_OK : hip_err(e, "correlation kernels");
+}
+
+int check_shifts(const Sky* sk, const int32_t* shifts, int T) {
+  if (!shifts || T < 1) return set_err(FGL_EINVAL, "need T >= 1 shifts");
+  for (int t = 0; t < T; ++t)
+    if (shifts[t] < 0 || shifts[t] >= sk->d.nlon)
+      return set_err(FGL_EINVAL, "shifts[%d]=%d outside 0..%d", t, shifts[t], sk->d.nlon - 1);
+  return FGL_OK;
+}
+
+// device buffer holding a host array
+template <typename T>
+int to_device(T** dst, const T* src, size_t count, const char* what) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(count * sizeof(T), 16));
+  if (e == hipSuccess && count) e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    return hip_err(e, what);
+  }
+  return FGL_OK;
+}
+
+void free_sky(Sky* sk) {
+  const void* ps[] = {sk->d.omega, sk->d.t_ex, sk->d.beta, sk->d.beam, sk->d.hor, sk->d.lr};
+  for (const void* p : ps)
+    if (p) (void)hipFree(const_cast<void*>(p));
+  if (sk->stream) (void)hipStreamDestroy(sk->stream);
+  delete sk;
+}
+
+}  // namespace
+
+// Algs. method1 and method2 on the importance-weighted CDF (host).
+int partition_host(const double* beta, const double* weight, int n, int n_regions, int method,
+                   double* edges) {
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return beta[a] < beta[b]; });
+  std::vector<double> xs(n), cs(n);
+  double run = 0.0;
+  for (int k = 0; k < n; ++k) {
+    xs[k] = beta[order[k]];
+    run += weight[order[k]];
+    cs[k] = run;
+  }
+  const double total = cs[n - 1];
+  if (!(total > 0.0)) return set_err(FGL_EINVAL, "the weights sum to zero");
+  for (int k = 0; k < n; ++k) cs[k] = cs[k] / total;
+  auto cdf_at = [&](double x) {
+    const int k = (int)(std::upper_bound(xs.begin(), xs.end(), x) - xs.begin());
+    return k == 0 ? 0.0 : cs[k - 1];
+  };
+  auto cdf_inv = [&](double c) {
+    const int k = (int)(std::lower_bound(cs.begin(), cs.end(), c) - cs.begin());
+    return xs[std::min(k, n - 1)];
+  };
+  std::vector<double> e;
+  if (method == FGL_PARTITION_HIERARCHICAL) {
+    int base = 1;
+    while (base * 2 <= n_regions) base *= 2;
+    e.push_back(xs[0]);
+    for (int k = 1; k < base; ++k) e.push_back(cdf_inv((double)k / (double)base));
+    e.push_back(xs[n - 1]);
+    for (int r = base; r < n_regions; ++r) {
+      int j = 0;
+      double best = e[1] - e[0];
+      for (int i = 1; i + 1 < (int)e.size(); ++i)
+        if (e[i + 1] - e[i] > best) {
+          best = e[i + 1] - e[i];
+          j = i;
+        }
+      const double cm = 0.5 * (cdf_at(e[j]) + cdf_at(e[j + 1]));
+      e.insert(e.begin() + j + 1, cdf_inv(cm));
+    }
+  } else {
+    e = {xs[0], xs[n - 1]};
+    while ((int)e.size() - 1 < n_regions) {
+      const int nr = (int)e.size() - 1;
+      int j = 0;
+      double best = -1.0;
+      for (int i = 0; i < nr; ++i) {
+        const bool last = i == nr - 1;
+        const int lo = (int)(std::lower_bound(xs.begin(), xs.end(), e[i]) - xs.begin());
+        const int hi = last ? (int)(std::upper_bound(xs.begin(), xs.end(), e[i + 1]) - xs.begin())
+                            : (int)(std::lower_bound(xs.begin(), xs.end(), e[i + 1]) - xs.begin());
+        const double top = hi > 0 ? cs[hi - 1] : 0.0, bottom = lo > 0 ? cs[lo - 1] : 0.0;
+        const double m = top - bottom;
+        if (i == 0 || m > best) {
+          best = m;
+          j = i;
+        }
+      }
+      e.insert(e.begin() + j + 1, 0.5 * (e[j] + e[j + 1]));
+    }
+  }
+  std::copy(e.begin(), e.end(), edges);
+  return FGL_OK;
+}
+
+}  // namespace fgl
+
+using namespace fgl;
+
+extern "C" {
+
+int fgl_sky_create(int nlat, int nlon, int F, const double* omega, const double* t_ex,
+                   const double* beta, const float* beam, const uint8_t* horizon,
+                   const double* freqs, double nu0, double t_cmb, fgl_sky** out) {
+  if (!out) return set_err(FGL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nlat < 1 || nlon < 1 || F < 1) return set_err(FGL_EINVAL, "need nlat, nlon, F >= 1");
+  if (!omega || !t_ex || !beta || !beam || !horizon || !freqs)
+    return set_err(FGL_EINVAL, "array arguments must be non-NULL");
+  if (!(nu0 > 0.0) || !std::isfinite(nu0) || !std::isfinite(t_cmb))
+    return set_err(FGL_EINVAL, "nu0 must be finite and > 0, t_cmb finite");
+  const size_t np = (size_t)nlat * nlon;
+  for (int r = 0; r < nlat; ++r)
+    if (!(omega[r] > 0.0) || !std::isfinite(omega[r])) return set_err(FGL_EINVAL, "omega[%d] must be finite and > 0", r);
+  for (size_t k = 0; k < np; ++k)
+    if (!std::isfinite(t_ex[k]) || !std::isfinite(beta[k]) || std::fabs(beta[k]) > 64.0)
+      return set_err(FGL_EINVAL, "t_ex/beta[%zu] must be finite with |beta| <= 64", k);
+  for (size_t k = 0; k < np * F; ++k)
+    if (!std::isfinite(beam[k])) return set_err(FGL_EINVAL, "beam[%zu] is not finite", k);
+  std::vector<double> lr(F);
+  for (int f = 0; f < F; ++f) {
+    if (!(freqs[f] > 0.0) || !std::isfinite(freqs[f])) return set_err(FGL_EINVAL, "freqs[%d] must be finite and > 0", f);
+    lr[f] = std::log2(freqs[f] / nu0);
+  }
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != FGL_OK) return rc;
+  Sky* sk = new (std::nothrow) Sky();
+  if (!sk) return set_err(FGL_ENOMEM, "host allocation");
+  sk->dev = dev;
+  sk->nu0 = nu0;
+  sk->d.nlat = nlat;
+  sk->d.nlon = nlon;
+  sk->d.F = F;
+  sk->d.t_cmb = t_cmb;
+  sk->h_beta.assign(beta, beta + np);
+  double *om = nullptr, *tx = nullptr, *bt = nullptr, *l2 = nullptr;
+  float* bm = nullptr;
+  uint8_t* hz = nullptr;
+  if ((rc = to_device(&om, omega, (size_t)nlat, "uploading omega")) != FGL_OK ||
+      (rc = to_device(&tx, t_ex, np, "uploading t_ex")) != FGL_OK ||
+      (rc = to_device(&bt, beta, np, "uploading beta")) != FGL_OK ||
+      (rc = to_device(&bm, beam, np * F, "uploading the beam")) != FGL_OK ||
+      (rc = to_device(&hz, horizon, np, "uploading the horizon")) != FGL_OK ||
+      (rc = to_device(&l2, lr.data(), (size_t)F, "uploading frequencies")) != FGL_OK) {
+    sk->d.omega = om; sk->d.t_ex = tx; sk->d.beta = bt; sk->d.beam = bm; sk->d.hor = hz; sk->d.lr = l2;
+    free_sky(sk);
+    return rc;
+  }
+  sk->d.omega = om;
+  sk->d.t_ex = tx;
+  sk->d.beta = bt;
+  sk->d.beam = bm;
+  sk->d.hor = hz;
+  sk->d.lr = l2;
+  hipError_t e = hipStreamCreateWithFlags(&sk->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    sk->stream = nullptr;
+    free_sky(sk);
+    return hip_err(e, "hipStreamCreate");
+  }
+  *out = reinterpret_cast<fgl_sky*>(sk);
+  return FGL_OK;
+}
+
+int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, double* importance) {
+  Sky* sk = reinterpret_cast<Sky*>(sh);
+  if (!sk || !importance) return set_err(FGL_EINVAL, "sky and importance must be non-NULL");
+  if (scheme < FGL_WEIGHT_HORIZON || scheme > FGL_WEIGHT_BEAM)
+    return set_err(FGL_EINVAL, "unknown weighting scheme %d", scheme);
+  int rc = check_shifts(sk, shifts, T);
+  if (rc != FGL_OK) return rc;
+  if (corr_lds(corr_block(T, 1, sk->d.nlon), 1, sk->d.nlon) > 160 * 1024)
+    return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", sk->d.nlon);
+  hipError_t e = hipSetDevice(sk->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  const SkyDev& d = sk->d;
+  int* d_sh = nullptr;
+  double *Z = nullptr, *imp = nullptr;
+  if ((rc = to_device(&d_sh, shifts, (size_t)T, "uploading shifts")) != FGL_OK) return rc;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&Z), (size_t)d.F * T * 8)) != hipSuccess ||
+      (e = hipMalloc(reinterpret_cast<void**>(&imp), (size_t)d.nlat * d.nlon * 8)) != hipSuccess) {
+    rc = hip_err(e, "allocating importance buffers");
+  }
+  if (rc == FGL_OK) {
+    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, nullptr, nullptr, 1, Z, nullptr)
+         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, nullptr, nullptr, 1, Z, nullptr)
+                                    : run_corr<kCorrHorizon>(sk, d_sh, T, nullptr, nullptr, 1, Z, nullptr);
+  }
+  if (rc == FGL_OK) {
+    std::vector<double> hz((size_t)d.F * T);
+    if ((e = hipMemcpy(hz.data(), Z, hz.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+      rc = hip_err(e, "copy normalisers");
+    for (size_t k = 0; rc == FGL_OK && k < hz.size(); ++k)
+      if (!(hz[k] > 0.0))
+        rc = set_err(FGL_EINVAL, "the weight of channel %zu, step %zu integrates to %g",
+                     k / T, k % T, hz[k]);
+  }
+  if (rc == FGL_OK) {
+    const size_t lds = (size_t)T * 12 + 8 + (size_t)d.nlon * 4;
+    if (lds > 160 * 1024) {
+      rc = set_err(FGL_EINVAL, "T=%d and nlon=%d do not fit one workgroup's LDS", T, d.nlon);
+    } else {
+      auto launch = [&](auto kern) {
+        hipError_t ee = set_lds(kern);
+        if (ee != hipSuccess) return ee;
+        hipLaunchKernelGGL(kern, dim3(d.nlat), dim3(256), lds, sk->stream, d, d_sh, T, Z, imp);
+        return hipGetLastError();
+      };
+      e = scheme == FGL_WEIGHT_BEAM ? launch(k_sky_importance<kCorrBeam>)
+          : scheme == FGL_WEIGHT_SKY ? launch(k_sky_importance<kCorrSky>)
+                                     : launch(k_sky_importance<kCorrHorizon>);
+      if (e == hipSuccess) e = hipStreamSynchronize(sk->stream);
+      if (e == hipSuccess)
+        e = hipMemcpy(importance, imp, (size_t)d.nlat * d.nlon * 8, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) rc = hip_err(e, "importance kernel");
+    }
+  }
+  if (d_sh) (void)hipFree(d_sh);
+  if (Z) (void)hipFree(Z);
+  if (imp) (void)hipFree(imp);
+  return rc;
+}
+
+int fgl_partition(const double* beta, const double* weight, int n, int n_regions, int method,
+                  double* edges) {
+  if (!beta || !weight || !edges) return set_err(FGL_EINVAL, "arrays must be non-NULL");
+  if (n < 1 || n_regions < 1) return set_err(FGL_EINVAL, "need n >= 1 and n_regions >= 1");
+  if (method != FGL_PARTITION_HIERARCHICAL && method != FGL_PARTITION_RECURSIVE)
+    return set_err(FGL_EINVAL, "unknown partition method %d", method);
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(beta[k]) || !std::isfinite(weight[k]) || weight[k] < 0.0)
+      return set_err(FGL_EINVAL, "beta[%d] must be finite and weight[%d] finite and >= 0", k, k);
+  return partition_host(beta, weight, n, n_regions, method, edges);
+}
+
+int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int32_t* shifts,
+                      int T, double* K) {
+  Sky* sk = reinterpret_cast<Sky*>(sh);
+  if (!sk || !edges || !K) return set_err(FGL_EINVAL, "sky, edges and K must be non-NULL");
+  if (n_regions < 1 || n_regions > 1024) return set_err(FGL_EINVAL, "n_regions=%d outside 1..1024", n_regions);
+  for (int j = 0; j <= n_regions; ++j)
+    if (!std::isfinite(edges[j]) || (j > 0 && edges[j] < edges[j - 1]))
+      return set_err(FGL_EINVAL, "edges must be finite and non-decreasing");
+  int rc = check_shifts(sk, shifts, T);
+  if (rc != FGL_OK) return rc;
+  hipError_t e = hipSetDevice(sk->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  const SkyDev& d = sk->d;
+  const int N = n_regions, nlon = d.nlon;
+  if (corr_lds(corr_block(T, N, nlon), N, nlon) > 160 * 1024)
+    return set_err(FGL_EINVAL, "n_regions=%d with nlon=%d does not fit one workgroup's LDS", N, nlon);
+  // masks: region j holds e_j <= beta < e_{j+1}, the last closed; then the
+  // columns of each ring grouped by region (ascending column within one)
+  std::vector<int> order((size_t)d.nlat * nlon), seg((size_t)d.nlat * (N + 1));
+  std::vector<int> reg(nlon), count(N + 1);
+  for (int r = 0; r < d.nlat; ++r) {
+    std::fill(count.begin(), count.end(), 0);
+    for (int c = 0; c < nlon; ++c) {
+      const double b = sk->h_beta[(size_t)r * nlon + c];
+      int j = (int)(std::upper_bound(edges, edges + N + 1, b) - edges) - 1;
+      if (b == edges[N]) j = N - 1;
+      if (b < edges[0] || b > edges[N]) j = -1;
+      reg[c] = j;
+      if (j >= 0) ++count[j + 1];
+    }
+    int* sg = &seg[(size_t)r * (N + 1)];
+    sg[0] = 0;
+    for (int j = 0; j < N; ++j) sg[j + 1] = sg[j] + count[j + 1];
+    std::vector<int> fill(sg, sg + N);
+    for (int c = 0; c < nlon; ++c)
+      if (reg[c] >= 0) order[(size_t)r * nlon + fill[reg[c]]++] = c;
+  }
+  int *d_sh = nullptr, *d_order = nullptr, *d_seg = nullptr;
+  double* d_K = nullptr;
+  if ((rc = to_device(&d_sh, shifts, (size_t)T, "uploading shifts")) == FGL_OK &&
+      (rc = to_device(&d_order, order.data(), order.size(), "uploading the region order")) == FGL_OK &&
+      (rc = to_device(&d_seg, seg.data(), seg.size(), "uploading region segments")) == FGL_OK) {
+    if ((e = hipMalloc(reinterpret_cast<void**>(&d_K), (size_t)N * d.F * T * 8)) != hipSuccess)
+      rc = hip_err(e, "allocating K");
+  }
+  float ms = 0.0f;
+  if (rc == FGL_OK) rc = run_corr<kCorrK>(sk, d_sh, T, d_order, d_seg, N, d_K, &ms);
+  if (rc == FGL_OK) {
+    sk->last_ms = ms;
+    if ((e = hipMemcpy(K, d_K, (size_t)N * d.F * T * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+      rc = hip_err(e, "copy K");
+  }
+  const void* ps[] = {d_sh, d_order, d_seg, d_K};
+  for (const void* p : ps)
+    if (p) (void)hipFree(const_cast<void*>(p));
+  return rc;
+}
+
+int fgl_sky_kernel_ms(const fgl_sky* sh, double* ms) {
+  const Sky* sk = reinterpret_cast<const Sky*>(sh);
+  if (!sk || !ms) return set_err(FGL_EINVAL, "sky and ms must be non-NULL");
+  *ms = sk->last_ms;
+  return FGL_OK;
+}
+
+int fgl_sky_destroy(fgl_sky* sh) {
+  Sky* sk = reinterpret_cast<Sky*>(sh);
+  if (!sk) return set_err(FGL_EINVAL, "sky is NULL");
+  (void)hipSetDevice(sk->dev);
+  if (sk->stream) (void)hipStreamSynchronize(sk->stream);
+  free_sky(sk);
+  return FGL_OK;
+}
+
+}  // extern "C"

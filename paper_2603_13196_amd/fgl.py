@@ -91,6 +91,16 @@ _SIGS = {
                         ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_int64),
                         ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "fgl_chains_destroy": ([_vp], ctypes.c_int),
+    "fgl_sky_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _fp,
+                        ctypes.POINTER(ctypes.c_uint8), _dp, ctypes.c_double, ctypes.c_double,
+                        ctypes.POINTER(_vp)], ctypes.c_int),
+    "fgl_sky_importance": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, ctypes.c_int, _dp],
+                           ctypes.c_int),
+    "fgl_partition": ([_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
+    "fgl_sky_chromatic": ([_vp, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                           _dp], ctypes.c_int),
+    "fgl_sky_kernel_ms": ([_vp, _dp], ctypes.c_int),
+    "fgl_sky_destroy": ([_vp], ctypes.c_int),
     "fgl_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -405,5 +415,89 @@ class Chains:
         try:
             if self.handle is not None:
                 _lib.fgl_chains_destroy(self.handle)
+        except Exception:
+            pass
+
+
+# --- region construction -------------------------------------------------------
+
+WEIGHTS = {"horizon": 0, "sky": 1, "beam": 2}
+PARTITIONS = {"hierarchical": 0, "recursive": 1}
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def fgl_partition(beta, weight, n_regions: int, method="recursive") -> np.ndarray:
+    """Edges [n_regions + 1] of Alg. method1 / method2 on the weighted CDF
+    (host computation in the library)."""
+    b, w = _f64(beta).ravel(), _f64(weight).ravel()
+    if b.size != w.size:
+        raise ValueError("beta and weight differ in size")
+    edges = np.empty(int(n_regions) + 1, dtype=np.float64)
+    m = PARTITIONS[method] if isinstance(method, str) else int(method)
+    _check(_lib.fgl_partition(b.ctypes.data_as(_dp), w.ctypes.data_as(_dp), b.size,
+                              int(n_regions), m, edges.ctypes.data_as(_dp)))
+    return edges
+
+
+class SkyModel:
+    """A resident sky for region construction: maps as in workload.sky.Sky
+    (omega [nlat], t_ex / beta [nlat, nlon], beam [F, nlat, nlon] FP32,
+    horizon [nlat, nlon], freqs [F])."""
+
+    def __init__(self, omega, t_ex, beta, beam, horizon, freqs, nu0=230.0, t_cmb=2.725):
+        self._keep = (_f64(omega), _f64(t_ex), _f64(beta),
+                      np.ascontiguousarray(beam, dtype=np.float32),
+                      np.ascontiguousarray(horizon, dtype=np.uint8), _f64(freqs))
+        om, tx, bt, bm, hz, fr = self._keep
+        self.nlat, self.nlon = tx.shape
+        self.F = fr.size
+        h = _vp()
+        _check(_lib.fgl_sky_create(self.nlat, self.nlon, self.F, om.ctypes.data_as(_dp),
+                                   tx.ctypes.data_as(_dp), bt.ctypes.data_as(_dp),
+                                   bm.ctypes.data_as(_fp),
+                                   hz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   fr.ctypes.data_as(_dp), float(nu0), float(t_cmb),
+                                   ctypes.byref(h)))
+        self.handle = h
+        self._keep = None
+
+    @classmethod
+    def from_sky(cls, s) -> "SkyModel":
+        return cls(s.omega, s.t_ex, s.beta, s.beam, s.horizon, s.freqs, s.nu0, s.t_cmb)
+
+    def importance(self, shifts, scheme="beam") -> np.ndarray:
+        sh = _i32(shifts)
+        out = np.empty((self.nlat, self.nlon), dtype=np.float64)
+        sc = WEIGHTS[scheme] if isinstance(scheme, str) else int(scheme)
+        _check(_lib.fgl_sky_importance(self.handle, sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       sh.size, sc, out.ctypes.data_as(_dp)))
+        return out
+
+    def chromatic(self, edges, shifts) -> np.ndarray:
+        e, sh = _f64(edges), _i32(shifts)
+        N = e.size - 1
+        K = np.empty((N, self.F, sh.size), dtype=np.float64)
+        _check(_lib.fgl_sky_chromatic(self.handle, e.ctypes.data_as(_dp), N,
+                                      sh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), sh.size,
+                                      K.ctypes.data_as(_dp)))
+        return K
+
+    def kernel_ms(self) -> float:
+        ms = ctypes.c_double()
+        _check(_lib.fgl_sky_kernel_ms(self.handle, ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if self.handle is not None:
+            _check(_lib.fgl_sky_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle is not None:
+                _lib.fgl_sky_destroy(self.handle)
         except Exception:
             pass
