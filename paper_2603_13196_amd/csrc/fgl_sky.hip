@@ -69,52 +69,86 @@ __device__ inline double aval(const SkyDev& s, int f, int ring, int ra) {
 }
 
 // partial[((chunk * NJ + j) * F + f) * T + t]: the sum over the chunk's
-// rings.  order[ring][k] lists the ring's columns by region, seg[ring][j]
-// the start of region j (seg[ring][NJ] = pixels in regions); without them
-// (Z) every pixel is region 0 in column order.
+// rings.  For K, order[ring][k] (k < L) lists the ring's columns by region,
+// asort the matching weights omega t_ex and seg[ring][j] the start of region
+// j; every region's run is padded to a multiple of eight with weight-zero
+// entries, so the inner loop has no tail.  For Z every pixel is region 0 in
+// column order, padded the same way.  Per ring the b row (twice in a
+// row, so that column ra at step t is entry ra + nlon - s_t with no wrap
+// test), the columns and the weights are staged in LDS; all lanes of a wave
+// take the same pixel (broadcast reads) at their own shift.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restrict__ shifts,
                                                   int T, int t0, const int* __restrict__ order,
-                                                  const int* __restrict__ seg, int NJ,
+                                                  const double* __restrict__ asort,
+                                                  const int* __restrict__ seg, int NJ, int L,
                                                   double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, chunk = blockIdx.y;
   const int nlon = s.nlon;
-  double* s_acc = reinterpret_cast<double*>(smem);             // [blockDim][NJ]
-  double* s_a = s_acc + (size_t)blockDim.x * NJ;               // [nlon]
-  float* s_b = reinterpret_cast<float*>(s_a + nlon);            // [nlon]
-  int* s_idx = reinterpret_cast<int*>(s_b + nlon);             // [nlon]
-  int* s_seg = s_idx + nlon;                                   // [NJ + 1]
+  double* s_acc = reinterpret_cast<double*>(smem);             // [NJ][blockDim]
+  double* s_a = s_acc + (size_t)blockDim.x * NJ;               // [L]
+  float* s_b = reinterpret_cast<float*>(s_a + L);              // [2 nlon]
+  int* s_idx = reinterpret_cast<int*>(s_b + 2 * nlon);         // [L]
+  int* s_seg = s_idx + L;                                      // [NJ + 1]
   const int tl = threadIdx.x, t = t0 + tl;
   const bool live = t < T;
-  const int sh = live ? shifts[t] : 0;
-  for (int j = 0; j < NJ; ++j) s_acc[(size_t)tl * NJ + j] = 0.0;
+  const int o = nlon - (live ? shifts[t] : 0);                 // in [1, nlon]
+  for (int j = 0; j < NJ; ++j) s_acc[(size_t)j * blockDim.x + tl] = 0.0;
   const int r0 = chunk * kRingChunk, r1 = min(s.nlat, r0 + kRingChunk);
   for (int ring = r0; ring < r1; ++ring) {
     __syncthreads();
     for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
-      const int ra = order ? order[(size_t)ring * nlon + k] : k;
-      s_idx[k] = ra;
-      s_a[k] = aval<MODE>(s, f, ring, ra);
-      s_b[k] = (float)bval<MODE>(s, f, ring, k);   // b values are FP32 or 0/1
+      const float b = (float)bval<MODE>(s, f, ring, k);   // FP32 beam values or 0/1
+      s_b[k] = b;
+      s_b[k + nlon] = b;
+    }
+    for (int k = threadIdx.x; k < L; k += blockDim.x) {
+      if constexpr (MODE == kCorrK) {
+        s_idx[k] = order[(size_t)ring * L + k];
+        s_a[k] = asort[(size_t)ring * L + k];
+      } else {
+        s_idx[k] = k < nlon ? k : 0;
+        s_a[k] = k < nlon ? aval<MODE>(s, f, ring, k) : 0.0;
+      }
     }
     for (int j = threadIdx.x; j <= NJ; j += blockDim.x)
-      s_seg[j] = seg ? seg[(size_t)ring * (NJ + 1) + j] : (j == 0 ? 0 : nlon);
+      s_seg[j] = MODE == kCorrK ? seg[(size_t)ring * (NJ + 1) + j] : (j == 0 ? 0 : L);
     __syncthreads();
     if (!live) continue;
+    const float* bo = s_b + o;
     for (int j = 0; j < NJ; ++j) {
-      double acc = 0.0;
-      for (int k = s_seg[j]; k < s_seg[j + 1]; ++k) {
-        int ha = s_idx[k] - sh;
-        ha += ha < 0 ? nlon : 0;
-        acc = fma(s_a[k], (double)s_b[ha], acc);
+      const int k1 = s_seg[j + 1];
+      int k = s_seg[j];
+      if (k == k1) continue;
+      double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      // software pipelined: the next group's columns and weights are read
+      // while the current group's beam values are gathered
+      int id[8];
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        id[u] = s_idx[k + u];
+        av[u] = s_a[k + u];
       }
-      s_acc[(size_t)tl * NJ + j] += acc;
+      for (; k < k1; k += 8) {
+        float bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = bo[id[u]];
+        const int kn = k + 8 < k1 ? k + 8 : k;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          c[u] = fma(av[u], (double)bv[u], c[u]);
+          id[u] = s_idx[kn + u];
+          av[u] = s_a[kn + u];
+        }
+      }
+      s_acc[(size_t)j * blockDim.x + tl] += ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
     }
   }
   if (!live) return;
   for (int j = 0; j < NJ; ++j)
-    partial[(((size_t)chunk * NJ + j) * s.F + f) * T + t] = s_acc[(size_t)tl * NJ + j];
+    partial[(((size_t)chunk * NJ + j) * s.F + f) * T + t] = s_acc[(size_t)j * blockDim.x + tl];
 }
 
 // out[i] = sum over chunks (in order) of partial[chunk * n + i]
@@ -128,50 +162,62 @@ __global__ __launch_bounds__(256) void k_sky_reduce(const double* __restrict__ p
   out[i] = acc;
 }
 
-// I(ring, ra) = sum_nu a(q, nu) sum_t b(nu, ring, ra - s_t) / Z(nu, t); one
-// thread per column of one ring
+// I(ring, ra) = sum_nu a(q, nu) sum_t b(nu, ring, ra - s_t) / Z(nu, t): one
+// workgroup per (ring, channel chunk), one thread per column, the chunk's
+// partial sum written to imp[(chunk * nlat + ring) * nlon + ra].  The b row
+// is staged twice in a row, so column ra at step t is entry ra + nlon - s_t.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sky_importance(SkyDev s, const int* __restrict__ shifts,
                                                         int T, const double* __restrict__ Z,
-                                                        double* __restrict__ imp) {
+                                                        int fper, double* __restrict__ imp) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ring = blockIdx.x;
+  const int ring = blockIdx.x, chunk = blockIdx.y;
   const int nlon = s.nlon;
   double* s_iz = reinterpret_cast<double*>(smem);   // [T]
-  int* s_sh = reinterpret_cast<int*>(s_iz + T);      // [T]
-  float* s_b = reinterpret_cast<float*>(s_sh + T + (T & 1));   // [nlon]
-  for (int t = threadIdx.x; t < T; t += blockDim.x) s_sh[t] = shifts[t];
+  int* s_o = reinterpret_cast<int*>(s_iz + T);       // [T] nlon - s_t
+  float* s_b = reinterpret_cast<float*>(s_o + T + (T & 1));   // [2 nlon]
+  for (int t = threadIdx.x; t < T; t += blockDim.x) s_o[t] = nlon - shifts[t];
+  const int f0 = chunk * fper, f1 = min(s.F, f0 + fper);
   for (int ra0 = 0; ra0 < nlon; ra0 += blockDim.x) {
     const int ra = ra0 + threadIdx.x;
     double total = 0.0;
-    for (int f = 0; f < s.F; ++f) {
+    for (int f = f0; f < f1; ++f) {
       __syncthreads();
       for (int t = threadIdx.x; t < T; t += blockDim.x) s_iz[t] = 1.0 / Z[(size_t)f * T + t];
-      for (int k = threadIdx.x; k < nlon; k += blockDim.x) s_b[k] = (float)bval<MODE>(s, f, ring, k);
+      for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
+        const float b = (float)bval<MODE>(s, f, ring, k);
+        s_b[k] = b;
+        s_b[k + nlon] = b;
+      }
       __syncthreads();
       if (ra < nlon) {
-        double acc = 0.0;
-        for (int t = 0; t < T; ++t) {
-          int ha = ra - s_sh[t];
-          ha += ha < 0 ? nlon : 0;
-          acc = fma((double)s_b[ha], s_iz[t], acc);
+        double c0 = 0.0, c1 = 0.0;
+        int t = 0;
+        for (; t + 2 <= T; t += 2) {
+          c0 = fma((double)s_b[ra + s_o[t]], s_iz[t], c0);
+          c1 = fma((double)s_b[ra + s_o[t + 1]], s_iz[t + 1], c1);
         }
-        total = fma(aval<MODE>(s, f, ring, ra), acc, total);
+        if (t < T) c0 = fma((double)s_b[ra + s_o[t]], s_iz[t], c0);
+        total = fma(aval<MODE>(s, f, ring, ra), c0 + c1, total);
       }
     }
-    if (ra < nlon) imp[(size_t)ring * nlon + ra] = total;
+    if (ra < nlon) imp[((size_t)chunk * s.nlat + ring) * nlon + ra] = total;
   }
 }
 
-int corr_block(int T, int NJ, int nlon) {
+// padded pixel-list length: every region's run rounded up to eight
+size_t corr_lds(int tb, int NJ, int nlon, int L) {
+  return (size_t)tb * NJ * 8 + (size_t)L * 12 + (size_t)nlon * 8 + (size_t)(NJ + 1) * 4;
+}
+
+int corr_block(int T, int NJ, int nlon, int L) {
   int tb = std::min(256, (T + 63) / 64 * 64);
-  while (tb > 64 && (size_t)tb * NJ * 8 + (size_t)nlon * 16 + (NJ + 1) * 4 > 96 * 1024) tb -= 64;
+  while (tb > 64 && corr_lds(tb, NJ, nlon, L) > 96 * 1024) tb -= 64;
   return tb;
 }
 
-size_t corr_lds(int tb, int NJ, int nlon) {
-  return (size_t)tb * NJ * 8 + (size_t)nlon * 16 + (size_t)(NJ + 1) * 4;
-}
+int pad8(int n) { return (n + 7) / 8 * 8; }
+
 
 struct Sky {
   int dev = 0;
@@ -179,6 +225,7 @@ struct Sky {
   double nu0 = 0.0;
   hipStream_t stream = nullptr;
   std::vector<double> h_beta;      // for the masks of a partition
+  std::vector<double> h_omega, h_tex;   // for the region-sorted pixel weights
   double last_ms = 0.0;            // last k_sky_corr duration (chromatic)
 };
 
@@ -190,16 +237,16 @@ hipError_t set_lds(KernelT k) {
 
 // Z or K partial sums and their chunk reduction into out (device).
 template <int MODE>
-int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const int* d_seg, int NJ,
-             double* d_out, float* ms) {
+int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const double* d_asort,
+             const int* d_seg, int NJ, int L, double* d_out, float* ms) {
   const SkyDev& d = sk->d;
   const int chunks = (d.nlat + kRingChunk - 1) / kRingChunk;
   const size_t n = (size_t)NJ * d.F * T;
   double* part = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&part), n * chunks * 8);
   if (e != hipSuccess) return hip_err(e, "allocating partial sums");
-  const int tb = corr_block(T, NJ, d.nlon);
-  const size_t lds = corr_lds(tb, NJ, d.nlon);
+  const int tb = corr_block(T, NJ, d.nlon, L);
+  const size_t lds = corr_lds(tb, NJ, d.nlon, L);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
     (void)hipEventCreate(&e0);
@@ -209,7 +256,7 @@ int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const int*
   if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {
     for (int t0 = 0; t0 < T && e == hipSuccess; t0 += tb) {
       hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks), dim3(tb), lds, sk->stream, d,
-                         d_shifts, T, t0, d_order, d_seg, NJ, part);
+                         d_shifts, T, t0, d_order, d_asort, d_seg, NJ, L, part);
       e = hipGetLastError();
     }
   }
@@ -366,6 +413,8 @@ int fgl_sky_create(int nlat, int nlon, int F, const double* omega, const double*
   sk->d.F = F;
   sk->d.t_cmb = t_cmb;
   sk->h_beta.assign(beta, beta + np);
+  sk->h_omega.assign(omega, omega + nlat);
+  sk->h_tex.assign(t_ex, t_ex + np);
   double *om = nullptr, *tx = nullptr, *bt = nullptr, *l2 = nullptr;
   float* bm = nullptr;
   uint8_t* hz = nullptr;
@@ -402,7 +451,8 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
     return set_err(FGL_EINVAL, "unknown weighting scheme %d", scheme);
   int rc = check_shifts(sk, shifts, T);
   if (rc != FGL_OK) return rc;
-  if (corr_lds(corr_block(T, 1, sk->d.nlon), 1, sk->d.nlon) > 160 * 1024)
+  const int Lz = pad8(sk->d.nlon);
+  if (corr_lds(corr_block(T, 1, sk->d.nlon, Lz), 1, sk->d.nlon, Lz) > 160 * 1024)
     return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", sk->d.nlon);
   hipError_t e = hipSetDevice(sk->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
@@ -415,9 +465,9 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
     rc = hip_err(e, "allocating importance buffers");
   }
   if (rc == FGL_OK) {
-    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, nullptr, nullptr, 1, Z, nullptr)
-         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, nullptr, nullptr, 1, Z, nullptr)
-                                    : run_corr<kCorrHorizon>(sk, d_sh, T, nullptr, nullptr, 1, Z, nullptr);
+    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, Z, nullptr)
+         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, Z, nullptr)
+                                    : run_corr<kCorrHorizon>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, Z, nullptr);
   }
   if (rc == FGL_OK) {
     std::vector<double> hz((size_t)d.F * T);
@@ -429,24 +479,38 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
                      k / T, k % T, hz[k]);
   }
   if (rc == FGL_OK) {
-    const size_t lds = (size_t)T * 12 + 8 + (size_t)d.nlon * 4;
+    const size_t lds = (size_t)T * 12 + 8 + (size_t)d.nlon * 8;
+    // channel chunks: enough workgroups to fill the device, summed in order
+    const int fchunks = std::max(1, std::min(d.F, (2048 + d.nlat - 1) / d.nlat));
+    const int fper = (d.F + fchunks - 1) / fchunks;
+    const int nch = (d.F + fper - 1) / fper;
+    const size_t np = (size_t)d.nlat * d.nlon;
+    double* part = nullptr;
     if (lds > 160 * 1024) {
       rc = set_err(FGL_EINVAL, "T=%d and nlon=%d do not fit one workgroup's LDS", T, d.nlon);
+    } else if ((e = hipMalloc(reinterpret_cast<void**>(&part), np * nch * 8)) != hipSuccess) {
+      rc = hip_err(e, "allocating importance partials");
     } else {
       auto launch = [&](auto kern) {
         hipError_t ee = set_lds(kern);
         if (ee != hipSuccess) return ee;
-        hipLaunchKernelGGL(kern, dim3(d.nlat), dim3(256), lds, sk->stream, d, d_sh, T, Z, imp);
+        hipLaunchKernelGGL(kern, dim3(d.nlat, nch), dim3(256), lds, sk->stream, d, d_sh, T, Z,
+                           fper, part);
         return hipGetLastError();
       };
       e = scheme == FGL_WEIGHT_BEAM ? launch(k_sky_importance<kCorrBeam>)
           : scheme == FGL_WEIGHT_SKY ? launch(k_sky_importance<kCorrSky>)
                                      : launch(k_sky_importance<kCorrHorizon>);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_sky_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0,
+                           sk->stream, part, nch, np, imp);
+        e = hipGetLastError();
+      }
       if (e == hipSuccess) e = hipStreamSynchronize(sk->stream);
-      if (e == hipSuccess)
-        e = hipMemcpy(importance, imp, (size_t)d.nlat * d.nlon * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(importance, imp, np * 8, hipMemcpyDeviceToHost);
       if (e != hipSuccess) rc = hip_err(e, "importance kernel");
     }
+    if (part) (void)hipFree(part);
   }
   if (d_sh) (void)hipFree(d_sh);
   if (Z) (void)hipFree(Z);
@@ -480,45 +544,58 @@ int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   const SkyDev& d = sk->d;
   const int N = n_regions, nlon = d.nlon;
-  if (corr_lds(corr_block(T, N, nlon), N, nlon) > 160 * 1024)
-    return set_err(FGL_EINVAL, "n_regions=%d with nlon=%d does not fit one workgroup's LDS", N, nlon);
   // masks: region j holds e_j <= beta < e_{j+1}, the last closed; then the
-  // columns of each ring grouped by region (ascending column within one)
-  std::vector<int> order((size_t)d.nlat * nlon), seg((size_t)d.nlat * (N + 1));
-  std::vector<int> reg(nlon), count(N + 1);
+  // columns of each ring grouped by region (ascending column within one),
+  // every region's run padded to a multiple of eight with weight-zero entries
+  std::vector<int> regs((size_t)d.nlat * nlon), counts((size_t)d.nlat * N, 0);
+  int L = 8;
   for (int r = 0; r < d.nlat; ++r) {
-    std::fill(count.begin(), count.end(), 0);
+    int len = 0;
     for (int c = 0; c < nlon; ++c) {
       const double b = sk->h_beta[(size_t)r * nlon + c];
       int j = (int)(std::upper_bound(edges, edges + N + 1, b) - edges) - 1;
       if (b == edges[N]) j = N - 1;
       if (b < edges[0] || b > edges[N]) j = -1;
-      reg[c] = j;
-      if (j >= 0) ++count[j + 1];
+      regs[(size_t)r * nlon + c] = j;
+      if (j >= 0) ++counts[(size_t)r * N + j];
     }
+    for (int j = 0; j < N; ++j) len += pad8(counts[(size_t)r * N + j]);
+    L = std::max(L, len);
+  }
+  if (corr_lds(corr_block(T, N, nlon, L), N, nlon, L) > 160 * 1024)
+    return set_err(FGL_EINVAL, "n_regions=%d with nlon=%d does not fit one workgroup's LDS", N, nlon);
+  std::vector<int> order((size_t)d.nlat * L, 0), seg((size_t)d.nlat * (N + 1));
+  std::vector<double> asort((size_t)d.nlat * L, 0.0);
+  for (int r = 0; r < d.nlat; ++r) {
     int* sg = &seg[(size_t)r * (N + 1)];
     sg[0] = 0;
-    for (int j = 0; j < N; ++j) sg[j + 1] = sg[j] + count[j + 1];
+    for (int j = 0; j < N; ++j) sg[j + 1] = sg[j] + pad8(counts[(size_t)r * N + j]);
     std::vector<int> fill(sg, sg + N);
-    for (int c = 0; c < nlon; ++c)
-      if (reg[c] >= 0) order[(size_t)r * nlon + fill[reg[c]]++] = c;
+    for (int c = 0; c < nlon; ++c) {
+      const int j = regs[(size_t)r * nlon + c];
+      if (j < 0) continue;
+      const size_t at = (size_t)r * L + fill[j]++;
+      order[at] = c;
+      asort[at] = sk->h_omega[r] * sk->h_tex[(size_t)r * nlon + c];
+    }
   }
   int *d_sh = nullptr, *d_order = nullptr, *d_seg = nullptr;
-  double* d_K = nullptr;
+  double *d_K = nullptr, *d_as = nullptr;
   if ((rc = to_device(&d_sh, shifts, (size_t)T, "uploading shifts")) == FGL_OK &&
       (rc = to_device(&d_order, order.data(), order.size(), "uploading the region order")) == FGL_OK &&
+      (rc = to_device(&d_as, asort.data(), asort.size(), "uploading pixel weights")) == FGL_OK &&
       (rc = to_device(&d_seg, seg.data(), seg.size(), "uploading region segments")) == FGL_OK) {
     if ((e = hipMalloc(reinterpret_cast<void**>(&d_K), (size_t)N * d.F * T * 8)) != hipSuccess)
       rc = hip_err(e, "allocating K");
   }
   float ms = 0.0f;
-  if (rc == FGL_OK) rc = run_corr<kCorrK>(sk, d_sh, T, d_order, d_seg, N, d_K, &ms);
+  if (rc == FGL_OK) rc = run_corr<kCorrK>(sk, d_sh, T, d_order, d_as, d_seg, N, L, d_K, &ms);
   if (rc == FGL_OK) {
     sk->last_ms = ms;
     if ((e = hipMemcpy(K, d_K, (size_t)N * d.F * T * 8, hipMemcpyDeviceToHost)) != hipSuccess)
       rc = hip_err(e, "copy K");
   }
-  const void* ps[] = {d_sh, d_order, d_seg, d_K};
+  const void* ps[] = {d_sh, d_order, d_seg, d_K, d_as};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
   return rc;
