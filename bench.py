@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-sampler", action="store_true",
                    help="skip the nested-sampling run (10 regions, T = 1, benchmark settings)")
+    p.add_argument("--no-regions", action="store_true",
+                   help="skip the region-construction leg (importance, partition, K)")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the FP64 gradient leg")
     p.add_argument("--no-masks", action="store_true",
@@ -230,6 +232,37 @@ def grad_leg(fgl, w, steps, warmup):
             "kernel_ms": kms / max(n, 1), "kernel": "k_grad64", "precision": "fp64"}
 
 
+def regions_leg(fgl, n_regions=32):
+    """Region construction upstream of the likelihood (Sec. 4, Eq.
+    chromatic_function) on the synthetic 256 x 512 sky, 301 channels, 96
+    LST steps: beam-weighted importance map, recursive partition into
+    n_regions regions, and the chromatic functions K [N][F][T]."""
+    from workload.sky import sky_config, SKY_NAME
+    s = sky_config()
+    sm = fgl.SkyModel.from_sky(s)
+    sm.importance(s.shifts, "beam")                       # warm-up
+    t0 = time.perf_counter()
+    imp = sm.importance(s.shifts, "beam")
+    t1 = time.perf_counter()
+    edges = fgl.fgl_partition(s.beta, imp, n_regions, "recursive")
+    t2 = time.perf_counter()
+    sm.chromatic(edges, s.shifts)                         # warm-up
+    t3 = time.perf_counter()
+    sm.chromatic(edges, s.shifts)
+    t4 = time.perf_counter()
+    kms = sm.kernel_ms()
+    sm.close()
+    npix = s.nlat * s.nlon
+    flops = 2.0 * s.F * s.T * npix                        # one FMA per (pixel, channel, step)
+    achieved = flops / (kms * 1e-3) / 1e12
+    return {"workload": SKY_NAME, "pixels": npix, "regions": n_regions,
+            "importance_s": t1 - t0, "partition_s": t2 - t1, "chromatic_s": t4 - t3,
+            "chromatic_kernel_ms": kms,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                         "kernel": "k_sky_corr"}}
+
+
 def cpu_leg(w, gpu_out, seconds):
     import oracle
     orc = oracle.load()
@@ -338,6 +371,9 @@ def main():
     if not a.no_masks and not a.no_plain:
         log("crossed-mask leg")
         line["masks"] = masks_leg(fgl, a.steps, a.warmup, not a.no_tune)
+    if not a.no_regions and not a.no_plain:
+        log("region construction leg")
+        line["region_construction"] = regions_leg(fgl)
     if not a.no_serve:
         log("serving leg")
         line["serving"] = serving_leg(fgl, a.serve_seconds)
