@@ -278,10 +278,17 @@ def cpu_leg(w, gpu_out, seconds):
         ref = orc.loglike_w(w, w.theta[:n2])
         dt = time.perf_counter() - t0
         n = n2
+    # when the whole batch takes less than `seconds`, time repeated passes
+    passes = max(1, int(round(seconds / max(dt, 1e-6)))) if n == w.B else 1
+    if passes > 1:
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            orc.loglike_w(w, w.theta[:n])
+        dt = time.perf_counter() - t0
     d = np.abs(gpu_out[:n] - ref)
     tol = 1e-6 * np.abs(ref) + 1e-3
-    return ({"value": n / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-             "sample": f"first {n} of the {w.B} rows, all host threads",
+    return ({"value": n * passes / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+             "sample": f"first {n} of the {w.B} rows x {passes} passes, all host threads",
              "seconds": dt},
             {"rows": n, "max_abs_dlogL": float(d.max()),
              "max_dlogL_over_tol": float((d / tol).max()),
