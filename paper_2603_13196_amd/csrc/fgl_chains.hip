@@ -2,19 +2,25 @@
 //
 // One call advances n hit-and-run slice chains, each by `steps` steps under
 // the constraint lnL > lnL* inside the prior box (the replacement step of
-// nested slice sampling, Tutt et al. Sec. 3.1.2 and 3.1.3).  Every round
-// proposes one point per chain (k_chain_propose), evaluates all n rows with
-// the model's likelihood kernels, and advances each chain's state machine
-// (k_chain_update):
-//   stepping out:  the interval ends move out by one unit (in the geometry
-//                  whitened by the caller's Cholesky factor) while they are
-//                  inside the constrained region;
-//   shrinking:     a uniform point of the interval is accepted if inside,
-//                  otherwise the interval is cut at it.
-// A chain that has finished its steps keeps its point and proposes nothing
-// new.  Rounds are captured once into a hipGraph (R rounds per graph) and
-// replayed; the host reads the chains' stages after each replay and stops
-// when every chain is done.
+// nested slice sampling, Tutt et al. Sec. 3.1.2 and 3.1.3).  A round is the
+// model's row preparation and likelihood kernel over the n proposal rows,
+// then k_chain_step, one wavefront per chain, which
+//   * forms each row's lnL from the likelihood kernel's partial sums, in the
+//     order and arithmetic of the library's finalize (so it equals what
+//     fgl_loglike_batch returns for that row, bit for bit),
+//   * advances the chain's state machine:
+//       stepping out:  the interval ends move out by one unit (in the
+//                      geometry whitened by the caller's Cholesky factor)
+//                      while they are inside the constrained region;
+//       shrinking:     a uniform point of the interval is accepted if
+//                      inside, otherwise the interval is cut at it,
+//   * and writes the chain's next proposal row.
+// The lanes of a chain's wavefront share its coordinates (directions,
+// Cholesky product, proposal) and its lnL reduction.  A chain that has
+// finished its steps keeps its point and proposes nothing new.  Rounds are
+// captured once into a hipGraph (R rounds per graph) and replayed; the host
+// reads the chains' stages after each replay and stops when every chain is
+// done.
 //
 // Coordinates: the sampler works in z = [beta.., A, nu21, w, log sigma] (or
 // [beta.., log sigma] without the 21-cm term), uniform over the box; the
@@ -88,9 +94,10 @@ __device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-// Two uniforms in [0, 1) with 53 random bits each, from one Philox block.
-__device__ inline void uniform2(const ChainState& s, int i, double& u0, double& u1) {
-  const unsigned long long c = s.ctr[i]++;
+// Two uniforms in [0, 1) with 53 random bits each, from Philox block c of
+// chain i.
+__device__ inline void uniform2(const ChainState& s, int i, unsigned long long c, double& u0,
+                                double& u1) {
   uint32_t v[4] = {(uint32_t)c, (uint32_t)(c >> 32), (uint32_t)i, 0x5eed5eedu};
   philox(v, (uint32_t)s.seed, (uint32_t)(s.seed >> 32));
   const uint64_t a = ((uint64_t)v[0] << 32 | v[1]) >> 11;
@@ -99,149 +106,218 @@ __device__ inline void uniform2(const ChainState& s, int i, double& u0, double& 
   u1 = (double)b * 0x1.0p-53;
 }
 
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+constexpr int kMaxP = 160;            // parameters a chain's LDS direction holds
+constexpr int kWaves = 4;             // chains (wavefronts) per workgroup
+
+// Per-chain scalars, held in registers (uniform across the wavefront) while a
+// kernel works on the chain and written back by lane 0.
+struct Scal {
+  double a, b, t, lx;
+  int stage, done, expand, evals;
+  unsigned long long ctr;
+};
+
+__device__ inline Scal load_scal(const ChainState& s, int i) {
+  return Scal{s.a[i], s.b[i], s.t[i], s.lx[i], s.stage[i], s.done[i], s.expand[i], s.evals[i],
+              s.ctr[i]};
+}
+
+__device__ inline void store_scal(const ChainState& s, int i, const Scal& c, int lane) {
+  if (lane != 0) return;
+  s.a[i] = c.a;
+  s.b[i] = c.b;
+  s.t[i] = c.t;
+  s.lx[i] = c.lx;
+  s.stage[i] = c.stage;
+  s.done[i] = c.done;
+  s.expand[i] = c.expand;
+  s.evals[i] = c.evals;
+  s.ctr[i] = c.ctr;
+}
+
 // A new slice step: direction uniform on the unit sphere in whitened
 // coordinates, mapped by the Cholesky factor; unit interval at a random
-// offset around the current point.
-__device__ void new_step(const ChainState& s, int i) {
-  const int P = s.P;
-  double* d = s.dir + (size_t)i * P;
+// offset around the current point.  Lane k/2 draws the normal pair of
+// coordinates k, k + 1 (Philox block ctr + k/2); the pairs go through LDS
+// so that lane j can form row j of the Cholesky product.
+__device__ void new_step(const ChainState& s, int i, Scal& c, int lane, double* u) {
+  const int P = s.P, np = (P + 1) / 2;
   double nrm = 0.0;
   // the direction needs randomness, not precision: the Box-Muller pairs are
   // formed with the FP32 hardware transcendentals
-  for (int k = 0; k < P; k += 2) {
+  for (int pr = lane; pr < np; pr += 64) {
     double u0, u1;
-    uniform2(s, i, u0, u1);
+    uniform2(s, i, c.ctr + pr, u0, u1);
     const float v = (float)(1.0 - u0);                  // in (0, 1]
     const float rad = __builtin_sqrtf(-2.0f * __logf(v));
     const float ang = 6.2831853f * (float)u1;
     const double z0 = (double)(rad * __cosf(ang)), z1 = (double)(rad * __sinf(ang));
-    d[k] = z0;
+    u[2 * pr] = z0;
     nrm += z0 * z0;
-    if (k + 1 < P) {
-      d[k + 1] = z1;
+    if (2 * pr + 1 < P) {
+      u[2 * pr + 1] = z1;
       nrm += z1 * z1;
     }
   }
+  nrm = wave_sum(nrm);
+  __builtin_amdgcn_wave_barrier();                      // u written by all lanes
   const double inv = 1.0 / sqrt(nrm);
-  // dir = L u, L lower triangular; walk rows from the bottom so each u_k is
-  // read before it is overwritten
-  for (int j = P - 1; j >= 0; --j) {
+  double* d = s.dir + (size_t)i * P;
+  for (int j = lane; j < P; j += 64) {                  // dir = L u, L lower triangular
     double acc = 0.0;
-    for (int k = 0; k <= j; ++k) acc += s.chol[(size_t)j * P + k] * d[k];
+    for (int k = 0; k <= j; ++k) acc += s.chol[(size_t)j * P + k] * u[k];
     d[j] = acc * inv;
   }
+  __builtin_amdgcn_wave_barrier();                      // u read by all lanes
   double r, unused;
-  uniform2(s, i, r, unused);
-  s.a[i] = -r;
-  s.b[i] = 1.0 - r;
-  s.stage[i] = kLeft;
-  s.expand[i] = 0;
+  uniform2(s, i, c.ctr + np, r, unused);
+  c.ctr += np + 1;
+  c.a = -r;
+  c.b = 1.0 - r;
+  c.stage = kLeft;
+  c.expand = 0;
 }
 
-__global__ void k_chain_init(ChainState s, const double* x0, const double* l0) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s.n) return;
-  for (int k = 0; k < s.P; ++k) s.x[(size_t)i * s.P + k] = x0[(size_t)i * s.P + k];
-  s.lx[i] = l0[i];
-  s.done[i] = 0;
-  s.evals[i] = 0;
-  s.t[i] = 0.0;                   // ctr keeps counting across calls: fresh numbers every call
-  if (s.steps > 0)
-    new_step(s, i);
-  else
-    s.stage[i] = kDone;
-}
-
-// The likelihood row of a point: z with log sigma exponentiated.
-__device__ inline void write_row(const ChainState& s, int i, const double* z) {
-  double* th = s.theta + (size_t)i * s.P;
-  for (int k = 0; k < s.P - 1; ++k) th[k] = z[k];
-  th[s.P - 1] = exp(z[s.P - 1]);
-}
-
-__global__ void k_chain_propose(ChainState s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s.n) return;
+// The chain's next likelihood row: the proposal x + t dir when it is inside
+// the box, else (and for a finished chain) the chain's point itself, whose
+// result is ignored.  The last coordinate is log sigma.
+__device__ void propose(const ChainState& s, int i, Scal& c, int lane) {
   const int P = s.P;
   const double* x = s.x + (size_t)i * P;
-  const int st = s.stage[i];
-  if (st == kDone) {
-    write_row(s, i, x);
-    s.inbox[i] = 0;
+  double* th = s.theta + (size_t)i * P;
+  if (c.stage == kDone) {
+    for (int k = lane; k < P; k += 64) th[k] = k == P - 1 ? exp(x[k]) : x[k];
+    if (lane == 0) s.inbox[i] = 0;
     return;
   }
   double t;
-  if (st == kShrink) {
+  if (c.stage == kShrink) {
     double u, unused;
-    uniform2(s, i, u, unused);
-    t = s.a[i] + (s.b[i] - s.a[i]) * u;
+    uniform2(s, i, c.ctr, u, unused);
+    c.ctr += 1;
+    t = c.a + (c.b - c.a) * u;
   } else {
-    t = st == kLeft ? s.a[i] : s.b[i];
+    t = c.stage == kLeft ? c.a : c.b;
   }
-  s.t[i] = t;
+  c.t = t;
   const double* d = s.dir + (size_t)i * P;
-  double* th = s.theta + (size_t)i * P;
-  int in = 1;
-  for (int k = 0; k < P; ++k) {
+  int out = 0;
+  for (int k = lane; k < P; k += 64) {
     const double p = x[k] + t * d[k];
-    in &= (p >= s.lo[k]) & (p <= s.hi[k]);
-    th[k] = p;
+    out |= !((p >= s.lo[k]) & (p <= s.hi[k]));
   }
-  if (in)
-    th[P - 1] = exp(th[P - 1]);
-  else
-    write_row(s, i, x);        // a valid row; its result is ignored
-  s.inbox[i] = in;
+  const bool in = __builtin_amdgcn_ballot_w64(out != 0) == 0;
+  for (int k = lane; k < P; k += 64) {
+    const double v = in ? x[k] + t * d[k] : x[k];
+    th[k] = k == P - 1 ? exp(v) : v;
+  }
+  if (lane == 0) s.inbox[i] = in ? 1 : 0;
 }
 
-__device__ inline void finish_step(const ChainState& s, int i) {
-  s.done[i] += 1;
-  if (s.done[i] >= s.steps)
-    s.stage[i] = kDone;
+__device__ inline void finish_step(const ChainState& s, int i, Scal& c, int lane, double* u) {
+  c.done += 1;
+  if (c.done >= s.steps)
+    c.stage = kDone;
   else
-    new_step(s, i);
+    new_step(s, i, c, lane, u);
 }
 
-__global__ void k_chain_update(ChainState s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// The likelihood kernel's partial sums of row b, reduced as the library's
+// finalize does (sixteen strided sums, then an xor tree).
+struct RowSums {
+  const double* partial;
+  const RowParams* rows;
+  int ngroup, Bpad;
+  double nFT, chi0;
+};
+
+__device__ inline double row_lnl(const RowSums& r, int b, int lane) {
+  double acc = 0.0;
+  if (lane < 16)
+    for (int c = lane; c < r.ngroup; c += 16) acc += r.partial[(size_t)c * r.Bpad + b];
+  acc += __shfl_xor(acc, 8);
+  acc += __shfl_xor(acc, 4);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 1);
+  acc = __shfl(acc, 0);
+  const RowParams rp = r.rows[b];
+  if (!rp.valid) return -INFINITY;
+  const double s2 = rp.sigma * rp.sigma;
+  return -0.5 * (acc + r.chi0) / s2 - 0.5 * r.nFT * log(2.0 * M_PI * s2);
+}
+
+// Start: copy the starting points, draw every chain's first step and write
+// its first proposal.
+__global__ __launch_bounds__(64 * kWaves) void k_chain_start(ChainState s, const double* x0,
+                                                             const double* l0) {
+  __shared__ double s_u[kWaves][kMaxP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * kWaves + wv;
+  if (i >= s.n) return;
+  const int P = s.P;
+  for (int k = lane; k < P; k += 64) s.x[(size_t)i * P + k] = x0[(size_t)i * P + k];
+  Scal c = load_scal(s, i);             // ctr keeps counting across calls: fresh numbers
+  c.lx = l0[i];
+  c.done = 0;
+  c.evals = 0;
+  c.t = 0.0;
+  if (s.steps > 0)
+    new_step(s, i, c, lane, s_u[wv]);
+  else
+    c.stage = kDone;
+  propose(s, i, c, lane);
+  store_scal(s, i, c, lane);
+}
+
+// One round's update from the likelihood of the last proposals, then the
+// next proposal.
+__global__ __launch_bounds__(64 * kWaves) void k_chain_step(ChainState s, RowSums rs) {
+  __shared__ double s_u[kWaves][kMaxP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * kWaves + wv;
   if (i >= s.n) return;
   const double lstar = *s.lstar;
-  const int st = s.stage[i];
-  if (st == kDone) return;
-  const double lp = s.lnl[i];
+  Scal c = load_scal(s, i);
+  if (c.stage == kDone) return;
+  const double lp = row_lnl(rs, i, lane);
+  if (lane == 0) s.lnl[i] = lp;
   const bool in = s.inbox[i] != 0;
-  if (in) s.evals[i] += 1;
+  if (in) c.evals += 1;
   const bool inside = in && (lp > lstar);          // NaN and -inf are outside
-  if (st == kLeft || st == kRight) {
-    if (inside && s.expand[i] < kMaxExpand) {
-      if (st == kLeft)
-        s.a[i] -= 1.0;
+  if (c.stage == kLeft || c.stage == kRight) {
+    if (inside && c.expand < kMaxExpand) {
+      if (c.stage == kLeft)
+        c.a -= 1.0;
       else
-        s.b[i] += 1.0;
-      s.expand[i] += 1;
+        c.b += 1.0;
+      c.expand += 1;
     } else {
-      s.stage[i] = st == kLeft ? kRight : kShrink;
-      s.expand[i] = 0;
+      c.stage = c.stage == kLeft ? kRight : kShrink;
+      c.expand = 0;
     }
-    return;
-  }
-  // shrinking
-  const double t = s.t[i];
-  if (inside) {
+  } else if (inside) {                             // shrinking: accepted
     const int P = s.P;
     double* x = s.x + (size_t)i * P;
     const double* d = s.dir + (size_t)i * P;
-    for (int k = 0; k < P; ++k) x[k] = x[k] + t * d[k];    // the proposal, recomputed exactly
-    s.lx[i] = lp;
-    finish_step(s, i);
-    return;
+    for (int k = lane; k < P; k += 64) x[k] = x[k] + c.t * d[k];   // the proposal, exactly
+    c.lx = lp;
+    finish_step(s, i, c, lane, s_u[wv]);
+  } else {                                         // shrinking: cut the interval
+    if (c.t < 0.0)
+      c.a = c.t;
+    else
+      c.b = c.t;
+    // an interval shrunk to nothing (a likelihood plateau at lnL*): keep the point
+    if (c.b - c.a < 1e-12) finish_step(s, i, c, lane, s_u[wv]);
   }
-  if (t < 0.0)
-    s.a[i] = t;
-  else
-    s.b[i] = t;
-  // an interval shrunk to nothing (a likelihood plateau at lnL*): keep the point
-  if (s.b[i] - s.a[i] < 1e-12) finish_step(s, i);
+  propose(s, i, c, lane);
+  store_scal(s, i, c, lane);
 }
 
 }  // namespace
@@ -299,6 +375,7 @@ int fgl_chains_create(fgl_model* mh, int max_chains, const double* lo, const dou
   if (!m || !lo || !hi) return set_err(FGL_EINVAL, "model, lo and hi must be non-NULL");
   if (max_chains < 1) return set_err(FGL_EINVAL, "max_chains=%d < 1", max_chains);
   const int P = m->P;
+  if (P > kMaxP) return set_err(FGL_EINVAL, "P=%d exceeds the chains' %d parameters", P, kMaxP);
   for (int k = 0; k < P; ++k)
     if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]) || !(lo[k] < hi[k]))
       return set_err(FGL_EINVAL, "box coordinate %d: need finite lo < hi", k);
@@ -389,24 +466,25 @@ int fgl_chains_run(fgl_chains* ch, const double* x0, const double* l0, int n, do
       (e = hipMemcpyAsync(c->d_chol, chol, (size_t)P * P * 8, hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(c->d_lstar, &lstar, 8, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_err(e, "copy chain inputs");
-  const int threads = 128, blocks = (n + threads - 1) / threads;
-  hipLaunchKernelGGL(k_chain_init, dim3(blocks), dim3(threads), 0, s, st, c->d_x0, c->d_l0);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "chain init");
+  if (P > kMaxP) return set_err(FGL_EINVAL, "P=%d exceeds the chains' %d parameters", P, kMaxP);
+  const int blocks = (n + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL(k_chain_start, dim3(blocks), dim3(64 * kWaves), 0, s, st, c->d_x0, c->d_l0);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "chain start");
   // the likelihood's workspace for n rows on this stream, fixed before capture
   const Kind k = kind_of(prec);
   const Tile tile = tile_for(m, k, n);
   WorkBuf& wb = m->work[s];
   wb.stream_synced_free = true;
   if ((rc = ensure_work(m, wb, n, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
+  RowSums rs{wb.w.partial, wb.w.rows, n_groups(m->dm, tile), wb.w.Bpad,
+             (double)m->dm.F * (double)m->dm.T,
+             (k == kMixed && m->dm.proj) ? m->dm.chi0 : 0.0};
   auto round = [&]() -> int {
-    hipLaunchKernelGGL(k_chain_propose, dim3(blocks), dim3(threads), 0, s, st);
-    hipError_t e2 = hipGetLastError();
-    if (e2 != hipSuccess) return hip_err(e2, "chain proposal");
-    int rc2 = enqueue(m, k, tile, wb, st.theta, n, st.lnl, s);
+    int rc2 = enqueue_partials(m, k, tile, wb, st.theta, n, s);
     if (rc2 != FGL_OK) return rc2;
-    hipLaunchKernelGGL(k_chain_update, dim3(blocks), dim3(threads), 0, s, st);
-    e2 = hipGetLastError();
-    return e2 == hipSuccess ? FGL_OK : hip_err(e2, "chain update");
+    hipLaunchKernelGGL(k_chain_step, dim3(blocks), dim3(64 * kWaves), 0, s, st, rs);
+    hipError_t e2 = hipGetLastError();
+    return e2 == hipSuccess ? FGL_OK : hip_err(e2, "chain step");
   };
   // one eager round (it also sets the kernels' launch attributes outside
   // any capture), then kRoundsPerGraph rounds captured once and replayed

@@ -554,6 +554,18 @@ Tile default_tile(Kind k, const DevModel& d, int B) {
 
 int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const double* d_theta,
             int B, double* d_out, hipStream_t s) {
+  const int rc = enqueue_partials(m, k, tile, wb, d_theta, B, s);
+  if (rc != FGL_OK) return rc;
+  hipError_t e;
+  if ((e = launch_finalize(k, m->dm, wb.w, tile, d_out, s)) != hipSuccess)
+    return hip_err(e, "finalize kernel");
+  return FGL_OK;
+}
+
+// prep -> main: the likelihood kernel's per-(group, row) partial sums in
+// wb.w.partial (the chain engine reduces them itself)
+int enqueue_partials(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const double* d_theta,
+                     int B, hipStream_t s) {
   hipError_t e;
   if ((e = launch_prep(m->dm, d_theta, B, wb.w, m->dm.KC * 32, s)) != hipSuccess)
     return hip_err(e, "prep kernel");
@@ -574,8 +586,6 @@ int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const double* d_the
     if ((e = hipEventRecord(ev.second, s)) != hipSuccess) return hip_err(e, "hipEventRecord");
     m->ev_used.push_back(ev);
   }
-  if ((e = launch_finalize(k, m->dm, wb.w, tile, d_out, s)) != hipSuccess)
-    return hip_err(e, "finalize kernel");
   return FGL_OK;
 }
 

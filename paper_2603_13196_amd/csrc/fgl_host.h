@@ -100,6 +100,8 @@ Tile tile_for(Model* m, Kind k, int B);
 int bucket_of(int B);
 int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb,
             const double* d_theta, int B, double* d_out, hipStream_t s);
+int enqueue_partials(Model* m, Kind k, const Tile& tile, WorkBuf& wb,
+                     const double* d_theta, int B, hipStream_t s);
 int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
          double* d_out, hipStream_t s);
 void drop_stream_work(hipStream_t s);   // fgl_host.cpp
