@@ -82,19 +82,21 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
                                                   int T, int t0, const int* __restrict__ order,
                                                   const double* __restrict__ asort,
                                                   const int* __restrict__ seg, int NJ, int L,
+                                                  int jper, int Lg,
                                                   double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, chunk = blockIdx.y;
+  const int j0 = blockIdx.z * jper, nj = min(jper, NJ - j0);   // this workgroup's regions
   const int nlon = s.nlon;
-  double* s_acc = reinterpret_cast<double*>(smem);             // [NJ][blockDim]
-  double* s_a = s_acc + (size_t)blockDim.x * NJ;               // [L]
-  float* s_b = reinterpret_cast<float*>(s_a + L);              // [2 nlon]
-  int* s_idx = reinterpret_cast<int*>(s_b + 2 * nlon);         // [L]
-  int* s_seg = s_idx + L;                                      // [NJ + 1]
+  double* s_acc = reinterpret_cast<double*>(smem);             // [jper][blockDim]
+  double* s_a = s_acc + (size_t)blockDim.x * jper;             // [Lg]
+  float* s_b = reinterpret_cast<float*>(s_a + Lg);             // [2 nlon]
+  int* s_idx = reinterpret_cast<int*>(s_b + 2 * nlon);         // [Lg]
+  int* s_seg = s_idx + Lg;                                     // [jper + 1]
   const int tl = threadIdx.x, t = t0 + tl;
   const bool live = t < T;
   const int o = nlon - (live ? shifts[t] : 0);                 // in [1, nlon]
-  for (int j = 0; j < NJ; ++j) s_acc[(size_t)j * blockDim.x + tl] = 0.0;
+  for (int j = 0; j < nj; ++j) s_acc[(size_t)j * blockDim.x + tl] = 0.0;
   const int r0 = chunk * kRingChunk, r1 = min(s.nlat, r0 + kRingChunk);
   for (int ring = r0; ring < r1; ++ring) {
     __syncthreads();
@@ -103,21 +105,25 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
       s_b[k] = b;
       s_b[k + nlon] = b;
     }
-    for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    // the slice of the ring's list holding this workgroup's regions
+    const int* sg = MODE == kCorrK ? seg + (size_t)ring * (NJ + 1) : nullptr;
+    const int k0 = MODE == kCorrK ? sg[j0] : 0;
+    const int kn = (MODE == kCorrK ? sg[j0 + nj] : L) - k0;
+    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
       if constexpr (MODE == kCorrK) {
-        s_idx[k] = order[(size_t)ring * L + k];
-        s_a[k] = asort[(size_t)ring * L + k];
+        s_idx[k] = order[(size_t)ring * L + k0 + k];
+        s_a[k] = asort[(size_t)ring * L + k0 + k];
       } else {
         s_idx[k] = k < nlon ? k : 0;
         s_a[k] = k < nlon ? aval<MODE>(s, f, ring, k) : 0.0;
       }
     }
-    for (int j = threadIdx.x; j <= NJ; j += blockDim.x)
-      s_seg[j] = MODE == kCorrK ? seg[(size_t)ring * (NJ + 1) + j] : (j == 0 ? 0 : L);
+    for (int j = threadIdx.x; j <= nj; j += blockDim.x)
+      s_seg[j] = MODE == kCorrK ? sg[j0 + j] - k0 : (j == 0 ? 0 : L);
     __syncthreads();
     if (!live) continue;
     const float* bo = s_b + o;
-    for (int j = 0; j < NJ; ++j) {
+    for (int j = 0; j < nj; ++j) {
       const int k1 = s_seg[j + 1];
       int k = s_seg[j];
       if (k == k1) continue;
@@ -147,8 +153,8 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
     }
   }
   if (!live) return;
-  for (int j = 0; j < NJ; ++j)
-    partial[(((size_t)chunk * NJ + j) * s.F + f) * T + t] = s_acc[(size_t)j * blockDim.x + tl];
+  for (int j = 0; j < nj; ++j)
+    partial[(((size_t)chunk * NJ + j0 + j) * s.F + f) * T + t] = s_acc[(size_t)j * blockDim.x + tl];
 }
 
 // out[i] = sum over chunks (in order) of partial[chunk * n + i]
@@ -205,14 +211,17 @@ __global__ __launch_bounds__(256) void k_sky_importance(SkyDev s, const int* __r
   }
 }
 
-// padded pixel-list length: every region's run rounded up to eight
-size_t corr_lds(int tb, int NJ, int nlon, int L) {
-  return (size_t)tb * NJ * 8 + (size_t)L * 12 + (size_t)nlon * 8 + (size_t)(NJ + 1) * 4;
+// LDS of a k_sky_corr workgroup of tb threads holding jper regions whose
+// longest padded pixel slice is Lg
+size_t corr_lds(int tb, int jper, int nlon, int Lg) {
+  return (size_t)tb * jper * 8 + (size_t)Lg * 12 + (size_t)nlon * 8 + (size_t)(jper + 1) * 4;
 }
 
-int corr_block(int T, int NJ, int nlon, int L) {
+constexpr int kRegionsPerGroup = 8;     // regions per k_sky_corr workgroup
+
+int corr_block(int T, int jper, int nlon, int Lg) {
   int tb = std::min(256, (T + 63) / 64 * 64);
-  while (tb > 64 && corr_lds(tb, NJ, nlon, L) > 96 * 1024) tb -= 64;
+  while (tb > 64 && corr_lds(tb, jper, nlon, Lg) > 96 * 1024) tb -= 64;
   return tb;
 }
 
@@ -238,15 +247,16 @@ hipError_t set_lds(KernelT k) {
 // Z or K partial sums and their chunk reduction into out (device).
 template <int MODE>
 int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const double* d_asort,
-             const int* d_seg, int NJ, int L, double* d_out, float* ms) {
+             const int* d_seg, int NJ, int L, int jper, int Lg, double* d_out, float* ms) {
   const SkyDev& d = sk->d;
   const int chunks = (d.nlat + kRingChunk - 1) / kRingChunk;
   const size_t n = (size_t)NJ * d.F * T;
   double* part = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&part), n * chunks * 8);
   if (e != hipSuccess) return hip_err(e, "allocating partial sums");
-  const int tb = corr_block(T, NJ, d.nlon, L);
-  const size_t lds = corr_lds(tb, NJ, d.nlon, L);
+  const int tb = corr_block(T, jper, d.nlon, Lg);
+  const size_t lds = corr_lds(tb, jper, d.nlon, Lg);
+  const int groups = (NJ + jper - 1) / jper;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
     (void)hipEventCreate(&e0);
@@ -255,8 +265,8 @@ int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const doub
   }
   if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {
     for (int t0 = 0; t0 < T && e == hipSuccess; t0 += tb) {
-      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks), dim3(tb), lds, sk->stream, d,
-                         d_shifts, T, t0, d_order, d_asort, d_seg, NJ, L, part);
+      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks, groups), dim3(tb), lds, sk->stream,
+                         d, d_shifts, T, t0, d_order, d_asort, d_seg, NJ, L, jper, Lg, part);
       e = hipGetLastError();
     }
   }
@@ -465,9 +475,9 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
     rc = hip_err(e, "allocating importance buffers");
   }
   if (rc == FGL_OK) {
-    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, Z, nullptr)
-         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, Z, nullptr)
-                                    : run_corr<kCorrHorizon>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, Z, nullptr);
+    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, 1, Lz, Z, nullptr)
+         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, 1, Lz, Z, nullptr)
+                                    : run_corr<kCorrHorizon>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, 1, Lz, Z, nullptr);
   }
   if (rc == FGL_OK) {
     std::vector<double> hz((size_t)d.F * T);
@@ -562,8 +572,17 @@ int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int
     for (int j = 0; j < N; ++j) len += pad8(counts[(size_t)r * N + j]);
     L = std::max(L, len);
   }
-  if (corr_lds(corr_block(T, N, nlon, L), N, nlon, L) > 160 * 1024)
-    return set_err(FGL_EINVAL, "n_regions=%d with nlon=%d does not fit one workgroup's LDS", N, nlon);
+  // longest padded slice of one workgroup's regions
+  const int jper = std::min(N, kRegionsPerGroup);
+  int Lg = 8;
+  for (int r = 0; r < d.nlat; ++r)
+    for (int j0 = 0; j0 < N; j0 += jper) {
+      int len = 0;
+      for (int j = j0; j < std::min(N, j0 + jper); ++j) len += pad8(counts[(size_t)r * N + j]);
+      Lg = std::max(Lg, len);
+    }
+  if (corr_lds(corr_block(T, jper, nlon, Lg), jper, nlon, Lg) > 160 * 1024)
+    return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", nlon);
   std::vector<int> order((size_t)d.nlat * L, 0), seg((size_t)d.nlat * (N + 1));
   std::vector<double> asort((size_t)d.nlat * L, 0.0);
   for (int r = 0; r < d.nlat; ++r) {
@@ -589,7 +608,7 @@ int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int
       rc = hip_err(e, "allocating K");
   }
   float ms = 0.0f;
-  if (rc == FGL_OK) rc = run_corr<kCorrK>(sk, d_sh, T, d_order, d_as, d_seg, N, L, d_K, &ms);
+  if (rc == FGL_OK) rc = run_corr<kCorrK>(sk, d_sh, T, d_order, d_as, d_seg, N, L, jper, Lg, d_K, &ms);
   if (rc == FGL_OK) {
     sk->last_ms = ms;
     if ((e = hipMemcpy(K, d_K, (size_t)N * d.F * T * 8, hipMemcpyDeviceToHost)) != hipSuccess)
