@@ -630,7 +630,13 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
 #pragma unroll
       for (int it = 0; it < NU; ++it) u[it] = f64x4{0.0, 0.0, 0.0, 0.0};
       double rho = 0.0;
-      for (int tt = 0; tt < TR; ++tt) {
+      // projected rows with N a multiple of 16 (and 4 NQB = N): the last row
+      // (N) is alone in its tile and holds one entry, R[N-1][N-1] on region
+      // N - 1 = 4 (NQB - 1) + 3; it is done in FP64 below instead of as a
+      // tile of MFMAs
+      const bool peel = PROJ && (N & 15) == 0 && 4 * NQB == N;
+      const int TL = peel ? TR - 1 : TR;
+      for (int tt = 0; tt < TL; ++tt) {
         AT Ak[NQB];
 #pragma unroll
         for (int k = 0; k < NQB; ++k) Ak[k] = kf[(k * TR + tt) * 64 + lane];
@@ -676,6 +682,14 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
             u[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(at, r[j], u[it], 0, 0, 0);
           }
         }
+      }
+      if (peel && g == 3) {
+        // row N: target z_{N-1}; the entry is read from the forward layout
+        // (tile TR - 1, lane 16 * 3: row 16 (TR - 1), region 4 (NQB - 1) + 3)
+        const double rl = (double)kf[((NQB - 1) * TR + TR - 1) * 64 + 48];
+        const double e = s_D[(size_t)f * drow + N] - rl * Bp[NQB - 1];
+        chi_a = fma(e, e, chi_a);
+        u[NU - 1][3] = fma(rl, e, u[NU - 1][3]);
       }
       // u[it][j] is region 16 it + 4 j + g = 4 q + g with q = 4 it + j
 #pragma unroll
