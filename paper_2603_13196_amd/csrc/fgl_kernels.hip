@@ -1117,7 +1117,8 @@ hipError_t grad_wa(const DevModel& m, const Work& w, const GradShape& gs, hipStr
 
 // 4-wave workgroups (64 rows); chunks of kGradChunk channels, fixed per
 // model so that a row's sums do not depend on the batch it came in; as many
-// channels staged at once as fit in 64 KB (at least one).
+// channels staged at once as fit in 40 KB (at least one; measured faster than
+// 24 KB or 64 KB at the headline shape, for the workgroups it lets share a CU).
 constexpr int kGradChunk = 16;
 
 GradShape grad_shape(const DevModel& m, int Bpad) {
@@ -1127,7 +1128,7 @@ GradShape grad_shape(const DevModel& m, int Bpad) {
                            : m.NQ * m.TT16 * 64 * 4 + m.TT * 32 * 8;
   g.per = std::min(m.F, kGradChunk);
   g.chunks = (m.F + g.per - 1) / g.per;
-  g.fs = std::max(1, std::min(g.per, (64 * 1024) / per_ch));
+  g.fs = std::max(1, std::min(g.per, (40 * 1024) / per_ch));
   g.lds = g.fs * per_ch;
   return g;
 }
