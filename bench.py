@@ -46,6 +46,8 @@ def parse():
                    help="skip the nested-sampling run (10 regions, T = 1, benchmark settings)")
     p.add_argument("--no-regions", action="store_true",
                    help="skip the region-construction leg (importance, partition, K)")
+    p.add_argument("--no-small", action="store_true",
+                   help="skip the launch-bound small-batch workloads")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the FP64 gradient leg")
     p.add_argument("--no-masks", action="store_true",
@@ -209,6 +211,44 @@ def masks_leg(fgl, steps, warmup, tune):
     res["mixed_over_fp32"] = res["mixed"]["value"] / res["fp32"]["value"]
     m.close()
     return res
+
+
+def small_batch_leg(fgl, calls=200):
+    """The launch-bound workloads (N4_F151_T1_B1000 and N16_F151_T20_B4096):
+    median latency of a synchronous host-pointer call (θ in, lnL out over
+    PCIe, the call's kernels replayed from a captured hipGraph) and the time
+    per device-pointer call enqueued back to back, for each precision."""
+    import torch
+    import workload
+    out = {}
+    for k in (0, 1):
+        w = workload.config(k)
+        m = fgl.Model.from_workload(w)
+        th = torch.from_numpy(w.theta).cuda()
+        o = torch.empty(w.B, dtype=torch.float64, device="cuda")
+        r = {"B": w.B}
+        for prec in PRECS:
+            for _ in range(3):
+                m.loglike(w.theta, prec)                   # eager, capture, replay
+            lat = []
+            for _ in range(calls):
+                t0 = time.perf_counter()
+                m.loglike(w.theta, prec)
+                lat.append(time.perf_counter() - t0)
+            host_us = float(np.median(lat)) * 1e6
+            for _ in range(3):
+                m.loglike_device(th, o, prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                m.loglike_device(th, o, prec)
+            torch.cuda.synchronize()
+            dev_us = (time.perf_counter() - t0) / calls * 1e6
+            r[prec] = {"host_call_median_us": host_us, "device_call_us": dev_us,
+                       "evals_per_s_device": w.B / (dev_us * 1e-6)}
+        out[w.name] = r
+        m.close()
+    return out
 
 
 def grad_leg(fgl, w, steps, warmup):
@@ -389,6 +429,9 @@ def main():
                                      "ms_per_step": res["mixed_direct"]["ms_per_step"],
                                      "kernel_ms": res["mixed_direct"]["kernel_ms"]}
     m.close()
+    if not a.no_small and not a.no_plain:
+        log("small-batch leg")
+        line["small_batch"] = small_batch_leg(fgl)
     if not a.no_grad and not a.no_plain:
         log("gradient leg")
         line["gradient"] = grad_leg(fgl, w, a.steps, a.warmup)
