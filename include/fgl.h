@@ -37,9 +37,16 @@
  *                   T >= N + 1, N <= 96 and it needs fewer 32-row tiles,
  *                   evaluates the time sum of each channel exactly in an
  *                   orthonormal basis of the channel's centred responses
- *                   (N + 1 rows instead of T).
+ *                   (N + 1 rows instead of T).  Models with few time bins
+ *                   (T <= 16, N <= 32; the paper's time-integrated fits
+ *                   have T = 1) are evaluated per row in FP64 on the vector
+ *                   units instead (FGL_FORM_THIN): the time bins would fill
+ *                   only a sliver of a matrix tile, and FP64 meets the
+ *                   bound exactly.  FGL_MIXED_DIRECT keeps the digit
+ *                   kernel's direct form for them.
  *   FGL_PREC_FP32   the model in FP32, residual and chi-square in FP64.
- *   FGL_PREC_FP64   everything in FP64.
+ *   FGL_PREC_FP64   everything in FP64 (per row on the vector units for the
+ *                   models with few time bins described above).
  *
  * Errors: every call returns an FGL_* status; fgl_last_error() gives a
  * message for the calling thread's last failure.  Nothing is ever printed.
@@ -79,7 +86,7 @@ enum { FGL_PREC_MIXED = 0, FGL_PREC_FP32 = 1, FGL_PREC_FP64 = 2 };
 #define FGL_MIXED_DIRECT 2u /* mixed precision: always use the direct form */
 
 /* Forms of the mixed-precision evaluation (fgl_mixed_form). */
-enum { FGL_FORM_DIRECT = 0, FGL_FORM_PROJECTED = 1 };
+enum { FGL_FORM_DIRECT = 0, FGL_FORM_PROJECTED = 1, FGL_FORM_THIN = 2 };
 
 /*
  * Create a model: the fixed inputs of the likelihood (Sec. 2.2 precomputes
@@ -135,8 +142,9 @@ int fgl_model_create_masks(const float* K, const double* freqs,
  * masks n_beta + n_alpha + 4 or + 1); -1 for NULL. */
 int fgl_model_nparams(const fgl_model* m);
 
-/* Form of the model's mixed-precision evaluation: FGL_FORM_DIRECT or
- * FGL_FORM_PROJECTED (fixed at creation); FGL_EINVAL for NULL. */
+/* Form of the model's mixed-precision evaluation: FGL_FORM_DIRECT,
+ * FGL_FORM_PROJECTED or FGL_FORM_THIN (fixed at creation); FGL_EINVAL for
+ * NULL. */
 int fgl_mixed_form(const fgl_model* m);
 
 /*

@@ -471,7 +471,7 @@ int fgl_chains_run(fgl_chains* ch, const double* x0, const double* l0, int n, do
   hipLaunchKernelGGL(k_chain_start, dim3(blocks), dim3(64 * kWaves), 0, s, st, c->d_x0, c->d_l0);
   if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "chain start");
   // the likelihood's workspace for n rows on this stream, fixed before capture
-  const Kind k = kind_of(prec);
+  const Kind k = kind_of(prec, m->dm);
   const Tile tile = tile_for(m, k, n);
   WorkBuf& wb = m->work[s];
   wb.stream_synced_free = true;

@@ -134,6 +134,14 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
           const float v = (t < T && i < N) ? Kat(i, f, t) : 0.0f;
           m->h_k32[(((size_t)f * NP2 + k) * TT + tt) * 64 + lane] = v;
         }
+  // thin-kernel K [F][T][NT], zero padded in regions
+  if (m->dm.thin) {
+    const int NT = m->dm.NT;
+    m->h_kthin.assign((size_t)F * T * NT, 0.0f);
+    for (int f = 0; f < F; ++f)
+      for (int t = 0; t < T; ++t)
+        for (int i = 0; i < N; ++i) m->h_kthin[((size_t)f * T + t) * NT + i] = Kat(i, f, t);
+  }
   // FP64 A operands (exact FP32 values) [F][NQ][TT16][64]: lane ->
   // (t = tt*16 + lane%16, i = 4k + lane/16); regions >= N are zero
   m->h_k64.assign((size_t)F * NQ * TT16 * 64, 0.0f);
@@ -174,6 +182,7 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
   m->dm.c2 = (double)(c1 * c1 / 2.0L);
   m->dm.c3 = (double)(c1 * c1 * c1 / 6.0L);
   m->dm.c4 = (double)(c1 * c1 * c1 * c1 / 24.0L);
+  m->dm.c5 = (double)(c1 * c1 * c1 * c1 * c1 / 120.0L);
   if (m->dm.proj) build_projected(m, K, data);
 }
 
@@ -315,7 +324,7 @@ static hipError_t upload(T** dptr, const std::vector<T>& h) {
 
 size_t resident_bytes(const Model* m) {
   return m->h_kd.size() + m->h_eK.size() * 4 + m->h_k32.size() * 4 +
-         m->h_k64.size() * 4 + (m->h_nl64.size() + m->h_nl2.size() + m->h_nu.size()) * 8 +
+         m->h_k64.size() * 4 + m->h_kthin.size() * 4 + (m->h_nl64.size() + m->h_nl2.size() + m->h_nu.size()) * 8 +
          m->h_D.size() * 8 + m->h_tab.size() * 8 + m->h_rd.size() + m->h_eR.size() * 4 +
          (m->h_tg.size() + m->h_dbar.size() + m->h_pk.size()) * 8 +
          (m->h_pa64.size() + m->h_pt64.size()) * 8;
@@ -327,18 +336,19 @@ int make_resident(Model* m) {
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   int8_t *kd = nullptr, *rd = nullptr;
   int32_t *eK = nullptr, *eR = nullptr;
-  float *k32 = nullptr, *k64 = nullptr;
+  float *k32 = nullptr, *k64 = nullptr, *kthin = nullptr;
   double *nl64 = nullptr, *nl2 = nullptr, *nu = nullptr, *D = nullptr, *tab = nullptr;
   double *tg = nullptr, *dbar = nullptr, *pk = nullptr, *pa64 = nullptr, *pt64 = nullptr;
   if ((e = upload(&kd, m->h_kd)) != hipSuccess || (e = upload(&eK, m->h_eK)) != hipSuccess ||
       (e = upload(&pa64, m->h_pa64)) != hipSuccess || (e = upload(&pt64, m->h_pt64)) != hipSuccess ||
       (e = upload(&k32, m->h_k32)) != hipSuccess || (e = upload(&k64, m->h_k64)) != hipSuccess ||
+      (e = upload(&kthin, m->h_kthin)) != hipSuccess ||
       (e = upload(&nl64, m->h_nl64)) != hipSuccess || (e = upload(&nl2, m->h_nl2)) != hipSuccess ||
       (e = upload(&nu, m->h_nu)) != hipSuccess || (e = upload(&D, m->h_D)) != hipSuccess ||
       (e = upload(&tab, m->h_tab)) != hipSuccess || (e = upload(&rd, m->h_rd)) != hipSuccess ||
       (e = upload(&eR, m->h_eR)) != hipSuccess || (e = upload(&tg, m->h_tg)) != hipSuccess ||
       (e = upload(&dbar, m->h_dbar)) != hipSuccess || (e = upload(&pk, m->h_pk)) != hipSuccess) {
-    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk, pa64, pt64};
+    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk, pa64, pt64, kthin};
     for (void* p : ps)
       if (p) (void)hipFree(p);
     return hip_err(e, "uploading model");
@@ -354,6 +364,7 @@ int make_resident(Model* m) {
   m->dm.eK = eK;
   m->dm.k32 = k32;
   m->dm.k64 = k64;
+  m->dm.kthin = kthin;
   m->dm.nl64 = nl64;
   m->dm.nl2 = nl2;
   m->dm.nu = nu;
@@ -370,7 +381,8 @@ void evict(Model* m) {
   (void)hipDeviceSynchronize();
   const void* ps[] = {m->dm.kd, m->dm.eK, m->dm.k32, m->dm.k64, m->dm.nl64,
                       m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab, m->dm.rd,
-                      m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk, m->dm.pa64, m->dm.pt64};
+                      m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk, m->dm.pa64, m->dm.pt64,
+                      m->dm.kthin};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
   m->dm.rd = nullptr;
@@ -378,7 +390,7 @@ void evict(Model* m) {
   m->dm.tg = m->dm.dbar = m->dm.pk = m->dm.pa64 = m->dm.pt64 = nullptr;
   m->dm.kd = nullptr;
   m->dm.eK = nullptr;
-  m->dm.k32 = m->dm.k64 = nullptr;
+  m->dm.k32 = m->dm.k64 = m->dm.kthin = nullptr;
   m->dm.nl64 = m->dm.nl2 = m->dm.nu = m->dm.D = m->dm.tab = nullptr;
   m->resident = false;
   // graphs captured against the old buffers are stale
@@ -479,12 +491,18 @@ int ensure_work(Model* m, WorkBuf& wb, int B, int ngroups, bool host_io) {
 // ---------------------------------------------------------------------------
 // tiles
 
-Kind kind_of(int prec) {
-  return prec == FGL_PREC_FP32 ? kFP32 : (prec == FGL_PREC_FP64 ? kFP64 : kMixed);
+// Kernel family of a precision on a model: thin models evaluate the mixed
+// (unless the direct digit form is forced) and FP64 precisions per row in
+// FP64, which is exact and cheaper than MFMA tiles holding a few time bins.
+Kind kind_of(int prec, const DevModel& d) {
+  if (prec == FGL_PREC_FP32) return kFP32;
+  if (d.thin && (prec == FGL_PREC_FP64 || !(d.flags & FGL_MIXED_DIRECT))) return kThin;
+  return prec == FGL_PREC_FP64 ? kFP64 : kMixed;
 }
 
 // Largest wave count whose kernel fits in registers without spilling.
 static int max_waves(Kind k, const DevModel& d) {
+  if (k == kThin) return 4;
   if (k == kMixed) return d.KC <= 2 ? 8 : 4;
   if (k == kFP32) return 8;
   return 8;
@@ -764,6 +782,8 @@ static int create_model(const float* K, const double* freqs, const double* data,
   d.KC = (N + 31) / 32;
   d.NP2 = fp32_slots(N);
   d.NQ = fp64_slots(N);
+  d.thin = (T <= kThinMaxT && N <= kThinMaxN) ? 1 : 0;
+  d.NT = d.thin ? thin_slots(N) : 0;
   d.t_cmb = t_cmb;
   d.flags = flags;
   // the projected form when its N + 1 rows take fewer 32-row tiles than T
@@ -777,7 +797,8 @@ static int create_model(const float* K, const double* freqs, const double* data,
       d.peel = peel;
     }
   }
-  for (Kind k : {kMixed, kFP32, kFP64}) {
+  for (Kind k : {kMixed, kFP32, kFP64, kThin}) {
+    if (k == kThin && !d.thin) continue;
     if (group_of(k, d) == 0) {
       delete m;
       return set_err(FGL_EINVAL, "T=%d with N=%d does not fit one channel in LDS", T, N);
@@ -857,7 +878,7 @@ int fgl_loglike_batch(fgl_model* mh, const double* theta, int B, double* out, in
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   if ((rc = make_resident(m)) != FGL_OK) return rc;
-  const Kind k = kind_of(prec);
+  const Kind k = kind_of(prec, m->dm);
   hipStream_t s = m->stream;
   WorkBuf& wb = m->work[s];
   wb.stream_synced_free = true;   // this stream is synchronised after every call
@@ -926,7 +947,7 @@ int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   if ((rc = make_resident(m)) != FGL_OK) return rc;
-  const Kind k = kind_of(prec);
+  const Kind k = kind_of(prec, m->dm);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   WorkBuf& wb = m->work[s];
   const uint64_t tkey = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
@@ -1015,6 +1036,7 @@ int fgl_loglike_grad_batch_device(fgl_model* mh, const double* d_theta, int B,
 int fgl_mixed_form(const fgl_model* mh) {
   if (!mh) return set_err(FGL_EINVAL, "model is NULL");
   const Model* m = reinterpret_cast<const Model*>(mh);
+  if (kind_of(FGL_PREC_MIXED, m->dm) == kThin) return FGL_FORM_THIN;
   return m->dm.proj ? FGL_FORM_PROJECTED : FGL_FORM_DIRECT;
 }
 
@@ -1023,7 +1045,7 @@ int fgl_get_tile(fgl_model* mh, int B, int prec, int* waves, int* chans, int* oc
   int rc = check_call(m, B, prec);
   if (rc != FGL_OK) return rc;
   std::lock_guard<std::mutex> lk(m->mu);
-  const Tile t = tile_for(m, kind_of(prec), std::max(B, 1));
+  const Tile t = tile_for(m, kind_of(prec, m->dm), std::max(B, 1));
   if (waves) *waves = t.waves;
   if (chans) *chans = t.fc;
   if (occupancy) *occupancy = t.occ;
@@ -1035,7 +1057,7 @@ int fgl_set_tile(fgl_model* mh, int B, int prec, int waves, int chans, int occup
   int rc = check_call(m, B, prec);
   if (rc != FGL_OK) return rc;
   std::lock_guard<std::mutex> lk(m->mu);
-  const Kind k = kind_of(prec);
+  const Kind k = kind_of(prec, m->dm);
   for (const Tile& t : candidates(k, m->dm)) {
     if (t.waves == waves && t.fc == chans && t.occ == occupancy) {
       const uint64_t key = ((uint64_t)k << 32) | (uint32_t)bucket_of(std::max(B, 1));
@@ -1060,7 +1082,7 @@ int fgl_tune(fgl_model* mh, int B, int prec) {
   hipStream_t s = m->stream;
   WorkBuf& wb = m->work[s];
   wb.stream_synced_free = true;
-  if ((rc = ensure_work(m, wb, B, n_groups(m->dm, default_tile(kind_of(prec), m->dm, B)), true)) != FGL_OK)
+  if ((rc = ensure_work(m, wb, B, n_groups(m->dm, default_tile(kind_of(prec, m->dm), m->dm, B)), true)) != FGL_OK)
     return rc;
   // tune on prior-like rows: beta = 2.75, A = -0.1, nu0 = 100, w = 15, sigma = 0.025
   for (int b = 0; b < B; ++b) {
@@ -1077,7 +1099,7 @@ int fgl_tune(fgl_model* mh, int B, int prec) {
   }
   if ((e = hipMemcpyAsync(wb.d_theta, wb.h_theta, (size_t)B * m->P * 8, hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_err(e, "copy theta");
-  rc = tune(m, kind_of(prec), wb, wb.d_theta, B, wb.d_out, s);
+  rc = tune(m, kind_of(prec, m->dm), wb, wb.d_theta, B, wb.d_out, s);
   if (rc != FGL_OK) return rc;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_err(e, "hipStreamSynchronize");
   return FGL_OK;

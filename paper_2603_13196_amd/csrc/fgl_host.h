@@ -64,7 +64,7 @@ struct Model {
   // host copies of the device layouts (re-uploaded after an eviction)
   std::vector<int8_t> h_kd;
   std::vector<int32_t> h_eK;
-  std::vector<float> h_k32, h_k64;
+  std::vector<float> h_k32, h_k64, h_kthin;
   std::vector<double> h_nl64, h_nl2, h_nu, h_D, h_tab;
   std::vector<int8_t> h_rd;                  // projected form (empty if unused)
   std::vector<int32_t> h_eR;
@@ -92,7 +92,7 @@ size_t resident_bytes(const Model* m);
 int make_resident(Model* m);
 void evict(Model* m);
 int ensure_work(Model* m, WorkBuf& wb, int B, int ngroups, bool host_io);
-Kind kind_of(int prec);
+Kind kind_of(int prec, const DevModel& d);
 int group_of(Kind k, const DevModel& d);
 std::vector<Tile> candidates(Kind k, const DevModel& d);
 Tile default_tile(Kind k, const DevModel& d, int B);

@@ -53,8 +53,19 @@ inline int fp64_slots(int N) {
   return 0;
 }
 
-// Kernel families behind one entry point.
-enum Kind { kMixed = 0, kFP32 = 1, kFP64 = 2 };
+// Kernel families behind one entry point.  kThin: models with few time bins
+// (T <= kThinMaxT, N <= kThinMaxN), evaluated per row in FP64 on the vector
+// units; used for the mixed and FP64 precisions of such models.
+enum Kind { kMixed = 0, kFP32 = 1, kFP64 = 2, kThin = 3 };
+constexpr int kThinMaxT = 16;
+constexpr int kThinMaxN = 32;
+
+// Compiled region counts of the thin kernel (regions >= N have K = 0).
+inline int thin_slots(int N) {
+  for (int s : {4, 8, 12, 16, 24, 32})
+    if (N <= s) return s;
+  return 0;
+}
 
 // Tile configuration of one launch (chosen by the tuner).
 // The channel sum of a row is cut into reduction groups of `group`
@@ -93,6 +104,7 @@ struct DevModel {
   const double* D;       // [F][TT*32] data, zero padded in t
   const double* tab;     // [kTabSize + kFracSize] exponent tables
   double c1, c2, c3, c4; // Taylor coefficients of 2^(r/64)
+  double c5;             // and its fifth-order term (thin kernel)
   // projected form of the mixed kernel (proj = 1): per channel, the rows
   // [sqrt(T) mean_t K ; R] where K~^T = Q R is the QR factorisation of the
   // time-centred responses, and targets [sqrt(T) mean_t D ; (Q^T D~)_0..]
@@ -111,6 +123,10 @@ struct DevModel {
   int RT16;              // 16-row tiles of the N + 1 rows
   const double* pa64;    // [F][NQ][RT16][64]: lane -> (row 16 tt + lane%16, region 4 q + lane/16)
   const double* pt64;    // [F][RT16*16] targets: row 0 sqrt(T) mean_t D, rows 1.. z
+  // thin models (T <= kThinMaxT, N <= kThinMaxN)
+  int thin;              // 1: mixed (unless the direct form is forced) and FP64 use k_thin64
+  int NT;                // regions rounded up to a compiled count
+  const float* kthin;    // [F][T][NT] K, zero padded in regions
 };
 
 // Per-call workspace (device memory owned by the model, per stream).

@@ -548,6 +548,83 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 }
 
 // ---------------------------------------------------------------------------
+// thin models: FP64 on the vector units
+//
+// With T <= kThinMaxT the time bins fill only a sliver of an MFMA tile, so
+// the model is evaluated per parameter row on the vector units: one lane per
+// row, the channel's N powers in FP64, then for each time bin the region sum
+// (ascending i), the residual and the chi-square, all in FP64.  A power
+// 2^y is 2^(j/64) 2^(r/64) with j = round(64 y): 2^floor(j/64) by ldexp,
+// 2^((j mod 64)/64) from a 64-entry LDS table and 2^(r/64), |r| <= 1/2, by
+// its Taylor series to fifth order (truncation below 4e-17 relative).  K and
+// D of the workgroup's channels are staged in LDS and read as broadcasts
+// (every lane takes the same channel and time bin).  One partial per row and
+// reduction group, as the other kernels.
+
+template <int NT, bool AB>
+__global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int G, int nb,
+                                                int nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int bt, ch;
+  map_block(nb, nc, bt, ch);
+  const int T = m.T, TD = m.TT * 32, N = m.N;
+  const int f0 = ch * fc;
+  const int fn = min(fc, m.F - f0);
+  double* s_t64 = reinterpret_cast<double*>(smem);                   // [64] 2^(m/64)
+  float* s_k = reinterpret_cast<float*>(smem + 512);                 // [fc][T][NT]
+  double* s_D = reinterpret_cast<double*>(smem + 512 + (size_t)fc * T * NT * 4);   // [fc][TD]
+  stage(s_k, m.kthin + (size_t)f0 * T * NT, fn * T * NT * 4);
+  stage(s_D, m.D + (size_t)f0 * TD, fn * TD * 8);
+  if (threadIdx.x < 64) s_t64[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+  __syncthreads();
+  const double MAGIC = 0x1.8p52;                  // rint via the low word
+  const int b = bt * blockDim.x + threadIdx.x;
+  const RowParams rp = w.rows[b];
+  double beta[NT];
+  double off[AB ? NT : 1];                        // 64 log2 alpha (AB)
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    beta[i] = i < N ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
+    if constexpr (AB) off[i] = i < N ? 64.0 * w.offT[(size_t)i * w.Bpad + b] : 0.0;
+  }
+  double acc = 0.0;
+  for (int f = 0; f < fn; ++f) {
+    const int fi = f0 + f;
+    const double nl = m.nl64[fi];                 // -64 log2(nu / nu_ref)
+    const double z = (m.nu[fi] - rp.nu0) * rp.inv_w;
+    const double c = m.t_cmb + rp.A * exp(-0.5 * z * z);
+    double P[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const double y = AB ? fma(beta[i], nl, off[i]) : beta[i] * nl;   // 64 log2 P
+      const double t = y + MAGIC;
+      const int j = (int)(uint32_t)__double_as_longlong(t);
+      const double r = y - (t - MAGIC);                               // |r| <= 1/2
+      double p = fma(r, m.c5, m.c4);
+      p = fma(r, p, m.c3);
+      p = fma(r, p, m.c2);
+      p = fma(r, p, m.c1);
+      p = fma(r, p, 1.0);
+      P[i] = ldexp(s_t64[j & 63] * p, j >> 6);
+    }
+    const float* kf = s_k + (size_t)f * T * NT;
+    const double* Df = s_D + (size_t)f * TD;
+    for (int t = 0; t < T; ++t) {
+      double msum = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) msum = fma((double)kf[t * NT + i], P[i], msum);
+      const double r = (Df[t] - c) - msum;
+      acc = fma(r, r, acc);
+    }
+    // one partial per reduction group of G channels (f0 is a multiple of G)
+    if ((f + 1) % G == 0 || f == fn - 1) {
+      w.partial[(size_t)((f0 + f) / G) * w.Bpad + b] = acc;
+      acc = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // gradient (FP64)
 //
 // d lnL / d theta by the chain rule through Eqs. likelihood,
@@ -912,7 +989,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 // ---------------------------------------------------------------------------
 // launchers
 
-int cols_per_wave(Kind k) { return k == kFP64 ? 16 : 32; }
+int cols_per_wave(Kind k) { return k == kFP64 ? 16 : (k == kThin ? 64 : 32); }
 
 int max_lds_bytes() { return 160 * 1024; }
 
@@ -925,6 +1002,7 @@ int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
                (kTabSize + 2 * kFracSize) * 8;
       return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + 2 * kFracSize) * 8;
     case kFP32: return t.fc * m.NP2 * m.TT * 64 * 4 + d;
+    case kThin: return 512 + t.fc * m.T * m.NT * 4 + d;
     default: return t.fc * m.NQ * m.TT16 * 64 * 4 + d;
   }
 }
@@ -1045,6 +1123,21 @@ hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   : fp64_wa<W, false>(m, w, fc, G, nb, nc, lds, s);
 }
 
+template <bool AB>
+hipError_t thin_wa(const DevModel& m, const Work& w, int fc, int G, int nb, int nc, int lds,
+                   hipStream_t s, int threads) {
+  const int blocks = nb * nc;
+  switch (m.NT) {
+    case 4: return go(k_thin64<4, AB>, blocks, threads, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_thin64<8, AB>, blocks, threads, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_thin64<12, AB>, blocks, threads, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_thin64<16, AB>, blocks, threads, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_thin64<24, AB>, blocks, threads, lds, s, m, w, fc, G, nb, nc);
+    case 32: return go(k_thin64<32, AB>, blocks, threads, lds, s, m, w, fc, G, nb, nc);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prep(const DevModel& m, const double* theta, int B,
@@ -1068,6 +1161,11 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
   if (w.Bpad % cols != 0 || n_groups(m, tile) > w.ngroup_cap ||
       tile.group < 1 || tile.fc % tile.group != 0 || lds > max_lds_bytes())
     return hipErrorInvalidValue;
+  if (k == kThin) {
+    if (!m.thin || tile.waves != 4) return hipErrorInvalidValue;
+    return m.NA > 0 ? thin_wa<true>(m, w, tile.fc, tile.group, nb, nc, lds, s, 256)
+                    : thin_wa<false>(m, w, tile.fc, tile.group, nb, nc, lds, s, 256);
+  }
   if (k == kMixed) {
     return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s)
                            : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s);

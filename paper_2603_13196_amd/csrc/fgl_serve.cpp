@@ -183,7 +183,7 @@ static int launch_slot(Server* srv, Slot* sl) {
     std::memcpy(sl->h_theta + off, r->theta, (size_t)r->B * m->P * 8);
     off += (size_t)r->B * m->P;
   }
-  const Kind k = kind_of(prec);
+  const Kind k = kind_of(prec, m->dm);
   WorkBuf& wb = m->work[sl->s];
   wb.stream_synced_free = true;     // the slot's stream is idle here
   const Tile tile = tile_for(m, k, rows);

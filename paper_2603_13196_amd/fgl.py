@@ -23,7 +23,7 @@ FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EBUSY, FGL_EDEVICE, FGL_EAGAIN = 0, -1, -2, 
 FGL_PREC_MIXED, FGL_PREC_FP32, FGL_PREC_FP64 = 0, 1, 2
 FGL_NO_21CM = 1
 FGL_MIXED_DIRECT = 2
-FGL_FORM_DIRECT, FGL_FORM_PROJECTED = 0, 1
+FGL_FORM_DIRECT, FGL_FORM_PROJECTED, FGL_FORM_THIN = 0, 1, 2
 PREC = {"mixed": FGL_PREC_MIXED, "fp32": FGL_PREC_FP32, "fp64": FGL_PREC_FP64}
 _NAMES = {FGL_EINVAL: "EINVAL", FGL_ENOMEM: "ENOMEM", FGL_EBUSY: "EBUSY",
           FGL_EDEVICE: "EDEVICE", FGL_EAGAIN: "EAGAIN"}
@@ -251,8 +251,9 @@ class Model:
 
     @property
     def form(self) -> str:
-        """'direct' or 'projected': the form of the mixed evaluation."""
-        return "projected" if _lib.fgl_mixed_form(self.handle) == FGL_FORM_PROJECTED else "direct"
+        """'direct', 'projected' or 'thin': the form of the mixed evaluation."""
+        f = _lib.fgl_mixed_form(self.handle)
+        return {FGL_FORM_PROJECTED: "projected", FGL_FORM_THIN: "thin"}.get(f, "direct")
 
     def loglike(self, theta, prec="mixed") -> np.ndarray:
         th = _f64(theta).reshape(-1, self.P)

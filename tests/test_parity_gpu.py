@@ -119,19 +119,24 @@ def test_large_config_subsample(fgl, orc):
     (1, 7, 1, 1), (3, 5, 2, 257), (31, 13, 31, 300), (32, 9, 32, 64),
     (33, 11, 33, 100), (64, 6, 65, 70), (100, 5, 17, 40), (128, 3, 40, 33),
     (7, 1, 96, 512), (12, 40, 130, 129), (32, 6, 40, 100), (32, 5, 33, 64),
-    (40, 9, 96, 200), (70, 4, 100, 50), (96, 3, 130, 40), (1, 3, 50, 65)])
+    (40, 9, 96, 200), (70, 4, 100, 50), (96, 3, 130, 40), (1, 3, 50, 65),
+    (8, 9, 16, 300), (17, 5, 3, 70), (32, 7, 16, 257), (31, 4, 9, 33), (33, 5, 2, 40),
+    (11, 6, 5, 90), (14, 5, 12, 66)])
 def test_shapes_and_ragged_tails(fgl, orc, N, F, T, B):
     """Region chunks (N over 32), ragged time tiles, ragged batches, a single
     channel, a single row, with chromatic K and mixed prior/shell rows; the
     mixed evaluation in both forms wherever the projected one applies
-    (T >= N + 1 with fewer row tiles; with and without the peeled row)."""
+    (T >= N + 1 with fewer row tiles; with and without the peeled row), and
+    the per-row FP64 form of models with few time bins (T <= 16, N <= 32)
+    beside the forced direct form."""
     freqs = np.linspace(55.0, 190.0, F) if F > 1 else np.array([123.0])
     w = workload.make(N, freqs, T, B, 1000 + N * 7 + T, chroma=0.05, batch="mixed")
     say(f"shape N={N} F={F} T={T} B={B}")
     ref = orc.loglike_w(w)
     proj = T >= N + 1 and N <= 96 and (N + 1 - (N % 32 == 0) + 31) // 32 < (T + 31) // 32
+    thin = T <= 16 and N <= 32
     _mixed_forms(fgl, w, w.theta, ref, f"N{N}F{F}T{T}B{B}",
-                 expect="projected" if proj else "direct")
+                 expect="thin" if thin else ("projected" if proj else "direct"))
     m = _model(fgl, w)
     for prec in ("fp32", "fp64"):
         got = m.loglike(w.theta, prec)
@@ -173,6 +178,11 @@ def test_edge_rows_and_values(fgl, orc):
     assert np.all(ref[1:6] == -np.inf)
     for prec in ("mixed", "fp64"):
         check(m.loglike(th, prec), ref, prec, "edge", th, F * T)
+    # the digit kernel on the same edges (the model above is evaluated per row)
+    md = fgl.Model(K, freqs, D, 230.0, 2.725, fgl.FGL_MIXED_DIRECT)
+    assert m.form == "thin" and md.form == "direct"
+    check(md.loglike(th, "mixed"), ref, "mixed", "edge/direct", th, F * T)
+    md.close()
     got32 = m.loglike(th, "fp32")
     assert np.all(got32[1:6] == -np.inf)
     m.close()
