@@ -34,8 +34,11 @@ EXP_FLOPS = 20               # FP64 flops counted per power-law value
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    # the device clock ramps to its steady state over ~40 ms of load and
+    # drops again after idling, so the warm-up runs ~60 ms and the timed
+    # region ~100 ms of the headline call
+    p.add_argument("--steps", type=int, default=500)
+    p.add_argument("--warmup", type=int, default=300)
     p.add_argument("--workload", type=int, default=2, choices=[0, 1, 2, 4])
     p.add_argument("--no-serve", action="store_true")
     p.add_argument("--no-cpu", action="store_true")

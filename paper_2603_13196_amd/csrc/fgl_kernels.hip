@@ -21,7 +21,7 @@
 // are bitwise reproducible, independent of the tuned tile and of what else
 // runs on the device.
 //
-// Three arithmetic forms share that skeleton:
+// Four arithmetic forms share that skeleton:
 //   k_mixed: exact integer slicing.  The powers are computed in FP64,
 //            rounded to 39-bit fixed point relative to the row's largest
 //            power at the channel and cut into five signed 8-bit digits; the
@@ -33,6 +33,9 @@
 //   k_fp32:  the model in FP32 (v_mfma_f32_32x32x2_f32, FP32 powers),
 //            residual and chi-square in FP64.
 //   k_fp64:  the model in FP64 (v_mfma_f64_16x16x4_f64, FP64 powers).
+//   k_thin64: models with few time bins (T <= 16, N <= 32), where a matrix
+//            tile would be mostly padding: each lane evaluates its row's
+//            model values as FP64 sums on the vector units.
 #include "fgl_internal.h"
 
 #include <math.h>
@@ -184,87 +187,94 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   const double MAGIC = 0x1.8p52;                        // rint via the low word
   const double DIGITS = 0x1.0p52 + (double)0x80808080u;  // digit offsets
   double acc_a = 0.0, acc_b = 0.0;
-  // per-channel scalars, fetched one channel ahead
-  double nl_n = m.nl64[f0], nu_n = m.nu[f0];
-  int ek_n = PROJ ? m.eR[f0] : m.eK[f0];
-  for (int f = 0; f < fn; ++f) {
-    const int fi = f0 + f;
-    const double nl = nl_n, nuf = nu_n;
-    const int ek = ek_n;
-    {
-      const int fx = min(fi + 1, m.F - 1);
-      nl_n = m.nl64[fx];
-      nu_n = m.nu[fx];
-      ek_n = PROJ ? m.eR[fx] : m.eK[fx];
-    }
+
+  // Per-channel scalars (fetched ahead of use) and the row's state at one
+  // channel: level units, the constant term's digits (direct form), the
+  // target of the mean row and the last region's rounded power (projected
+  // form), and the power-law digits, the MFMA B operands of this lane (row
+  // b, 16 regions per 32-region chunk, five significance levels).
+  struct Scal {
+    double nl, nu;
+    int ek;
+  };
+  struct Chan {
+    double s0, s1, s2, t0, qlast;
+    int c0, c1, ey, fm;
+    i32x4 B[KC][5];
+  };
+  auto fetch = [&](int fi) {
+    const int fx = min(fi, m.F - 1);
+    return Scal{m.nl64[fx], m.nu[fx], PROJ ? m.eR[fx] : m.eK[fx]};
+  };
+  auto make = [&](const Scal& sc, int fi, Chan& C) {
+    const double nl = sc.nl;
     // row constants at this channel: normalisation, level units, constant term
-    const double c = m.t_cmb + rp.A * gauss21(nuf, rp);
+    const double c = m.t_cmb + rp.A * gauss21(sc.nu, rp);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
     // with amplitude masks the bound adds the row's largest 64 log2 alpha;
     // fl is monotone, so no region's rounded exponent exceeds it
     double ymax = AB ? ceil(fma(bext, nl, 64.0 * rp.omax)) : ceil(bext * nl);
     const int ey = (int)floor(ymax * (1.0 / 64.0));
     const int fm = (int)(ymax - 64.0 * ey);
-    double s0, s1, s2, t0 = 0.0;
-    int c0 = 0, c1 = 0;
+    C.ey = ey;
+    C.fm = fm;
+    C.t0 = 0.0;
+    C.c0 = C.c1 = 0;
+    C.qlast = 0.0;
     if constexpr (PROJ) {
-      const double u = ldexp(s_frac[fm], ey + ek + 72 - kProjBits - 39);
-      s0 = u * 0x1.0p-8;
-      s1 = u * 0x1.0p-24;
-      s2 = u * 0x1.0p-40;
-      t0 = m.dbar[fi] - m.sqrtT * c;               // target of the mean row
+      const double u = ldexp(s_frac[fm], ey + sc.ek + 72 - kProjBits - 39);
+      C.s0 = u * 0x1.0p-8;
+      C.s1 = u * 0x1.0p-24;
+      C.s2 = u * 0x1.0p-40;
+      C.t0 = m.dbar[fi] - m.sqrtT * c;             // target of the mean row
     } else {
-      int eu = ey + ek - 14;
+      int eu = ey + sc.ek - 14;
       double ic = c * ldexp(s_ifrac[fm], 8 - eu);   // ~ c / unit of acc0
       int ec;
       frexp(ic, &ec);                               // |ic| < 2^ec
-      if (ec > 29) {                                // constant term dominates:
-        ymax += 64.0 * (ec - 29);                   // coarser power-law digits
-        eu += ec - 29;
-        ic = ldexp(ic, 29 - ec);
-      }
+      // constant term dominates: coarser power-law digits (branch-free)
+      const int sh = max(ec - 29, 0);
+      ymax += 64.0 * sh;
+      eu += sh;
+      ic = ldexp(ic, -sh);
       const double u0 = ldexp(s_frac[fm], eu);
-      s0 = u0 * 0x1.0p-8;
-      s1 = u0 * 0x1.0p-24;
-      s2 = u0 * 0x1.0p-32;
+      C.s0 = u0 * 0x1.0p-8;
+      C.s1 = u0 * 0x1.0p-24;
+      C.s2 = u0 * 0x1.0p-32;
       const double c0f = rint(ic);
-      c0 = (int)c0f;
+      C.c0 = (int)c0f;
       // exact remainder (fma), then to level-3 units; c1 in [-2^15, 2^15]
-      c1 = (int)rint(fma(-c0f, s0, c) * ldexp(s_ifrac[fm], 24 - eu));
+      C.c1 = (int)rint(fma(-c0f, C.s0, c) * ldexp(s_ifrac[fm], 24 - eu));
     }
-
-    // power-law digits: the MFMA B operands of this lane (row b, 16 regions
-    // per 32-region chunk), five significance levels.  Exponents below the
-    // table (x < 2^-40, digits all zero) are clamped to its end; the clamp
-    // is skipped when no lane of the wave can reach it at this channel.
-    const double bfar = nl > 0.0 ? rp.bmin : rp.bmax;
-    const double ylow = (AB ? fma(bfar, nl, 64.0 * rp.omin) : bfar * nl) - ymax;
-    const bool clamp = __builtin_amdgcn_ballot_w64(ylow < -(double)kTabLo) != 0;
-    i32x4 Bop[KC][5];
-    double qlast = 0.0;                              // rounded power, last region
-    auto digits = [&](auto clamp_c) {
-    constexpr bool CL = decltype(clamp_c)::value;
+    // Powers 2^(y/64), y = 64 log2(x) <= 0, as tab[round(y)] 2^(r/64).
+    // Exponents below the table (x < 2^-40, all digits zero) take its last
+    // entry, which rounds to zero digits for any |r| <= 1/2.
+    const double cm = MAGIC - ymax;                 // exact: ymax is an integer
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       uint32_t lo[16], hi[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double y;                                  // 64 log2(x), <= 0
-        if constexpr (AB)
-          y = fma(beta[kc][j], nl, off[kc][j]) - ymax;
-        else
-          y = fma(beta[kc][j], nl, -ymax);
-        if (CL) y = fmax(y, -(double)kTabLo);
-        const double t = y + MAGIC;
-        const int jj = (int)(uint32_t)__double_as_longlong(t);
-        const double r = y - (t - MAGIC);          // |r| <= 1/2
+        double t, r;
+        if constexpr (AB) {
+          const double y = fma(beta[kc][j], nl, off[kc][j]) - ymax;
+          t = y + MAGIC;
+          r = y - (t - MAGIC);                     // |r| <= 1/2
+        } else {
+          // t = MAGIC + round(beta nl - ymax); u = that integer + ymax
+          // (exact, same binade); r = beta nl - u with one rounding
+          t = fma(beta[kc][j], nl, cm);
+          const double u = t - cm;
+          r = fma(beta[kc][j], nl, -u);            // |r| <= 1/2
+        }
+        const int jj = max((int)(uint32_t)__double_as_longlong(t), -kTabLo);
         const double T2 = s_tab0[jj];              // Q 2^(jj/64)
         double p = fma(r, m.c4, m.c3);
         p = fma(r, p, m.c2);
         p = fma(r, p, m.c1);
         p = fma(r, p, 1.0);                        // 2^(r/64)
         const double q = fma(T2, p, DIGITS);       // 2^52 + q + offsets
-        if (PROJ && kc == KC - 1 && j == 15) qlast = q - DIGITS;
+        if (PROJ && kc == KC - 1 && j == 15) C.qlast = q - DIGITS;
         const unsigned long long bits = __double_as_longlong(q);
         lo[j] = (uint32_t)bits ^ 0x80808080u;      // digits d4 d3 d2 d1
         hi[j] = (uint32_t)(bits >> 32);            // low byte: d0
@@ -275,106 +285,107 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
         transpose4(lo[4 * m4], lo[4 * m4 + 1], lo[4 * m4 + 2], lo[4 * m4 + 3], o);
         // o[L] holds byte (3 - L) of the low words: d(L+1)
 #pragma unroll
-        for (int L = 0; L < 4; ++L) Bop[kc][L + 1][m4] = (int32_t)o[L];
+        for (int L = 0; L < 4; ++L) C.B[kc][L + 1][m4] = (int32_t)o[L];
         const uint32_t h01 = __builtin_amdgcn_perm(hi[4 * m4 + 1], hi[4 * m4], 0x0c0c0400u);
         const uint32_t h23 = __builtin_amdgcn_perm(hi[4 * m4 + 3], hi[4 * m4 + 2], 0x0c0c0400u);
-        Bop[kc][0][m4] = (int32_t)(h01 | (h23 << 16));
+        C.B[kc][0][m4] = (int32_t)(h01 | (h23 << 16));
       }
     }
-    };
-    if (clamp)
-      digits(std::true_type{});
-    else
-      digits(std::false_type{});
+  };
 
+  auto load_A = [&](int f, int tt, i32x4 (&A)[ND][KC]) {
+    const unsigned char* kf = s_kd + (size_t)f * kbytes + lane * 16;
+#pragma unroll
+    for (int L = 0; L < ND; ++L)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc)
+        A[L][kc] = *reinterpret_cast<const i32x4*>(kf + ((L * KC + kc) * TT + tt) * 1024);
+  };
+#define MF(acc, q, p) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[q][kc], C.B[kc][p], acc, 0, 0, 0)
+  // levels 0, 2 and 4 (no dependence on a shift)
+  auto part1 = [&](const i32x4 (&A)[ND][KC], const Chan& C, i32x16& a0, i32x16& a1,
+                   i32x16& a2) {
+    a0 = i32x16{};
+    a1 = i32x16{};
+    a2 = i32x16{};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      MF(a0, 0, 0);
+      MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);
+      MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);
+      if constexpr (PROJ) MF(a2, 4, 0);
+    }
+  };
+  // shift-adds (direct form: with the constant term), then levels 1, 3
+  // (and 5 in the projected form)
+  auto part2 = [&](const i32x4 (&A)[ND][KC], const Chan& C, i32x16& a0, i32x16& a1,
+                   i32x16& a2) {
+    if constexpr (PROJ) {
+      a0 = (i32x16)((u32x16)a0 << 8u);
+      a1 = (i32x16)((u32x16)a1 << 8u);
+      a2 = (i32x16)((u32x16)a2 << 8u);
+    } else {
+      a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)C.c0);
+      a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)C.c1);
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      MF(a0, 0, 1); MF(a0, 1, 0);
+      MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);
+      if constexpr (PROJ) {
+        MF(a2, 1, 4); MF(a2, 2, 3); MF(a2, 3, 2); MF(a2, 4, 1); MF(a2, 5, 0);
+      }
+    }
+  };
+#undef MF
+  auto epi = [&](int f, int tt, const Chan& C, const i32x16& a0, const i32x16& a1,
+                 const i32x16& a2) {
+    const double* Dt = s_D + (size_t)f * TT * 32 + g * 4 + tt * 32;
+    if (!PROJ && tt == TT - 1 && (m.T & 31)) {     // ragged last tile (uniform)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double r = fma(-C.s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
+        r = fma(-C.s1, (double)a1[j], r);
+        r = fma(-C.s2, (double)a2[j], r);
+        const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
+        r = t < m.T ? r : 0.0;
+        if (j & 1) acc_b = fma(r, r, acc_b);
+        else acc_a = fma(r, r, acc_a);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double d = Dt[(j >> 2) * 8 + (j & 3)];
+        // projected form: row 0 (element 0 of the first tile in lanes
+        // 0..31) is the mean row, whose target depends on the row b
+        if (PROJ && j == 0) d = (tt == 0 && g == 0) ? C.t0 : d;
+        double r = fma(-C.s0, (double)a0[j], d);
+        r = fma(-C.s1, (double)a1[j], r);
+        r = fma(-C.s2, (double)a2[j], r);
+        if (j & 1) acc_b = fma(r, r, acc_b);
+        else acc_a = fma(r, r, acc_a);
+      }
+    }
+  };
+  // the row tiles of channel f, the peeled row, the partial
+  auto finish = [&](int f, const Chan& C) {
     // A wave finishes one row tile before the next; the other waves of its
     // SIMD overlap their vector work with its matrix work.
-    const unsigned char* kf = s_kd + (size_t)f * kbytes + lane * 16;
-    const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
-    auto load_A = [&](int tt, i32x4 (&A)[ND][KC]) {
-#pragma unroll
-      for (int L = 0; L < ND; ++L)
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-          A[L][kc] = *reinterpret_cast<const i32x4*>(kf + ((L * KC + kc) * TT + tt) * 1024);
-    };
-#define MF(acc, q, p) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[q][kc], Bop[kc][p], acc, 0, 0, 0)
-    // levels 0, 2 and 4 (no dependence on a shift)
-    auto part1 = [&](const i32x4 (&A)[ND][KC], i32x16& a0, i32x16& a1, i32x16& a2) {
-      a0 = i32x16{};
-      a1 = i32x16{};
-      a2 = i32x16{};
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        MF(a0, 0, 0);
-        MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);
-        MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);
-        if constexpr (PROJ) MF(a2, 4, 0);
-      }
-    };
-    // shift-adds (direct form: with the constant term), then levels 1, 3
-    // (and 5 in the projected form)
-    auto part2 = [&](const i32x4 (&A)[ND][KC], i32x16& a0, i32x16& a1, i32x16& a2) {
-      if constexpr (PROJ) {
-        a0 = (i32x16)((u32x16)a0 << 8u);
-        a1 = (i32x16)((u32x16)a1 << 8u);
-        a2 = (i32x16)((u32x16)a2 << 8u);
-      } else {
-        a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)c0);
-        a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)c1);
-      }
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        MF(a0, 0, 1); MF(a0, 1, 0);
-        MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);
-        if constexpr (PROJ) {
-          MF(a2, 1, 4); MF(a2, 2, 3); MF(a2, 3, 2); MF(a2, 4, 1); MF(a2, 5, 0);
-        }
-      }
-    };
-#undef MF
-    auto epi = [&](int tt, const i32x16& a0, const i32x16& a1, const i32x16& a2) {
-      const double* Dt = Df + tt * 32;
-      if (!PROJ && tt == TT - 1 && (m.T & 31)) {   // ragged last tile (uniform)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          double r = fma(-s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
-          r = fma(-s1, (double)a1[j], r);
-          r = fma(-s2, (double)a2[j], r);
-          const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
-          r = t < m.T ? r : 0.0;
-          if (j & 1) acc_b = fma(r, r, acc_b);
-          else acc_a = fma(r, r, acc_a);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          double d = Dt[(j >> 2) * 8 + (j & 3)];
-          // projected form: row 0 (element 0 of the first tile in lanes
-          // 0..31) is the mean row, whose target depends on the row b
-          if (PROJ && j == 0) d = (tt == 0 && g == 0) ? t0 : d;
-          double r = fma(-s0, (double)a0[j], d);
-          r = fma(-s1, (double)a1[j], r);
-          r = fma(-s2, (double)a2[j], r);
-          if (j & 1) acc_b = fma(r, r, acc_b);
-          else acc_a = fma(r, r, acc_a);
-        }
-      }
-    };
     for (int tt = 0; tt < TT; ++tt) {
       i32x4 A[ND][KC];
       i32x16 x0, x1, x2;
-      load_A(tt, A);
-      part1(A, x0, x1, x2);
-      part2(A, x0, x1, x2);
-      epi(tt, x0, x1, x2);
+      load_A(f, tt, A);
+      part1(A, C, x0, x1, x2);
+      part2(A, C, x0, x1, x2);
+      epi(f, tt, C, x0, x1, x2);
     }
     if constexpr (PROJ) {
       // peeled last row of R: R[N-1][N-1] P_{N-1}, P from the same rounding
       // (region N - 1 = 32 KC - 1 is element 15 of the last chunk, g = 1)
       if (m.peel) {
-        const double v = ldexp(s_frac[fm], ey - 39) * m.pk[2 * fi];
-        const double r = fma(-v, qlast, m.pk[2 * fi + 1]);
+        const int fi = f0 + f;
+        const double v = ldexp(s_frac[C.fm], C.ey - 39) * m.pk[2 * fi];
+        const double r = fma(-v, C.qlast, m.pk[2 * fi + 1]);
         acc_a = fma(r, g ? r : 0.0, acc_a);
       }
     }
@@ -386,6 +397,15 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       acc_a = 0.0;
       acc_b = 0.0;
     }
+  };
+
+  Scal sc = fetch(f0);
+  for (int f = 0; f < fn; ++f) {
+    const Scal cur = sc;
+    sc = fetch(f0 + f + 1);                        // one channel ahead
+    Chan C;
+    make(cur, f0 + f, C);
+    finish(f, C);
   }
 }
 

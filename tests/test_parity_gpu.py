@@ -288,6 +288,34 @@ def test_determinism_and_row_independence(fgl):
     other.close()
 
 
+def test_every_tile_same_bits(fgl):
+    """Every candidate tile (waves, channels per workgroup, register budget)
+    gives bitwise the same lnL, in each form and precision."""
+    cases = [("projected", workload.config(2, B=1024, batch="mixed"), 0),
+             ("direct", workload.config(2, B=1024, batch="mixed"), fgl.FGL_MIXED_DIRECT),
+             ("masks", workload.make_masks(2, 5, np.linspace(60.0, 190.0, 41), 40, 700, 31,
+                                           batch="mixed"), 0)]
+    for label, w, flags in cases:
+        m = fgl.Model.from_workload(w, flags)
+        for prec in PRECS:
+            ref, n = None, 0
+            for W in (4, 8):
+                for fc in (1, 2, 4, 8, 16, 32):
+                    for occ in (2, 3):
+                        try:
+                            m.set_tile(w.B, prec, W, fc, occ)
+                        except fgl.FGLError:
+                            continue
+                        got = m.loglike(w.theta, prec)
+                        if ref is None:
+                            ref = got
+                        assert np.array_equal(got, ref), (label, prec, W, fc, occ)
+                        n += 1
+            say(f"tiles {label}/{m.form}/{prec}: {n} candidates, same bits")
+            assert n >= 2
+        m.close()
+
+
 def test_device_entry_point_matches_host(fgl):
     import torch
     w = workload.config(2, B=2048, batch="mixed")
