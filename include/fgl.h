@@ -37,16 +37,22 @@
  *                   T >= N + 1, N <= 96 and it needs fewer 32-row tiles,
  *                   evaluates the time sum of each channel exactly in an
  *                   orthonormal basis of the channel's centred responses
- *                   (N + 1 rows instead of T).  Models with few time bins
- *                   (T <= 16, N <= 32; the paper's time-integrated fits
- *                   have T = 1) are evaluated per row in FP64 on the vector
- *                   units instead (FGL_FORM_THIN): the time bins would fill
- *                   only a sliver of a matrix tile, and FP64 meets the
- *                   bound exactly.  FGL_MIXED_DIRECT keeps the digit
- *                   kernel's direct form for them.
+ *                   (N + 1 rows instead of T).  Small models are
+ *                   evaluated per row in FP64 on the vector units instead
+ *                   (FGL_FORM_THIN): N <= 32, T <= 64 and a measured cost
+ *                   model of the two kernels favours it (S = N rounded up to
+ *                   4, 8, 12, 16, 24 or 32; thin when
+ *                   (S T + 12 S + 2 T) c(S) <= 650 for T <= 32 or 580
+ *                   above, with c(24) = 1.17, c(32) = 0.90, c(12) = 0.97,
+ *                   else 1: e.g. N <= 32 at T <= 8, N <= 16 at T <= 24,
+ *                   N <= 8 at T <= 46; the paper's time-integrated fits
+ *                   have T = 1).
+ *                   There the matrix tiles would be mostly padding, and FP64
+ *                   meets the bound exactly.  FGL_MIXED_DIRECT keeps the
+ *                   digit kernel's direct form for them.
  *   FGL_PREC_FP32   the model in FP32, residual and chi-square in FP64.
  *   FGL_PREC_FP64   everything in FP64 (per row on the vector units for the
- *                   models with few time bins described above).
+ *                   small models described above).
  *
  * Errors: every call returns an FGL_* status; fgl_last_error() gives a
  * message for the calling thread's last failure.  Nothing is ever printed.

@@ -787,7 +787,7 @@ static int create_model(const float* K, const double* freqs, const double* data,
   d.KC = (N + 31) / 32;
   d.NP2 = fp32_slots(N);
   d.NQ = fp64_slots(N);
-  d.thin = (T <= kThinMaxT && N <= kThinMaxN) ? 1 : 0;
+  d.thin = thin_model(N, T) ? 1 : 0;
   d.NT = d.thin ? thin_slots(N) : 0;
   d.t_cmb = t_cmb;
   d.flags = flags;

@@ -53,18 +53,35 @@ inline int fp64_slots(int N) {
   return 0;
 }
 
-// Kernel families behind one entry point.  kThin: models with few time bins
-// (T <= kThinMaxT, N <= kThinMaxN), evaluated per row in FP64 on the vector
-// units; used for the mixed and FP64 precisions of such models.
+// Kernel families behind one entry point.  kThin: small models evaluated
+// per row in FP64 on the vector units; used for the mixed and FP64
+// precisions of such models (thin_model below).
 enum Kind { kMixed = 0, kFP32 = 1, kFP64 = 2, kThin = 3 };
-constexpr int kThinMaxT = 16;
+constexpr int kThinMaxT = 64;
 constexpr int kThinMaxN = 32;
+constexpr int kThinCostDirect = 650;
+constexpr int kThinCostProj = 580;
 
 // Compiled region counts of the thin kernel (regions >= N have K = 0).
 inline int thin_slots(int N) {
   for (int s : {4, 8, 12, 16, 24, 32})
     if (N <= s) return s;
   return 0;
+}
+
+// A row and channel cost the thin kernel about NT T + 12 NT + 2 T vector
+// operations per lane (NT region slots: the model sums, the powers, the
+// residuals), scaled by what the compiled slot count measured per operation
+// (percent; 24 slots spill into more registers, 32 unroll best).  The digit
+// kernel costs the same whatever the shape below one tile: its direct form
+// (T <= 32) matched ~650 such operations, its projected form (always taken
+// for 32 < T <= 64 since T > N) ~580.
+inline int thin_scale(int nt) { return nt == 24 ? 117 : nt == 32 ? 90 : nt == 12 ? 97 : 100; }
+inline bool thin_model(int N, int T) {
+  const int nt = thin_slots(N);
+  if (nt == 0 || T > kThinMaxT) return false;
+  const int ops = nt * T + 12 * nt + 2 * T;
+  return ops * thin_scale(nt) <= (T <= 32 ? kThinCostDirect : kThinCostProj) * 100;
 }
 
 // Tile configuration of one launch (chosen by the tuner).
@@ -123,7 +140,7 @@ struct DevModel {
   int RT16;              // 16-row tiles of the N + 1 rows
   const double* pa64;    // [F][NQ][RT16][64]: lane -> (row 16 tt + lane%16, region 4 q + lane/16)
   const double* pt64;    // [F][RT16*16] targets: row 0 sqrt(T) mean_t D, rows 1.. z
-  // thin models (T <= kThinMaxT, N <= kThinMaxN)
+  // thin models (thin_model(N, T))
   int thin;              // 1: mixed (unless the direct form is forced) and FP64 use k_thin64
   int NT;                // regions rounded up to a compiled count
   const float* kthin;    // [F][T][NT] K, zero padded in regions

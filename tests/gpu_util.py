@@ -27,6 +27,17 @@ def lib():
     return fgl
 
 
+def thin_form(N: int, T: int) -> bool:
+    """Whether the library evaluates a model per row in FP64 (its thin
+    form): N <= 32, T <= 64 and the cost rule documented with
+    FGL_FORM_THIN in include/fgl.h."""
+    slots = next((s for s in (4, 8, 12, 16, 24, 32) if N <= s), None)
+    if slots is None or T > 64:
+        return False
+    scale = {24: 117, 32: 90, 12: 97}.get(slots, 100)
+    return (slots * T + 12 * slots + 2 * T) * scale <= (650 if T <= 32 else 580) * 100
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workload
-from tests.gpu_util import check, lib, say
+from tests.gpu_util import check, lib, say, thin_form
 
 pytestmark = pytest.mark.gpu
 
@@ -121,20 +121,20 @@ def test_large_config_subsample(fgl, orc):
     (7, 1, 96, 512), (12, 40, 130, 129), (32, 6, 40, 100), (32, 5, 33, 64),
     (40, 9, 96, 200), (70, 4, 100, 50), (96, 3, 130, 40), (1, 3, 50, 65),
     (8, 9, 16, 300), (17, 5, 3, 70), (32, 7, 16, 257), (31, 4, 9, 33), (33, 5, 2, 40),
-    (11, 6, 5, 90), (14, 5, 12, 66)])
+    (11, 6, 5, 90), (14, 5, 12, 66), (16, 7, 25, 70), (8, 5, 48, 90), (4, 3, 64, 40),
+    (20, 5, 10, 33)])
 def test_shapes_and_ragged_tails(fgl, orc, N, F, T, B):
     """Region chunks (N over 32), ragged time tiles, ragged batches, a single
     channel, a single row, with chromatic K and mixed prior/shell rows; the
     mixed evaluation in both forms wherever the projected one applies
     (T >= N + 1 with fewer row tiles; with and without the peeled row), and
-    the per-row FP64 form of models with few time bins (T <= 16, N <= 32)
-    beside the forced direct form."""
+    the per-row FP64 form of small models beside the forced direct form."""
     freqs = np.linspace(55.0, 190.0, F) if F > 1 else np.array([123.0])
     w = workload.make(N, freqs, T, B, 1000 + N * 7 + T, chroma=0.05, batch="mixed")
     say(f"shape N={N} F={F} T={T} B={B}")
     ref = orc.loglike_w(w)
     proj = T >= N + 1 and N <= 96 and (N + 1 - (N % 32 == 0) + 31) // 32 < (T + 31) // 32
-    thin = T <= 16 and N <= 32
+    thin = thin_form(N, T)
     _mixed_forms(fgl, w, w.theta, ref, f"N{N}F{F}T{T}B{B}",
                  expect="thin" if thin else ("projected" if proj else "direct"))
     m = _model(fgl, w)
@@ -207,7 +207,7 @@ def test_edge_rows_projected_form(fgl, orc):
     after centring), data constant in time, T = N + 1, and the invalid and
     extreme rows of the direct-form edge test."""
     rng = np.random.Generator(np.random.PCG64(78))
-    for N, T in ((6, 40), (32, 33), (33, 96)):
+    for N, T in ((6, 70), (32, 33), (33, 96)):
         F = 7
         freqs = np.linspace(60.0, 180.0, F)
         K = rng.lognormal(2.0, 0.5, size=(N, F, T)).astype(np.float32)
@@ -237,7 +237,7 @@ def test_nesting_projected_form(fgl, orc):
     """Strict nesting through the projected form: splitting a region into
     two halves with the same spectral index leaves lnL unchanged (the split
     model is rank-deficient)."""
-    w = workload.make(8, np.linspace(50.0, 200.0, 31), 48, 256, 4242, chroma=0.05, batch="mixed")
+    w = workload.make(8, np.linspace(50.0, 200.0, 31), 72, 256, 4242, chroma=0.05, batch="mixed")
     K2 = np.concatenate([w.K[:3], w.K[3:4] * np.float32(0.5), w.K[3:4] * np.float32(0.5), w.K[4:]])
     th2 = np.concatenate([w.theta[:, :4], w.theta[:, 3:4], w.theta[:, 4:]], axis=1)
     ref = orc.loglike_w(w)
@@ -286,6 +286,27 @@ def test_determinism_and_row_independence(fgl):
         assert np.array_equal(m.loglike(w.theta, prec), a), f"{prec}: tile changed bits"
     m.close()
     other.close()
+
+
+def test_form_rule(fgl):
+    """The library's choice of form follows the documented rule over a grid
+    of (N, T): thin by the cost rule, else projected when N + 1 rows take
+    fewer 32-row tiles than T, else direct."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    freqs = np.array([70.0, 150.0])
+    n = 0
+    for N in (1, 3, 4, 5, 8, 9, 12, 13, 16, 17, 20, 24, 25, 31, 32, 33):
+        for T in (1, 6, 8, 9, 10, 20, 25, 26, 32, 33, 40, 48, 49, 58, 64, 65):
+            K = rng.uniform(0.5, 2.0, size=(N, 2, T)).astype(np.float32)
+            D = rng.normal(100.0, 1.0, size=(2, T))
+            m = fgl.Model(K, freqs, D, 230.0, 2.725)
+            peel = 1 if N % 32 == 0 else 0
+            proj = T >= N + 1 and (N + 1 - peel + 31) // 32 < (T + 31) // 32
+            want = "thin" if thin_form(N, T) else ("projected" if proj else "direct")
+            assert m.form == want, (N, T, m.form, want)
+            m.close()
+            n += 1
+    say(f"form rule: {n} models")
 
 
 def test_every_tile_same_bits(fgl):
