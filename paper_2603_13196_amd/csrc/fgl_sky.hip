@@ -109,24 +109,27 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
     const int* sg = MODE == kCorrK ? seg + (size_t)ring * (NJ + 1) : nullptr;
     const int k0 = MODE == kCorrK ? sg[j0] : 0;
     const int kn = (MODE == kCorrK ? sg[j0 + nj] : L) - k0;
-    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-      if constexpr (MODE == kCorrK) {
-        s_idx[k] = order[(size_t)ring * L + k0 + k];
-        s_a[k] = asort[(size_t)ring * L + k0 + k];
-      } else {
+    if constexpr (MODE != kCorrK) {
+      for (int k = threadIdx.x; k < kn; k += blockDim.x) {
         s_idx[k] = k < nlon ? k : 0;
         s_a[k] = k < nlon ? aval<MODE>(s, f, ring, k) : 0.0;
       }
+      for (int j = threadIdx.x; j <= nj; j += blockDim.x) s_seg[j] = j == 0 ? 0 : L;
     }
-    for (int j = threadIdx.x; j <= nj; j += blockDim.x)
-      s_seg[j] = MODE == kCorrK ? sg[j0 + j] - k0 : (j == 0 ? 0 : L);
     __syncthreads();
     if (!live) continue;
     const float* bo = s_b + o;
+    // K: the ring's columns and weights are read straight from global
+    // memory at wave-uniform addresses (scalar loads, no LDS traffic); Z
+    // uses the staged copies
+    const int* gidx = MODE == kCorrK ? order + (size_t)ring * L + k0 : nullptr;
+    const double* ga = MODE == kCorrK ? asort + (size_t)ring * L + k0 : nullptr;
     for (int j = 0; j < nj; ++j) {
-      const int k1 = s_seg[j + 1];
-      int k = s_seg[j];
+      const int k1 = MODE == kCorrK ? sg[j0 + j + 1] - k0 : s_seg[j + 1];
+      int k = MODE == kCorrK ? sg[j0 + j] - k0 : s_seg[j];
       if (k == k1) continue;
+      const int* xi = MODE == kCorrK ? gidx : s_idx;
+      const double* xa = MODE == kCorrK ? ga : s_a;
       double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       // software pipelined: the next group's columns and weights are read
       // while the current group's beam values are gathered
@@ -134,8 +137,8 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
       double av[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        id[u] = s_idx[k + u];
-        av[u] = s_a[k + u];
+        id[u] = xi[k + u];
+        av[u] = xa[k + u];
       }
       for (; k < k1; k += 8) {
         float bv[8];
@@ -145,8 +148,8 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           c[u] = fma(av[u], (double)bv[u], c[u]);
-          id[u] = s_idx[kn + u];
-          av[u] = s_a[kn + u];
+          id[u] = xi[kn + u];
+          av[u] = xa[kn + u];
         }
       }
       s_acc[(size_t)j * blockDim.x + tl] += ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
