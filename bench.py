@@ -39,7 +39,9 @@ def parse():
     # region ~100 ms of the headline call
     p.add_argument("--steps", type=int, default=500)
     p.add_argument("--warmup", type=int, default=300)
-    p.add_argument("--workload", type=int, default=2, choices=[0, 1, 2, 4])
+    p.add_argument("--workload", default="N32_F301_T96_B16384",
+                   choices=["N4_F151_T1_B1000", "N16_F151_T20_B4096", "N32_F301_T96_B16384",
+                            "N64_F401_T240_B65536"])
     p.add_argument("--no-serve", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
@@ -224,7 +226,7 @@ def small_batch_leg(fgl, calls=200):
     import torch
     import workload
     out = {}
-    for k in (0, 1):
+    for k in (workload.SMALL, workload.MEDIUM):
         w = workload.config(k)
         m = fgl.Model.from_workload(w)
         th = torch.from_numpy(w.theta).cuda()

@@ -120,7 +120,7 @@ def test_grad_headline_sampled(fgl, orc):
     point; the oracle on 48 sampled prior rows and 16 posterior-shell rows;
     host and device entry points agree bitwise."""
     import torch
-    w = workload.config(2)
+    w = workload.config(workload.HEADLINE)
     m = fgl.Model.from_workload(w)
     th = torch.from_numpy(w.theta).cuda()
     out, grad = m.loglike_grad_device(th)
@@ -129,18 +129,18 @@ def test_grad_headline_sampled(fgl, orc):
     rng = np.random.Generator(np.random.PCG64(12))
     idx = np.sort(rng.choice(w.B, 48, replace=False))
     rl, rg = orc.grad_w(w, w.theta[idx])
-    check(out[idx], rl, "fp64", "cfg2/grad-sampled", w.theta[idx], w.F * w.T)
-    check_grad(grad[idx], rg, term_scale(orc, w, w.theta[idx]), "cfg2/grad-sampled")
+    check(out[idx], rl, "fp64", "headline/grad-sampled", w.theta[idx], w.F * w.T)
+    check_grad(grad[idx], rg, term_scale(orc, w, w.theta[idx]), "headline/grad-sampled")
     hl, hg = m.loglike_grad(w.theta[idx])
     assert np.array_equal(hl, out[idx]) and np.array_equal(hg, grad[idx])
-    sh = workload.posterior_shell(2, 16)
+    sh = workload.posterior_shell(workload.HEADLINE, 16)
     rl, rg = orc.grad_w(sh)
     sc = term_scale(orc, sh, sh.theta)
     assert m.form == "projected"
     for mm in (m, fgl.Model.from_workload(sh, fgl.FGL_MIXED_DIRECT)):
         sl, sg = mm.loglike_grad(sh.theta)
-        check(sl, rl, "fp64", f"cfg2/grad-shell/{mm.form}", sh.theta, sh.F * sh.T)
-        check_grad(sg, rg, sc, f"cfg2/grad-shell/{mm.form}")
+        check(sl, rl, "fp64", f"headline/grad-shell/{mm.form}", sh.theta, sh.F * sh.T)
+        check_grad(sg, rg, sc, f"headline/grad-shell/{mm.form}")
         mm.close()
 
 

@@ -18,7 +18,7 @@ def test_pin(orc, pin):
 def test_threads_do_not_change_results(orc):
     import numpy as np
     import workload
-    w = workload.config(1, B=64)
+    w = workload.config(workload.MEDIUM, B=64)
     a = orc.loglike_w(w, threads=1)
     b = orc.loglike_w(w, threads=4)
     assert np.array_equal(a, b)
@@ -30,7 +30,7 @@ def test_workload_truth_is_near_best_fit(orc):
     mismatch of the sky simulation is far below the 25 mK noise)."""
     import numpy as np
     import workload
-    w = workload.config(0, B=8)
+    w = workload.config(workload.SMALL, B=8)
     th = w.truth[None, :]
     ll = orc.loglike_w(w, th)[0]
     n = w.F * w.T

@@ -44,10 +44,10 @@ def _mixed_forms(fgl, w, theta, ref, label, expect=None):
         m.close()
 
 
-@pytest.mark.parametrize("k", [0, 1])
-def test_small_configs_all_rows(fgl, orc, k):
-    """Workloads 0 (N=4, F=151, T=1) and 1 (N=16, F=151, T=20): every row of
-    the prior batch and of a 1024-row posterior shell."""
+@pytest.mark.parametrize("k", [workload.SMALL, workload.MEDIUM])
+def test_small_workloads_all_rows(fgl, orc, k):
+    """The small workloads (N=4, F=151, T=1 and N=16, F=151, T=20): every row
+    of the prior batch and of a 1024-row posterior shell."""
     for kind in ("prior", "shell"):
         w = workload.config(k) if kind == "prior" else workload.posterior_shell(k)
         say(f"workload {k} {kind}: N={w.N} F={w.F} T={w.T} B={w.B}")
@@ -59,21 +59,21 @@ def test_small_configs_all_rows(fgl, orc, k):
                 d = np.abs(got - ref)
                 say(f"  fp32 shell (reported, not asserted): max|d|={d.max():.3e}")
                 continue
-            check(got, ref, prec, f"cfg{k}/{kind}", w.theta, w.F * w.T)
+            check(got, ref, prec, f"{k}/{kind}", w.theta, w.F * w.T)
         m.close()
 
 
 def test_headline_shape_reduced_batch(fgl, orc):
     """N=32, F=301, T=96 (the headline shape): 1024 prior rows and the
     1024-row posterior shell, every row."""
-    wp = workload.config(2, B=1024)
-    ws = workload.posterior_shell(2, 1024)
-    say(f"workload 2 reduced: N={wp.N} F={wp.F} T={wp.T}")
+    wp = workload.config(workload.HEADLINE, B=1024)
+    ws = workload.posterior_shell(workload.HEADLINE, 1024)
+    say(f"headline workload reduced: N={wp.N} F={wp.F} T={wp.T}")
     m = _model(fgl, wp)
     for w, kind in ((wp, "prior"), (ws, "shell")):
         ref = orc.loglike_w(w)
-        _mixed_forms(fgl, w, w.theta, ref, f"cfg2/{kind}", expect="projected")
-        check(m.loglike(w.theta, "fp64"), ref, "fp64", f"cfg2/{kind}", w.theta, w.F * w.T)
+        _mixed_forms(fgl, w, w.theta, ref, f"headline/{kind}", expect="projected")
+        check(m.loglike(w.theta, "fp64"), ref, "fp64", f"headline/{kind}", w.theta, w.F * w.T)
         got32 = m.loglike(w.theta, "fp32")
         d = np.abs(got32 - ref)
         say(f"  fp32 {kind}: max|d|={d.max():.3e} "
@@ -84,35 +84,35 @@ def test_headline_shape_reduced_batch(fgl, orc):
 def test_headline_full_batch_sampled(fgl, orc):
     """Full N=32, F=301, T=96, B=16384 call (the benchmark's launch), with
     the oracle on 512 sampled rows, plus a full posterior shell."""
-    w = workload.config(2)
-    say(f"workload 2 full: B={w.B}")
+    w = workload.config(workload.HEADLINE)
+    say(f"headline workload full: B={w.B}")
     m = _model(fgl, w)
     rng = np.random.Generator(np.random.PCG64(5))
     idx = np.sort(rng.choice(w.B, 512, replace=False))
     ref = orc.loglike_w(w, w.theta[idx])
     for prec in ("mixed", "fp64"):
         got = m.loglike(w.theta, prec)
-        check(got[idx], ref, prec, "cfg2/full-sampled", w.theta[idx], w.F * w.T)
+        check(got[idx], ref, prec, "headline/full-sampled", w.theta[idx], w.F * w.T)
     m.close()
 
 
-def test_large_config_subsample(fgl, orc):
+def test_large_workload_subsample(fgl, orc):
     """N=64, F=401, T=240, B=65536: full launch, oracle on 256 rows."""
-    w = workload.config(4)
-    say(f"workload 4: N={w.N} F={w.F} T={w.T} B={w.B}")
+    w = workload.config(workload.LARGE)
+    say(f"large workload: N={w.N} F={w.F} T={w.T} B={w.B}")
     m = _model(fgl, w)
     rng = np.random.Generator(np.random.PCG64(9))
     idx = np.sort(rng.choice(w.B, 256, replace=False))
     ref = orc.loglike_w(w, w.theta[idx])
     assert m.form == "projected"
     got = m.loglike(w.theta, "mixed")
-    check(got[idx], ref, "mixed", "cfg4/sampled")
+    check(got[idx], ref, "mixed", "large/sampled")
     m.close()
     md = _model(fgl, w, fgl.FGL_MIXED_DIRECT)
-    check(md.loglike(w.theta, "mixed")[idx], ref, "mixed", "cfg4/sampled/direct")
+    check(md.loglike(w.theta, "mixed")[idx], ref, "mixed", "large/sampled/direct")
     md.close()
-    sh = workload.posterior_shell(4, 256)
-    _mixed_forms(fgl, sh, sh.theta, orc.loglike_w(sh), "cfg4/shell", expect="projected")
+    sh = workload.posterior_shell(workload.LARGE, 256)
+    _mixed_forms(fgl, sh, sh.theta, orc.loglike_w(sh), "large/shell", expect="projected")
 
 
 @pytest.mark.parametrize("N,F,T,B", [
@@ -251,7 +251,7 @@ def test_nesting_projected_form(fgl, orc):
     m2.close()
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [workload.MEDIUM, workload.HEADLINE])
 def test_no_21cm_flag(fgl, orc, k):
     w = workload.config(k, B=512)
     th = np.concatenate([w.theta[:, :w.N], w.theta[:, -1:]], axis=1)
@@ -268,14 +268,14 @@ def test_determinism_and_row_independence(fgl):
     """Bitwise: repeated calls (eager, then graph capture, then replays with
     other work in between), one row alone vs inside a large batch, batch
     permutation, and tuned vs default tiles."""
-    w = workload.config(2, B=4096, batch="mixed")
+    w = workload.config(workload.HEADLINE, B=4096, batch="mixed")
     m = _model(fgl, w)
-    other = _model(fgl, workload.config(1, B=64))
+    other = _model(fgl, workload.config(workload.MEDIUM, B=64))
     for prec in PRECS:
         say(f"determinism {prec}")
         a = m.loglike(w.theta, prec)
         for rep in range(4):
-            other.loglike(workload.config(1, B=64).theta, prec)
+            other.loglike(workload.config(workload.MEDIUM, B=64).theta, prec)
             b = m.loglike(w.theta, prec)
             assert np.array_equal(a, b), (prec, rep)
         one = m.loglike(w.theta[123:124], prec)
@@ -312,8 +312,8 @@ def test_form_rule(fgl):
 def test_every_tile_same_bits(fgl):
     """Every candidate tile (waves, channels per workgroup, register budget)
     gives bitwise the same lnL, in each form and precision."""
-    cases = [("projected", workload.config(2, B=1024, batch="mixed"), 0),
-             ("direct", workload.config(2, B=1024, batch="mixed"), fgl.FGL_MIXED_DIRECT),
+    cases = [("projected", workload.config(workload.HEADLINE, B=1024, batch="mixed"), 0),
+             ("direct", workload.config(workload.HEADLINE, B=1024, batch="mixed"), fgl.FGL_MIXED_DIRECT),
              ("masks", workload.make_masks(2, 5, np.linspace(60.0, 190.0, 41), 40, 700, 31,
                                            batch="mixed"), 0)]
     for label, w, flags in cases:
@@ -339,7 +339,7 @@ def test_every_tile_same_bits(fgl):
 
 def test_device_entry_point_matches_host(fgl):
     import torch
-    w = workload.config(2, B=2048, batch="mixed")
+    w = workload.config(workload.HEADLINE, B=2048, batch="mixed")
     m = _model(fgl, w)
     th = torch.from_numpy(w.theta).to("cuda")
     for prec in PRECS:
@@ -356,7 +356,7 @@ def test_device_entry_point_matches_host(fgl):
 
 
 def test_errors_and_zero_rows(fgl):
-    w = workload.config(0, B=8)
+    w = workload.config(workload.SMALL, B=8)
     m = _model(fgl, w)
     assert m.loglike(np.zeros((0, m.P))).shape == (0,)
     with pytest.raises(fgl.FGLError) as e:

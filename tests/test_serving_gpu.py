@@ -124,7 +124,7 @@ def test_forced_failure_is_reported(fgl, monkeypatch):
     """The request named by FGL_SERVE_FAIL_TICKET fails from the host; the
     others complete normally."""
     monkeypatch.setenv("FGL_SERVE_FAIL_TICKET", "3")
-    w = workload.config(1, B=1024)
+    w = workload.config(workload.MEDIUM, B=1024)
     m = fgl.Model.from_workload(w)
     srv = fgl.Server(max_inflight=2)
     tickets = [srv.submit(m, w.theta[k * 100:(k + 1) * 100]) for k in range(6)]
@@ -142,9 +142,9 @@ def test_destroy_while_busy(fgl):
     """fgl_model_destroy and fgl_serve_destroy return FGL_EBUSY, freeing
     nothing, while requests on them are queued or running; after a drain
     both succeed and completions stay pollable until then."""
-    wl = workload.config(4, B=65536)
+    wl = workload.config(workload.LARGE, B=65536)
     blocker = fgl.Model.from_workload(wl)
-    ws = workload.config(0, B=256)
+    ws = workload.config(workload.SMALL, B=256)
     small = fgl.Model.from_workload(ws)
     srv = fgl.Server(max_inflight=1)
     # one slot: the small model's request waits behind the large launches
@@ -163,7 +163,7 @@ def test_destroy_while_busy(fgl):
 
 
 def test_serving_argument_errors(fgl):
-    w = workload.config(0, B=8)
+    w = workload.config(workload.SMALL, B=8)
     m = fgl.Model.from_workload(w)
     with pytest.raises(fgl.FGLError):
         fgl.Server(max_inflight=0)

@@ -214,21 +214,19 @@ def make(N: int, freqs: np.ndarray, T: int, B: int, seed: int, *,
                     np.ascontiguousarray(theta), truth, nu_ref, t_cmb)
 
 
-# The five benchmark workloads (0-based index k): shapes, grids and batch
-# sizes of the small plain-FP64 case, the plain-FP32 case, the mixed
-# precision headline case, the serving mix and the large case.
-CONFIGS = {
-    0: dict(N=4, grid=(50.0, 200.0, 1.0), T=1, B=1000, t_mod=0.0),
-    1: dict(N=16, grid=(50.0, 200.0, 1.0), T=20, B=4096, t_mod=0.3),
-    2: dict(N=32, grid=(50.0, 200.0, 0.5), T=96, B=16384, t_mod=0.3),
-    4: dict(N=64, grid=(50.0, 250.0, 0.5), T=240, B=65536, t_mod=0.3),
-}
-
-CONFIG_NAMES = {
-    0: "N4_F151_T1_B1000",
-    1: "N16_F151_T20_B4096",
-    2: "N32_F301_T96_B16384",
-    4: "N64_F401_T240_B65536",
+# The benchmark workloads by name: the small plain-FP64 case, the plain-FP32
+# case, the mixed-precision headline case and the large case, each with its
+# own seed (the serving mix, seed SEED_BASE + 3, is drawn by
+# serving_clients).
+SMALL = "N4_F151_T1_B1000"
+MEDIUM = "N16_F151_T20_B4096"
+HEADLINE = "N32_F301_T96_B16384"
+LARGE = "N64_F401_T240_B65536"
+WORKLOADS = {
+    SMALL: dict(N=4, grid=(50.0, 200.0, 1.0), T=1, B=1000, t_mod=0.0, seed=SEED_BASE + 0),
+    MEDIUM: dict(N=16, grid=(50.0, 200.0, 1.0), T=20, B=4096, t_mod=0.3, seed=SEED_BASE + 1),
+    HEADLINE: dict(N=32, grid=(50.0, 200.0, 0.5), T=96, B=16384, t_mod=0.3, seed=SEED_BASE + 2),
+    LARGE: dict(N=64, grid=(50.0, 250.0, 0.5), T=240, B=65536, t_mod=0.3, seed=SEED_BASE + 4),
 }
 
 
@@ -289,23 +287,24 @@ MASKS_NAME = "A2xB16_F301_T96_B16384"
 
 
 def masks_config(*, B: int = 16384, batch: str = "prior") -> Workload:
-    c = CONFIGS[2]
+    c = WORKLOADS[HEADLINE]
     return make_masks(2, 16, freq_grid(*c["grid"]), c["T"], B, SEED_BASE + 5,
                       t_mod=c["t_mod"], batch=batch, name=MASKS_NAME)
 
 
-def config(k: int, *, B: Optional[int] = None, batch: str = "prior",
+def config(name: str, *, B: Optional[int] = None, batch: str = "prior",
            chroma: float = 0.0) -> Workload:
-    c = CONFIGS[k]
+    """The named benchmark workload (SMALL, MEDIUM, HEADLINE or LARGE),
+    optionally with another batch size or batch kind."""
+    c = WORKLOADS[name]
     freqs = freq_grid(*c["grid"])
     return make(c["N"], freqs, c["T"], c["B"] if B is None else B,
-                SEED_BASE + k, t_mod=c["t_mod"], chroma=chroma, batch=batch,
-                name=CONFIG_NAMES[k])
+                c["seed"], t_mod=c["t_mod"], chroma=chroma, batch=batch, name=name)
 
 
-def posterior_shell(k: int, B: int = 1024) -> Workload:
-    """Workload k with its theta batch replaced by a posterior shell."""
-    return config(k, B=B, batch="shell")
+def posterior_shell(name: str, B: int = 1024) -> Workload:
+    """The named workload with its theta batch replaced by a posterior shell."""
+    return config(name, B=B, batch="shell")
 
 
 @dataclasses.dataclass
