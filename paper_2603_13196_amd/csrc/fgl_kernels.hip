@@ -33,7 +33,7 @@
 //   k_fp32:  the model in FP32 (v_mfma_f32_32x32x2_f32, FP32 powers),
 //            residual and chi-square in FP64.
 //   k_fp64:  the model in FP64 (v_mfma_f64_16x16x4_f64, FP64 powers).
-//   k_thin64: models with few time bins (T <= 16, N <= 32), where a matrix
+//   k_thin64: small models (few time bins and regions), where a matrix
 //            tile would be mostly padding: each lane evaluates its row's
 //            model values as FP64 sums on the vector units.
 #include "fgl_internal.h"
@@ -570,8 +570,9 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 // ---------------------------------------------------------------------------
 // thin models: FP64 on the vector units
 //
-// With T <= kThinMaxT the time bins fill only a sliver of an MFMA tile, so
-// the model is evaluated per parameter row on the vector units: one lane per
+// For small models (thin_model: few time bins and regions) the matrix tiles
+// would be mostly padding, so the model is evaluated per parameter row on
+// the vector units: one lane per
 // row, the channel's N powers in FP64, then for each time bin the region sum
 // (ascending i), the residual and the chi-square, all in FP64.  A power
 // 2^y is 2^(j/64) 2^(r/64) with j = round(64 y): 2^floor(j/64) by ldexp,
