@@ -572,9 +572,9 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 //
 // For small models (thin_model: few time bins and regions) the matrix tiles
 // would be mostly padding, so the model is evaluated per parameter row on
-// the vector units: one lane per
-// row, the channel's N powers in FP64, then for each time bin the region sum
-// (ascending i), the residual and the chi-square, all in FP64.  A power
+// the vector units: one lane per row, the channel's N powers in FP64, then
+// for each time bin the region sum (ascending i), the residual and the
+// chi-square, all in FP64.  A power
 // 2^y is 2^(j/64) 2^(r/64) with j = round(64 y): 2^floor(j/64) by ldexp,
 // 2^((j mod 64)/64) from a 64-entry LDS table and 2^(r/64), |r| <= 1/2, by
 // its Taylor series to fifth order (truncation below 4e-17 relative).  K and
