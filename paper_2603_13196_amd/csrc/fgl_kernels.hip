@@ -101,6 +101,26 @@ __device__ inline double gauss21(double nu, const RowParams& rp) {
   return (double)__builtin_amdgcn_exp2f(-0.7213475204444817f * z * z);
 }
 
+// FP64 powers of the plain-FP64, thin and gradient kernels: 2^(y/64) for
+// |y| < 2^31 as 2^floor(j/64) (ldexp) times 2^((j mod 64)/64) from the
+// 64-entry LDS table t64 times 2^(r/64), j = round(y), |r| <= 1/2, by its
+// Taylor series to fifth order (truncation below 4e-17 relative).
+__device__ inline void init_t64(double* t64) {
+  if (threadIdx.x < 64) t64[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+}
+__device__ inline double pow2_64(double y, const double* t64, const DevModel& m) {
+  const double MAGIC = 0x1.8p52;                  // rint via the low word
+  const double t = y + MAGIC;
+  const int j = (int)(uint32_t)__double_as_longlong(t);
+  const double r = y - (t - MAGIC);               // |r| <= 1/2
+  double p = fma(r, m.c5, m.c4);
+  p = fma(r, p, m.c3);
+  p = fma(r, p, m.c2);
+  p = fma(r, p, m.c1);
+  p = fma(r, p, 1.0);
+  return ldexp(t64[j & 63] * p, j >> 6);
+}
+
 // ---------------------------------------------------------------------------
 // mixed: exact int8 slices on MFMA
 //
@@ -506,32 +526,35 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
   const int kdl = NQB * TT16 * 64;          // values per channel
-  float* s_k = reinterpret_cast<float*>(smem);
-  double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kdl * 4);
+  double* s_t64 = reinterpret_cast<double*>(smem);                  // [64] 2^(m/64)
+  float* s_k = reinterpret_cast<float*>(smem + 512);
+  double* s_D = reinterpret_cast<double*>(smem + 512 + (size_t)fc * kdl * 4);
   stage(s_k, m.k64 + (size_t)f0 * kdl, fn * kdl * 4);
   stage(s_D, m.D + (size_t)f0 * m.TT * 32, fn * m.TT * 32 * 8);
+  init_t64(s_t64);
   __syncthreads();
 
   const int g = lane >> 4;                  // 0..3
   const int b = bt * (W * 16) + wave * 16 + (lane & 15);
   const RowParams rp = w.rows[b];
   double beta[NQB];
-  double off[AB ? NQB : 1];                   // log2 alpha (AB)
+  double off[AB ? NQB : 1];                   // 64 log2 alpha (AB)
 #pragma unroll
   for (int k = 0; k < NQB; ++k) {
     const int i = 4 * k + g;
     beta[k] = i < N ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
-    if constexpr (AB) off[k] = i < N ? w.offT[(size_t)i * w.Bpad + b] : 0.0;
+    if constexpr (AB) off[k] = i < N ? 64.0 * w.offT[(size_t)i * w.Bpad + b] : 0.0;
   }
   double acc0 = 0.0, acc1 = 0.0;
   for (int f = 0; f < fn; ++f) {
     const int fi = f0 + f;
-    const double nl = m.nl2[fi];
+    const double nl = m.nl64[fi];             // -64 log2(nu / nu_ref)
     const double z = (m.nu[fi] - rp.nu0) * rp.inv_w;
     const double c = m.t_cmb + rp.A * exp(-0.5 * z * z);
     double Bp[NQB];
 #pragma unroll
-    for (int k = 0; k < NQB; ++k) Bp[k] = exp2(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl);
+    for (int k = 0; k < NQB; ++k)
+      Bp[k] = pow2_64(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl, s_t64, m);
     const float* kf = s_k + (size_t)f * kdl + lane;
     // 16x16 FP64 MFMA output: register j of lane l holds row l/16 + 4 j
     const double* Df = s_D + (size_t)f * m.TT * 32 + g;
@@ -596,9 +619,8 @@ __global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int 
   double* s_D = reinterpret_cast<double*>(smem + 512 + (size_t)fc * T * NT * 4);   // [fc][TD]
   stage(s_k, m.kthin + (size_t)f0 * T * NT, fn * T * NT * 4);
   stage(s_D, m.D + (size_t)f0 * TD, fn * TD * 8);
-  if (threadIdx.x < 64) s_t64[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 64.0));
+  init_t64(s_t64);
   __syncthreads();
-  const double MAGIC = 0x1.8p52;                  // rint via the low word
   const int b = bt * blockDim.x + threadIdx.x;
   const RowParams rp = w.rows[b];
   double beta[NT];
@@ -616,18 +638,8 @@ __global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int 
     const double c = m.t_cmb + rp.A * exp(-0.5 * z * z);
     double P[NT];
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const double y = AB ? fma(beta[i], nl, off[i]) : beta[i] * nl;   // 64 log2 P
-      const double t = y + MAGIC;
-      const int j = (int)(uint32_t)__double_as_longlong(t);
-      const double r = y - (t - MAGIC);                               // |r| <= 1/2
-      double p = fma(r, m.c5, m.c4);
-      p = fma(r, p, m.c3);
-      p = fma(r, p, m.c2);
-      p = fma(r, p, m.c1);
-      p = fma(r, p, 1.0);
-      P[i] = ldexp(s_t64[j & 63] * p, j >> 6);
-    }
+    for (int i = 0; i < NT; ++i)
+      P[i] = pow2_64(AB ? fma(beta[i], nl, off[i]) : beta[i] * nl, s_t64, m);   // 64 log2 P
     const float* kf = s_k + (size_t)f * T * NT;
     const double* Df = s_D + (size_t)f * TD;
     for (int t = 0; t < T; ++t) {
@@ -666,9 +678,18 @@ __global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int 
 // workgroup owns 64 rows for a chunk of channels, restaging K and D every
 // `fs` channels, and writes one set of partial sums per (chunk, row).
 
+// Register budgets that compile without spills: three waves per SIMD up to
+// 32 regions without amplitude masks, two up to 64 (48 with masks), else
+// what the variant needs.
+template <int NQB, bool AB>
+constexpr int grad_waves() {
+  return (!AB && NQB <= 8) ? 3 : (NQB <= (AB ? 12 : 16) ? 2 : 1);
+}
+
 template <int W, int NQB, bool AB, bool PROJ>
-__global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, int fs,
-                                                   int nb, int nc) {
+__global__ __launch_bounds__(W * 64)
+__attribute__((amdgpu_waves_per_eu(grad_waves<NQB, AB>()))) void k_grad64(
+    DevModel m, Work w, int per, int fs, int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   using AT = typename std::conditional<PROJ, double, float>::type;   // operand type
   constexpr int NU = (NQB + 3) / 4;         // 16-region output groups
@@ -679,20 +700,22 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
   const int N = m.N;
   const int kdl = NQB * TR * 64;            // operand values per channel
   const int drow = PROJ ? m.RT16 * 16 : m.TT * 32;   // targets per channel
-  AT* s_k = reinterpret_cast<AT*>(smem);
-  double* s_D = reinterpret_cast<double*>(smem + (size_t)fs * kdl * sizeof(AT));
+  double* s_t64 = reinterpret_cast<double*>(smem);                  // [64] 2^(m/64)
+  AT* s_k = reinterpret_cast<AT*>(smem + 512);
+  double* s_D = reinterpret_cast<double*>(smem + 512 + (size_t)fs * kdl * sizeof(AT));
+  init_t64(s_t64);                          // visible after the first stage's barrier
   const AT* kg = PROJ ? reinterpret_cast<const AT*>(m.pa64) : reinterpret_cast<const AT*>(m.k64);
   const double* dg = PROJ ? m.pt64 : m.D;
   const int g = lane >> 4;                  // 0..3
   const int b = bt * (W * 16) + wave * 16 + (lane & 15);
   const RowParams rp = w.rows[b];
   double beta[NQB];
-  double off[AB ? NQB : 1];
+  double off[AB ? NQB : 1];                 // 64 log2 alpha (AB)
 #pragma unroll
   for (int k = 0; k < NQB; ++k) {
     const int i = 4 * k + g;
     beta[k] = i < N ? w.betaT[(size_t)i * w.Bpad + b] : 0.0;
-    if constexpr (AB) off[k] = i < N ? w.offT[(size_t)i * w.Bpad + b] : 0.0;
+    if constexpr (AB) off[k] = i < N ? 64.0 * w.offT[(size_t)i * w.Bpad + b] : 0.0;
   }
   double s1[NQB], s2[AB ? NQB : 1];
 #pragma unroll
@@ -715,13 +738,15 @@ __global__ __launch_bounds__(W * 64) void k_grad64(DevModel m, Work w, int per, 
     for (int f = 0; f < fn; ++f) {
       const int fi = cs + f;
       const double nl = m.nl2[fi];
+      const double nl64 = m.nl64[fi];       // 64 nl exactly
       const double dnu = m.nu[fi] - rp.nu0;
       const double z = dnu * rp.inv_w;
       const double gg = exp(-0.5 * z * z);
       const double c = m.t_cmb + rp.A * gg;
       double Bp[NQB];
 #pragma unroll
-      for (int k = 0; k < NQB; ++k) Bp[k] = exp2(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl);
+      for (int k = 0; k < NQB; ++k)
+        Bp[k] = pow2_64(AB ? fma(beta[k], nl64, off[k]) : beta[k] * nl64, s_t64, m);
       const AT* kf = s_k + (size_t)f * kdl;
       const double* Df = s_D + (size_t)f * drow + g;
       f64x4 u[NU];
@@ -1024,7 +1049,7 @@ int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
       return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + 2 * kFracSize) * 8;
     case kFP32: return t.fc * m.NP2 * m.TT * 64 * 4 + d;
     case kThin: return 512 + t.fc * m.T * m.NT * 4 + d;
-    default: return t.fc * m.NQ * m.TT16 * 64 * 4 + d;
+    default: return 512 + t.fc * m.NQ * m.TT16 * 64 * 4 + d;
   }
 }
 
@@ -1247,8 +1272,9 @@ GradShape grad_shape(const DevModel& m, int Bpad) {
                            : m.NQ * m.TT16 * 64 * 4 + m.TT * 32 * 8;
   g.per = std::min(m.F, kGradChunk);
   g.chunks = (m.F + g.per - 1) / g.per;
-  g.fs = std::max(1, std::min(g.per, (40 * 1024) / per_ch));
-  g.lds = g.fs * per_ch;
+  // stages of <= 40 KB with the power table (four workgroups per CU)
+  g.fs = std::max(1, std::min(g.per, (40 * 1024 - 512) / per_ch));
+  g.lds = 512 + g.fs * per_ch;
   return g;
 }
 
