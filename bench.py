@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
 PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 matrix, published
+PEAK_HBM_BPS = 8.0e12        # MI355X HBM3E, published
 PRECS = ("mixed", "fp32", "fp64")
 EXP_FLOPS = 20               # FP64 flops counted per power-law value
 
@@ -419,6 +420,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic, "kernel": "k_mixed",
+                     # the counted HBM bytes over the event-timed kernel time
+                     "traffic_gbs": (traffic / (mix["kernel_ms"] * 1e-3) / 1e9
+                                     if traffic else None),
+                     "traffic_frac_of_hbm": (traffic / (mix["kernel_ms"] * 1e-3) / PEAK_HBM_BPS
+                                             if traffic else None),
                      "kernel_ms": mix["kernel_ms"],
                      "as_designed": {"int8_mfma": mfma_tops, "peak": PEAK_INT8_TOPS,
                                      "unit": "TOP/s", "frac": mfma_tops / PEAK_INT8_TOPS}},
