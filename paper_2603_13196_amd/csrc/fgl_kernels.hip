@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, doubl
 // rows: the rows are read coalesced into LDS, one thread per row derives
 // the row record, and all threads write the transposed indices coalesced.
 // Invalid rows are given harmless values (finalize writes -inf for them).
-constexpr int kPrepRows = 64;
+constexpr int kPrepRows = 16;
 
 __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, int B, int Bpad,
                                               int N, int NA, int NB, int P, unsigned flags,
@@ -928,65 +928,80 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
                                               double* __restrict__ offT,
                                               RowParams* __restrict__ rows) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double* s_th = reinterpret_cast<double*>(smem);                 // [64][P]
-  double* s_fill = s_th + (size_t)kPrepRows * P;                 // [64] bmin or 0
-  double* s_ofill = s_fill + kPrepRows;                          // [64] omin or 0
-  int* s_ok = reinterpret_cast<int*>(s_ofill + kPrepRows);       // [64]
+  double* s_th = reinterpret_cast<double*>(smem);                 // [rows][P]
+  double* s_fill = s_th + (size_t)kPrepRows * P;                 // [rows] bmin or 0
+  double* s_ofill = s_fill + kPrepRows;                          // [rows] omin or 0
+  int* s_ok = reinterpret_cast<int*>(s_ofill + kPrepRows);       // [rows]
   const int b0 = blockIdx.x * kPrepRows;
   const int nrow = max(0, min(kPrepRows, B - b0));
   for (int k = threadIdx.x; k < nrow * P; k += blockDim.x)
     s_th[k] = theta[(size_t)b0 * P + k];
   __syncthreads();
   const bool no21 = flags & 1u;
-  if (threadIdx.x < kPrepRows) {
-    const int r = threadIdx.x;
+  {
+    // sixteen threads per row (r = t / 16): each checks and bounds the
+    // entries q, q + 16, ... of the row; xor-shuffles within the sixteen
+    // combine them (min, max and "and" do not depend on the order)
+    static_assert(kPrepRows * 16 == 256, "sixteen threads per row");
+    const int r = threadIdx.x >> 4, q = threadIdx.x & 15;
     const double* th = s_th + (size_t)r * P;
-    bool ok = r < nrow;
+    int ok = r < nrow;
+    double bmin = INFINITY, bmax = -INFINITY, omin = INFINITY, omax = -INFINITY;
     if (ok) {
-      for (int k = 0; k < P; ++k) ok = ok && isfinite(th[k]);
-      for (int j = 0; j < NB; ++j) ok = ok && fabs(th[j]) <= 64.0;
-      for (int i = 0; i < NA; ++i) ok = ok && th[NB + i] >= 0x1p-32 && th[NB + i] <= 0x1p32;
-      ok = ok && th[P - 1] > 0.0;
-      if (!no21) ok = ok && th[P - 2] > 0.0;
-    }
-    RowParams rp;
-    rp.valid = ok ? 1 : 0;
-    rp.pad = 0;
-    rp.A = 0.0;
-    rp.nu0 = 0.0;
-    rp.inv_w = 1.0;
-    rp.sigma = 1.0;
-    rp.t21 = no21 ? 0.0 : 1.0;
-    double bmin = 0.0, bmax = 0.0, omin = 0.0, omax = 0.0;
-    if (ok) {
-      bmin = bmax = th[0];
-      for (int j = 1; j < NB; ++j) {
+      for (int k = q; k < P; k += 16) ok = ok && isfinite(th[k]);
+      for (int j = q; j < NB; j += 16) {
+        ok = ok && fabs(th[j]) <= 64.0;
         bmin = fmin(bmin, th[j]);
         bmax = fmax(bmax, th[j]);
       }
-      if (NA > 0) {
-        omin = omax = log2(th[NB]);
-        for (int i = 1; i < NA; ++i) {
-          const double o = log2(th[NB + i]);
-          omin = fmin(omin, o);
-          omax = fmax(omax, o);
-        }
-      }
-      rp.sigma = th[P - 1];
-      if (!no21) {
-        rp.A = th[P - 4];
-        rp.nu0 = th[P - 3];
-        rp.inv_w = 1.0 / th[P - 2];
+      for (int i = q; i < NA; i += 16) {
+        ok = ok && th[NB + i] >= 0x1p-32 && th[NB + i] <= 0x1p32;
+        const double o = log2(th[NB + i]);
+        omin = fmin(omin, o);
+        omax = fmax(omax, o);
       }
     }
-    rp.bmin = bmin;
-    rp.bmax = bmax;
-    rp.omin = omin;
-    rp.omax = omax;
-    s_fill[r] = bmin;
-    s_ofill[r] = omin;
-    s_ok[r] = ok ? 1 : 0;
-    if (b0 + r < Bpad) rows[b0 + r] = rp;
+#pragma unroll
+    for (int sh = 8; sh >= 1; sh >>= 1) {
+      ok = ok & __shfl_xor(ok, sh);
+      bmin = fmin(bmin, __shfl_xor(bmin, sh));
+      bmax = fmax(bmax, __shfl_xor(bmax, sh));
+      omin = fmin(omin, __shfl_xor(omin, sh));
+      omax = fmax(omax, __shfl_xor(omax, sh));
+    }
+    if (q == 0) {
+      if (ok) {
+        ok = th[P - 1] > 0.0;
+        if (!no21) ok = ok && th[P - 2] > 0.0;
+      }
+      RowParams rp;
+      rp.valid = ok ? 1 : 0;
+      rp.pad = 0;
+      rp.A = 0.0;
+      rp.nu0 = 0.0;
+      rp.inv_w = 1.0;
+      rp.sigma = 1.0;
+      rp.t21 = no21 ? 0.0 : 1.0;
+      if (ok) {
+        rp.sigma = th[P - 1];
+        if (!no21) {
+          rp.A = th[P - 4];
+          rp.nu0 = th[P - 3];
+          rp.inv_w = 1.0 / th[P - 2];
+        }
+      } else {
+        bmin = bmax = 0.0;
+      }
+      if (!ok || NA == 0) omin = omax = 0.0;
+      rp.bmin = bmin;
+      rp.bmax = bmax;
+      rp.omin = omin;
+      rp.omax = omax;
+      s_fill[r] = bmin;
+      s_ofill[r] = omin;
+      s_ok[r] = ok ? 1 : 0;
+      if (b0 + r < Bpad) rows[b0 + r] = rp;
+    }
   }
   __syncthreads();
   // betaT[i][b]: the index of region i's spectral-index mask for valid rows
@@ -1005,24 +1020,33 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
 
 // lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2), with chi2_b
 // the sum of the row's partials plus chi0 (a per-model constant of the
-// projected form, 0 otherwise).  Sixteen
-// threads per row: thread s sums the partials of groups s, s+16, ... in
-// order, then a fixed xor-shuffle tree adds the sixteen sums, so the
-// result does not depend on timing.
+// projected form, 0 otherwise).  Sixteen sums per row: sum s adds the
+// partials of groups s, s+16, ... in order; then a fixed tree adds the
+// sixteen (s with s + 8, then + 4, + 2, + 1), so the result does not depend
+// on timing.  (The chain-step kernel adds a row the same way.)  A
+// workgroup takes 16 rows: thread t sums s = t / 16 for row t % 16, so a
+// wave's loads are runs of 16 consecutive rows.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int ngroup,
                                                   int Bpad, const RowParams* __restrict__ rows,
                                                   int B, double nFT, double chi0,
                                                   double* __restrict__ out) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = gid >> 4, s = gid & 15;
+  __shared__ double s_acc[16][16];                 // [s][row]
+  const int bl = threadIdx.x & 15, s = threadIdx.x >> 4;
+  const int b = blockIdx.x * 16 + bl;
   double acc = 0.0;
   if (b < B)
     for (int c = s; c < ngroup; c += 16) acc += partial[(size_t)c * Bpad + b];
-  acc += __shfl_xor(acc, 8);
-  acc += __shfl_xor(acc, 4);
-  acc += __shfl_xor(acc, 2);
-  acc += __shfl_xor(acc, 1);
-  if (b >= B || s != 0) return;
+  s_acc[s][bl] = acc;
+  __syncthreads();
+  if (threadIdx.x >= 16 || b >= B) return;
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = s_acc[k][bl];
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+    for (int k = 0; k < h; ++k) v[k] = v[k] + v[k + h];
+  acc = v[0];
   const RowParams rp = rows[b];
   if (!rp.valid) {
     out[b] = -INFINITY;
