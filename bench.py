@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
 PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 matrix, published
 PEAK_HBM_BPS = 8.0e12        # MI355X HBM3E, published
+TIMING_EVERY = 10            # kernel events on every 10th timed call (an event pair adds ~9 us)
 PRECS = ("mixed", "fp32", "fp64")
 EXP_FLOPS = 20               # FP64 flops counted per power-law value
 
@@ -75,7 +76,7 @@ def time_prec(fgl, m, th, out, prec, steps, warmup):
     for _ in range(warmup):
         m.loglike_device(th, out, prec)
     torch.cuda.synchronize()
-    m.kernel_timing(True)
+    m.kernel_timing(True, every=TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -268,7 +269,7 @@ def grad_leg(fgl, w, steps, warmup):
     for _ in range(warmup):
         m.loglike_grad_device(th, out, grad)
     torch.cuda.synchronize()
-    m.kernel_timing(True)
+    m.kernel_timing(True, every=TIMING_EVERY)
     t0 = time.perf_counter()
     for _ in range(steps):
         m.loglike_grad_device(th, out, grad)

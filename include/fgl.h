@@ -228,11 +228,14 @@ size_t fgl_model_bytes(const fgl_model* m);
 
 /*
  * Kernel timing (instrumentation for benchmarks and roofline reports).
- * fgl_kernel_timing(m, 1) resets the counters and, from then on, records a
- * HIP event pair around the likelihood kernel of every call on m, on the
- * stream that kernel runs on (graph replay is bypassed meanwhile);
- * fgl_kernel_timing(m, 0) stops recording.  fgl_kernel_time waits for the
- * recorded kernels and returns their summed duration (ms) and count.
+ * fgl_kernel_timing(m, n) with n >= 1 resets the counters and, from then on,
+ * records a HIP event pair around the likelihood kernel of every n-th call
+ * on m (n = 1: every call), on the stream that kernel runs on (graph replay
+ * is bypassed meanwhile).  The events carry no system-scope fence; each pair
+ * still adds a few microseconds to its call, which n > 1 spreads over n
+ * calls.  fgl_kernel_timing(m, 0) stops recording; n < 0 is FGL_EINVAL.
+ * fgl_kernel_time waits for the recorded kernels and returns their summed
+ * duration (ms) and count.
  */
 int fgl_kernel_timing(fgl_model* m, int enable);
 int fgl_kernel_time(fgl_model* m, double* total_ms, int64_t* launches);

@@ -72,8 +72,10 @@ struct Model {
   std::vector<double> h_pa64, h_pt64;        // projected rows in FP64 (gradient)
   // serving bookkeeping
   uint64_t last_use = 0;
-  // kernel timing (fgl_kernel_timing)
-  bool timing = false;
+  // kernel timing (fgl_kernel_timing): 0 off, n > 0 events around every
+  // n-th launch (timing_n counts the launches since it was set)
+  int timing = 0;
+  uint64_t timing_n = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
 };
 

@@ -262,8 +262,9 @@ int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const doub
   const int groups = (NJ + jper - 1) / jper;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    // timing only: no system-scope fence around the kernel
+    (void)hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    (void)hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     (void)hipEventRecord(e0, sk->stream);
   }
   if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {

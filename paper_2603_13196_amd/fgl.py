@@ -313,8 +313,10 @@ class Model:
                                  ctypes.byref(c), ctypes.byref(p)))
         return w.value, c.value, p.value
 
-    def kernel_timing(self, enable: bool = True):
-        _check(_lib.fgl_kernel_timing(self.handle, int(bool(enable))))
+    def kernel_timing(self, enable: bool = True, every: int = 1):
+        """Record the likelihood kernel's duration on every `every`-th call
+        (from now on, counters reset) or stop recording."""
+        _check(_lib.fgl_kernel_timing(self.handle, int(every) if enable else 0))
 
     def kernel_time(self):
         """(summed likelihood-kernel milliseconds, launches) since the last
