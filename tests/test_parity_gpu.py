@@ -337,6 +337,24 @@ def test_every_tile_same_bits(fgl):
         m.close()
 
 
+def test_kernel_timing_every_nth_call(fgl):
+    """fgl_kernel_timing(m, n) records the kernel of calls 0, n, 2n, ... and
+    changes no result; n < 0 is refused."""
+    w = workload.config(workload.SMALL, B=64)
+    m = _model(fgl, w)
+    ref = m.loglike(w.theta, "mixed")
+    m.kernel_timing(True, every=3)
+    for _ in range(7):
+        assert np.array_equal(m.loglike(w.theta, "mixed"), ref)
+    ms, n = m.kernel_time()
+    assert n == 3 and ms > 0.0, (n, ms)
+    m.kernel_timing(False)
+    with pytest.raises(fgl.FGLError) as e:
+        m.kernel_timing(True, every=-1)
+    assert e.value.code == fgl.FGL_EINVAL
+    m.close()
+
+
 def test_device_entry_point_matches_host(fgl):
     import torch
     w = workload.config(workload.HEADLINE, B=2048, batch="mixed")
