@@ -586,7 +586,7 @@ int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const double* d_the
 // (a cache write-back and invalidate that otherwise adds ~5.5 us before and
 // after the timed kernel on this device).  Results are read only after a
 // stream or device synchronisation, never through these events.
-hipError_t timing_event(hipEvent_t* ev) {
+static hipError_t timing_event(hipEvent_t* ev) {
   return hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
 }
 
