@@ -337,11 +337,20 @@ def cpu_leg(w, gpu_out, seconds):
         dt = time.perf_counter() - t0
     d = np.abs(gpu_out[:n] - ref)
     tol = 1e-6 * np.abs(ref) + 1e-3
+    # the same oracle on one host thread, over about a fifth of the time
+    # (last: the thread count stays set for the process)
+    n1 = max(1, min(w.B, int(n * passes / dt / max(cores, 1) * seconds / 5)))
+    t0 = time.perf_counter()
+    orc.loglike_w(w, w.theta[:n1], threads=1)
+    dt1 = time.perf_counter() - t0
     return ({"value": n * passes / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
              "sample": f"first {n} of the {w.B} rows x {passes} passes, all host threads",
-             "seconds": dt},
+             "seconds": dt,
+             "single_thread": {"value": n1 / dt1, "unit": "evals/s",
+                               "sample": f"first {n1} rows, one host thread", "seconds": dt1}},
             {"rows": n, "max_abs_dlogL": float(d.max()),
              "max_dlogL_over_tol": float((d / tol).max()),
+             "p99_dlogL_over_tol": float(np.quantile(d / tol, 0.99)),
              "within_tol": bool(np.all(d <= tol))})
 
 
