@@ -527,7 +527,7 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
   std::vector<Tile> out;
   const int G = group_of(k, d);
   if (G == 0) return out;
-  const bool occ3 = k == kMixed && d.proj && d.KC == 1 && d.NA == 0;
+  const bool occ3 = k == kMixed && mixed_occ3(d);
   for (int w : {4, 8}) {
     if (w > max_waves(k, d)) continue;
     for (int occ = 2; occ <= (occ3 ? 3 : 2); ++occ) {
@@ -551,7 +551,7 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
 Tile default_tile(Kind k, const DevModel& d, int B) {
   const int G = group_of(k, d);
   const int W = max_waves(k, d);
-  const int occ = (k == kMixed && d.proj && d.KC == 1 && d.NA == 0) ? 3 : 2;
+  const int occ = (k == kMixed && mixed_occ3(d)) ? 3 : 2;
   Tile best{W, G, G, occ};
   const int cols = cols_per_wave(k) * W;
   const int nb = padded_rows(B) / cols;

@@ -146,6 +146,19 @@ struct DevModel {
   const float* kthin;    // [F][T][NT] K, zero padded in regions
 };
 
+// Amplitude-mask mode of the mixed kernel: 0 without amplitude masks, 2 when
+// the index masks come in multiples of 16 (a 16-region half chunk then lies
+// within one amplitude mask, so a lane holds one alpha per chunk), else 1
+// (one alpha per region).
+inline int mixed_alpha_mode(const DevModel& d) {
+  return d.NA == 0 ? 0 : (d.NB % 16 == 0 ? 2 : 1);
+}
+// The mixed kernel's three-waves-per-SIMD compile exists for the projected
+// form with one region chunk and at most one alpha per lane and chunk.
+inline bool mixed_occ3(const DevModel& d) {
+  return d.proj && d.KC == 1 && mixed_alpha_mode(d) != 1;
+}
+
 // Per-call workspace (device memory owned by the model, per stream).
 struct Work {
   int B, Bpad;           // rows and rows padded to the widest b-tile

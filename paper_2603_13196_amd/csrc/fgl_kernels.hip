@@ -164,7 +164,7 @@ __device__ inline double pow2_64(double y, const double* t64, const DevModel& m)
 
 // OCC: waves per SIMD the register allocation targets (2, or 3 for the
 // projected form with one region chunk, which fits in 168 registers).
-template <int W, int KC, bool PROJ, int OCC, bool AB>
+template <int W, int KC, bool PROJ, int OCC, int AM>
 __global__ __launch_bounds__(W * 64)
 __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
                                                     int nb, int nc) {
@@ -193,15 +193,22 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   const int g = lane >> 5;
   const int b = bt * (W * 32) + wave * 32 + (lane & 31);
   const RowParams rp = w.rows[b];
+  // amplitude masks (AM): 64 log2 alpha per region (AM = 1), or one value
+  // per 16-region half chunk when the index masks come in multiples of 16,
+  // so that each half chunk lies within one amplitude mask (AM = 2)
+  constexpr bool AB = AM != 0;
   double beta[KC][16];
-  double off[AB ? KC : 1][16];                     // 64 log2 alpha (AB)
+  double off[AM == 1 ? KC : 1][16];
+  double off1[AM == 2 ? KC : 1];
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const size_t at = (size_t)(kc * 32 + g * 16 + j) * w.Bpad + b;
       beta[kc][j] = w.betaT[at];
-      if constexpr (AB) off[kc][j] = 64.0 * w.offT[at];
+      if constexpr (AM == 1) off[kc][j] = 64.0 * w.offT[at];
+      if constexpr (AM == 2)
+        if (j == 0) off1[kc] = 64.0 * w.offT[at];
     }
 
   const double MAGIC = 0x1.8p52;                        // rint via the low word
@@ -277,7 +284,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       for (int j = 0; j < 16; ++j) {
         double t, r;
         if constexpr (AB) {
-          const double y = fma(beta[kc][j], nl, off[kc][j]) - ymax;
+          const double y = fma(beta[kc][j], nl, AM == 1 ? off[kc][j] : off1[kc]) - ymax;
           t = y + MAGIC;
           r = y - (t - MAGIC);                     // |r| <= 1/2
         } else {
@@ -1110,27 +1117,27 @@ hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
   return hipGetLastError();
 }
 
-template <int W, bool AB>
+template <int W, int AM>
 hipError_t mixed_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
                     int nc, int occ, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
   if (m.proj) {
     switch (m.KC) {
       case 1:
-        if constexpr (!AB)
+        if constexpr (AM != 1)
           if (occ == 3)
-            return go(k_mixed<W, 1, true, 3, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-        return go(k_mixed<W, 1, true, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 2: return go(k_mixed<W, 2, true, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 3: return go(k_mixed<W, 3, true, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+            return go(k_mixed<W, 1, true, 3, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+        return go(k_mixed<W, 1, true, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 2: return go(k_mixed<W, 2, true, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      case 3: return go(k_mixed<W, 3, true, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
       default: return hipErrorInvalidValue;
     }
   }
   switch (m.KC) {
-    case 1: return go(k_mixed<W, 1, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_mixed<W, 2, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 3: return go(k_mixed<W, 3, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_mixed<W, 4, false, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go(k_mixed<W, 1, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_mixed<W, 2, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 3: return go(k_mixed<W, 3, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_mixed<W, 4, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1138,9 +1145,12 @@ hipError_t mixed_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
 template <int W>
 hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                    int nc, int occ, int lds, hipStream_t s) {
-  if (occ == 3 && m.NA > 0) return hipErrorInvalidValue;
-  return m.NA > 0 ? mixed_wa<W, true>(m, w, fc, G, nb, nc, occ, lds, s)
-                  : mixed_wa<W, false>(m, w, fc, G, nb, nc, occ, lds, s);
+  if (occ == 3 && !mixed_occ3(m)) return hipErrorInvalidValue;
+  switch (mixed_alpha_mode(m)) {
+    case 0: return mixed_wa<W, 0>(m, w, fc, G, nb, nc, occ, lds, s);
+    case 1: return mixed_wa<W, 1>(m, w, fc, G, nb, nc, occ, lds, s);
+    default: return mixed_wa<W, 2>(m, w, fc, G, nb, nc, occ, lds, s);
+  }
 }
 
 template <int W, bool AB>
