@@ -86,3 +86,14 @@ def test_product_path_never_uses_the_oracle():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"\bimport\s+oracle|from\s+oracle|fgl_oracle|liboracle",
                                      txt), fn
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message (one GPU only)."""
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode == 2
+    line = json.loads(p.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
