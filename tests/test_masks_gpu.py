@@ -38,9 +38,12 @@ def _forms(fgl, w, ref, label):
 
 @pytest.mark.parametrize("NA,NB,F,T,B", [
     (1, 1, 5, 1, 7),        # one region
-    (2, 3, 9, 20, 300),     # projected form, ragged row tile
-    (3, 5, 7, 4, 65),       # direct form (T < N + 1)
-    (2, 16, 11, 96, 200),   # the headline split, projected
+    (2, 3, 9, 20, 300),     # thin (per-row FP64) form
+    (3, 5, 7, 4, 65),       # thin form, 16 slots
+    (2, 4, 6, 40, 90),      # thin form beyond one 32-bin tile
+    (2, 3, 9, 70, 300),     # projected form, ragged row tile
+    (4, 5, 7, 19, 65),      # direct form (T < N + 1)
+    (2, 16, 11, 96, 200),   # the headline split, projected, one alpha per half chunk
     (4, 8, 6, 40, 100),     # 32 regions: projected with the peeled row
     (3, 11, 5, 40, 70),     # 33 regions: two chunks
     (8, 8, 4, 70, 40),      # 64 regions
