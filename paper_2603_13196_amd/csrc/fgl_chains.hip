@@ -70,6 +70,14 @@ struct ChainState {
                        // captured graph stays valid across iterations)
   unsigned long long seed;
   int steps;
+  // the likelihood's row records and transposed indices of the proposals,
+  // written by the chain kernels themselves (the model's N = NA' NB regions,
+  // NA' = max(NA, 1), betaRows = 32 KC transposed rows)
+  RowParams* rows;
+  double* betaT;
+  double* offT;
+  int Bpad, N, NA, NB, betaRows;
+  unsigned flags;
 };
 
 // --- Philox4x32-10 --------------------------------------------------------
@@ -184,16 +192,116 @@ __device__ void new_step(const ChainState& s, int i, Scal& c, int lane, double* 
   c.expand = 0;
 }
 
+// The row record and the transposed spectral indices (and log2 alpha) of
+// likelihood row i, from the row's entries held by the chain's wavefront
+// (v[q] is entry lane + 64 q), with the row-preparation kernel's rules:
+// finite entries, |beta| <= 64, alpha in [2^-32, 2^32], sigma > 0 and
+// w > 0; extremes of beta and log2 alpha; fills of the row's minimum for
+// padded regions (zero for an invalid row).
+__device__ void prep_row(const ChainState& s, int i, int lane, const double (&v)[3]) {
+  const int P = s.P, NB = s.NB, NA = s.NA;
+  const bool no21 = s.flags & 1u;
+  int ok = 1;
+  double bmin = INFINITY, bmax = -INFINITY, omin = INFINITY, omax = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int k = lane + 64 * q;
+    if (k < P) {
+      const double x = v[q];
+      ok = ok && isfinite(x);
+      if (k < NB) {
+        ok = ok && fabs(x) <= 64.0;
+        bmin = fmin(bmin, x);
+        bmax = fmax(bmax, x);
+      } else if (k < NB + NA) {
+        ok = ok && x >= 0x1p-32 && x <= 0x1p32;
+        const double o = log2(x);
+        omin = fmin(omin, o);
+        omax = fmax(omax, o);
+      }
+    }
+  }
+  ok = __builtin_amdgcn_ballot_w64(!ok) == 0;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    bmin = fmin(bmin, __shfl_xor(bmin, m));
+    bmax = fmax(bmax, __shfl_xor(bmax, m));
+    omin = fmin(omin, __shfl_xor(omin, m));
+    omax = fmax(omax, __shfl_xor(omax, m));
+  }
+  // entry k of the row (k may differ between lanes; every lane takes part)
+  auto entry = [&](int k) {
+    const double a0 = __shfl(v[0], k & 63), a1 = __shfl(v[1], k & 63);
+    const double a2 = __shfl(v[2], k & 63);
+    return k < 64 ? a0 : (k < 128 ? a1 : a2);
+  };
+  const double sig = entry(P - 1);
+  const double wd = entry(no21 ? P - 1 : P - 2);
+  const double amp = entry(no21 ? P - 1 : P - 4);
+  const double nu0 = entry(no21 ? P - 1 : P - 3);
+  if (ok) {
+    ok = sig > 0.0;
+    if (!no21) ok = ok && wd > 0.0;
+  }
+  if (!ok) bmin = bmax = 0.0;
+  if (!ok || NA == 0) omin = omax = 0.0;
+  if (lane == 0) {
+    RowParams rp;
+    rp.valid = ok ? 1 : 0;
+    rp.pad = 0;
+    rp.A = 0.0;
+    rp.nu0 = 0.0;
+    rp.inv_w = 1.0;
+    rp.sigma = 1.0;
+    rp.t21 = no21 ? 0.0 : 1.0;
+    if (ok) {
+      rp.sigma = sig;
+      if (!no21) {
+        rp.A = amp;
+        rp.nu0 = nu0;
+        rp.inv_w = 1.0 / wd;
+      }
+    }
+    rp.bmin = bmin;
+    rp.bmax = bmax;
+    rp.omin = omin;
+    rp.omax = omax;
+    s.rows[i] = rp;
+  }
+  const int nq = (s.betaRows + 63) / 64;
+  for (int q = 0; q < nq; ++q) {
+    const int r = lane + 64 * q;
+    const int ia = r / NB, jb = r - ia * NB;
+    const bool real = ok && r < s.N;
+    const double bv = entry(min(jb, P - 1));
+    const double av = NA > 0 ? entry(min(NB + ia, P - 1)) : 1.0;
+    if (r < s.betaRows) {
+      s.betaT[(size_t)r * s.Bpad + i] = real ? bv : bmin;
+      if (NA > 0) s.offT[(size_t)r * s.Bpad + i] = real ? log2(av) : omin;
+    }
+  }
+}
+
 // The chain's next likelihood row: the proposal x + t dir when it is inside
 // the box, else (and for a finished chain) the chain's point itself, whose
-// result is ignored.  The last coordinate is log sigma.
+// result is ignored.  The last coordinate is log sigma.  The row's record
+// and transposed indices are prepared here too.
 __device__ void propose(const ChainState& s, int i, Scal& c, int lane) {
   const int P = s.P;
   const double* x = s.x + (size_t)i * P;
   double* th = s.theta + (size_t)i * P;
+  double v[3] = {0.0, 0.0, 0.0};
   if (c.stage == kDone) {
-    for (int k = lane; k < P; k += 64) th[k] = k == P - 1 ? exp(x[k]) : x[k];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int k = lane + 64 * q;
+      if (k < P) {
+        v[q] = k == P - 1 ? exp(x[k]) : x[k];
+        th[k] = v[q];
+      }
+    }
     if (lane == 0) s.inbox[i] = 0;
+    prep_row(s, i, lane, v);
     return;
   }
   double t;
@@ -213,11 +321,17 @@ __device__ void propose(const ChainState& s, int i, Scal& c, int lane) {
     out |= !((p >= s.lo[k]) & (p <= s.hi[k]));
   }
   const bool in = __builtin_amdgcn_ballot_w64(out != 0) == 0;
-  for (int k = lane; k < P; k += 64) {
-    const double v = in ? x[k] + t * d[k] : x[k];
-    th[k] = k == P - 1 ? exp(v) : v;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int k = lane + 64 * q;
+    if (k < P) {
+      const double p = in ? x[k] + t * d[k] : x[k];
+      v[q] = k == P - 1 ? exp(p) : p;
+      th[k] = v[q];
+    }
   }
   if (lane == 0) s.inbox[i] = in ? 1 : 0;
+  prep_row(s, i, lane, v);
 }
 
 __device__ inline void finish_step(const ChainState& s, int i, Scal& c, int lane, double* u) {
@@ -468,19 +582,35 @@ int fgl_chains_run(fgl_chains* ch, const double* x0, const double* l0, int n, do
     return hip_err(e, "copy chain inputs");
   if (P > kMaxP) return set_err(FGL_EINVAL, "P=%d exceeds the chains' %d parameters", P, kMaxP);
   const int blocks = (n + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k_chain_start, dim3(blocks), dim3(64 * kWaves), 0, s, st, c->d_x0, c->d_l0);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "chain start");
-  // the likelihood's workspace for n rows on this stream, fixed before capture
+  // the likelihood's workspace for n rows on this stream, fixed before the
+  // start kernel (which writes the first proposals' row records into it)
+  // and before capture
   const Kind k = kind_of(prec, m->dm);
   const Tile tile = tile_for(m, k, n);
   WorkBuf& wb = m->work[s];
   wb.stream_synced_free = true;
   if ((rc = ensure_work(m, wb, n, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
+  st.rows = wb.w.rows;
+  st.betaT = wb.w.betaT;
+  st.offT = wb.w.offT;
+  st.Bpad = wb.w.Bpad;
+  st.N = m->dm.N;
+  st.NA = m->dm.NA;
+  st.NB = m->dm.NB;
+  st.betaRows = m->dm.KC * 32;
+  st.flags = m->dm.flags;
+  hipLaunchKernelGGL(k_chain_start, dim3(blocks), dim3(64 * kWaves), 0, s, st, c->d_x0, c->d_l0);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "chain start");
+  // the padding rows up to Bpad (and the first proposals again, with the
+  // same result) by the row-preparation kernel, once per call; later rounds
+  // take the records the step kernel writes with each proposal
+  if ((e = launch_prep(m->dm, st.theta, n, wb.w, m->dm.KC * 32, s)) != hipSuccess)
+    return hip_err(e, "prep kernel");
   RowSums rs{wb.w.partial, wb.w.rows, n_groups(m->dm, tile), wb.w.Bpad,
              (double)m->dm.F * (double)m->dm.T,
              (k == kMixed && m->dm.proj) ? m->dm.chi0 : 0.0};
   auto round = [&]() -> int {
-    int rc2 = enqueue_partials(m, k, tile, wb, st.theta, n, s);
+    int rc2 = enqueue_main(m, k, tile, wb, s);
     if (rc2 != FGL_OK) return rc2;
     hipLaunchKernelGGL(k_chain_step, dim3(blocks), dim3(64 * kWaves), 0, s, st, rs);
     hipError_t e2 = hipGetLastError();

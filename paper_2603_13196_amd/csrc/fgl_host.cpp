@@ -595,6 +595,11 @@ int enqueue_partials(Model* m, Kind k, const Tile& tile, WorkBuf& wb, const doub
   hipError_t e;
   if ((e = launch_prep(m->dm, d_theta, B, wb.w, m->dm.KC * 32, s)) != hipSuccess)
     return hip_err(e, "prep kernel");
+  return enqueue_main(m, k, tile, wb, s);
+}
+
+int enqueue_main(Model* m, Kind k, const Tile& tile, WorkBuf& wb, hipStream_t s) {
+  hipError_t e;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   const bool rec = m->timing > 0 && m->timing_n++ % (uint64_t)m->timing == 0;
   if (rec) {

@@ -104,6 +104,9 @@ int enqueue(Model* m, Kind k, const Tile& tile, WorkBuf& wb,
             const double* d_theta, int B, double* d_out, hipStream_t s);
 int enqueue_partials(Model* m, Kind k, const Tile& tile, WorkBuf& wb,
                      const double* d_theta, int B, hipStream_t s);
+// The likelihood kernel alone, on rows whose records the caller has already
+// prepared (the chain kernels prepare their proposals' rows themselves).
+int enqueue_main(Model* m, Kind k, const Tile& tile, WorkBuf& wb, hipStream_t s);
 int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
          double* d_out, hipStream_t s);
 void drop_stream_work(hipStream_t s);   // fgl_host.cpp
