@@ -528,7 +528,8 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
   const int G = group_of(k, d);
   if (G == 0) return out;
   const bool occ3 = k == kMixed && mixed_occ3(d);
-  for (int w : {4, 8}) {
+  const std::vector<int> waves = k == kThin ? std::vector<int>{1, 2, 4} : std::vector<int>{4, 8};
+  for (int w : waves) {
     if (w > max_waves(k, d)) continue;
     for (int occ = 2; occ <= (occ3 ? 3 : 2); ++occ) {
       const int per_cu = occ == 3 ? std::max(1, 12 / w) : 1;
@@ -550,7 +551,11 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
 // given two workgroups per CU), with >= 2048 workgroups in flight.
 Tile default_tile(Kind k, const DevModel& d, int B) {
   const int G = group_of(k, d);
-  const int W = max_waves(k, d);
+  int W = max_waves(k, d);
+  // the thin kernel on small batches: fewer waves per workgroup until the
+  // row tiles times the channel groups give ~1024 workgroups
+  if (k == kThin)
+    while (W > 1 && (padded_rows(B) / (64 * W)) * ((d.F + G - 1) / G) < 1024) W /= 2;
   const int occ = (k == kMixed && mixed_occ3(d)) ? 3 : 2;
   Tile best{W, G, G, occ};
   const int cols = cols_per_wave(k) * W;

@@ -1242,9 +1242,13 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
       tile.group < 1 || tile.fc % tile.group != 0 || lds > max_lds_bytes())
     return hipErrorInvalidValue;
   if (k == kThin) {
-    if (!m.thin || tile.waves != 4) return hipErrorInvalidValue;
-    return m.NA > 0 ? thin_wa<true>(m, w, tile.fc, tile.group, nb, nc, lds, s, 256)
-                    : thin_wa<false>(m, w, tile.fc, tile.group, nb, nc, lds, s, 256);
+    // one, two or four waves of 64 rows per workgroup (small batches take
+    // fewer, so that more workgroups share the channels)
+    if (!m.thin || !(tile.waves == 1 || tile.waves == 2 || tile.waves == 4))
+      return hipErrorInvalidValue;
+    const int th = 64 * tile.waves;
+    return m.NA > 0 ? thin_wa<true>(m, w, tile.fc, tile.group, nb, nc, lds, s, th)
+                    : thin_wa<false>(m, w, tile.fc, tile.group, nb, nc, lds, s, th);
   }
   if (k == kMixed) {
     return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s)

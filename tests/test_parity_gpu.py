@@ -312,7 +312,8 @@ def test_form_rule(fgl):
 def test_every_tile_same_bits(fgl):
     """Every candidate tile (waves, channels per workgroup, register budget)
     gives bitwise the same lnL, in each form and precision."""
-    cases = [("projected", workload.config(workload.HEADLINE, B=1024, batch="mixed"), 0),
+    cases = [("thin", workload.config(workload.MEDIUM, B=700, batch="mixed"), 0),
+             ("projected", workload.config(workload.HEADLINE, B=1024, batch="mixed"), 0),
              ("direct", workload.config(workload.HEADLINE, B=1024, batch="mixed"), fgl.FGL_MIXED_DIRECT),
              ("masks", workload.make_masks(2, 5, np.linspace(60.0, 190.0, 41), 40, 700, 31,
                                            batch="mixed"), 0)]
@@ -320,7 +321,7 @@ def test_every_tile_same_bits(fgl):
         m = fgl.Model.from_workload(w, flags)
         for prec in PRECS:
             ref, n = None, 0
-            for W in (4, 8):
+            for W in (1, 2, 4, 8):
                 for fc in (1, 2, 4, 8, 16, 32):
                     for occ in (2, 3):
                         try:
