@@ -75,6 +75,8 @@ def test_device_chains_sample_the_box_uniformly():
         p = stats.kstest((x[:, k] - lo[k]) / (hi[k] - lo[k]), "uniform").pvalue
         assert p > 1e-3, (k, p)
     ref = model.loglike(ns.to_theta(x), "mixed")
+    # equal up to the last bits of sigma: the chains exponentiate log sigma
+    # on the device, to_theta with numpy
     assert np.allclose(lx, ref, rtol=1e-12, atol=1e-9)
     x2, lx2, ev2, _ = fgl.Chains(model, n, lo, hi, seed=5).run(x0, l0, -np.inf, chol, 20)
     assert np.array_equal(x, x2) and np.array_equal(lx, lx2) and ev == ev2
