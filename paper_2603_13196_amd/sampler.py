@@ -45,6 +45,7 @@ class NSResult:
     dead_logl: np.ndarray           # [n_dead]
     log_weights: np.ndarray         # [n_dead + n_live] normalised posterior log weights
     samples: np.ndarray             # [n_dead + n_live, d] dead points then final live points
+    sample_logl: np.ndarray         # [n_dead + n_live] lnL of each sample
     n_like: int                     # likelihood evaluations
     n_calls: int                    # batched likelihood calls
     iterations: int
@@ -61,6 +62,17 @@ class NSResult:
         mu = (w[:, None] * self.samples).sum(0)
         x = self.samples - mu
         return (w[:, None] * x).T @ x
+
+    def median_loglike(self) -> float:
+        """Median of lnL under the posterior weights: the fit's median a
+        posteriori likelihood that the accuracy criterion (Sec. 5) compares
+        with the noise-only reference distribution.  The smallest sample lnL
+        at which the posterior mass of lnL <= it reaches one half."""
+        order = np.argsort(self.sample_logl, kind="stable")
+        w = np.exp(self.log_weights[order] - self.log_weights.max())
+        c = np.cumsum(w)
+        k = int(np.searchsorted(c, 0.5 * c[-1], side="left"))
+        return float(self.sample_logl[order][k])
 
 
 def expected_logx_decrement(n: int, b: int) -> float:
@@ -249,6 +261,7 @@ def nested_slice_sampling(loglike: Callable[[np.ndarray], np.ndarray],
     return NSResult(logz=float(logz), logz_err=math.sqrt(max(h, 0.0) / n_live),
                     information=h, dead=np.array(dead).reshape(-1, d),
                     dead_logl=np.array(dead_l), log_weights=logp, samples=samples,
+                    sample_logl=logl_all,
                     n_like=like.n, n_calls=like.calls, iterations=it,
                     seconds=time.perf_counter() - t0, logx=logx_hist)
 

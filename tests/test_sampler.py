@@ -48,6 +48,11 @@ def test_gaussian_evidence_and_moments():
     c = r.posterior_cov()
     assert np.all(np.abs(m - mu) < 0.25 * np.sqrt(np.diag(cov)) + 0.01), (m, mu)
     assert np.all(np.abs(np.sqrt(np.diag(c)) / np.sqrt(np.diag(cov)) - 1) < 0.2), np.diag(c)
+    # posterior median of lnL = c - chi2_d median / 2 (Sec. 5 accuracy criterion input)
+    c = -0.5 * (d * math.log(2 * math.pi) + np.linalg.slogdet(cov)[1])
+    med = c - 0.5 * stats.chi2(d).median()
+    assert abs(r.median_loglike() - med) < 0.3, (r.median_loglike(), med)
+    assert r.sample_logl.shape == (r.samples.shape[0],)
     # the recorded volume follows the expected contraction
     assert abs(r.logx[0] - ns.expected_logx_decrement(300, 60)) < 1e-12
     assert abs(r.logx[-1] - r.iterations * ns.expected_logx_decrement(300, 60)) < 1e-9
