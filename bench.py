@@ -55,6 +55,8 @@ def parse():
                    help="skip the region-construction leg (importance, partition, K)")
     p.add_argument("--no-small", action="store_true",
                    help="skip the launch-bound small-batch workloads")
+    p.add_argument("--no-noise", action="store_true",
+                   help="skip the residual-likelihood reference distribution leg")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the FP64 gradient leg")
     p.add_argument("--no-masks", action="store_true",
@@ -313,6 +315,23 @@ def regions_leg(fgl, n_regions=32):
                          "kernel": "k_sky_corr"}}
 
 
+def noise_leg(fgl, n=301 * 96, R=4096, reps=20, sigma=0.025):
+    """Reference distribution of the accuracy criterion (Sec. 5): lnL of R
+    data sets that the model describes up to 25 mK Gaussian noise, n
+    residuals each (the 301-channel, 96-bin grid), drawn and reduced on the
+    device.  The median over reps calls of the kernel's duration."""
+    fgl.fgl_noise_loglike(n, R, sigma, sigma, 0)                 # warm-up
+    kms = []
+    t0 = time.perf_counter()
+    for i in range(reps):
+        kms.append(fgl.fgl_noise_loglike(n, R, sigma, sigma, i + 1, timed=True)[1])
+    dt = (time.perf_counter() - t0) / reps
+    k = float(np.median(kms))
+    return {"realisations": R, "residuals": n, "kernel": "k_noise_lnl", "kernel_ms": k,
+            "call_ms": dt * 1e3, "realisations_per_s": R / (k * 1e-3),
+            "normals_per_s": R * n / (k * 1e-3)}
+
+
 def cpu_leg(w, gpu_out, seconds):
     import oracle
     orc = oracle.load()
@@ -462,6 +481,9 @@ def main():
     if not a.no_regions and not a.no_plain:
         log("region construction leg")
         line["region_construction"] = regions_leg(fgl)
+    if not a.no_noise and not a.no_plain:
+        log("noise reference leg")
+        line["noise_reference"] = noise_leg(fgl)
     if not a.no_serve:
         log("serving leg")
         line["serving"] = serving_leg(fgl, a.serve_seconds)

@@ -389,6 +389,40 @@ int fgl_sky_chromatic(fgl_sky* s, const double* edges, int n_regions,
 int fgl_sky_kernel_ms(const fgl_sky* s, double* ms);
 int fgl_sky_destroy(fgl_sky* s);
 
+/* ---- Residual-likelihood reference distribution (accuracy criterion) ----
+ * Sec. 5 classifies a fit as consistent with noise when its median
+ * posterior lnL is not in the lower q_threshold tail of the likelihood over
+ * data sets that the model describes exactly up to realisations of the
+ * assumed noise (uncorrelated Gaussian).  For data = M(theta) + e the
+ * residual at theta is e, so Eq. likelihood at theta is
+ *   lnl[r] = -sum_{k<n} e_rk^2 / (2 sigma_like^2) - (n/2) ln(2 pi sigma_like^2)
+ * with e_rk = sigma_noise z_rk and n = F T residuals per data set.
+ */
+
+/*
+ * lnL of R noise-only data sets (FP64 host [R]).  The standard normals z_rk
+ * are fixed by (seed, r, k): block b of realisation r is Philox4x64-10
+ * (Salmon et al., SC 2011) of counter (b, r, 0, 0) under key (seed, 0); its
+ * words (x0, x1) and (x2, x3) give normals 4b, 4b+1 and 4b+2, 4b+3 by the
+ * Box-Muller transform with u1 = (floor(x0/2^11) + 1) 2^-53, u2 =
+ * floor(x1/2^11) 2^-53, z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
+ * n in 1..2^40; R in 1..2^24; sigma_noise finite >= 0; sigma_like finite
+ * > 0.  kernel_ms (may be NULL) receives the kernel's duration.
+ * Synchronous.  Returns FGL_OK, FGL_EINVAL, FGL_ENOMEM or FGL_EDEVICE.
+ */
+int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like,
+                      uint64_t seed, double* lnl, double* kernel_ms);
+
+/*
+ * q[i] = #{r < R : lnl_noise[r] <= lbar[i]} / R (host FP64 arrays
+ * lnl_noise [R], lbar [nb], q [nb]): the fraction of the reference
+ * distribution at or below each fit's median lnL.  R >= 1, nb in 1..2^24.
+ * Computed on the device.  Synchronous.  Returns FGL_OK, FGL_EINVAL,
+ * FGL_ENOMEM or FGL_EDEVICE.
+ */
+int fgl_noise_quantile(const double* lnl_noise, int R, const double* lbar,
+                       int nb, double* q);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,232 @@
+// Residual-likelihood reference distribution of the accuracy criterion
+// (Tutt et al., Sec. 5): the likelihood of Eq. likelihood over data sets that
+// the model describes exactly up to uncorrelated Gaussian noise, and the
+// lower-tail fraction q of a fit's median likelihood within it.
+//
+// For data = M(theta) + e the residual at theta is e itself, so realisation r
+// has lnL_r = -(sigma_noise^2 / (2 sigma_like^2)) S_r - (n/2) ln(2 pi
+// sigma_like^2) with S_r = sum_k z_rk^2 over its n standard normals.  The
+// normals come from Philox4x64-10 (Salmon et al., SC 2011; counter (b, r, 0,
+// 0), key (seed, 0)) through the Box-Muller transform; the two normals of one
+// word pair (u1, u2) have z0^2 + z1^2 = -2 ln u1, so a full pair adds
+// -2 ln u1 to S without the trigonometric part, and only a pair cut by the
+// end of the realisation needs the cosine.
+//
+// k_noise_lnl: one workgroup per realisation.  Each thread walks its Philox
+// blocks keeping the product of its u1 values as mantissa and binary
+// exponent (frexp after every block; u1 >= 2^-53, so nothing underflows) and
+// takes one logarithm at the end: per block the work is the generator and
+// two multiplies.  The per-thread sums meet in a fixed shuffle-and-LDS tree.
+// Nothing is read from memory; the kernel is bound by integer multiplies.
+//
+// k_noise_q: one workgroup per fit; its threads count the reference values at
+// or below the fit's lnL in a fixed tree, and q = count / R.
+#include "fgl_host.h"
+
+#include <cmath>
+
+namespace fgl {
+
+namespace {
+
+constexpr int kNoiseThreads = 256;
+constexpr int kNoiseMaxGroups = 1 << 24;           // R and nb: grid of < 2^32 work-items
+constexpr uint64_t kPhM0 = 0xD2E7470EE14C6C93ull;   // Philox4x64 multipliers
+constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;   // Weyl key increments
+constexpr uint64_t kPhW1 = 0xBB67AE8584CAA73Bull;
+
+// Philox4x64-10 of counter (c0, c1, 0, 0) under key (k0, 0).
+__device__ inline void philox4x64(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t x[4]) {
+  uint64_t c2 = 0, c3 = 0, k1 = 0;
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    if (i) {
+      k0 += kPhW0;
+      k1 += kPhW1;
+    }
+    const uint64_t hi0 = __umul64hi(kPhM0, c0), lo0 = kPhM0 * c0;
+    const uint64_t hi1 = __umul64hi(kPhM1, c2), lo1 = kPhM1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  x[0] = c0;
+  x[1] = c1;
+  x[2] = c2;
+  x[3] = c3;
+}
+
+__device__ inline double u_open0(uint64_t w) {   // (0, 1]
+  return (double)((w >> 11) + 1) * 0x1p-53;
+}
+__device__ inline double u_open1(uint64_t w) {   // [0, 1)
+  return (double)(w >> 11) * 0x1p-53;
+}
+
+// lnL of realisations 0..R-1, one per workgroup.
+__global__ __launch_bounds__(kNoiseThreads) void k_noise_lnl(int64_t n, uint64_t seed,
+                                                             double sigma_noise,
+                                                             double sigma_like, double* out) {
+  const uint64_t r = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t nfull = n >> 2;                 // blocks whose four normals all count
+  double p = 1.0;                               // product of u1, times 2^-e
+  int e = 0;
+  for (int64_t b = tid; b < nfull; b += kNoiseThreads) {
+    uint64_t x[4];
+    philox4x64((uint64_t)b, r, seed, x);
+    p *= u_open0(x[0]);
+    p *= u_open0(x[2]);
+    int ex;
+    p = frexp(p, &ex);
+    e += ex;
+  }
+  // S contribution of the full pairs: -2 sum ln u1
+  double s = -2.0 * (log(p) + (double)e * 0.69314718055994530942);
+  const int tail = (int)(n & 3);
+  if (tail && tid == 0) {
+    uint64_t x[4];
+    philox4x64((uint64_t)nfull, r, seed, x);
+    const double rho2a = -2.0 * log(u_open0(x[0]));
+    if (tail == 1) {
+      const double c = cospi(2.0 * u_open1(x[1]));
+      s += rho2a * c * c;
+    } else {
+      s += rho2a;
+      if (tail == 3) {
+        const double c = cospi(2.0 * u_open1(x[3]));
+        s += -2.0 * log(u_open0(x[2])) * c * c;
+      }
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+  __shared__ double part[kNoiseThreads / 64];
+  if ((tid & 63) == 0) part[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    const double S = (part[0] + part[1]) + (part[2] + part[3]);
+    const double v = sigma_like * sigma_like;
+    out[r] = -(sigma_noise * sigma_noise) / (2.0 * v) * S -
+             0.5 * (double)n * log(6.28318530717958647693 * v);
+  }
+}
+
+// q[i] = #{r : ref[r] <= lbar[i]} / R, one workgroup per i.
+__global__ __launch_bounds__(kNoiseThreads) void k_noise_q(const double* __restrict__ ref, int R,
+                                                           const double* __restrict__ lbar,
+                                                           double* __restrict__ q) {
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const double x = lbar[i];
+  int c = 0;
+  for (int r = tid; r < R; r += kNoiseThreads) c += ref[r] <= x ? 1 : 0;
+  for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+  __shared__ int part[kNoiseThreads / 64];
+  if ((tid & 63) == 0) part[tid >> 6] = c;
+  __syncthreads();
+  if (tid == 0) q[i] = (double)((part[0] + part[1]) + (part[2] + part[3])) / (double)R;
+}
+
+// Device buffers and a stream for one synchronous call.
+struct Call {
+  hipStream_t s = nullptr;
+  void* buf[3] = {nullptr, nullptr, nullptr};
+  ~Call() {
+    if (s) (void)hipStreamSynchronize(s);
+    for (void* b : buf)
+      if (b) (void)hipFree(b);
+    if (s) (void)hipStreamDestroy(s);
+  }
+  int open() {
+    int dev = 0;
+    const int rc = check_device(&dev);
+    if (rc != FGL_OK) return rc;
+    const hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      s = nullptr;
+      return hip_err(e, "hipStreamCreate");
+    }
+    return FGL_OK;
+  }
+  int alloc(int k, size_t bytes) {
+    const hipError_t e = hipMalloc(&buf[k], bytes);
+    if (e != hipSuccess) {
+      buf[k] = nullptr;
+      return hip_err(e, "hipMalloc");
+    }
+    return FGL_OK;
+  }
+};
+
+}  // namespace
+
+}  // namespace fgl
+
+using namespace fgl;
+
+extern "C" {
+
+int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like, uint64_t seed,
+                      double* lnl, double* kernel_ms) {
+  if (!lnl) return set_err(FGL_EINVAL, "lnl is NULL");
+  if (n < 1 || n > ((int64_t)1 << 40)) return set_err(FGL_EINVAL, "n=%lld outside 1..2^40", (long long)n);
+  if (R < 1 || R > kNoiseMaxGroups)
+    return set_err(FGL_EINVAL, "R=%d outside 1..%d", R, kNoiseMaxGroups);
+  if (!(sigma_noise >= 0.0) || !std::isfinite(sigma_noise) || !(sigma_like > 0.0) ||
+      !std::isfinite(sigma_like))
+    return set_err(FGL_EINVAL, "need finite sigma_noise >= 0 and sigma_like > 0");
+  Call c;
+  int rc = c.open();
+  if (rc == FGL_OK) rc = c.alloc(0, (size_t)R * 8);
+  if (rc != FGL_OK) return rc;
+  double* d_out = static_cast<double*>(c.buf[0]);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms) {
+    // timing only: no system-scope fence around the kernel
+    (void)hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+    (void)hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    (void)hipEventRecord(e0, c.s);
+  }
+  hipLaunchKernelGGL(k_noise_lnl, dim3(R), dim3(kNoiseThreads), 0, c.s, n, seed, sigma_noise,
+                     sigma_like, d_out);
+  hipError_t e = hipGetLastError();
+  if (kernel_ms && e == hipSuccess) (void)hipEventRecord(e1, c.s);
+  if (e == hipSuccess) e = hipMemcpyAsync(lnl, d_out, (size_t)R * 8, hipMemcpyDeviceToHost, c.s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+  if (kernel_ms && e == hipSuccess) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *kernel_ms = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e == hipSuccess ? FGL_OK : hip_err(e, "noise likelihood kernel");
+}
+
+int fgl_noise_quantile(const double* lnl_noise, int R, const double* lbar, int nb, double* q) {
+  if (!lnl_noise || !lbar || !q) return set_err(FGL_EINVAL, "arrays must be non-NULL");
+  if (R < 1 || nb < 1 || nb > kNoiseMaxGroups)
+    return set_err(FGL_EINVAL, "need R >= 1 and nb in 1..%d", kNoiseMaxGroups);
+  Call c;
+  int rc = c.open();
+  if (rc == FGL_OK) rc = c.alloc(0, (size_t)R * 8);
+  if (rc == FGL_OK) rc = c.alloc(1, (size_t)nb * 8);
+  if (rc == FGL_OK) rc = c.alloc(2, (size_t)nb * 8);
+  if (rc != FGL_OK) return rc;
+  double* d_ref = static_cast<double*>(c.buf[0]);
+  double* d_lbar = static_cast<double*>(c.buf[1]);
+  double* d_q = static_cast<double*>(c.buf[2]);
+  hipError_t e = hipMemcpyAsync(d_ref, lnl_noise, (size_t)R * 8, hipMemcpyHostToDevice, c.s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_lbar, lbar, (size_t)nb * 8, hipMemcpyHostToDevice, c.s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_noise_q, dim3(nb), dim3(kNoiseThreads), 0, c.s, d_ref, R, d_lbar, d_q);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(q, d_q, (size_t)nb * 8, hipMemcpyDeviceToHost, c.s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+  return e == hipSuccess ? FGL_OK : hip_err(e, "noise quantile kernel");
+}
+
+}  // extern "C"

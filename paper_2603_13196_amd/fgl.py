@@ -101,6 +101,9 @@ _SIGS = {
                            _dp], ctypes.c_int),
     "fgl_sky_kernel_ms": ([_vp, _dp], ctypes.c_int),
     "fgl_sky_destroy": ([_vp], ctypes.c_int),
+    "fgl_noise_loglike": ([ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_uint64, _dp, _dp], ctypes.c_int),
+    "fgl_noise_quantile": ([_dp, ctypes.c_int, _dp, ctypes.c_int, _dp], ctypes.c_int),
     "fgl_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -504,3 +507,24 @@ class SkyModel:
                 _lib.fgl_sky_destroy(self.handle)
         except Exception:
             pass
+
+
+def fgl_noise_loglike(n: int, R: int, sigma_noise: float, sigma_like: float,
+                      seed: int = 0, timed: bool = False):
+    """lnL [R] of noise-only data sets of n residuals (accuracy criterion,
+    Sec. 5); with timed=True also the kernel's duration in ms."""
+    out = np.empty(int(R), dtype=np.float64)
+    ms = ctypes.c_double(0.0)
+    _check(_lib.fgl_noise_loglike(int(n), int(R), float(sigma_noise), float(sigma_like),
+                                  int(seed) & 0xFFFFFFFFFFFFFFFF, out.ctypes.data_as(_dp),
+                                  ctypes.byref(ms) if timed else None))
+    return (out, ms.value) if timed else out
+
+
+def fgl_noise_quantile(lnl_noise, lbar) -> np.ndarray:
+    """q = fraction of lnl_noise at or below each lbar (computed on the device)."""
+    ref, lb = _f64(lnl_noise).ravel(), _f64(lbar).ravel()
+    q = np.empty(lb.size, dtype=np.float64)
+    _check(_lib.fgl_noise_quantile(ref.ctypes.data_as(_dp), ref.size, lb.ctypes.data_as(_dp),
+                                   lb.size, q.ctypes.data_as(_dp)))
+    return q

@@ -67,6 +67,21 @@ def test_last_error_without_device_call(libpath):
         assert what in fgl.fgl_last_error(), fgl.fgl_last_error()
 
 
+@pytest.mark.parametrize("args", [
+    (0, 1, 0.025, 0.025), (2**40 + 1, 1, 0.025, 0.025), (4, 0, 0.025, 0.025),
+    (4, 2**24 + 1, 0.025, 0.025), (4, 1, -1.0, 0.025), (4, 1, 0.025, 0.0),
+    (4, 1, float("nan"), 0.025), (4, 1, 0.025, float("inf")),
+])
+def test_noise_entry_rejects_bad_arguments(libpath, args):
+    from paper_2603_13196_amd import fgl
+    with pytest.raises(fgl.FGLError) as e:
+        fgl.fgl_noise_loglike(*args)
+    assert e.value.code == fgl.FGL_EINVAL
+    for ref, lbar in (([], [1.0]), ([1.0], [])):
+        with pytest.raises(fgl.FGLError) as e:
+            fgl.fgl_noise_quantile(ref, lbar)
+        assert e.value.code == fgl.FGL_EINVAL
+
 def test_binding_fails_loudly_without_library(tmp_path, libpath):
     pkg = tmp_path / "pkgcopy"
     pkg.mkdir()
