@@ -1,7 +1,8 @@
 """Pins of the residual-likelihood oracle (accuracy criterion, Sec. 5).
 
 - The generator against numpy's own Philox4x64-10 bit generator (an
-  implementation of the same published generator, written independently).
+  implementation of the same published generator, written independently),
+  and the counter layout of the normals through that generator.
 - The normals against the standard normal law (Kolmogorov-Smirnov), and the
   reference lnL against the chi-squared law with n degrees of freedom that
   the sum of n squared standard normals follows.
@@ -9,8 +10,12 @@
   the parameters that generated data = model + noise: the definition of the
   reference distribution, through an independent code path.
 - The quantile q against brute-force special cases.
+
+Every pin takes the oracle module as an argument, so that copies of it with
+a planted mistake can be run through the same pins.
 """
 import math
+import types
 
 import numpy as np
 import pytest
@@ -20,84 +25,140 @@ import oracle
 import workload
 from oracle import noise as nz
 
-
-@pytest.mark.parametrize("key,ctr", [
+PHILOX_CASES = [
     ((1, 2), (5, 0, 0, 0)),
     ((0, 0), (1, 0, 0, 0)),
     ((2**64 - 1, 0x123), (2**64 - 16, 7, 9, 2**64 - 1)),
     ((0x0123456789ABCDEF, 2**63), (2**40 + 3, 2**63 + 5, 0, 12345)),
-])
-def test_philox_matches_numpy_bit_generator(key, ctr):
-    # numpy's Philox increments its counter before each block, so start it
-    # one below the block wanted
-    g = np.random.Philox(key=np.array(key, dtype=np.uint64),
-                         counter=np.array([ctr[0] - 1, *ctr[1:]], dtype=np.uint64))
-    ref = g.random_raw(8)
-    c2 = (ctr[0] + 1, *ctr[1:])
-    got = nz.philox4x64(np.array([ctr, c2], dtype=np.uint64), key).reshape(-1)
-    assert np.array_equal(got, ref)
+]
 
 
-def test_normals_are_standard_normal():
-    z = np.concatenate([nz.normals(50_001, r, 7) for r in range(4)])
+def pin_philox(m):
+    for key, ctr in PHILOX_CASES:
+        # numpy's Philox increments its counter before each block, so start it
+        # one below the block wanted
+        g = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                             counter=np.array([ctr[0] - 1, *ctr[1:]], dtype=np.uint64))
+        ref = g.random_raw(8)
+        c2 = (ctr[0] + 1, *ctr[1:])
+        got = m.philox4x64(np.array([ctr, c2], dtype=np.uint64), key).reshape(-1)
+        assert np.array_equal(got, ref), key
+
+
+def pin_layout(m):
+    # block b of realisation r is Philox of counter (b, r, 0, 0) under key
+    # (seed, 0); normals 2j and 2j+1 share u1 = (x0 / 2^11 + 1) 2^-53 from
+    # the first word of pair j.  numpy's generator gives the words: started
+    # at counter (2^64 - 1, r - 1) it carries into (0, r) for block 0.
+    r, seed, nblk = 3, 11, 600
+    g = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                         counter=np.array([2**64 - 1, r - 1, 0, 0], dtype=np.uint64))
+    words = g.random_raw(4 * nblk).reshape(-1, 2)
+    u1 = ((words[:, 0] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    z = m.normals(4 * nblk, r, seed)
+    np.testing.assert_allclose(z[0::2] ** 2 + z[1::2] ** 2, -2.0 * np.log(u1), rtol=1e-12)
+    # a prefix of a realisation does not depend on its length; realisations
+    # and seeds differ
+    a = m.normals(13, 3, 11)
+    for n in (1, 2, 3, 4, 5, 8, 12):
+        assert np.array_equal(m.normals(n, 3, 11), a[:n])
+    assert not np.array_equal(m.normals(13, 4, 11), a)
+    assert not np.array_equal(m.normals(13, 3, 12), a)
+
+
+def pin_normals(m):
+    z = np.concatenate([m.normals(50_001, r, 7) for r in range(4)])
+    assert np.all(np.isfinite(z))
     assert stats.kstest(z, "norm").pvalue > 1e-3
     assert abs(z.mean()) < 5.0 / math.sqrt(z.size)
     assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / z.size)
-    # pairs from one (u1, u2) are uncorrelated
-    assert abs(np.corrcoef(z[0::2], z[1::2])[0, 1]) < 5.0 / math.sqrt(z.size / 2)
+    # the two normals of a pair are uncorrelated, and so are their squares
+    k = 5.0 / math.sqrt(z.size / 2)
+    assert abs(np.corrcoef(z[0::2], z[1::2])[0, 1]) < k
+    assert abs(np.corrcoef(z[0::2] ** 2, z[1::2] ** 2)[0, 1]) < k
 
 
-def test_normals_layout():
-    # a prefix of a realisation does not depend on its length; realisations
-    # and seeds differ
-    a = nz.normals(13, 3, 11)
-    for n in (1, 2, 3, 4, 5, 8, 12):
-        assert np.array_equal(nz.normals(n, 3, 11), a[:n])
-    assert not np.array_equal(nz.normals(13, 4, 11), a)
-    assert not np.array_equal(nz.normals(13, 3, 12), a)
-    # word pairs: normals 2j and 2j+1 share rho
-    z = nz.normals(4000, 0, 5)
-    rho2 = z[0::2] ** 2 + z[1::2] ** 2
-    ctr = np.zeros((1000, 4), dtype=np.uint64)
-    ctr[:, 0] = np.arange(1000, dtype=np.uint64)
-    x = nz.philox4x64(ctr, (5, 0)).reshape(-1, 2)
-    u1 = ((x[:, 0] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
-    np.testing.assert_allclose(rho2, -2.0 * np.log(u1), rtol=1e-13)
-
-
-def test_noise_loglike_is_chi_squared():
+def pin_chi2(m):
     n, R, s_n, s_l = 60, 600, 0.025, 0.03
-    lnl = nz.noise_loglike(n, R, s_n, s_l, seed=3)
+    lnl = m.noise_loglike(n, R, s_n, s_l, seed=3)
     norm = 0.5 * n * math.log(2.0 * math.pi * s_l * s_l)
     chi2 = -2.0 * (lnl + norm) * s_l * s_l / (s_n * s_n)
     assert stats.kstest(chi2, stats.chi2(n).cdf).pvalue > 1e-3
     assert abs(chi2.mean() - n) < 5.0 * math.sqrt(2.0 * n / R)
 
 
-@pytest.mark.parametrize("T", [1, 4])
-def test_noise_loglike_is_the_likelihood_of_model_plus_noise(T):
+def pin_likelihood(m, T=4):
     w = workload.make(4, workload.freq_grid(50.0, 200.0, 1.0), T, 2,
                       workload.SEED_BASE + 41)
     orc = oracle.load()
     F = w.freqs.size
     n, R, s_n, s_l, seed = F * T, 5, 0.025, 0.02, 99
-    m = orc.model(w.K, w.freqs, w.nu_ref, w.t_cmb, w.truth)
+    mod = orc.model(w.K, w.freqs, w.nu_ref, w.t_cmb, w.truth)
     row = w.truth.copy()
     row[-1] = s_l
-    ref = np.array([orc.loglike(w.K, w.freqs, m + s_n * nz.normals(n, r, seed).reshape(F, T),
+    ref = np.array([orc.loglike(w.K, w.freqs, mod + s_n * m.normals(n, r, seed).reshape(F, T),
                                 w.nu_ref, w.t_cmb, row[None, :])[0] for r in range(R)])
-    got = nz.noise_loglike(n, R, s_n, s_l, seed)
+    got = m.noise_loglike(n, R, s_n, s_l, seed)
     np.testing.assert_allclose(got, ref, rtol=1e-9)
 
 
-def test_quantile_special_cases():
+def pin_quantile(m):
     rng = np.random.default_rng(1)
     ref = rng.normal(size=1000)
     srt = np.sort(ref)
-    assert nz.quantile(ref, [srt[0] - 1.0])[0] == 0.0
-    assert nz.quantile(ref, [srt[-1]])[0] == 1.0
+    assert m.quantile(ref, [srt[0] - 1.0])[0] == 0.0
+    assert m.quantile(ref, [srt[-1]])[0] == 1.0
     k = np.array([0, 9, 499, 998])
-    np.testing.assert_array_equal(nz.quantile(ref, srt[k]), (k + 1) / 1000.0)
+    np.testing.assert_array_equal(m.quantile(ref, srt[k]), (k + 1) / 1000.0)
     # ties count as "at or below"
-    np.testing.assert_array_equal(nz.quantile([1.0, 1.0, 2.0, 3.0], [1.0, 0.5, 2.5]),
+    np.testing.assert_array_equal(m.quantile([1.0, 1.0, 2.0, 3.0], [1.0, 0.5, 2.5]),
                                   [0.5, 0.0, 0.75])
+
+
+PINS = [pin_philox, pin_layout, pin_normals, pin_chi2, pin_likelihood, pin_quantile]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
+def test_pin(pin):
+    pin(nz)
+
+
+def test_likelihood_identity_time_integrated():
+    pin_likelihood(nz, T=1)
+
+
+# Plausible mistakes, each planted into a copy of the oracle's source.
+MUTANTS = {
+    "philox multiplier": ("0xD2E7470EE14C6C93", "0xD2E7470EE14C6C95"),
+    "key bumped before the first round": ("            if rnd:\n", "            if True:\n"),
+    "round outputs swapped": ("(hi1 ^ c1 ^ np.uint64(k0), lo1,", "(lo1, hi1 ^ c1 ^ np.uint64(k0),"),
+    "realisation in the wrong counter word": ("ctr[:, 1] = np.uint64(r)", "ctr[:, 2] = np.uint64(r)"),
+    "cosine for both normals": ("rho * np.sin(ang)", "rho * np.cos(ang)"),
+    "u2 from the first word": ("u2 = (x[:, 1] >>", "u2 = (x[:, 0] >>"),
+    "u1 scale": ("+ 1.0) * scale", "+ 1.0) * scale * 2.0"),
+    "normalisation without the half": ("norm = 0.5 * n * math.log", "norm = n * math.log"),
+    "quadratic term without the 2": ("/ (2.0 * sigma_like * sigma_like)", "/ (sigma_like * sigma_like)"),
+    "noise scaled by sigma_like": ("e = sigma_noise * normals", "e = sigma_like * normals"),
+    "strict quantile": ("ref <= x", "ref < x"),
+}
+
+
+def _mutant(old, new):
+    src = open(nz.__file__).read()
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("noise_mutant")
+    exec(compile(src.replace(old, new), "noise_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_every_planted_mistake_is_caught(name):
+    mod = _mutant(*MUTANTS[name])
+    caught = []
+    for pin in PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except (AssertionError, ValueError, FloatingPointError):
+            caught.append(pin.__name__)
+    assert caught, f"no pin catches: {name}"
