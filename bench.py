@@ -188,11 +188,19 @@ def sampler_leg(fgl, regions=10, T=1):
     l_truth = float(m.loglike(ns.to_theta(zt), "mixed")[0])
     ch.engine.close()
     m.close()
+    # accuracy criterion (Sec. 5): the fit's median posterior lnL against 4096
+    # noise-only data sets at the simulated noise level
+    sig = float(w.truth[-1])
+    ref = fgl.fgl_noise_loglike(w.F * T, 4096, sig, sig, seed=regions * 1000 + T)
+    lbar = r.median_loglike()
+    q, q_truth = fgl.fgl_noise_quantile(ref, [lbar, l_truth])
     return {"model": f"N{regions}_F{w.F}_T{T}", "d": d, "n_live": n_live, "num_delete": b,
             "num_inner_steps": inner, "seconds": dt, "iterations": r.iterations,
             "likelihood_evals": r.n_like, "evals_per_s": r.n_like / dt,
             "logz": r.logz, "logz_err": r.logz_err,
-            "max_lnL_found": float(r.dead_logl.max()), "lnL_at_truth": l_truth}
+            "max_lnL_found": float(r.dead_logl.max()), "lnL_at_truth": l_truth,
+            "accuracy": {"median_lnL": lbar, "q": float(q), "q_at_truth": float(q_truth),
+                         "passes": bool(q >= 0.01)}}
 
 
 def masks_leg(fgl, steps, warmup, tune):
