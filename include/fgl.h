@@ -406,8 +406,9 @@ int fgl_sky_destroy(fgl_sky* s);
  * words (x0, x1) and (x2, x3) give normals 4b, 4b+1 and 4b+2, 4b+3 by the
  * Box-Muller transform with u1 = (floor(x0/2^11) + 1) 2^-53, u2 =
  * floor(x1/2^11) 2^-53, z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
- * n in 1..2^40; R in 1..2^24; sigma_noise finite >= 0; sigma_like finite
- * > 0.  kernel_ms (may be NULL) receives the kernel's duration.
+ * n in 1..2^31; R in 1..2^24; n R <= 2^40 (a call runs at most a few
+ * seconds); sigma_noise finite >= 0; sigma_like finite > 0.  kernel_ms (may
+ * be NULL) receives the kernel's duration.
  * Synchronous.  Returns FGL_OK, FGL_EINVAL, FGL_ENOMEM or FGL_EDEVICE.
  */
 int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like,

@@ -31,6 +31,8 @@ namespace {
 
 constexpr int kNoiseThreads = 256;
 constexpr int kNoiseMaxGroups = 1 << 24;           // R and nb: grid of < 2^32 work-items
+constexpr int64_t kNoiseMaxN = (int64_t)1 << 31;    // residuals per data set
+constexpr double kNoiseMaxNormals = 1099511627776.0;  // 2^40 per call: about 2 s of work
 constexpr uint64_t kPhM0 = 0xD2E7470EE14C6C93ull;   // Philox4x64 multipliers
 constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;   // Weyl key increments
@@ -171,9 +173,11 @@ extern "C" {
 int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like, uint64_t seed,
                       double* lnl, double* kernel_ms) {
   if (!lnl) return set_err(FGL_EINVAL, "lnl is NULL");
-  if (n < 1 || n > ((int64_t)1 << 40)) return set_err(FGL_EINVAL, "n=%lld outside 1..2^40", (long long)n);
+  if (n < 1 || n > kNoiseMaxN) return set_err(FGL_EINVAL, "n=%lld outside 1..2^31", (long long)n);
   if (R < 1 || R > kNoiseMaxGroups)
     return set_err(FGL_EINVAL, "R=%d outside 1..%d", R, kNoiseMaxGroups);
+  if ((double)n * (double)R > kNoiseMaxNormals)
+    return set_err(FGL_EINVAL, "n R = %.3g normals exceeds 2^40 in one call", (double)n * R);
   if (!(sigma_noise >= 0.0) || !std::isfinite(sigma_noise) || !(sigma_like > 0.0) ||
       !std::isfinite(sigma_like))
     return set_err(FGL_EINVAL, "need finite sigma_noise >= 0 and sigma_like > 0");
