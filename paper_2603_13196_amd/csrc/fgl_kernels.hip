@@ -923,10 +923,12 @@ __global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, doubl
 
 // Row preparation: validate, sanitise, expand the spectral indices (and,
 // with amplitude masks, log2 of the amplitude scales) to one value per
-// region, transposed to [i][b], and record the row constants.  A block of 256 threads takes 64
-// rows: the rows are read coalesced into LDS, one thread per row derives
-// the row record, and all threads write the transposed indices coalesced.
-// Invalid rows are given harmless values (finalize writes -inf for them).
+// region, transposed to [i][b], and record the row constants.  A block of
+// 256 threads takes 16 rows: the rows are read coalesced into LDS, sixteen
+// threads per row check it and derive its bounds, one of them writes the
+// row record, and all threads write the transposed indices in runs of 16
+// consecutive rows.  Invalid rows are given harmless values (finalize
+// writes -inf for them).
 constexpr int kPrepRows = 16;
 
 __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, int B, int Bpad,
