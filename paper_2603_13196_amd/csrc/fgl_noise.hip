@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kNoiseThreads) void k_noise_q(const double* __restr
   const int i = blockIdx.x, tid = threadIdx.x;
   const double x = lbar[i];
   int c = 0;
-  for (int r = tid; r < R; r += kNoiseThreads) c += ref[r] <= x ? 1 : 0;
+  for (int64_t r = tid; r < R; r += kNoiseThreads) c += ref[r] <= x ? 1 : 0;
   for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
   __shared__ int part[kNoiseThreads / 64];
   if ((tid & 63) == 0) part[tid >> 6] = c;
