@@ -7,7 +7,11 @@ over one batch of B parameter rows already resident in HBM.  The headline
 workload is N=32 regions, F=301 channels, T=96 time bins, B=16384 rows,
 mixed precision; the plain FP32 and FP64 forms are timed the same way on
 the same rows, the serving mix is run briefly for its p50/p99 latency, and
-the FP64 CPU oracle is timed on a bounded sample on the host cores.
+the FP64 CPU oracle is timed on a bounded sample on the host cores.  Further
+legs time the kernels of the other parts of the method (small batches, the
+gradient, crossed masks, region construction, the noise reference
+distribution of the accuracy criterion, nested sampling); each has a --no-*
+switch.
 
 Prints ONE JSON line.
 """
