@@ -417,8 +417,8 @@ int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like,
 /*
  * q[i] = #{r < R : lnl_noise[r] <= lbar[i]} / R (host FP64 arrays
  * lnl_noise [R], lbar [nb], q [nb]): the fraction of the reference
- * distribution at or below each fit's median lnL.  R >= 1, nb in 1..2^24.
- * Computed on the device.  Synchronous.  Returns FGL_OK, FGL_EINVAL,
+ * distribution at or below each fit's median lnL (a NaN on either side
+ * never counts).  R >= 1, nb in 1..2^24.  Computed on the device.  Synchronous.  Returns FGL_OK, FGL_EINVAL,
  * FGL_ENOMEM or FGL_EDEVICE.
  */
 int fgl_noise_quantile(const double* lnl_noise, int R, const double* lbar,
