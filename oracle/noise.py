@@ -17,14 +17,13 @@ fraction of these values at or below a fit's median lnL is q_i
 
 Random numbers.  Each realisation r draws its n normals from the
 counter-based generator Philox4x64-10 (Salmon, Moraes, Dror and Shaw,
-"Parallel random numbers: as easy as 1, 2, 3", SC 2011): block b of
-realisation r is Philox on counter (b, r, 0, 0) under key (seed, 0) and
-gives four 64-bit words x0..x3.  Each pair of words (x0, x1), (x2, x3)
-becomes two normals by the Box-Muller transform (Box and Muller 1958):
-u1 = (floor(x0 / 2^11) + 1) 2^-53 in (0, 1], u2 = floor(x1 / 2^11) 2^-53 in
-[0, 1), rho = sqrt(-2 ln u1), z = rho cos(2 pi u2), rho sin(2 pi u2).  Normal
-k of realisation r is word pair k // 2 of block k // 4 (cosine for even k,
-sine for odd k); the last block may be used in part.
+"Parallel random numbers: as easy as 1, 2, 3", SC 2011) under key (seed, 0),
+in two streams: block b of stream s is Philox on counter (b, r, s, 0) and
+gives four 64-bit words.  Normals 2j and 2j+1 are the Box-Muller pair (Box
+and Muller 1958) of u1 = (floor(w / 2^11) + 1) 2^-53 in (0, 1], w the word
+j % 4 of stream-0 block j // 4, and u2 = floor(v / 2^11) 2^-53 in [0, 1),
+v the same word of stream 1: rho = sqrt(-2 ln u1), z = rho cos(2 pi u2),
+rho sin(2 pi u2).  When n is odd the last pair is used in part.
 """
 from __future__ import annotations
 
@@ -78,14 +77,17 @@ def philox4x64(ctr, key):
 
 def normals(n: int, r: int, seed: int) -> np.ndarray:
     """The n standard normals of realisation r (FP64)."""
-    nblk = (n + 3) // 4
+    npair = (n + 1) // 2
+    nblk = (npair + 3) // 4
     ctr = np.zeros((nblk, 4), dtype=np.uint64)
     ctr[:, 0] = np.arange(nblk, dtype=np.uint64)
     ctr[:, 1] = np.uint64(r)
-    x = philox4x64(ctr, (seed, 0)).reshape(-1, 2)            # word pairs
+    w = philox4x64(ctr, (seed, 0)).reshape(-1)[:npair]        # stream 0: u1
+    ctr[:, 2] = np.uint64(1)
+    v = philox4x64(ctr, (seed, 0)).reshape(-1)[:npair]        # stream 1: u2
     scale = 2.0 ** -53
-    u1 = ((x[:, 0] >> np.uint64(11)).astype(np.float64) + 1.0) * scale
-    u2 = (x[:, 1] >> np.uint64(11)).astype(np.float64) * scale
+    u1 = ((w >> np.uint64(11)).astype(np.float64) + 1.0) * scale
+    u2 = (v >> np.uint64(11)).astype(np.float64) * scale
     rho = np.sqrt(-2.0 * np.log(u1))
     ang = 2.0 * math.pi * u2
     z = np.stack([rho * np.cos(ang), rho * np.sin(ang)], axis=-1).reshape(-1)

@@ -6,18 +6,22 @@
 // For data = M(theta) + e the residual at theta is e itself, so realisation r
 // has lnL_r = -(sigma_noise^2 / (2 sigma_like^2)) S_r - (n/2) ln(2 pi
 // sigma_like^2) with S_r = sum_k z_rk^2 over its n standard normals.  The
-// normals come from Philox4x64-10 (Salmon et al., SC 2011; counter (b, r, 0,
-// 0), key (seed, 0)) through the Box-Muller transform; the two normals of one
-// word pair (u1, u2) have z0^2 + z1^2 = -2 ln u1, so a full pair adds
-// -2 ln u1 to S without the trigonometric part, and only a pair cut by the
-// end of the realisation needs the cosine.
+// normals come from Philox4x64-10 (Salmon et al., SC 2011; key (seed, 0),
+// block b of stream s on counter (b, r, s, 0)) through the Box-Muller
+// transform: pair j takes u1 from word j % 4 of stream-0 block j / 4 and u2
+// from the same word of stream 1.  The two normals of a pair have
+// z0^2 + z1^2 = -2 ln u1, so a full pair adds -2 ln u1 to S and needs
+// neither u2 nor any trigonometry: only the stream-0 words are drawn, four
+// pairs (eight normals) per block, and stream 1 and the cosine are touched
+// only for a pair cut by the end of an odd-length realisation.
 //
-// k_noise_lnl: one workgroup per realisation.  Each thread walks its Philox
-// blocks keeping the product of its u1 values as mantissa and binary
-// exponent (frexp after every block; u1 >= 2^-53, so nothing underflows) and
-// takes one logarithm at the end: per block the work is the generator and
-// two multiplies.  The per-thread sums meet in a fixed shuffle-and-LDS tree.
-// Nothing is read from memory; the kernel is bound by integer multiplies.
+// k_noise_lnl: one workgroup per realisation.  Each thread walks its
+// stream-0 blocks keeping the product of its u1 values as mantissa and
+// binary exponent (frexp after every block; u1 >= 2^-53, so four factors
+// never underflow) and takes one logarithm at the end: per block the work
+// is the generator and four multiplies.  The per-thread sums meet in a
+// fixed shuffle-and-LDS tree.  Nothing is read from memory; the kernel is
+// bound by the generator's integer multiplies.
 //
 // k_noise_q: one workgroup per fit; its threads count the reference values at
 // or below the fit's lnL in a fixed tree, and q = count / R.
@@ -38,9 +42,10 @@ constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;   // Weyl key increments
 constexpr uint64_t kPhW1 = 0xBB67AE8584CAA73Bull;
 
-// Philox4x64-10 of counter (c0, c1, 0, 0) under key (k0, 0).
-__device__ inline void philox4x64(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t x[4]) {
-  uint64_t c2 = 0, c3 = 0, k1 = 0;
+// Philox4x64-10 of counter (c0, c1, c2, 0) under key (k0, 0).
+__device__ inline void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t k0,
+                                  uint64_t x[4]) {
+  uint64_t c3 = 0, k1 = 0;
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     if (i) {
@@ -61,6 +66,11 @@ __device__ inline void philox4x64(uint64_t c0, uint64_t c1, uint64_t k0, uint64_
   x[3] = c3;
 }
 
+// word j (0..3) of a block, without indexing the array at run time
+__device__ inline uint64_t word(const uint64_t x[4], int j) {
+  return j == 0 ? x[0] : j == 1 ? x[1] : j == 2 ? x[2] : x[3];
+}
+
 __device__ inline double u_open0(uint64_t w) {   // (0, 1]
   return (double)((w >> 11) + 1) * 0x1p-53;
 }
@@ -74,34 +84,34 @@ __global__ __launch_bounds__(kNoiseThreads) void k_noise_lnl(int64_t n, uint64_t
                                                              double sigma_like, double* out) {
   const uint64_t r = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t nfull = n >> 2;                 // blocks whose four normals all count
+  const int64_t npair = n >> 1;                 // pairs whose two normals both count
+  const int64_t nfull = npair >> 2;             // stream-0 blocks of four such pairs
   double p = 1.0;                               // product of u1, times 2^-e
   int e = 0;
   for (int64_t b = tid; b < nfull; b += kNoiseThreads) {
     uint64_t x[4];
-    philox4x64((uint64_t)b, r, seed, x);
+    philox4x64((uint64_t)b, r, 0, seed, x);
     p *= u_open0(x[0]);
+    p *= u_open0(x[1]);
     p *= u_open0(x[2]);
+    p *= u_open0(x[3]);
     int ex;
     p = frexp(p, &ex);
     e += ex;
   }
   // S contribution of the full pairs: -2 sum ln u1
   double s = -2.0 * (log(p) + (double)e * 0.69314718055994530942);
-  const int tail = (int)(n & 3);
-  if (tail && tid == 0) {
+  const int rem = (int)(npair & 3);             // full pairs in the last block
+  const bool odd = n & 1;                       // and a pair cut in half
+  if ((rem || odd) && tid == 0) {
     uint64_t x[4];
-    philox4x64((uint64_t)nfull, r, seed, x);
-    const double rho2a = -2.0 * log(u_open0(x[0]));
-    if (tail == 1) {
-      const double c = cospi(2.0 * u_open1(x[1]));
-      s += rho2a * c * c;
-    } else {
-      s += rho2a;
-      if (tail == 3) {
-        const double c = cospi(2.0 * u_open1(x[3]));
-        s += -2.0 * log(u_open0(x[2])) * c * c;
-      }
+    philox4x64((uint64_t)nfull, r, 0, seed, x);
+    for (int j = 0; j < rem; ++j) s += -2.0 * log(u_open0(word(x, j)));
+    if (odd) {
+      uint64_t y[4];
+      philox4x64((uint64_t)nfull, r, 1, seed, y);
+      const double c = cospi(2.0 * u_open1(word(y, rem)));
+      s += -2.0 * log(u_open0(word(x, rem))) * c * c;
     }
   }
   for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);

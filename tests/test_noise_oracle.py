@@ -2,7 +2,8 @@
 
 - The generator against numpy's own Philox4x64-10 bit generator (an
   implementation of the same published generator, written independently),
-  and the counter layout of the normals through that generator.
+  and the counter layout of both streams of the normals through that
+  generator.
 - The normals against the standard normal law (Kolmogorov-Smirnov), and the
   reference lnL against the chi-squared law with n degrees of freedom that
   the sum of n squared standard normals follows.
@@ -46,21 +47,29 @@ def pin_philox(m):
 
 
 def pin_layout(m):
-    # block b of realisation r is Philox of counter (b, r, 0, 0) under key
-    # (seed, 0); normals 2j and 2j+1 share u1 = (x0 / 2^11 + 1) 2^-53 from
-    # the first word of pair j.  numpy's generator gives the words: started
-    # at counter (2^64 - 1, r - 1) it carries into (0, r) for block 0.
-    r, seed, nblk = 3, 11, 600
-    g = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
-                         counter=np.array([2**64 - 1, r - 1, 0, 0], dtype=np.uint64))
-    words = g.random_raw(4 * nblk).reshape(-1, 2)
-    u1 = ((words[:, 0] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
-    z = m.normals(4 * nblk, r, seed)
+    # under key (seed, 0), block b of stream s is Philox of counter
+    # (b, r, s, 0); normals 2j and 2j+1 are the Box-Muller pair of
+    # u1 = (w / 2^11 + 1) 2^-53 and u2 = (v / 2^11) 2^-53, w and v word j of
+    # the two streams.  numpy's generator gives the words: started at
+    # counter (2^64 - 1, r - 1, s) it carries into (0, r, s) for block 0.
+    r, seed, nblk = 3, 11, 300
+
+    def words(stream):
+        g = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                             counter=np.array([2**64 - 1, r - 1, stream, 0], dtype=np.uint64))
+        return g.random_raw(4 * nblk)
+
+    u1 = ((words(0) >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (words(1) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    z = m.normals(8 * nblk, r, seed)
     np.testing.assert_allclose(z[0::2] ** 2 + z[1::2] ** 2, -2.0 * np.log(u1), rtol=1e-12)
+    ang = np.mod(np.arctan2(z[1::2], z[0::2]), 2.0 * math.pi)
+    d = np.abs(ang - 2.0 * math.pi * u2)
+    assert np.all(np.minimum(d, 2.0 * math.pi - d) < 1e-9)
     # a prefix of a realisation does not depend on its length; realisations
     # and seeds differ
     a = m.normals(13, 3, 11)
-    for n in (1, 2, 3, 4, 5, 8, 12):
+    for n in (1, 2, 3, 4, 5, 8, 9, 12):
         assert np.array_equal(m.normals(n, 3, 11), a[:n])
     assert not np.array_equal(m.normals(13, 4, 11), a)
     assert not np.array_equal(m.normals(13, 3, 12), a)
@@ -132,9 +141,10 @@ MUTANTS = {
     "philox multiplier": ("0xD2E7470EE14C6C93", "0xD2E7470EE14C6C95"),
     "key bumped before the first round": ("            if rnd:\n", "            if True:\n"),
     "round outputs swapped": ("(hi1 ^ c1 ^ np.uint64(k0), lo1,", "(lo1, hi1 ^ c1 ^ np.uint64(k0),"),
-    "realisation in the wrong counter word": ("ctr[:, 1] = np.uint64(r)", "ctr[:, 2] = np.uint64(r)"),
+    "realisation in the wrong counter word": ("ctr[:, 1] = np.uint64(r)", "ctr[:, 3] = np.uint64(r)"),
+    "one stream for u1 and u2": ("ctr[:, 2] = np.uint64(1)", "ctr[:, 2] = np.uint64(0)"),
     "cosine for both normals": ("rho * np.sin(ang)", "rho * np.cos(ang)"),
-    "u2 from the first word": ("u2 = (x[:, 1] >>", "u2 = (x[:, 0] >>"),
+    "u2 from the u1 words": ("u2 = (v >>", "u2 = (w >>"),
     "u1 scale": ("+ 1.0) * scale", "+ 1.0) * scale * 2.0"),
     "normalisation without the half": ("norm = 0.5 * n * math.log", "norm = n * math.log"),
     "quadratic term without the 2": ("/ (2.0 * sigma_like * sigma_like)", "/ (sigma_like * sigma_like)"),
