@@ -406,7 +406,7 @@ int fgl_sky_destroy(fgl_sky* s);
  * 2j and 2j+1 are the Box-Muller pair of u1 = (floor(w/2^11) + 1) 2^-53 and
  * u2 = floor(v/2^11) 2^-53, w and v the word j % 4 of block j / 4 of
  * streams 0 and 1: z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
- * n in 1..2^31; R in 1..2^24; n R <= 2^40 (a call runs at most a few
+ * n in 1..2^31; R in 1..2^23; n R <= 2^40 (a call runs at most a few
  * seconds); sigma_noise finite >= 0; sigma_like finite > 0.  kernel_ms (may
  * be NULL) receives the kernel's duration.
  * Synchronous.  Returns FGL_OK, FGL_EINVAL, FGL_ENOMEM or FGL_EDEVICE.
@@ -418,7 +418,7 @@ int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like,
  * q[i] = #{r < R : lnl_noise[r] <= lbar[i]} / R (host FP64 arrays
  * lnl_noise [R], lbar [nb], q [nb]): the fraction of the reference
  * distribution at or below each fit's median lnL (a NaN on either side
- * never counts).  R >= 1, nb in 1..2^24.  Computed on the device.  Synchronous.  Returns FGL_OK, FGL_EINVAL,
+ * never counts).  R >= 1, nb in 1..2^23.  Computed on the device.  Synchronous.  Returns FGL_OK, FGL_EINVAL,
  * FGL_ENOMEM or FGL_EDEVICE.
  */
 int fgl_noise_quantile(const double* lnl_noise, int R, const double* lbar,

@@ -95,14 +95,14 @@ def normals(n: int, r: int, seed: int) -> np.ndarray:
 
 
 def noise_loglike(n: int, R: int, sigma_noise: float, sigma_like: float,
-                  seed: int) -> np.ndarray:
-    """lnL_noise of realisations 0..R-1: Eq. likelihood with the residual
-    replaced by sigma_noise times that realisation's normals."""
+                  seed: int, first: int = 0) -> np.ndarray:
+    """lnL_noise of realisations first..first+R-1: Eq. likelihood with the
+    residual replaced by sigma_noise times that realisation's normals."""
     out = np.empty(R, dtype=np.float64)
     norm = 0.5 * n * math.log(2.0 * math.pi * sigma_like * sigma_like)
-    for r in range(R):
-        e = sigma_noise * normals(n, r, seed)
-        out[r] = -np.sum(e * e) / (2.0 * sigma_like * sigma_like) - norm
+    for i in range(R):
+        e = sigma_noise * normals(n, first + i, seed)
+        out[i] = -np.sum(e * e) / (2.0 * sigma_like * sigma_like) - norm
     return out
 
 

@@ -34,7 +34,7 @@ namespace fgl {
 namespace {
 
 constexpr int kNoiseThreads = 256;
-constexpr int kNoiseMaxGroups = 1 << 24;           // R and nb: grid of < 2^32 work-items
+constexpr int kNoiseMaxGroups = 1 << 23;           // R and nb: grids well below 2^32 work-items
 constexpr int64_t kNoiseMaxN = (int64_t)1 << 31;    // residuals per data set
 constexpr double kNoiseMaxNormals = 1099511627776.0;  // 2^40 per call: about 2 s of work
 constexpr uint64_t kPhM0 = 0xD2E7470EE14C6C93ull;   // Philox4x64 multipliers

@@ -70,7 +70,7 @@ def test_last_error_without_device_call(libpath):
 @pytest.mark.parametrize("args", [
     (0, 1, 0.025, 0.025), (2**31 + 1, 1, 0.025, 0.025), (2**30, 1025, 0.025, 0.025),
     (4, 0, 0.025, 0.025),
-    (4, 2**24 + 1, 0.025, 0.025), (4, 1, -1.0, 0.025), (4, 1, 0.025, 0.0),
+    (4, 2**23 + 1, 0.025, 0.025), (4, 1, -1.0, 0.025), (4, 1, 0.025, 0.0),
     (4, 1, float("nan"), 0.025), (4, 1, 0.025, float("inf")),
 ])
 def test_noise_entry_rejects_bad_arguments(libpath, args):

@@ -60,7 +60,7 @@ def test_noise_loglike_full_size_sampled_and_distribution():
     got, ms = _fgl().fgl_noise_loglike(FT, R, s_n, s_n, seed, timed=True)
     assert ms > 0.0
     for r in (0, 1, 2047, 4095):
-        ref = nz.noise_loglike(FT, r + 1, s_n, s_n, seed)[r]
+        ref = nz.noise_loglike(FT, 1, s_n, s_n, seed, first=r)[0]
         assert abs(got[r] - ref) <= _bar(ref, FT), (r, got[r] - ref)
     norm = 0.5 * FT * math.log(2 * math.pi * s_n * s_n)
     chi2 = -2.0 * (got + norm)
@@ -68,6 +68,27 @@ def test_noise_loglike_full_size_sampled_and_distribution():
     assert len(np.unique(got)) == R
     # the same call again gives the same values
     assert np.array_equal(got, _fgl().fgl_noise_loglike(FT, R, s_n, s_n, seed))
+
+
+def test_noise_loglike_largest_sizes():
+    # the most data sets a call takes (2^23, three residuals each: a full
+    # pair and a cut one), and the longest data set (2^31 residuals)
+    fgl = _fgl()
+    R, n, s_n, seed = 2**23, 3, 0.025, 21
+    print(f"noise largest R={R} n={n}", flush=True)
+    got = fgl.fgl_noise_loglike(n, R, s_n, s_n, seed)
+    assert got.shape == (R,) and np.all(np.isfinite(got))
+    for r in (0, 1, 2**22, R - 1):
+        ref = nz.noise_loglike(n, 1, s_n, s_n, seed, first=r)[0]
+        assert abs(got[r] - ref) <= _bar(ref, n), (r, got[r] - ref)
+    norm = 0.5 * n * math.log(2 * math.pi * s_n * s_n)
+    sub = got[np.random.default_rng(0).choice(R, 200_000, replace=False)]
+    assert stats.kstest(-2.0 * (sub + norm), stats.chi2(n).cdf).pvalue > 1e-3
+    n = 2**31
+    print(f"noise largest n={n}", flush=True)
+    one = fgl.fgl_noise_loglike(n, 1, 1.0, 1.0, 5)[0]
+    S = -2.0 * (one + 0.5 * n * math.log(2 * math.pi))
+    assert abs(S - n) < 6.0 * math.sqrt(2.0 * n), (S, n)
 
 
 def test_noise_quantile_is_exact():
