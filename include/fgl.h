@@ -156,7 +156,8 @@ int fgl_mixed_form(const fgl_model* m);
 /*
  * lnL for B rows (Eq. likelihood).
  *   theta  host, FP64 [B][P] (layout above), read during the call only.
- *   B      rows, >= 0 (B = 0 is a no-op).
+ *   B      rows, 0..2^26 (B = 0 is a no-op); the same bound holds for every
+ *          entry point that takes B.
  *   out    host, FP64 [B], written on success.
  *   prec   FGL_PREC_MIXED, FGL_PREC_FP32 or FGL_PREC_FP64.
  * Synchronous: returns when out is written.  Returns FGL_OK, FGL_EINVAL,
@@ -260,7 +261,7 @@ int fgl_serve_create(size_t hbm_budget_bytes, int max_inflight,
                      fgl_server** out);
 
 /*
- * Submit B rows of theta (host) for model m; out_logL (host, [B]) is
+ * Submit B rows (1..2^26) of theta (host) for model m; out_logL (host, [B]) is
  * written before the request is reported done.  theta and out_logL must
  * stay valid until fgl_serve_poll reports done.  *ticket identifies the
  * request.  Returns FGL_OK, FGL_EINVAL, or FGL_EAGAIN when the model alone

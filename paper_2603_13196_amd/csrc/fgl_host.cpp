@@ -885,7 +885,7 @@ size_t fgl_model_bytes(const fgl_model* mh) {
 
 static int check_call(Model* m, int B, int prec) {
   if (!m) return set_err(FGL_EINVAL, "model is NULL");
-  if (B < 0) return set_err(FGL_EINVAL, "B=%d < 0", B);
+  if (B < 0 || B > kMaxRows) return set_err(FGL_EINVAL, "B=%d outside 0..2^26", B);
   if (prec != FGL_PREC_MIXED && prec != FGL_PREC_FP32 && prec != FGL_PREC_FP64)
     return set_err(FGL_EINVAL, "unknown precision %d", prec);
   if (m->dying.load()) return set_err(FGL_EBUSY, "model is being destroyed");

@@ -19,6 +19,9 @@ constexpr int kTabBytes = (kTabSize + 2 * kFracSize) * 8;   // a multiple of 16
 // range bounds the region count of the mixed kernel: 128 for the direct
 // form, 96 for the projected form (which carries one more level).
 constexpr int kMixedMaxN = 128;
+// Rows per call: keeps every grid and row index of the likelihood kernels
+// far inside 32-bit work-item counts (2^26 rows of 36 parameters are 19 GB).
+constexpr int kMaxRows = 1 << 26;
 constexpr int kProjMaxN = 96;
 // Digits of the projected-form matrix and its fixed-point scale: entries
 // are scaled by 2^(kProjBits - eR(nu)) (|entry| < 2^eR) and cut into

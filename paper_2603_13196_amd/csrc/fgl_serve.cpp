@@ -353,7 +353,7 @@ int fgl_serve_submit(fgl_server* sh, fgl_model* mh, const double* theta, int B,
   Server* srv = reinterpret_cast<Server*>(sh);
   Model* m = reinterpret_cast<Model*>(mh);
   if (!srv || !m || !ticket) return set_err(FGL_EINVAL, "server, model and ticket must be non-NULL");
-  if (B < 1) return set_err(FGL_EINVAL, "B=%d < 1", B);
+  if (B < 1 || B > kMaxRows) return set_err(FGL_EINVAL, "B=%d outside 1..2^26", B);
   if (!theta || !out_logL) return set_err(FGL_EINVAL, "theta and out must be non-NULL");
   if (prec != FGL_PREC_MIXED && prec != FGL_PREC_FP32 && prec != FGL_PREC_FP64)
     return set_err(FGL_EINVAL, "unknown precision %d", prec);

@@ -83,6 +83,12 @@ def test_noise_entry_rejects_bad_arguments(libpath, args):
             fgl.fgl_noise_quantile(ref, lbar)
         assert e.value.code == fgl.FGL_EINVAL
 
+def test_batch_size_bound_without_device_call(libpath):
+    from paper_2603_13196_amd import fgl
+    rc = fgl._lib.fgl_loglike_batch(None, None, 2**26 + 1, None, 0)
+    assert rc == fgl.FGL_EINVAL    # a NULL model is refused first
+    assert "NULL" in fgl.fgl_last_error()
+
 def test_binding_fails_loudly_without_library(tmp_path, libpath):
     pkg = tmp_path / "pkgcopy"
     pkg.mkdir()

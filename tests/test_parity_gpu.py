@@ -389,4 +389,10 @@ def test_errors_and_zero_rows(fgl):
     bad[0, 0, 0] = np.nan
     with pytest.raises(fgl.FGLError):
         fgl.Model(bad, w.freqs, w.data)
+    # more than 2^26 rows per call is refused before theta is read
+    small = np.zeros(8)
+    for B in (-1, 2**26 + 1):
+        rc = fgl._lib.fgl_loglike_batch(m.handle, small.ctypes.data_as(fgl._dp), B,
+                                        small.ctypes.data_as(fgl._dp), 0)
+        assert rc == fgl.FGL_EINVAL and "B=" in fgl.fgl_last_error(), B
     m.close()
