@@ -291,7 +291,8 @@ int fgl_serve_destroy(fgl_server* s);
  * parameter row with its last entry (sigma) replaced by log sigma; the prior
  * is uniform over the box [lo, hi] in those coordinates.
  *
- * fgl_chains_create: an engine for model m with room for max_chains chains;
+ * fgl_chains_create: an engine for model m with room for max_chains chains
+ *   (1..2^26);
  *   lo, hi host [P] (finite, lo < hi), copied; seed keys the chains' Philox
  *   random streams.  The model cannot be destroyed while the engine exists
  *   (fgl_model_destroy returns FGL_EBUSY).

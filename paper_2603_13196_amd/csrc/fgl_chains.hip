@@ -487,7 +487,8 @@ int fgl_chains_create(fgl_model* mh, int max_chains, const double* lo, const dou
   *out = nullptr;
   Model* m = reinterpret_cast<Model*>(mh);
   if (!m || !lo || !hi) return set_err(FGL_EINVAL, "model, lo and hi must be non-NULL");
-  if (max_chains < 1) return set_err(FGL_EINVAL, "max_chains=%d < 1", max_chains);
+  if (max_chains < 1 || max_chains > kMaxRows)
+    return set_err(FGL_EINVAL, "max_chains=%d outside 1..2^26", max_chains);
   const int P = m->P;
   if (P > kMaxP) return set_err(FGL_EINVAL, "P=%d exceeds the chains' %d parameters", P, kMaxP);
   for (int k = 0; k < P; ++k)
