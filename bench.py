@@ -388,7 +388,7 @@ def cpu_leg(w, gpu_out, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; "
                                    "--gpus N with N > 1 is not supported",
                           "n_gpus": a.gpus}))
         sys.exit(2)
