@@ -91,6 +91,14 @@ def test_noise_loglike_largest_sizes():
     assert abs(S - n) < 6.0 * math.sqrt(2.0 * n), (S, n)
 
 
+def test_noise_realisation_does_not_depend_on_the_batch():
+    # realisation r is fixed by (seed, r): a smaller batch is a bitwise prefix
+    fgl = _fgl()
+    big = fgl.fgl_noise_loglike(1001, 300, 0.025, 0.02, 77)
+    for R in (1, 7, 256, 299):
+        assert np.array_equal(fgl.fgl_noise_loglike(1001, R, 0.025, 0.02, 77), big[:R]), R
+
+
 def test_noise_quantile_is_exact():
     ref = _fgl().fgl_noise_loglike(1000, 2000, 0.025, 0.025, 5)
     srt = np.sort(ref)
