@@ -90,8 +90,10 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
   };
   // mixed digits [F][4][KC][TT][64][16] and per-channel exponents: K at
   // channel f is scaled by 2^(31 - eK) (|K| < 2^eK), rounded, and cut into
-  // four balanced digits whose top digit must stay within [-127, 127]; if
-  // rounding reaches 128 the channel uses eK + 1.
+  // four balanced digits whose top digit must stay within [-125, 125] (the
+  // bound behind the int32 level sums of the mixed kernel); if rounding
+  // reaches 126 2^24 the channel uses eK + 1.  K values within 2^8 of the
+  // channel's largest are exact.
   m->h_kd.assign((size_t)F * 4 * KC * TT * 1024, 0);
   m->h_eK.assign(F, 0);
   for (int f = 0; f < F; ++f) {
@@ -102,7 +104,7 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
     if (mx > 0.0f) std::frexp((double)mx, &ek);   // mx < 2^ek
     for (;; ++ek) {
       const double q = std::nearbyint(std::ldexp((double)mx, 31 - ek));
-      if (q + (double)0x808080 < 2147483648.0) break;   // top digit <= 127
+      if (q + (double)0x808080 < 126.0 * 16777216.0) break;   // top digit <= 125
     }
     m->h_eK[f] = ek;
     int8_t* base = m->h_kd.data() + (size_t)f * 4 * KC * TT * 1024;
@@ -166,9 +168,9 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
   m->h_D.assign((size_t)F * TT * 32, 0.0);
   for (int f = 0; f < F; ++f)
     for (int t = 0; t < T; ++t) m->h_D[(size_t)f * TT * 32 + t] = data[(size_t)f * T + t];
-  // exponent tables: Q 2^((k - kTabLo)/64) with Q = 2^39 - 2^33, then
+  // exponent tables: Q 2^((k - kTabLo)/64) with Q = 2^47 - 2^41, then
   // 2^(m/64) / (1 - 2^-6) (the unit of the level-0 digit product)
-  const long double Q = 549755813888.0L - 8589934592.0L;
+  const long double Q = 140737488355328.0L - 2199023255552.0L;
   m->h_tab.resize(kTabSize + 2 * kFracSize);
   for (int k = 0; k < kTabSize; ++k)
     m->h_tab[k] = (double)(Q * std::exp2((long double)(k - kTabLo) / 64.0L));
@@ -509,11 +511,11 @@ static int max_waves(Kind k, const DevModel& d) {
 }
 
 // Channels of one reduction group: fixed per (model, precision).  Up to four
-// channels, as many as fit in the LDS budget of a 4-wave workgroup.
+// channels, as many as fit in half a CU's LDS (two workgroups per CU).
 int group_of(Kind k, const DevModel& d) {
   for (int g = 4; g >= 1; --g) {
     Tile t{4, g, g, 2};
-    if (lds_bytes(k, d, t) <= 76 * 1024) return g;
+    if (lds_bytes(k, d, t) <= max_lds_bytes() / 2) return g;
   }
   Tile t{4, 1, 1, 2};
   return lds_bytes(k, d, t) <= max_lds_bytes() ? 1 : 0;

@@ -7,17 +7,17 @@
 namespace fgl {
 
 // Exponent tables of the mixed kernel: tab[k] = Q 2^((k - kTabLo)/64) for
-// k in [0, kTabSize), Q = 2^39 - 2^33 (forty octaves below the row maximum
-// down to the maximum itself), then frac[m] = 2^(m/64) / (1 - 2^-6) for
-// m in [0, 64) at tab[kTabSize + m], then 1 / frac[m] at
-// tab[kTabSize + kFracSize + m].
-constexpr int kTabLo = 2560;
-constexpr int kTabSize = 2562;
+// k in [0, kTabSize), Q = 2^47 - 2^41 (forty-eight octaves below the row
+// maximum, where the power's fixed point ends, up to the maximum itself),
+// then frac[m] = 2^(m/64) / (1 - 2^-6) for m in [0, 64) at
+// tab[kTabSize + m], then 1 / frac[m] at tab[kTabSize + kFracSize + m].
+constexpr int kTabLo = 3072;
+constexpr int kTabSize = 3074;
 constexpr int kFracSize = 64;
 constexpr int kTabBytes = (kTabSize + 2 * kFracSize) * 8;   // a multiple of 16
 // Level sums are kept in int32 accumulators (see fgl_kernels.hip); their
 // range bounds the region count of the mixed kernel: 128 for the direct
-// form, 96 for the projected form (which carries one more level).
+// form, 96 for the projected form (whose matrix has two more digits).
 constexpr int kMixedMaxN = 128;
 // Rows per call: keeps every grid and row index of the likelihood kernels
 // far inside 32-bit work-item counts (2^26 rows of 36 parameters are 19 GB).
@@ -122,9 +122,9 @@ struct DevModel {
   const double* nl2;     // [F] -log2(nu/nu_ref)
   const double* nu;      // [F] MHz
   const double* D;       // [F][TT*32] data, zero padded in t
-  const double* tab;     // [kTabSize + kFracSize] exponent tables
+  const double* tab;     // [kTabSize + 2 kFracSize] exponent tables
   double c1, c2, c3, c4; // Taylor coefficients of 2^(r/64)
-  double c5;             // and its fifth-order term (thin kernel)
+  double c5;             // and its fifth-order term
   // projected form of the mixed kernel (proj = 1): per channel, the rows
   // [sqrt(T) mean_t K ; R] where K~^T = Q R is the QR factorisation of the
   // time-centred responses, and targets [sqrt(T) mean_t D ; (Q^T D~)_0..]

@@ -23,8 +23,8 @@
 //
 // Four arithmetic forms share that skeleton:
 //   k_mixed: exact integer slicing.  The powers are computed in FP64,
-//            rounded to 39-bit fixed point relative to the row's largest
-//            power at the channel and cut into five signed 8-bit digits; the
+//            rounded to 47-bit fixed point relative to the row's largest
+//            power at the channel and cut into six signed 8-bit digits; the
 //            matrix rows (K itself, or an orthonormal projection of it with
 //            N + 1 rows when that is shorter than T) are cut into digits once,
 //            at model creation.  The digit products run as
@@ -94,8 +94,7 @@ __device__ inline void transpose4(uint32_t v0, uint32_t v1, uint32_t v2,
   out[0] = __builtin_amdgcn_perm(d, b, 0x07060302u);  // byte 3
 }
 
-// exp(-z^2/2) in FP32 for the 21-cm profile; its error (~1e-7 relative)
-// is far below what the likelihood can resolve.
+// exp(-z^2/2) in FP32 for the 21-cm profile of the plain FP32 kernel.
 __device__ inline double gauss21(double nu, const RowParams& rp) {
   const float z = (float)((nu - rp.nu0) * rp.inv_w);
   return (double)__builtin_amdgcn_exp2f(-0.7213475204444817f * z * z);
@@ -127,24 +126,34 @@ __device__ inline double pow2_64(double y, const double* t64, const DevModel& m)
 // Digits.  At channel nu a row's powers are normalised by 2^(ymax/64), the
 // row's largest power rounded up to 1/64 octave (ymax from the extreme
 // spectral index), so x_i = P_i / 2^(ymax/64) lies in (0, 1].  Each x_i is
-// rounded to q_i = round(x_i Q), Q = 2^39 - 2^33, and written as five
-// balanced base-256 digits d0..d4 (d0 in [0, 127], the others in
-// [-128, 127]).  One FP64 fma produces all five: t = x Q + (2^52 + 2^31 +
-// 2^23 + 2^15 + 2^7) is an integer-valued double whose low word holds the
-// four low digits offset by 128 and whose high word's low byte holds d0.
+// rounded to q_i = round(x_i Q), Q = 2^47 - 2^41, and written as six
+// balanced base-256 digits d0..d5 (d0 in [0, 127], the others in
+// [-128, 127]).  One FP64 fma produces all six: t = x Q + (2^52 + 2^39 +
+// 2^31 + 2^23 + 2^15 + 2^7) is an integer-valued double whose low word
+// holds d2..d5 offset by 128 and whose high word holds d1 + 128 (byte 0)
+// and d0 (byte 1).  The powers need this width: a power's rounding error is
+// shared by every time bin of the channel, so on rows near the posterior
+// peak, whose residuals carry a coherent part of a few sigma, it adds up
+// over t; 39 bits used most of the tolerance there.
 //
-// Two forms share the power-law code and the digit products.
+// Two forms share the power-law code and the digit products.  S_l is the
+// sum of the digit products of significance l = p + q (power digit p,
+// matrix digit q); levels up to 5 are kept, in three accumulators
+// acc0 = S0 2^8 + S1, acc1 = S2 2^8 + S3, acc2 = S4 2^8 + S5, whose int32
+// sums are exact: each digit is within [-128, 127], d0 within [0, 127].
+// Direct form, top K digit within [-125, 125]: |S4|, |S5| <= 65152 N, so
+// |acc2| <= 257 65152 N + 2^15 < 2^31 for N <= 128 (acc0 and acc1 have
+// more room).  Projected form, top matrix digit within [-64, 64]:
+// |S4| <= 73600 N, |S5| <= 89984 N, so |acc2| < 2^31 for N <= 113.
 //
 // Direct form (the model on the time grid).  The MFMA rows are time bins:
 // K at channel nu is scaled by 2^(31 - eK(nu)) and cut into four digits
-// e0..e3 (e0 in [-127, 127]) once, at model creation.  The fourteen digit
-// products of significance p + q <= 4 run on v_mfma_i32_32x32x32_i8; their
-// int32 sums are exact.  Three accumulators hold them: acc0 = S0 2^8 + S1,
-// acc1 = S2 2^8 + S3, acc2 = S4 (S_l is the sum of the products of
-// significance l); the constant T_CMB + A g of the row enters acc0 and acc1
-// through the shift-adds that combine levels.  Dropped products
-// (significance >= 5) are below 2^-40 of the leading term; the power-law
-// rounding is below 2^-40 of the row's largest power.
+// e0..e3 (e0 in [-125, 125]) once, at model creation.  The eighteen digit
+// products with p + q <= 5 run on v_mfma_i32_32x32x32_i8; the constant
+// T_CMB + A g of the row enters the three accumulators as digits through
+// the shift-adds that combine levels.  Dropped products (significance
+// >= 6) are below 2^-47 of the leading term, as is the power-law rounding
+// relative to the row's largest power.
 //
 // Projected form (the residual in an orthonormal basis of each channel).
 // With Kbar, Dbar the time means at channel nu and K~, D~ the centred
@@ -157,8 +166,7 @@ __device__ inline double pow2_64(double y, const double* t64, const DevModel& m)
 // residual of each row is its target [sqrt(T) (Dbar - c) ; (Q^T D~)_k]
 // minus the row's product with P.  R is not exact in a few digits, so its
 // rows are cut into six digits (46-bit fixed point per channel) and the
-// twenty products of significance <= 5 run, in three accumulators
-// S0 2^8 + S1, S2 2^8 + S3, S4 2^8 + S5.  When N is a multiple of 32 the
+// twenty-one products of significance <= 5 run.  When N is a multiple of 32 the
 // last row of R (a single diagonal entry) is evaluated in FP64 from the
 // same rounded power, so the MFMA rows fill whole tiles.
 
@@ -169,6 +177,7 @@ __global__ __launch_bounds__(W * 64)
 __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
                                                     int nb, int nc) {
   constexpr int ND = PROJ ? kProjDigits : 4;       // digits of the matrix rows
+  constexpr int NP = 6;                            // digits of the powers
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
@@ -212,7 +221,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     }
 
   const double MAGIC = 0x1.8p52;                        // rint via the low word
-  const double DIGITS = 0x1.0p52 + (double)0x80808080u;  // digit offsets
+  const double DIGITS = 0x1.0p52 + (double)0x8080808080ull;  // digit offsets
   double acc_a = 0.0, acc_b = 0.0;
 
   // Per-channel scalars (fetched ahead of use) and the row's state at one
@@ -226,8 +235,8 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   };
   struct Chan {
     double s0, s1, s2, t0, qlast;
-    int c0, c1, ey, fm;
-    i32x4 B[KC][5];
+    int c0, c1, c2, ey, fm;
+    i32x4 B[KC][NP];
   };
   auto fetch = [&](int fi) {
     const int fx = min(fi, m.F - 1);
@@ -235,8 +244,23 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   };
   auto make = [&](const Scal& sc, int fi, Chan& C) {
     const double nl = sc.nl;
-    // row constants at this channel: normalisation, level units, constant term
-    const double c = m.t_cmb + rp.A * gauss21(sc.nu, rp);
+    // row constants at this channel: normalisation, level units, constant
+    // term.  The 21-cm profile is FP64 (its error is shared by all time
+    // bins): exp(-z^2/2) = 2^(y/64), y = -32 z^2 / ln 2, from the power
+    // table and polynomial below (y is clamped at -4096, far below the
+    // table, where the profile is < 2^-48 and takes the table's last entry).
+    const double zg = (sc.nu - rp.nu0) * rp.inv_w;
+    const double yg = fmax(zg * zg * (-32.0 / M_LN2), -4096.0);
+    const double tg = yg + MAGIC;
+    const double rg = yg - (tg - MAGIC);             // |rg| <= 1/2
+    const int jg = max((int)(uint32_t)__double_as_longlong(tg), -kTabLo);
+    double pg = fma(rg, m.c5, m.c4);
+    pg = fma(rg, pg, m.c3);
+    pg = fma(rg, pg, m.c2);
+    pg = fma(rg, pg, m.c1);
+    pg = fma(rg, pg, 1.0);
+    // tab = Q 2^(j/64) with 1/Q = 2^-47 (64/63)
+    const double c = fma(rp.A * (0x1.0p-47 * 64.0 / 63.0), s_tab0[jg] * pg, m.t_cmb);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
     // with amplitude masks the bound adds the row's largest 64 log2 alpha;
     // fl is monotone, so no region's rounded exponent exceeds it
@@ -246,15 +270,19 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     C.ey = ey;
     C.fm = fm;
     C.t0 = 0.0;
-    C.c0 = C.c1 = 0;
+    C.c0 = C.c1 = C.c2 = 0;
     C.qlast = 0.0;
     if constexpr (PROJ) {
-      const double u = ldexp(s_frac[fm], ey + sc.ek + 72 - kProjBits - 39);
+      // unit of the level-0 product: 2^(ymax/64) / Q times 2^(eR - 46)
+      // times its weight 2^80
+      const double u = ldexp(s_frac[fm], ey + sc.ek + 80 - kProjBits - 47);
       C.s0 = u * 0x1.0p-8;
       C.s1 = u * 0x1.0p-24;
       C.s2 = u * 0x1.0p-40;
       C.t0 = m.dbar[fi] - m.sqrtT * c;             // target of the mean row
     } else {
+      // unit of the level-0 product: 2^(ymax/64) / Q times 2^(eK - 31)
+      // times its weight 2^64, i.e. frac[fm] 2^(ey + eK - 14)
       int eu = ey + sc.ek - 14;
       double ic = c * ldexp(s_ifrac[fm], 8 - eu);   // ~ c / unit of acc0
       int ec;
@@ -267,15 +295,19 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       const double u0 = ldexp(s_frac[fm], eu);
       C.s0 = u0 * 0x1.0p-8;
       C.s1 = u0 * 0x1.0p-24;
-      C.s2 = u0 * 0x1.0p-32;
+      C.s2 = u0 * 0x1.0p-40;
       const double c0f = rint(ic);
       C.c0 = (int)c0f;
-      // exact remainder (fma), then to level-3 units; c1 in [-2^15, 2^15]
-      C.c1 = (int)rint(fma(-c0f, C.s0, c) * ldexp(s_ifrac[fm], 24 - eu));
+      // remainders by fma, in acc1 then acc2 units; c1, c2 in [-2^15, 2^15]
+      const double r1 = fma(-c0f, C.s0, c);
+      const double c1f = rint(r1 * ldexp(s_ifrac[fm], 24 - eu));
+      C.c1 = (int)c1f;
+      C.c2 = (int)rint(fma(-c1f, C.s1, r1) * ldexp(s_ifrac[fm], 40 - eu));
     }
-    // Powers 2^(y/64), y = 64 log2(x) <= 0, as tab[round(y)] 2^(r/64).
-    // Exponents below the table (x < 2^-40, all digits zero) take its last
-    // entry, which rounds to zero digits for any |r| <= 1/2.
+    // Powers 2^(y/64), y = 64 log2(x) <= 0, as tab[round(y)] 2^(r/64), the
+    // latter by its Taylor series to fifth order (truncation below 4e-17
+    // relative).  Exponents below the table (x < 2^-48, all digits zero)
+    // take its last entry, which rounds to zero digits for any |r| <= 1/2.
     const double cm = MAGIC - ymax;                 // exact: ymax is an integer
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
@@ -296,26 +328,31 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
         }
         const int jj = max((int)(uint32_t)__double_as_longlong(t), -kTabLo);
         const double T2 = s_tab0[jj];              // Q 2^(jj/64)
-        double p = fma(r, m.c4, m.c3);
+        double p = fma(r, m.c5, m.c4);
+        p = fma(r, p, m.c3);
         p = fma(r, p, m.c2);
         p = fma(r, p, m.c1);
         p = fma(r, p, 1.0);                        // 2^(r/64)
         const double q = fma(T2, p, DIGITS);       // 2^52 + q + offsets
         if (PROJ && kc == KC - 1 && j == 15) C.qlast = q - DIGITS;
         const unsigned long long bits = __double_as_longlong(q);
-        lo[j] = (uint32_t)bits ^ 0x80808080u;      // digits d4 d3 d2 d1
-        hi[j] = (uint32_t)(bits >> 32);            // low byte: d0
+        lo[j] = (uint32_t)bits ^ 0x80808080u;      // digits d2 d3 d4 d5 (byte 3..0)
+        hi[j] = (uint32_t)(bits >> 32);            // byte 1: d0, byte 0: d1 + 128
       }
 #pragma unroll
       for (int m4 = 0; m4 < 4; ++m4) {
         uint32_t o[4];
         transpose4(lo[4 * m4], lo[4 * m4 + 1], lo[4 * m4 + 2], lo[4 * m4 + 3], o);
-        // o[L] holds byte (3 - L) of the low words: d(L+1)
+        // o[L] holds byte (3 - L) of the low words: d(L+2)
 #pragma unroll
-        for (int L = 0; L < 4; ++L) C.B[kc][L + 1][m4] = (int32_t)o[L];
-        const uint32_t h01 = __builtin_amdgcn_perm(hi[4 * m4 + 1], hi[4 * m4], 0x0c0c0400u);
-        const uint32_t h23 = __builtin_amdgcn_perm(hi[4 * m4 + 3], hi[4 * m4 + 2], 0x0c0c0400u);
-        C.B[kc][0][m4] = (int32_t)(h01 | (h23 << 16));
+        for (int L = 0; L < 4; ++L) C.B[kc][L + 2][m4] = (int32_t)o[L];
+        // bytes 0 and 1 of the four high words: x = [h0.0 h0.1 h1.0 h1.1],
+        // y likewise for h2, h3; then d1 = [x.0 x.2 y.0 y.2] (offset 128
+        // removed) and d0 = [x.1 x.3 y.1 y.3]
+        const uint32_t x = __builtin_amdgcn_perm(hi[4 * m4 + 1], hi[4 * m4], 0x05040100u);
+        const uint32_t y = __builtin_amdgcn_perm(hi[4 * m4 + 3], hi[4 * m4 + 2], 0x05040100u);
+        C.B[kc][1][m4] = (int32_t)(__builtin_amdgcn_perm(y, x, 0x06040200u) ^ 0x80808080u);
+        C.B[kc][0][m4] = (int32_t)__builtin_amdgcn_perm(y, x, 0x07050301u);
       }
     }
   };
@@ -328,6 +365,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       for (int kc = 0; kc < KC; ++kc)
         A[L][kc] = *reinterpret_cast<const i32x4*>(kf + ((L * KC + kc) * TT + tt) * 1024);
   };
+  // MF(acc, q, p): the product of matrix digit q and power digit p
 #define MF(acc, q, p) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[q][kc], C.B[kc][p], acc, 0, 0, 0)
   // levels 0, 2 and 4 (no dependence on a shift)
   auto part1 = [&](const i32x4 (&A)[ND][KC], const Chan& C, i32x16& a0, i32x16& a1,
@@ -339,12 +377,12 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     for (int kc = 0; kc < KC; ++kc) {
       MF(a0, 0, 0);
       MF(a1, 0, 2); MF(a1, 1, 1); MF(a1, 2, 0);
-      MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1); MF(a2, 0, 4);
+      MF(a2, 0, 4); MF(a2, 1, 3); MF(a2, 2, 2); MF(a2, 3, 1);
       if constexpr (PROJ) MF(a2, 4, 0);
     }
   };
-  // shift-adds (direct form: with the constant term), then levels 1, 3
-  // (and 5 in the projected form)
+  // shift-adds (direct form: with the constant term's digits), then levels
+  // 1, 3 and 5
   auto part2 = [&](const i32x4 (&A)[ND][KC], const Chan& C, i32x16& a0, i32x16& a1,
                    i32x16& a2) {
     if constexpr (PROJ) {
@@ -354,13 +392,15 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     } else {
       a0 = (i32x16)(((u32x16)a0 << 8u) + (uint32_t)C.c0);
       a1 = (i32x16)(((u32x16)a1 << 8u) + (uint32_t)C.c1);
+      a2 = (i32x16)(((u32x16)a2 << 8u) + (uint32_t)C.c2);
     }
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       MF(a0, 0, 1); MF(a0, 1, 0);
       MF(a1, 0, 3); MF(a1, 1, 2); MF(a1, 2, 1); MF(a1, 3, 0);
+      MF(a2, 0, 5); MF(a2, 1, 4); MF(a2, 2, 3); MF(a2, 3, 2);
       if constexpr (PROJ) {
-        MF(a2, 1, 4); MF(a2, 2, 3); MF(a2, 3, 2); MF(a2, 4, 1); MF(a2, 5, 0);
+        MF(a2, 4, 1); MF(a2, 5, 0);
       }
     }
   };
@@ -411,7 +451,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       // (region N - 1 = 32 KC - 1 is element 15 of the last chunk, g = 1)
       if (m.peel) {
         const int fi = f0 + f;
-        const double v = ldexp(s_frac[C.fm], C.ey - 39) * m.pk[2 * fi];
+        const double v = ldexp(s_frac[C.fm], C.ey - 47) * m.pk[2 * fi];
         const double r = fma(-v, C.qlast, m.pk[2 * fi + 1]);
         acc_a = fma(r, g ? r : 0.0, acc_a);
       }

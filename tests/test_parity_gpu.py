@@ -322,7 +322,7 @@ def test_every_tile_same_bits(fgl):
         for prec in PRECS:
             ref, n = None, 0
             for W in (1, 2, 4, 8):
-                for fc in (1, 2, 4, 8, 16, 32):
+                for fc in range(1, 33):
                     for occ in (2, 3):
                         try:
                             m.set_tile(w.B, prec, W, fc, occ)
