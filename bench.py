@@ -63,6 +63,8 @@ def parse():
                    help="skip the residual-likelihood reference distribution leg")
     p.add_argument("--no-grad", action="store_true",
                    help="skip the FP64 gradient leg")
+    p.add_argument("--no-large", action="store_true",
+                   help="skip the N64 F401 T240 B65536 leg")
     p.add_argument("--no-masks", action="store_true",
                    help="skip the crossed-mask model (2 amplitude x 16 index masks)")
     p.add_argument("--no-tune", action="store_true",
@@ -344,6 +346,116 @@ def noise_leg(fgl, n=301 * 96, R=4096, reps=20, sigma=0.025):
             "normals_per_s": R * n / (k * 1e-3)}
 
 
+def _margins(got, ref, theta, n_ft):
+    """|dlnL| against each bar: the mixed tolerance, and for FP64 1e-9 |lnL|
+    (1e-9 S where the chi-square term and the normalisation cancel to less
+    than a tenth of their magnitude S)."""
+    fin = np.isfinite(ref)
+    got, ref = np.asarray(got)[fin], np.asarray(ref)[fin]
+    sig = np.asarray(theta)[fin, -1]
+    d = np.abs(got - ref)
+    tol_m = 1e-6 * np.abs(ref) + 1e-3
+    norm = -0.5 * n_ft * np.log(2.0 * np.pi * sig * sig)
+    S = np.abs(ref - norm) + np.abs(norm)
+    tol_64 = 1e-9 * np.where(np.abs(ref) >= 0.1 * S, np.abs(ref), S)
+    return d, tol_m, tol_64
+
+
+def parity_record(fgl, orc, name, rows=1024):
+    """Every precision and form against the oracle on the named workload's
+    posterior shell (the regime where precision bites) and on the shell of
+    its full-rank variant (several time harmonics and a per-value scatter
+    per region): max |dlnL|, max and p99 of |dlnL| / tolerance, pass/fail."""
+    import workload
+    out = {}
+    for label, rich in (("shell", False), ("shell_full_rank", True)):
+        w = workload.posterior_shell(name, rows, rich=rich)
+        ref = orc.loglike_w(w)
+        rec = {"rows": w.B}
+        models = {"": fgl.Model.from_workload(w),
+                  "direct": fgl.Model.from_workload(w, fgl.FGL_MIXED_DIRECT),
+                  "plain_projected": fgl.Model.from_workload(w, fgl.FGL_PLAIN_PROJECTED)}
+        evals = {"mixed_" + models[""].form: models[""].loglike(w.theta, "mixed"),
+                 "mixed_direct": models["direct"].loglike(w.theta, "mixed"),
+                 "fp64_direct": models["direct"].loglike(w.theta, "fp64"),
+                 "fp64_projected": models["plain_projected"].loglike(w.theta, "fp64"),
+                 "fp32_direct": models["direct"].loglike(w.theta, "fp32"),
+                 "fp32_projected": models["plain_projected"].loglike(w.theta, "fp32")}
+        for mm in models.values():
+            mm.close()
+        for key, got in evals.items():
+            d, tol_m, tol_64 = _margins(got, ref, w.theta, w.F * w.T)
+            r = {"max_abs_dlogL": float(d.max())}
+            if key.startswith("fp64"):
+                r.update(max_over_fp64_bar=float((d / tol_64).max()),
+                         within_fp64_bar=bool(np.all(d <= tol_64)))
+            else:
+                r.update(max_over_mixed_tol=float((d / tol_m).max()),
+                         p99_over_mixed_tol=float(np.quantile(d / tol_m, 0.99)),
+                         within_mixed_tol=bool(np.all(d <= tol_m)))
+            rec[key] = r
+        out[label] = rec
+    out["bars"] = {"mixed": "1e-6|lnL| + 1e-3",
+                   "fp64": "1e-9|lnL| (1e-9 S on rows whose two terms cancel below S/10)",
+                   "fp32": "reported against the mixed tolerance"}
+    return out
+
+
+def large_leg(fgl, orc, steps, warmup, tune):
+    """N=64, F=401 (50-250 MHz), T=240, B=65536: the mixed kernel in both
+    forms against plain FP32 in both forms, the oracle on 256 prior and 256
+    posterior-shell rows, and the mixed kernel's roofline."""
+    import torch
+    import workload
+    w = workload.config(workload.LARGE)
+    th = torch.from_numpy(w.theta).cuda()
+    out = torch.empty(w.B, dtype=torch.float64, device="cuda")
+    res, outs = {}, {}
+    for label, flags, precs in (("", 0, ("mixed",)),
+                                ("direct", fgl.FGL_MIXED_DIRECT, ("mixed", "fp32")),
+                                ("plain_projected", fgl.FGL_PLAIN_PROJECTED, ("fp32",))):
+        m = fgl.Model.from_workload(w, flags)
+        form = m.form
+        for prec in precs:
+            if tune:
+                m.tune(w.B, prec)
+            key = f"{prec}_{form}" if prec == "mixed" else f"{prec}_{'projected' if label == 'plain_projected' else 'direct'}"
+            res[key] = time_prec(fgl, m, th, out, prec, steps, warmup)
+            outs[key] = out.cpu().numpy().copy()
+            log(f"large {key}: {res[key]['evals_per_s']:.4e} evals/s, kernel {res[key]['kernel_ms']:.4f} ms")
+        m.close()
+    rng = np.random.Generator(np.random.PCG64(9))
+    idx = np.sort(rng.choice(w.B, 256, replace=False))
+    ref = orc.loglike_w(w, w.theta[idx])
+    line = {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "B": w.B}
+    for key, r in res.items():
+        d, tol_m, _ = _margins(outs[key][idx], ref, w.theta[idx], w.F * w.T)
+        line[key] = {"value": r["evals_per_s"], "ms_per_step": r["ms_per_step"],
+                     "kernel_ms": r["kernel_ms"],
+                     "prior_rows_max_over_mixed_tol": float((d / tol_m).max())}
+    sh = workload.posterior_shell(workload.LARGE, 256)
+    ref_sh = orc.loglike_w(sh)
+    for label, flags, prec in (("mixed_projected", 0, "mixed"),
+                               ("mixed_direct", fgl.FGL_MIXED_DIRECT, "mixed"),
+                               ("fp32_direct", fgl.FGL_MIXED_DIRECT, "fp32")):
+        m = fgl.Model.from_workload(sh, flags)
+        d, tol_m, _ = _margins(m.loglike(sh.theta, prec), ref_sh, sh.theta, sh.F * sh.T)
+        m.close()
+        line.setdefault(label, {})["shell_rows_max_over_mixed_tol"] = float((d / tol_m).max())
+    mix = res["mixed_projected"]
+    flops = w.B * (3.0 * w.F * w.T + EXP_FLOPS * w.N * w.F)
+    achieved = flops / (mix["kernel_ms"] * 1e-3) / 1e12
+    line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                        "kernel": "k_mixed", "kernel_ms": mix["kernel_ms"]}
+    line["mixed_over_fp32"] = {
+        "projected_vs_direct": mix["evals_per_s"] / res["fp32_direct"]["evals_per_s"],
+        "direct_vs_direct": res["mixed_direct"]["evals_per_s"] / res["fp32_direct"]["evals_per_s"],
+        "projected_vs_projected": mix["evals_per_s"] / res["fp32_projected"]["evals_per_s"]}
+    line["oracle_sample"] = "256 prior rows of the batch and 256 posterior-shell rows"
+    return line
+
+
 def cpu_leg(w, gpu_out, seconds):
     import oracle
     orc = oracle.load()
@@ -412,22 +524,32 @@ def main():
     if not a.no_tune:
         for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
             m.tune(w.B, prec)
-    res = {}
+    res, outs = {}, {}
     for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
         res[prec] = time_prec(fgl, m, th, out, prec, a.steps, a.warmup)
-        if prec == "mixed":
-            gpu_out = out.cpu().numpy().copy()
+        outs[prec] = out.cpu().numpy().copy()
         log(f"{prec}: {res[prec]['evals_per_s']:.4e} evals/s, "
             f"{res[prec]['ms_per_step']:.4f} ms/step, kernel {res[prec]['kernel_ms']:.4f} ms")
+    gpu_out = outs["mixed"]
     form = m.form
     if not a.no_plain and form == "projected":
-        # the same mixed evaluation in its direct form, for comparison
+        # the same mixed evaluation in its direct form, and the plain
+        # precisions in the projected form, for like-for-like ratios
         md = fgl.Model.from_workload(w, fgl.FGL_MIXED_DIRECT)
         if not a.no_tune:
             md.tune(w.B, "mixed")
         res["mixed_direct"] = time_prec(fgl, md, th, out, "mixed", a.steps, a.warmup)
         md.close()
         log(f"mixed (direct form): {res['mixed_direct']['evals_per_s']:.4e} evals/s")
+        mp = fgl.Model.from_workload(w, fgl.FGL_PLAIN_PROJECTED)
+        for prec in ("fp32", "fp64"):
+            if not a.no_tune:
+                mp.tune(w.B, prec)
+            res[prec + "_projected"] = time_prec(fgl, mp, th, out, prec, a.steps, a.warmup)
+            outs[prec + "_projected"] = out.cpu().numpy().copy()
+            log(f"{prec} (projected form): {res[prec + '_projected']['evals_per_s']:.4e} evals/s, "
+                f"kernel {res[prec + '_projected']['kernel_ms']:.4f} ms")
+        mp.close()
     mix = res["mixed"]
     # roofline of the likelihood kernel: FP64 work the method needs per
     # evaluation (residual and chi-square: 3 F T; power laws: N F values at
@@ -435,14 +557,14 @@ def main():
     flops = w.B * (3.0 * w.F * w.T + EXP_FLOPS * w.N * w.F)
     achieved = flops / (mix["kernel_ms"] * 1e-3) / 1e12
     # as designed: the kernel's int8 digit products on the matrix cores
-    # (20 v_mfma_i32_32x32x32_i8 per 32-row tile, region chunk and matrix tile
-    # in the projected form, 14 in the direct form), against the int8 peak
+    # (21 v_mfma_i32_32x32x32_i8 per 32-row tile, region chunk and matrix tile
+    # in the projected form, 18 in the direct form), against the int8 peak
     kc = (w.N + 31) // 32
     if form == "projected":
         peel = 1 if w.N % 32 == 0 else 0
-        mt, prods = (w.N + 1 - peel + 31) // 32, 20
+        mt, prods = (w.N + 1 - peel + 31) // 32, 21
     else:
-        mt, prods = (w.T + 31) // 32, 14
+        mt, prods = (w.T + 31) // 32, 18
     bpad = max(256, (w.B + 255) // 256 * 256)
     mfma_ops = (bpad // 32) * w.F * kc * mt * prods * 2.0 * 32 * 32 * 32
     mfma_tops = mfma_ops / (mix["kernel_ms"] * 1e-3) / 1e12
@@ -470,16 +592,24 @@ def main():
                      "as_designed": {"int8_mfma": mfma_tops, "peak": PEAK_INT8_TOPS,
                                      "unit": "TOP/s", "frac": mfma_tops / PEAK_INT8_TOPS}},
     }
+    def rate(key):
+        return {"value": res[key]["evals_per_s"], "ms_per_step": res[key]["ms_per_step"],
+                "kernel_ms": res[key]["kernel_ms"]}
     if "fp32" in res:
-        line["plain_fp32"] = {"value": res["fp32"]["evals_per_s"], "ms_per_step": res["fp32"]["ms_per_step"],
-                              "kernel_ms": res["fp32"]["kernel_ms"]}
-        line["plain_fp64"] = {"value": res["fp64"]["evals_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
-                              "kernel_ms": res["fp64"]["kernel_ms"]}
+        line["plain_fp32"] = rate("fp32")
+        line["plain_fp64"] = rate("fp64")
+        # the headline ratio: the mixed path as run against the paper's
+        # formulation in plain FP32 (the model on the time grid)
         line["mixed_over_fp32"] = mix["evals_per_s"] / res["fp32"]["evals_per_s"]
     if "mixed_direct" in res:
-        line["mixed_direct_form"] = {"value": res["mixed_direct"]["evals_per_s"],
-                                     "ms_per_step": res["mixed_direct"]["ms_per_step"],
-                                     "kernel_ms": res["mixed_direct"]["kernel_ms"]}
+        line["mixed_direct_form"] = rate("mixed_direct")
+        line["plain_fp32_projected"] = rate("fp32_projected")
+        line["plain_fp64_projected"] = rate("fp64_projected")
+        line["like_for_like"] = {
+            "direct": {"mixed_over_fp32": res["mixed_direct"]["evals_per_s"] / res["fp32"]["evals_per_s"],
+                       "mixed_over_fp64": res["mixed_direct"]["evals_per_s"] / res["fp64"]["evals_per_s"]},
+            "projected": {"mixed_over_fp32": mix["evals_per_s"] / res["fp32_projected"]["evals_per_s"],
+                          "mixed_over_fp64": mix["evals_per_s"] / res["fp64_projected"]["evals_per_s"]}}
     m.close()
     if not a.no_small and not a.no_plain:
         log("small-batch leg")
@@ -487,6 +617,11 @@ def main():
     if not a.no_grad and not a.no_plain:
         log("gradient leg")
         line["gradient"] = grad_leg(fgl, w, a.steps, a.warmup)
+    if not a.no_large and not a.no_plain:
+        import oracle
+        log("large-workload leg")
+        line["large"] = large_leg(fgl, oracle.load(), max(20, a.steps // 10),
+                                  max(10, a.warmup // 10), not a.no_tune)
     if not a.no_masks and not a.no_plain:
         log("crossed-mask leg")
         line["masks"] = masks_leg(fgl, a.steps, a.warmup, not a.no_tune)
@@ -503,9 +638,27 @@ def main():
         log("nested sampling leg")
         line["nested_sampling"] = [sampler_leg(fgl, 10, 1), sampler_leg(fgl, 10, 72)]
     if not a.no_cpu:
+        import oracle
         log("cpu baseline leg")
         cb, par = cpu_leg(w, gpu_out, a.cpu_seconds)
         line["cpu_baseline"] = cb
+        # the prior rows of the timed batch (every precision timed above),
+        # then the posterior shells
+        ref = oracle.load().loglike_w(w, w.theta[:par["rows"]])
+        prior = {"rows": par["rows"]}
+        for key, got in outs.items():
+            d, tol_m, tol_64 = _margins(got[:par["rows"]], ref, w.theta[:par["rows"]], w.F * w.T)
+            prior[key] = ({"max_abs_dlogL": float(d.max()),
+                           "max_over_fp64_bar": float((d / tol_64).max()),
+                           "within_fp64_bar": bool(np.all(d <= tol_64))}
+                          if key.startswith("fp64") else
+                          {"max_abs_dlogL": float(d.max()),
+                           "max_over_mixed_tol": float((d / tol_m).max()),
+                           "p99_over_mixed_tol": float(np.quantile(d / tol_m, 0.99)),
+                           "within_mixed_tol": bool(np.all(d <= tol_m))})
+        log("parity record leg")
+        par = {"prior": prior}
+        par.update(parity_record(fgl, oracle.load(), w.name))
         line["parity_vs_oracle"] = par
     print(json.dumps(line), flush=True)
 

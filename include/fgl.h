@@ -90,6 +90,12 @@ enum { FGL_PREC_MIXED = 0, FGL_PREC_FP32 = 1, FGL_PREC_FP64 = 2 };
 
 #define FGL_NO_21CM 1u      /* model without the 21-cm term: P = N + 1 */
 #define FGL_MIXED_DIRECT 2u /* mixed precision: always use the direct form */
+/* plain FP32 and FP64 precisions in the projected form where the model has
+ * it (fgl_mixed_form is FGL_FORM_PROJECTED): the time sum of each channel in
+ * the orthonormal basis, with FP32 (or FP64) rows and powers, residual and
+ * chi-square in FP64.  Without the flag they evaluate M on the T time bins,
+ * the paper's formulation. */
+#define FGL_PLAIN_PROJECTED 4u
 
 /* Forms of the mixed-precision evaluation (fgl_mixed_form). */
 enum { FGL_FORM_DIRECT = 0, FGL_FORM_PROJECTED = 1, FGL_FORM_THIN = 2 };
@@ -104,8 +110,10 @@ enum { FGL_FORM_DIRECT = 0, FGL_FORM_PROJECTED = 1, FGL_FORM_THIN = 2 };
  *   nu_ref reference frequency of the power laws (MHz, > 0).
  *   N      regions, 1..128;  F channels >= 1;  T time bins >= 1.
  *   t_cmb  CMB temperature added to the model (K), finite.
- *   flags  0, or FGL_NO_21CM and/or FGL_MIXED_DIRECT (keep the direct form
- *          of the mixed evaluation even where the projected one is shorter).
+ *   flags  0, or any of FGL_NO_21CM, FGL_MIXED_DIRECT (keep the direct
+ *          form of the mixed evaluation even where the projected one is
+ *          shorter) and FGL_PLAIN_PROJECTED (the plain precisions take the
+ *          projected form too, where the model has it).
  * The library copies everything to the device and re-lays it out for its
  * kernels; the caller may free its arrays on return.  *out receives the
  * model, owned by the library until fgl_model_destroy.

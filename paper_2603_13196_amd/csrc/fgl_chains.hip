@@ -609,7 +609,7 @@ int fgl_chains_run(fgl_chains* ch, const double* x0, const double* l0, int n, do
     return hip_err(e, "prep kernel");
   RowSums rs{wb.w.partial, wb.w.rows, n_groups(m->dm, tile), wb.w.Bpad,
              (double)m->dm.F * (double)m->dm.T,
-             (k == kMixed && m->dm.proj) ? m->dm.chi0 : 0.0};
+             chi0_of(k, m->dm)};
   auto round = [&]() -> int {
     int rc2 = enqueue_main(m, k, tile, wb, s);
     if (rc2 != FGL_OK) return rc2;

@@ -211,6 +211,7 @@ static void build_projected(Model* m, const float* K, const double* data) {
   const int rows = d.peel ? N : N + 1;              // rows in MFMA tiles
   const long double sT = std::sqrt((long double)T);
   m->h_rd.assign((size_t)F * kProjDigits * KC * RT * 1024, 0);
+  if (d.pplain) m->h_r32.assign((size_t)F * d.NP2 * RT * 64, 0.0f);
   m->h_eR.assign(F, 0);
   m->h_tg.assign((size_t)F * RT * 32, 0.0);
   m->h_dbar.assign(F, 0.0);
@@ -292,6 +293,14 @@ static void build_projected(Model* m, const float* K, const double* data) {
     if (mx > 0.0L) std::frexp((double)mx, &er);
     if (mx > 0.0L && std::ldexp((long double)1.0L, er) <= mx) ++er;   // mx < 2^er
     m->h_eR[f] = er;
+    if (d.pplain)
+      for (int p = 0; p < d.NP2; ++p)
+        for (int rt = 0; rt < RT; ++rt)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int i = 2 * p + (lane >> 5), k = rt * 32 + (lane & 31);
+            m->h_r32[(((size_t)f * d.NP2 + p) * RT + rt) * 64 + lane] =
+                (i < N && k < rows) ? (float)mat[(size_t)k * N + i] : 0.0f;
+          }
     int8_t* base = m->h_rd.data() + (size_t)f * kProjDigits * KC * RT * 1024;
     for (int kc = 0; kc < KC; ++kc)
       for (int rt = 0; rt < RT; ++rt)
@@ -329,7 +338,7 @@ size_t resident_bytes(const Model* m) {
          m->h_k64.size() * 4 + m->h_kthin.size() * 4 + (m->h_nl64.size() + m->h_nl2.size() + m->h_nu.size()) * 8 +
          m->h_D.size() * 8 + m->h_tab.size() * 8 + m->h_rd.size() + m->h_eR.size() * 4 +
          (m->h_tg.size() + m->h_dbar.size() + m->h_pk.size()) * 8 +
-         (m->h_pa64.size() + m->h_pt64.size()) * 8;
+         (m->h_pa64.size() + m->h_pt64.size()) * 8 + m->h_r32.size() * 4;
 }
 
 int make_resident(Model* m) {
@@ -338,19 +347,20 @@ int make_resident(Model* m) {
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   int8_t *kd = nullptr, *rd = nullptr;
   int32_t *eK = nullptr, *eR = nullptr;
-  float *k32 = nullptr, *k64 = nullptr, *kthin = nullptr;
+  float *k32 = nullptr, *k64 = nullptr, *kthin = nullptr, *r32 = nullptr;
   double *nl64 = nullptr, *nl2 = nullptr, *nu = nullptr, *D = nullptr, *tab = nullptr;
   double *tg = nullptr, *dbar = nullptr, *pk = nullptr, *pa64 = nullptr, *pt64 = nullptr;
   if ((e = upload(&kd, m->h_kd)) != hipSuccess || (e = upload(&eK, m->h_eK)) != hipSuccess ||
       (e = upload(&pa64, m->h_pa64)) != hipSuccess || (e = upload(&pt64, m->h_pt64)) != hipSuccess ||
       (e = upload(&k32, m->h_k32)) != hipSuccess || (e = upload(&k64, m->h_k64)) != hipSuccess ||
-      (e = upload(&kthin, m->h_kthin)) != hipSuccess ||
+      (e = upload(&kthin, m->h_kthin)) != hipSuccess || (e = upload(&r32, m->h_r32)) != hipSuccess ||
       (e = upload(&nl64, m->h_nl64)) != hipSuccess || (e = upload(&nl2, m->h_nl2)) != hipSuccess ||
       (e = upload(&nu, m->h_nu)) != hipSuccess || (e = upload(&D, m->h_D)) != hipSuccess ||
       (e = upload(&tab, m->h_tab)) != hipSuccess || (e = upload(&rd, m->h_rd)) != hipSuccess ||
       (e = upload(&eR, m->h_eR)) != hipSuccess || (e = upload(&tg, m->h_tg)) != hipSuccess ||
       (e = upload(&dbar, m->h_dbar)) != hipSuccess || (e = upload(&pk, m->h_pk)) != hipSuccess) {
-    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk, pa64, pt64, kthin};
+    void* ps[] = {kd, eK, k32, k64, nl64, nl2, nu, D, tab, rd, eR, tg, dbar, pk, pa64, pt64, kthin,
+                  r32};
     for (void* p : ps)
       if (p) (void)hipFree(p);
     return hip_err(e, "uploading model");
@@ -367,6 +377,7 @@ int make_resident(Model* m) {
   m->dm.k32 = k32;
   m->dm.k64 = k64;
   m->dm.kthin = kthin;
+  m->dm.r32 = r32;
   m->dm.nl64 = nl64;
   m->dm.nl2 = nl2;
   m->dm.nu = nu;
@@ -384,7 +395,7 @@ void evict(Model* m) {
   const void* ps[] = {m->dm.kd, m->dm.eK, m->dm.k32, m->dm.k64, m->dm.nl64,
                       m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab, m->dm.rd,
                       m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk, m->dm.pa64, m->dm.pt64,
-                      m->dm.kthin};
+                      m->dm.kthin, m->dm.r32};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
   m->dm.rd = nullptr;
@@ -392,7 +403,7 @@ void evict(Model* m) {
   m->dm.tg = m->dm.dbar = m->dm.pk = m->dm.pa64 = m->dm.pt64 = nullptr;
   m->dm.kd = nullptr;
   m->dm.eK = nullptr;
-  m->dm.k32 = m->dm.k64 = m->dm.kthin = nullptr;
+  m->dm.k32 = m->dm.k64 = m->dm.kthin = m->dm.r32 = nullptr;
   m->dm.nl64 = m->dm.nl2 = m->dm.nu = m->dm.D = m->dm.tab = nullptr;
   m->resident = false;
   // graphs captured against the old buffers are stale
@@ -771,7 +782,8 @@ static int create_model(const float* K, const double* freqs, const double* data,
                    NA, NB, kMixedMaxN);
   const int N = std::max(NA, 1) * NB;
   if (F < 1 || T < 1) return set_err(FGL_EINVAL, "F=%d and T=%d must be >= 1", F, T);
-  if (flags & ~(FGL_NO_21CM | FGL_MIXED_DIRECT)) return set_err(FGL_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(FGL_NO_21CM | FGL_MIXED_DIRECT | FGL_PLAIN_PROJECTED))
+    return set_err(FGL_EINVAL, "unknown flags 0x%x", flags);
   if (!(nu_ref > 0.0) || !std::isfinite(nu_ref)) return set_err(FGL_EINVAL, "nu_ref must be finite and > 0");
   if (!std::isfinite(t_cmb)) return set_err(FGL_EINVAL, "t_cmb must be finite");
   for (int f = 0; f < F; ++f) {
@@ -824,6 +836,7 @@ static int create_model(const float* K, const double* freqs, const double* data,
       d.peel = peel;
     }
   }
+  d.pplain = (d.proj && (flags & FGL_PLAIN_PROJECTED)) ? 1 : 0;
   for (Kind k : {kMixed, kFP32, kFP64, kThin}) {
     if (k == kThin && !d.thin) continue;
     if (group_of(k, d) == 0) {

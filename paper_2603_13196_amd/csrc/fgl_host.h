@@ -70,6 +70,7 @@ struct Model {
   std::vector<int32_t> h_eR;
   std::vector<double> h_tg, h_dbar, h_pk;
   std::vector<double> h_pa64, h_pt64;        // projected rows in FP64 (gradient)
+  std::vector<float> h_r32;                  // projected rows in FP32 (FGL_PLAIN_PROJECTED)
   // serving bookkeeping
   uint64_t last_use = 0;
   // kernel timing (fgl_kernel_timing): 0 off, n > 0 events around every

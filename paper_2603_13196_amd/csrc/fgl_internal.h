@@ -134,6 +134,11 @@ struct DevModel {
   double sqrtT;
   double chi0;           // sum over channels of the data's out-of-span part
   const int8_t* rd;      // digits [F][kProjDigits][KC][RT][64][16]
+  // plain precisions in the projected form (FGL_PLAIN_PROJECTED): the same
+  // rows in FP32 as A operands of the FP32 kernel, [F][NP2][RT][64]: lane ->
+  // (row 32 rt + lane%32, region 2 p + lane/32); the FP64 kernel reads pa64
+  int pplain;            // 1: the FP32 and FP64 kernels run the projected form
+  const float* r32;
   const int32_t* eR;     // [F] per-channel exponent of the digits
   const double* tg;      // [F][RT*32] targets (row 0 is per parameter row)
   const double* dbar;    // [F] sqrt(T) mean_t D
@@ -160,6 +165,15 @@ inline int mixed_alpha_mode(const DevModel& d) {
 // form with one region chunk and at most one alpha per lane and chunk.
 inline bool mixed_occ3(const DevModel& d) {
   return d.proj && d.KC == 1 && mixed_alpha_mode(d) != 1;
+}
+
+// The constant chi-square of the data's part outside the span of the
+// projected rows, added to every row's sum by the kernel families that run
+// the projected form.
+inline double chi0_of(Kind k, const DevModel& d) {
+  if (k == kMixed) return d.proj ? d.chi0 : 0.0;
+  if (k == kFP32 || k == kFP64) return d.pplain ? d.chi0 : 0.0;
+  return 0.0;
 }
 
 // Per-call workspace (device memory owned by the model, per stream).

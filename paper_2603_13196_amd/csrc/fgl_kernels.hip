@@ -482,23 +482,26 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
 // The region sum runs as v_mfma_f32_32x32x2_f32 over NPB region pairs (the
 // model's pair count rounded up to a compiled size; padded regions have
 // K = 0 and unit powers).  The constant T_CMB + A g is added to the FP32 sum
-// in the epilogue, then D - M and the chi-square run in FP64.
+// in the epilogue, then D - M and the chi-square run in FP64.  PROJ: the
+// same on the projected rows [sqrt(T) Kbar ; R] held in FP32 (the form the
+// mixed kernel describes above), each row's residual its target minus the
+// FP32 row product, the peeled last row of R in FP64 from the FP32 power.
 
-template <int W, int NPB, bool AB>
+template <int W, int NPB, bool AB, bool PROJ>
 __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int G,
                                                  int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
   map_block(nb, nc, bt, ch);
-  const int TT = m.TT, N = m.N;
+  const int TT = PROJ ? m.RT : m.TT, N = m.N;      // 32-row tiles
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
   const int kfl = NPB * TT * 64;            // floats per channel
   float* s_k = reinterpret_cast<float*>(smem);
   double* s_D = reinterpret_cast<double*>(smem + (size_t)fc * kfl * 4);
-  stage(s_k, m.k32 + (size_t)f0 * kfl, fn * kfl * 4);
-  stage(s_D, m.D + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
+  stage(s_k, (PROJ ? m.r32 : m.k32) + (size_t)f0 * kfl, fn * kfl * 4);
+  stage(s_D, (PROJ ? m.tg : m.D) + (size_t)f0 * TT * 32, fn * TT * 32 * 8);
   __syncthreads();
 
   const int g = lane >> 5;
@@ -516,13 +519,16 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
   for (int f = 0; f < fn; ++f) {
     const int fi = f0 + f;
     const float nl = (float)m.nl2[fi];
-    const float c = (float)(m.t_cmb + rp.A * gauss21(m.nu[fi], rp));
+    const double c64 = m.t_cmb + rp.A * gauss21(m.nu[fi], rp);
+    const float c = (float)c64;
     float Bp[NPB];
 #pragma unroll
     for (int k = 0; k < NPB; ++k)
       Bp[k] = __builtin_amdgcn_exp2f(AB ? fmaf(betaf[k], nl, offf[k]) : betaf[k] * nl);
     const float* kf = s_k + (size_t)f * kfl + lane;
     const double* Df = s_D + (size_t)f * TT * 32 + g * 4;
+    // projected form: the target of the mean row (row 0, lanes 0..31)
+    const double t0 = PROJ ? m.dbar[fi] - m.sqrtT * c64 : 0.0;
     for (int tt = 0; tt < TT; ++tt) {
       float Ak[NPB];
 #pragma unroll
@@ -532,16 +538,36 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
       for (int k = 0; k < NPB; ++k)
         a = __builtin_amdgcn_mfma_f32_32x32x2f32(Ak[k], Bp[k], a, 0, 0, 0);
       const double* Dt = Df + tt * 32;
-      const bool ragged = (tt == TT - 1) && (m.T & 31);
+      const bool ragged = !PROJ && (tt == TT - 1) && (m.T & 31);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double r = Dt[(j >> 2) * 8 + (j & 3)] - (double)(a[j] + c);
+        double r;
+        if constexpr (PROJ) {
+          // padded rows have zero operands and zero targets
+          double d = Dt[(j >> 2) * 8 + (j & 3)];
+          if (j == 0) d = (tt == 0 && g == 0) ? t0 : d;
+          r = d - (double)a[j];
+        } else {
+          r = Dt[(j >> 2) * 8 + (j & 3)] - (double)(a[j] + c);
+        }
         if (ragged) {
           const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
           r = t < m.T ? r : 0.0;
         }
         if (j & 1) acc1 = fma(r, r, acc1);
         else acc0 = fma(r, r, acc0);
+      }
+    }
+    if constexpr (PROJ) {
+      // peeled last row of R (N a multiple of 32): region N - 1 = 2 kl + 1
+      // is pair kl of the lanes with g = 1
+      if (m.peel) {
+        const int kl = (N - 2) >> 1;
+        float pl = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NPB; ++k) pl = k == kl ? Bp[k] : pl;
+        const double r = m.pk[2 * fi + 1] - m.pk[2 * fi] * (double)pl;
+        acc0 = fma(r, g ? r : 0.0, acc0);
       }
     }
     // one partial per reduction group of G channels (f0 is a multiple of G)
@@ -560,24 +586,30 @@ __global__ __launch_bounds__(W * 64) void k_fp32(DevModel m, Work w, int fc, int
 //
 // v_mfma_f64_16x16x4_f64 over NQB region quads (padded as above; K staged as
 // its exact FP32 values and widened in registers), the constant term added in
-// the FP64 epilogue.
+// the FP64 epilogue.  PROJ: the projected rows (all N + 1 of them, in FP64,
+// the gradient kernel's operands), each row's residual its target minus the
+// row product.
 
-template <int W, int NQB, bool AB>
+template <int W, int NQB, bool AB, bool PROJ>
 __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int G,
                                                  int nb, int nc) {
   extern __shared__ __align__(16) unsigned char smem[];
+  using AT = typename std::conditional<PROJ, double, float>::type;   // operand type
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
   map_block(nb, nc, bt, ch);
-  const int TT16 = m.TT16, N = m.N;
+  const int TT16 = PROJ ? m.RT16 : m.TT16, N = m.N;   // 16-row tiles
+  const int drow = PROJ ? m.RT16 * 16 : m.TT * 32;    // targets per channel
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
   const int kdl = NQB * TT16 * 64;          // values per channel
   double* s_t64 = reinterpret_cast<double*>(smem);                  // [64] 2^(m/64)
-  float* s_k = reinterpret_cast<float*>(smem + 512);
-  double* s_D = reinterpret_cast<double*>(smem + 512 + (size_t)fc * kdl * 4);
-  stage(s_k, m.k64 + (size_t)f0 * kdl, fn * kdl * 4);
-  stage(s_D, m.D + (size_t)f0 * m.TT * 32, fn * m.TT * 32 * 8);
+  AT* s_k = reinterpret_cast<AT*>(smem + 512);
+  double* s_D = reinterpret_cast<double*>(smem + 512 + (size_t)fc * kdl * sizeof(AT));
+  stage(s_k, (PROJ ? reinterpret_cast<const AT*>(m.pa64) : reinterpret_cast<const AT*>(m.k64)) +
+                 (size_t)f0 * kdl,
+        fn * kdl * (int)sizeof(AT));
+  stage(s_D, (PROJ ? m.pt64 : m.D) + (size_t)f0 * drow, fn * drow * 8);
   init_t64(s_t64);
   __syncthreads();
 
@@ -602,11 +634,13 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 #pragma unroll
     for (int k = 0; k < NQB; ++k)
       Bp[k] = pow2_64(AB ? fma(beta[k], nl, off[k]) : beta[k] * nl, s_t64, m);
-    const float* kf = s_k + (size_t)f * kdl + lane;
+    const AT* kf = s_k + (size_t)f * kdl + lane;
     // 16x16 FP64 MFMA output: register j of lane l holds row l/16 + 4 j
-    const double* Df = s_D + (size_t)f * m.TT * 32 + g;
+    const double* Df = s_D + (size_t)f * drow + g;
+    // projected form: the target of the mean row (row 0: lanes 0..15, j = 0)
+    const double t0 = PROJ ? s_D[(size_t)f * drow] - m.sqrtT * c : 0.0;
     for (int tt = 0; tt < TT16; ++tt) {
-      float Ak[NQB];
+      AT Ak[NQB];
 #pragma unroll
       for (int k = 0; k < NQB; ++k) Ak[k] = kf[(k * TT16 + tt) * 64];
       f64x4 a = {};
@@ -614,10 +648,17 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
       for (int k = 0; k < NQB; ++k)
         a = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Ak[k], Bp[k], a, 0, 0, 0);
       const double* Dt = Df + tt * 16;
-      const bool ragged = (tt == TT16 - 1) && (m.T & 15);
+      const bool ragged = !PROJ && (tt == TT16 - 1) && (m.T & 15);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        double r = (Dt[4 * j] - c) - a[j];
+        double r;
+        if constexpr (PROJ) {
+          // padded rows have zero operands and zero targets
+          const double d = (j == 0 && tt == 0 && g == 0) ? t0 : Dt[4 * j];
+          r = d - a[j];
+        } else {
+          r = (Dt[4 * j] - c) - a[j];
+        }
         if (ragged) {
           const int t = tt * 16 + g + 4 * j;
           r = t < m.T ? r : 0.0;
@@ -1120,9 +1161,13 @@ int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
         return t.fc * (kProjDigits * m.KC * m.RT * 1024 + m.RT * 32 * 8) +
                (kTabSize + 2 * kFracSize) * 8;
       return t.fc * 4 * m.KC * m.TT * 1024 + d + (kTabSize + 2 * kFracSize) * 8;
-    case kFP32: return t.fc * m.NP2 * m.TT * 64 * 4 + d;
+    case kFP32:
+      if (m.pplain) return t.fc * (m.NP2 * m.RT * 64 * 4 + m.RT * 32 * 8);
+      return t.fc * m.NP2 * m.TT * 64 * 4 + d;
     case kThin: return 512 + t.fc * m.T * m.NT * 4 + d;
-    default: return 512 + t.fc * m.NQ * m.TT16 * 64 * 4 + d;
+    default:
+      if (m.pplain) return 512 + t.fc * (m.NQ * m.RT16 * 64 * 8 + m.RT16 * 16 * 8);
+      return 512 + t.fc * m.NQ * m.TT16 * 64 * 4 + d;
   }
 }
 
@@ -1195,20 +1240,24 @@ hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
   }
 }
 
-template <int W, bool AB>
-hipError_t fp32_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
-                   int nc, int lds, hipStream_t s) {
+// The projected form needs N <= 96: region pairs up to 48, quads up to 24.
+template <int W, bool AB, bool PROJ>
+hipError_t fp32_wap(const DevModel& m, const Work& w, int fc, int G, int nb,
+                    int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
   switch (m.NP2) {
-    case 2: return go(k_fp32<W, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_fp32<W, 4, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 8: return go(k_fp32<W, 8, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 12: return go(k_fp32<W, 12, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 16: return go(k_fp32<W, 16, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 24: return go(k_fp32<W, 24, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 32: return go(k_fp32<W, 32, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 48: return go(k_fp32<W, 48, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 64: return go(k_fp32<W, 64, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_fp32<W, 2, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_fp32<W, 4, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_fp32<W, 8, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_fp32<W, 12, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_fp32<W, 16, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_fp32<W, 24, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 32: return go(k_fp32<W, 32, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 48: return go(k_fp32<W, 48, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 64:
+      if constexpr (!PROJ)
+        return go(k_fp32<W, 64, AB, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -1216,24 +1265,30 @@ hipError_t fp32_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
 template <int W>
 hipError_t fp32_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   int nc, int lds, hipStream_t s) {
-  return m.NA > 0 ? fp32_wa<W, true>(m, w, fc, G, nb, nc, lds, s)
-                  : fp32_wa<W, false>(m, w, fc, G, nb, nc, lds, s);
+  if (m.pplain)
+    return m.NA > 0 ? fp32_wap<W, true, true>(m, w, fc, G, nb, nc, lds, s)
+                    : fp32_wap<W, false, true>(m, w, fc, G, nb, nc, lds, s);
+  return m.NA > 0 ? fp32_wap<W, true, false>(m, w, fc, G, nb, nc, lds, s)
+                  : fp32_wap<W, false, false>(m, w, fc, G, nb, nc, lds, s);
 }
 
-template <int W, bool AB>
-hipError_t fp64_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
-                   int nc, int lds, hipStream_t s) {
+template <int W, bool AB, bool PROJ>
+hipError_t fp64_wap(const DevModel& m, const Work& w, int fc, int G, int nb,
+                    int nc, int lds, hipStream_t s) {
   const int blocks = nb * nc, th = W * 64;
   switch (m.NQ) {
-    case 1: return go(k_fp64<W, 1, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_fp64<W, 2, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_fp64<W, 4, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 6: return go(k_fp64<W, 6, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 8: return go(k_fp64<W, 8, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 12: return go(k_fp64<W, 12, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 16: return go(k_fp64<W, 16, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 24: return go(k_fp64<W, 24, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 32: return go(k_fp64<W, 32, AB>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go(k_fp64<W, 1, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 2: return go(k_fp64<W, 2, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 4: return go(k_fp64<W, 4, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 6: return go(k_fp64<W, 6, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 8: return go(k_fp64<W, 8, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 12: return go(k_fp64<W, 12, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 16: return go(k_fp64<W, 16, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 24: return go(k_fp64<W, 24, AB, PROJ>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 32:
+      if constexpr (!PROJ)
+        return go(k_fp64<W, 32, AB, false>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -1241,8 +1296,11 @@ hipError_t fp64_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
 template <int W>
 hipError_t fp64_w(const DevModel& m, const Work& w, int fc, int G, int nb,
                   int nc, int lds, hipStream_t s) {
-  return m.NA > 0 ? fp64_wa<W, true>(m, w, fc, G, nb, nc, lds, s)
-                  : fp64_wa<W, false>(m, w, fc, G, nb, nc, lds, s);
+  if (m.pplain)
+    return m.NA > 0 ? fp64_wap<W, true, true>(m, w, fc, G, nb, nc, lds, s)
+                    : fp64_wap<W, false, true>(m, w, fc, G, nb, nc, lds, s);
+  return m.NA > 0 ? fp64_wap<W, true, false>(m, w, fc, G, nb, nc, lds, s)
+                  : fp64_wap<W, false, false>(m, w, fc, G, nb, nc, lds, s);
 }
 
 template <bool AB>
@@ -1307,7 +1365,7 @@ hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
                            const Tile& tile, double* out, hipStream_t s) {
   const int threads = 256;
   const int blocks = (w.B * 16 + threads - 1) / threads;
-  const double chi0 = (k == kMixed && m.proj) ? m.chi0 : 0.0;
+  const double chi0 = chi0_of(k, m);
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, s, w.partial,
                      n_groups(m, tile), w.Bpad, w.rows, w.B,
                      (double)m.F * (double)m.T, chi0, out);

@@ -23,6 +23,7 @@ FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EBUSY, FGL_EDEVICE, FGL_EAGAIN = 0, -1, -2, 
 FGL_PREC_MIXED, FGL_PREC_FP32, FGL_PREC_FP64 = 0, 1, 2
 FGL_NO_21CM = 1
 FGL_MIXED_DIRECT = 2
+FGL_PLAIN_PROJECTED = 4
 FGL_FORM_DIRECT, FGL_FORM_PROJECTED, FGL_FORM_THIN = 0, 1, 2
 PREC = {"mixed": FGL_PREC_MIXED, "fp32": FGL_PREC_FP32, "fp64": FGL_PREC_FP64}
 _NAMES = {FGL_EINVAL: "EINVAL", FGL_ENOMEM: "ENOMEM", FGL_EBUSY: "EBUSY",

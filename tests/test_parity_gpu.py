@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workload
-from tests.gpu_util import check, lib, say, thin_form
+from tests.gpu_util import check, lib, record, say, thin_form
 
 pytestmark = pytest.mark.gpu
 
@@ -113,6 +113,60 @@ def test_large_workload_subsample(fgl, orc):
     md.close()
     sh = workload.posterior_shell(workload.LARGE, 256)
     _mixed_forms(fgl, sh, sh.theta, orc.loglike_w(sh), "large/shell", expect="projected")
+
+
+@pytest.mark.parametrize("N,F,T,B,rich", [
+    (32, 301, 96, 1024, False), (32, 301, 96, 1024, True), (33, 11, 70, 100, True),
+    (64, 6, 65, 70, True), (96, 3, 130, 40, True), (7, 5, 70, 257, True), (1, 3, 80, 65, True)])
+def test_plain_projected_form(fgl, orc, N, F, T, B, rich):
+    """FGL_PLAIN_PROJECTED: the plain FP64 kernel on the projected rows meets
+    the FP64 bar (prior and shell rows); the plain FP32 kernel on them is
+    reported and held to the loose FP32 bar on prior rows; the mixed
+    evaluation is unchanged by the flag."""
+    if (N, F, T) == (32, 301, 96):
+        w = workload.config(workload.HEADLINE, B=B, batch="mixed", rich=rich)
+    else:
+        w = workload.make(N, np.linspace(55.0, 190.0, F), T, B, 4000 + N + T,
+                          chroma=0.05, batch="mixed", rich=rich)
+    say(f"plain projected N={N} F={F} T={T} B={B} rich={rich}")
+    ref = orc.loglike_w(w)
+    m = fgl.Model.from_workload(w, fgl.FGL_PLAIN_PROJECTED)
+    m0 = fgl.Model.from_workload(w)
+    assert m.form == "projected"
+    lab = f"plain-proj/N{N}F{F}T{T}" + ("/rich" if rich else "")
+    check(m.loglike(w.theta, "fp64"), ref, "fp64", lab, w.theta, w.F * w.T)
+    got32 = m.loglike(w.theta, "fp32")
+    # one FP32 rounding of a projected row stands for the T roundings of the
+    # time bins it sums, so this baseline is held only to a gross bound
+    # (1e-3 relative) on the prior rows (the first half) and reported
+    half = w.B // 2
+    d = np.abs(got32[:half] - ref[:half])
+    t = 1e-3 * np.abs(ref[:half]) + 1e-3
+    record(lab + "/prior", "fp32", d, t)
+    assert np.all(d <= t), (lab, float((d / t).max()))
+    d = np.abs(got32 - ref)
+    say(f"  fp32 projected (reported): max|d|={d.max():.3e} "
+        f"max|d|/mixed-tol={(d / (1e-6 * np.abs(ref) + 1e-3)).max():.3e}")
+    assert np.array_equal(m.loglike(w.theta, "mixed"), m0.loglike(w.theta, "mixed"))
+    m.close()
+    m0.close()
+
+
+@pytest.mark.parametrize("name,B", [(workload.HEADLINE, 1024), (workload.LARGE, 256)])
+def test_full_rank_responses(fgl, orc, name, B):
+    """Full-rank responses (time harmonics and a per-value scatter for every
+    region, a chromatic ripple; the data simulated from them): the
+    posterior shell and a prior batch, every row, in both mixed forms and
+    in FP64, at the headline shape and at N=64, F=401, T=240."""
+    for kind in ("shell", "prior"):
+        w = workload.config(name, B=B, batch=kind, rich=True)
+        say(f"full-rank {name} {kind}: N={w.N} F={w.F} T={w.T} B={w.B}")
+        ref = orc.loglike_w(w)
+        _mixed_forms(fgl, w, w.theta, ref, f"{name}/rich/{kind}", expect="projected")
+        m = _model(fgl, w)
+        check(m.loglike(w.theta, "fp64"), ref, "fp64", f"{name}/rich/{kind}", w.theta,
+              w.F * w.T)
+        m.close()
 
 
 @pytest.mark.parametrize("N,F,T,B", [

@@ -111,16 +111,38 @@ def freq_grid(lo: float, hi: float, step: float) -> np.ndarray:
     return lo + step * np.arange(n, dtype=np.float64)
 
 
+# Time structure of the "rich" responses: harmonics per region and the
+# scatter of each (region, channel, time) value (see _draw_K).
+RICH_HARMONICS = 12
+RICH_SCATTER = 0.05
+
+
 def _draw_K(rng: np.random.Generator, N: int, freqs: np.ndarray, T: int,
-            t_mod: float, chroma: float) -> np.ndarray:
+            t_mod: float, chroma: float, rich: bool = False) -> np.ndarray:
     """Region responses: a_i ~ LogNormal(ln(300/N), 0.5) times an optional
     time modulation (1 + t_mod sin(2 pi t / T + phi_i)) and an optional
-    chromatic ripple (1 + chroma sin(2 pi nu / 17 MHz + psi_i))."""
+    chromatic ripple (1 + chroma sin(2 pi nu / 17 MHz + psi_i)).
+
+    With ``rich`` the time modulation is instead a sum of RICH_HARMONICS
+    harmonics h = 1, 2, ... of the day with amplitudes ~ U[0, 1]/h and
+    phases ~ U[0, 2 pi) per region (scaled to an r.m.s. of t_mod / sqrt(2)),
+    and every value carries a log-normal scatter exp(RICH_SCATTER e),
+    e ~ N(0, 1) per (region, channel, time): the regions then differ in
+    their time dependence and K varies with nu, so the time-centred
+    responses of a channel have full rank."""
     a = rng.lognormal(mean=math.log(300.0 / N), sigma=0.5, size=N)
     phi = rng.uniform(0.0, 2.0 * math.pi, size=N)
     psi = rng.uniform(0.0, 2.0 * math.pi, size=N)
     t = np.arange(T, dtype=np.float64)
-    if T > 1 and t_mod != 0.0:
+    if T > 1 and t_mod != 0.0 and rich:
+        H = RICH_HARMONICS
+        amp = rng.uniform(0.0, 1.0, size=(N, H)) / np.arange(1, H + 1)[None, :]
+        ph = rng.uniform(0.0, 2.0 * math.pi, size=(N, H))
+        ang = 2.0 * math.pi * np.arange(1, H + 1)[None, :, None] * t[None, None, :] / T
+        wave = np.sum(amp[:, :, None] * np.sin(ang + ph[:, :, None]), axis=1)     # [N, T]
+        rms = np.sqrt(np.mean(wave ** 2, axis=1, keepdims=True))
+        tm = 1.0 + (t_mod / math.sqrt(2.0)) * wave / np.where(rms > 0, rms, 1.0)
+    elif T > 1 and t_mod != 0.0:
         tm = 1.0 + t_mod * np.sin(2.0 * math.pi * t[None, :] / T + phi[:, None])
     else:
         tm = np.ones((N, T))
@@ -129,6 +151,8 @@ def _draw_K(rng: np.random.Generator, N: int, freqs: np.ndarray, T: int,
     else:
         cm = np.ones((N, freqs.size))
     K = a[:, None, None] * cm[:, :, None] * tm[:, None, :]
+    if rich:
+        K = K * np.exp(RICH_SCATTER * rng.standard_normal(size=K.shape))
     return np.ascontiguousarray(K.astype(np.float32))
 
 
@@ -190,11 +214,12 @@ def shell_batch(rng: np.random.Generator, truth: np.ndarray, B: int,
 def make(N: int, freqs: np.ndarray, T: int, B: int, seed: int, *,
          t_mod: float = 0.3, chroma: float = 0.0, batch: str = "prior",
          name: str = "custom", nu_ref: float = NU_REF,
-         t_cmb: float = T_CMB) -> Workload:
+         t_cmb: float = T_CMB, rich: bool = False) -> Workload:
     """Generic workload: K, simulated data at a drawn truth, and a batch of
-    B rows ('prior', 'shell', or 'mixed' = half of each)."""
+    B rows ('prior', 'shell', or 'mixed' = half of each).  ``rich`` draws
+    full-rank responses (see _draw_K)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    K = _draw_K(rng, N, freqs, T, t_mod, chroma)
+    K = _draw_K(rng, N, freqs, T, t_mod, chroma, rich)
     beta_true = rng.uniform(2.45, 3.15, size=N)
     a21, nu21, w21 = -0.15, 80.0, 15.0
     data = _simulate_sky(rng, K, freqs, nu_ref, t_cmb, beta_true, a21, nu21,
@@ -293,18 +318,25 @@ def masks_config(*, B: int = 16384, batch: str = "prior") -> Workload:
 
 
 def config(name: str, *, B: Optional[int] = None, batch: str = "prior",
-           chroma: float = 0.0) -> Workload:
+           chroma: float = 0.0, rich: bool = False) -> Workload:
     """The named benchmark workload (SMALL, MEDIUM, HEADLINE or LARGE),
-    optionally with another batch size or batch kind."""
+    optionally with another batch size or batch kind.  ``rich`` swaps the
+    responses for full-rank ones (several time harmonics per region, a
+    per-value scatter) with a chromatic ripple of 5 % unless ``chroma`` is
+    given, under a seed of its own (the workload's seed + 100)."""
     c = WORKLOADS[name]
     freqs = freq_grid(*c["grid"])
+    if rich:
+        return make(c["N"], freqs, c["T"], c["B"] if B is None else B,
+                    c["seed"] + 100, t_mod=c["t_mod"], chroma=chroma or 0.05,
+                    batch=batch, name=name + "_rich", rich=True)
     return make(c["N"], freqs, c["T"], c["B"] if B is None else B,
                 c["seed"], t_mod=c["t_mod"], chroma=chroma, batch=batch, name=name)
 
 
-def posterior_shell(name: str, B: int = 1024) -> Workload:
+def posterior_shell(name: str, B: int = 1024, rich: bool = False) -> Workload:
     """The named workload with its theta batch replaced by a posterior shell."""
-    return config(name, B=B, batch="shell")
+    return config(name, B=B, batch="shell", rich=rich)
 
 
 @dataclasses.dataclass
