@@ -186,6 +186,27 @@ int fgl_loglike_batch_device(fgl_model* m, const double* d_theta, int B,
                              double* d_out, int prec, void* hip_stream);
 
 /*
+ * fgl_loglike_batch_device for callers that cannot allocate device memory:
+ * code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It allocates nothing: the call's workspace (transposed
+ * spectral indices, row records, chi-square partials) lives in one 64 MiB
+ * array per GPU, held from the first call on that GPU to the end of the
+ * process.  Same arguments, kernels and results (bitwise) as
+ * fgl_loglike_batch_device; the tile is the tuned one if fgl_tune ran for
+ * this batch size, else the default (no tuning, no kernel timing here).
+ * Every call on one GPU shares the array: calls that overlap on one GPU,
+ * on any model or stream, race, so the caller orders them (one stream, or
+ * events).  Nothing in the array has to start at zero.
+ * Returns FGL_OK; FGL_EINVAL for the arguments fgl_loglike_batch_device
+ * refuses and for a batch whose workspace exceeds 64 MiB (the message gives
+ * the model's largest batch: about 70,000 rows of the N=32, F=301 model);
+ * FGL_EAGAIN if a server evicted the model (an allocating call makes it
+ * resident again); FGL_EBUSY; FGL_EDEVICE.
+ */
+int fgl_loglike_batch_device_noalloc(fgl_model* m, const double* d_theta, int B,
+                                     double* d_out, int prec, void* hip_stream);
+
+/*
  * lnL and its gradient d lnL / d theta for B rows (the chain rule through
  * Eq. likelihood, Eq. fast_forward_model and Eq. t21model; the paper's
  * pipeline is differentiable, Sec. 3).  Entries follow the row layout:

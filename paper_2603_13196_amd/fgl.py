@@ -66,6 +66,8 @@ _SIGS = {
     "fgl_loglike_batch": ([_vp, _dp, ctypes.c_int, _dp, ctypes.c_int], ctypes.c_int),
     "fgl_loglike_batch_device": ([_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp],
                                  ctypes.c_int),
+    "fgl_loglike_batch_device_noalloc": ([_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp],
+                                         ctypes.c_int),
     "fgl_loglike_grad_batch": ([_vp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int], ctypes.c_int),
     "fgl_loglike_grad_batch_device": ([_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp],
                                       ctypes.c_int),
@@ -168,6 +170,11 @@ def fgl_loglike_batch(model, theta, B, out, prec):
 def fgl_loglike_batch_device(model, d_theta: int, B, d_out: int, prec, stream: int = 0):
     return _check(_lib.fgl_loglike_batch_device(model, _vp(d_theta), int(B), _vp(d_out),
                                                 _prec(prec), _vp(stream)))
+
+
+def fgl_loglike_batch_device_noalloc(model, d_theta: int, B, d_out: int, prec, stream: int = 0):
+    return _check(_lib.fgl_loglike_batch_device_noalloc(model, _vp(d_theta), int(B), _vp(d_out),
+                                                        _prec(prec), _vp(stream)))
 
 
 def fgl_loglike_grad_batch(model, theta, B, out, grad, prec="fp64"):
@@ -301,6 +308,19 @@ class Model:
         s = stream if stream is not None else torch.cuda.current_stream(theta.device)
         fgl_loglike_batch_device(self.handle, theta.data_ptr(), B, out.data_ptr(), prec,
                                  s.cuda_stream)
+        return out
+
+    def loglike_device_noalloc(self, theta, out, prec="mixed", stream=None):
+        """As loglike_device, through the entry point that allocates
+        nothing (out must be given: a float64 device tensor [B])."""
+        import torch
+        if theta.dtype != torch.float64 or not theta.is_cuda or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous float64 device tensor")
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < theta.shape[0]:
+            raise ValueError("out must be a float64 device tensor of at least B values")
+        s = stream if stream is not None else torch.cuda.current_stream(theta.device)
+        fgl_loglike_batch_device_noalloc(self.handle, theta.data_ptr(), theta.shape[0],
+                                         out.data_ptr(), prec, s.cuda_stream)
         return out
 
     def tune(self, B: int, prec="mixed"):
