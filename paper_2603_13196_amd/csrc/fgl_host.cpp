@@ -542,9 +542,11 @@ std::vector<Tile> candidates(Kind k, const DevModel& d) {
   if (G == 0) return out;
   const bool occ3 = k == kMixed && mixed_occ3(d);
   const std::vector<int> waves = k == kThin ? std::vector<int>{1, 2, 4} : std::vector<int>{4, 8};
+  std::vector<int> occs{2};
+  if (occ3) occs.push_back(3);
   for (int w : waves) {
     if (w > max_waves(k, d)) continue;
-    for (int occ = 2; occ <= (occ3 ? 3 : 2); ++occ) {
+    for (int occ : occs) {
       const int per_cu = occ == 3 ? std::max(1, 12 / w) : 1;
       for (int mult = 1; mult <= 8; ++mult) {
         Tile t{w, G * mult, G, occ};

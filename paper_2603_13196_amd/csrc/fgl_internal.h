@@ -97,7 +97,7 @@ struct Tile {
   int waves;   // waves per workgroup: 4 or 8
   int fc;      // frequency channels staged per workgroup
   int group;   // channels per reduction group
-  int occ;     // waves per SIMD the kernel is compiled for (2)
+  int occ;     // waves per SIMD the kernel is compiled for (2 or 3)
 };
 
 // Device-side model (all pointers are device memory owned by the model).

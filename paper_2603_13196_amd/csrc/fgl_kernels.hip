@@ -233,9 +233,13 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     double nl, nu;
     int ek;
   };
+  struct Epi {                 // what the epilogue and the peeled row need
+    double s0, t0, qlast;      // s0: unit of acc0 (acc1: s0 2^-16, acc2: s0 2^-32)
+    int ey, fm;
+  };
   struct Chan {
-    double s0, s1, s2, t0, qlast;
-    int c0, c1, c2, ey, fm;
+    Epi e;
+    int c0, c1, c2;
     i32x4 B[KC][NP];
   };
   auto fetch = [&](int fi) {
@@ -267,19 +271,17 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     double ymax = AB ? ceil(fma(bext, nl, 64.0 * rp.omax)) : ceil(bext * nl);
     const int ey = (int)floor(ymax * (1.0 / 64.0));
     const int fm = (int)(ymax - 64.0 * ey);
-    C.ey = ey;
-    C.fm = fm;
-    C.t0 = 0.0;
+    C.e.ey = ey;
+    C.e.fm = fm;
+    C.e.t0 = 0.0;
     C.c0 = C.c1 = C.c2 = 0;
-    C.qlast = 0.0;
+    C.e.qlast = 0.0;
     if constexpr (PROJ) {
       // unit of the level-0 product: 2^(ymax/64) / Q times 2^(eR - 46)
       // times its weight 2^80
       const double u = ldexp(s_frac[fm], ey + sc.ek + 80 - kProjBits - 47);
-      C.s0 = u * 0x1.0p-8;
-      C.s1 = u * 0x1.0p-24;
-      C.s2 = u * 0x1.0p-40;
-      C.t0 = m.dbar[fi] - m.sqrtT * c;             // target of the mean row
+      C.e.s0 = u * 0x1.0p-8;
+      C.e.t0 = m.dbar[fi] - m.sqrtT * c;           // target of the mean row
     } else {
       // unit of the level-0 product: 2^(ymax/64) / Q times 2^(eK - 31)
       // times its weight 2^64, i.e. frac[fm] 2^(ey + eK - 14)
@@ -293,16 +295,14 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
       eu += sh;
       ic = ldexp(ic, -sh);
       const double u0 = ldexp(s_frac[fm], eu);
-      C.s0 = u0 * 0x1.0p-8;
-      C.s1 = u0 * 0x1.0p-24;
-      C.s2 = u0 * 0x1.0p-40;
+      C.e.s0 = u0 * 0x1.0p-8;
       const double c0f = rint(ic);
       C.c0 = (int)c0f;
       // remainders by fma, in acc1 then acc2 units; c1, c2 in [-2^15, 2^15]
-      const double r1 = fma(-c0f, C.s0, c);
+      const double r1 = fma(-c0f, C.e.s0, c);
       const double c1f = rint(r1 * ldexp(s_ifrac[fm], 24 - eu));
       C.c1 = (int)c1f;
-      C.c2 = (int)rint(fma(-c1f, C.s1, r1) * ldexp(s_ifrac[fm], 40 - eu));
+      C.c2 = (int)rint(fma(-c1f, u0 * 0x1.0p-24, r1) * ldexp(s_ifrac[fm], 40 - eu));
     }
     // Powers 2^(y/64), y = 64 log2(x) <= 0, as tab[round(y)] 2^(r/64), the
     // latter by its Taylor series to fifth order (truncation below 4e-17
@@ -334,7 +334,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
         p = fma(r, p, m.c1);
         p = fma(r, p, 1.0);                        // 2^(r/64)
         const double q = fma(T2, p, DIGITS);       // 2^52 + q + offsets
-        if (PROJ && kc == KC - 1 && j == 15) C.qlast = q - DIGITS;
+        if (PROJ && kc == KC - 1 && j == 15) C.e.qlast = q - DIGITS;
         const unsigned long long bits = __double_as_longlong(q);
         lo[j] = (uint32_t)bits ^ 0x80808080u;      // digits d2 d3 d4 d5 (byte 3..0)
         hi[j] = (uint32_t)(bits >> 32);            // byte 1: d0, byte 0: d1 + 128
@@ -405,15 +405,16 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     }
   };
 #undef MF
-  auto epi = [&](int f, int tt, const Chan& C, const i32x16& a0, const i32x16& a1,
+  auto epi = [&](int f, int tt, const Epi& C, const i32x16& a0, const i32x16& a1,
                  const i32x16& a2) {
     const double* Dt = s_D + (size_t)f * TT * 32 + g * 4 + tt * 32;
+    const double s0 = C.s0, s1 = C.s0 * 0x1.0p-16, s2 = C.s0 * 0x1.0p-32;
     if (!PROJ && tt == TT - 1 && (m.T & 31)) {     // ragged last tile (uniform)
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double r = fma(-C.s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
-        r = fma(-C.s1, (double)a1[j], r);
-        r = fma(-C.s2, (double)a2[j], r);
+        double r = fma(-s0, (double)a0[j], Dt[(j >> 2) * 8 + (j & 3)]);
+        r = fma(-s1, (double)a1[j], r);
+        r = fma(-s2, (double)a2[j], r);
         const int t = tt * 32 + (j >> 2) * 8 + g * 4 + (j & 3);
         r = t < m.T ? r : 0.0;
         if (j & 1) acc_b = fma(r, r, acc_b);
@@ -426,26 +427,16 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
         // projected form: row 0 (element 0 of the first tile in lanes
         // 0..31) is the mean row, whose target depends on the row b
         if (PROJ && j == 0) d = (tt == 0 && g == 0) ? C.t0 : d;
-        double r = fma(-C.s0, (double)a0[j], d);
-        r = fma(-C.s1, (double)a1[j], r);
-        r = fma(-C.s2, (double)a2[j], r);
+        double r = fma(-s0, (double)a0[j], d);
+        r = fma(-s1, (double)a1[j], r);
+        r = fma(-s2, (double)a2[j], r);
         if (j & 1) acc_b = fma(r, r, acc_b);
         else acc_a = fma(r, r, acc_a);
       }
     }
   };
-  // the row tiles of channel f, the peeled row, the partial
-  auto finish = [&](int f, const Chan& C) {
-    // A wave finishes one row tile before the next; the other waves of its
-    // SIMD overlap their vector work with its matrix work.
-    for (int tt = 0; tt < TT; ++tt) {
-      i32x4 A[ND][KC];
-      i32x16 x0, x1, x2;
-      load_A(f, tt, A);
-      part1(A, C, x0, x1, x2);
-      part2(A, C, x0, x1, x2);
-      epi(f, tt, C, x0, x1, x2);
-    }
+  // after a channel's last row tile: the peeled row, the partial
+  auto tail = [&](int f, const Epi& C) {
     if constexpr (PROJ) {
       // peeled last row of R: R[N-1][N-1] P_{N-1}, P from the same rounding
       // (region N - 1 = 32 KC - 1 is element 15 of the last chunk, g = 1)
@@ -466,13 +457,23 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
     }
   };
 
+  // A wave finishes one row tile before the next; the other waves of its
+  // SIMD overlap their vector work with its matrix work.
   Scal sc = fetch(f0);
   for (int f = 0; f < fn; ++f) {
     const Scal cur = sc;
     sc = fetch(f0 + f + 1);                        // one channel ahead
     Chan C;
     make(cur, f0 + f, C);
-    finish(f, C);
+    for (int tt = 0; tt < TT; ++tt) {
+      i32x4 A[ND][KC];
+      i32x16 x0, x1, x2;
+      load_A(f, tt, A);
+      part1(A, C, x0, x1, x2);
+      part2(A, C, x0, x1, x2);
+      epi(f, tt, C.e, x0, x1, x2);
+    }
+    tail(f, C.e);
   }
 }
 
