@@ -269,8 +269,21 @@ def small_batch_leg(fgl, calls=200):
             dev_us = (time.perf_counter() - t0) / calls * 1e6
             r[prec] = {"host_call_median_us": host_us, "device_call_us": dev_us,
                        "evals_per_s_device": w.B / (dev_us * 1e-6)}
-        out[w.name] = r
         m.close()
+        # the device call replayed from captured graphs (FGL_DEVICE_GRAPHS=1)
+        os.environ["FGL_DEVICE_GRAPHS"] = "1"
+        mg = fgl.Model.from_workload(w)
+        del os.environ["FGL_DEVICE_GRAPHS"]
+        for _ in range(3):
+            mg.loglike_device(th, o, "mixed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            mg.loglike_device(th, o, "mixed")
+        torch.cuda.synchronize()
+        r["mixed"]["device_call_us_graph_replay"] = (time.perf_counter() - t0) / calls * 1e6
+        mg.close()
+        out[w.name] = r
     return out
 
 

@@ -181,6 +181,10 @@ int fgl_loglike_batch(fgl_model* m, const double* theta, int B,
  * Asynchronous: returns after enqueueing; d_out is valid once the stream
  * reaches this point.  d_theta must stay valid until then.  The model's
  * per-stream workspace is reused by the next call on the same stream.
+ * With FGL_DEVICE_GRAPHS=1 in the environment when the model is created, a
+ * call seen before (same precision, B, tile, buffers and stream) is
+ * replayed from a captured hipGraph, with bitwise the same results; by
+ * default the kernels are launched directly, which costs the host less here.
  */
 int fgl_loglike_batch_device(fgl_model* m, const double* d_theta, int B,
                              double* d_out, int prec, void* hip_stream);
@@ -245,8 +249,24 @@ int fgl_get_tile(fgl_model* m, int B, int prec, int* waves, int* chans,
                  int* occupancy);
 
 /* Measure the candidate tiles for (model, B, prec) now and keep the
- * fastest for later calls.  Synchronous; uses the device. */
+ * fastest for later calls, and in the tuner cache.  Synchronous; uses the
+ * device. */
 int fgl_tune(fgl_model* m, int B, int prec);
+
+/*
+ * The tuner cache: the tiles fgl_tune (or FGL_TUNE=1) measured, by device
+ * architecture, kernel family, model shape (N, n_alpha, F, T) and form,
+ * and batch bucket (B rounded up to a power of two >= 256), shared by all
+ * models of the process.  A model without a tile of its own for a call uses
+ * the cached one when it is still a candidate for it, else the default.
+ * path: a file of one JSON object per line,
+ *   {"arch":"gfx950","kind":0,"N":32,...,"bucket":16384,"waves":8,"fc":8,"occ":3}
+ * whose entries are loaded now (a missing file is an empty cache) and which
+ * is rewritten after every tuning; NULL stops writing.  The environment
+ * variable FGL_TUNE_CACHE names such a file for the process when this is
+ * never called.  Tiles never change results.  Returns FGL_OK.
+ */
+int fgl_tune_cache(const char* path);
 
 /* Force the tile for (model, B's size class, prec); FGL_EINVAL unless it is
  * one of the tuner's candidates for this model.  Results are unchanged. */

@@ -10,6 +10,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <string>
+
+#include <unistd.h>
 
 namespace fgl {
 
@@ -697,10 +700,126 @@ int enqueue_grad(Model* m, WorkBuf& wb, const double* d_theta, int B, double* d_
   return FGL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// tuner cache: tuned tiles by (architecture, kernel family, model shape and
+// form, batch bucket), shared by the models of a process and kept in a file
+// of one JSON object per line (fgl_tune_cache or FGL_TUNE_CACHE), so that
+// later processes start from the tiles earlier ones measured.
+
+namespace {
+
+std::mutex g_tc_mu;
+std::map<std::string, Tile> g_tc;          // process cache
+std::string g_tc_path;                     // file ("" = not persisted)
+bool g_tc_env_done = false;
+std::atomic<uint64_t> g_tc_gen{1};         // bumped whenever the cache changes
+
+// The fields that fix a model's candidate tiles and their speeds.
+std::string tc_key(const Model* m, Kind k, int bucket) {
+  const DevModel& d = m->dm;
+  char buf[256];
+  std::snprintf(buf, sizeof buf,
+                "\"arch\":\"%s\",\"kind\":%d,\"N\":%d,\"NA\":%d,\"F\":%d,\"T\":%d,"
+                "\"proj\":%d,\"pplain\":%d,\"thin\":%d,\"bucket\":%d",
+                m->arch.c_str(), (int)k, d.N, d.NA, d.F, d.T, d.proj, d.pplain,
+                d.thin, bucket);
+  return buf;
+}
+
+// One line per entry: {<key fields>,"waves":w,"fc":c,"occ":o}.  Lines that
+// do not parse are skipped.
+void tc_load_file(const std::string& path) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    std::string l(line);
+    const size_t w = l.find(",\"waves\":");
+    if (l.size() < 2 || l[0] != '{' || w == std::string::npos) continue;
+    Tile t{0, 0, 0, 0};
+    if (std::sscanf(l.c_str() + w, ",\"waves\":%d,\"fc\":%d,\"occ\":%d}", &t.waves, &t.fc,
+                    &t.occ) != 3)
+      continue;
+    g_tc[l.substr(1, w - 1)] = t;
+  }
+  std::fclose(f);
+  ++g_tc_gen;
+}
+
+// Write the whole cache (a temporary file renamed over the old one, so a
+// reader never sees half a file).  Best effort: a failure leaves the file
+// as it was.
+void tc_save_file() {
+  if (g_tc_path.empty()) return;
+  const std::string tmp = g_tc_path + ".tmp" + std::to_string((long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  bool ok = true;
+  for (const auto& kv : g_tc)
+    ok = ok && std::fprintf(f, "{%s,\"waves\":%d,\"fc\":%d,\"occ\":%d}\n", kv.first.c_str(),
+                            kv.second.waves, kv.second.fc, kv.second.occ) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), g_tc_path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+void tc_env_once() {
+  if (g_tc_env_done) return;
+  g_tc_env_done = true;
+  const char* p = std::getenv("FGL_TUNE_CACHE");
+  if (p && p[0]) {
+    g_tc_path = p;
+    tc_load_file(g_tc_path);
+  }
+}
+
+}  // namespace
+
+int tune_cache_set(const char* path) {
+  std::lock_guard<std::mutex> lk(g_tc_mu);
+  g_tc_env_done = true;
+  g_tc_path = path ? path : "";
+  if (!g_tc_path.empty()) tc_load_file(g_tc_path);
+  return FGL_OK;
+}
+
+// A tile from the process cache, if one was measured for this model's shape
+// and is still a candidate for it.
+static bool tc_lookup(Model* m, Kind k, int bucket, Tile* out) {
+  std::lock_guard<std::mutex> lk(g_tc_mu);
+  tc_env_once();
+  auto it = g_tc.find(tc_key(m, k, bucket));
+  if (it == g_tc.end()) return false;
+  for (const Tile& t : candidates(k, m->dm))
+    if (t.waves == it->second.waves && t.fc == it->second.fc && t.occ == it->second.occ) {
+      *out = t;
+      return true;
+    }
+  return false;
+}
+
+static void tc_store(Model* m, Kind k, int bucket, const Tile& t) {
+  std::lock_guard<std::mutex> lk(g_tc_mu);
+  tc_env_once();
+  g_tc[tc_key(m, k, bucket)] = t;
+  ++g_tc_gen;
+  tc_save_file();
+}
+
 Tile tile_for(Model* m, Kind k, int B) {
   const uint64_t key = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
   auto it = m->tiles.find(key);
   if (it != m->tiles.end()) return it->second;
+  // the cache is consulted again only after it changed
+  const uint64_t gen = g_tc_gen.load();
+  auto miss = m->tc_miss.find(key);
+  if (miss == m->tc_miss.end() || miss->second != gen) {
+    Tile t;
+    if (tc_lookup(m, k, bucket_of(B), &t)) {
+      m->tiles[key] = t;
+      return t;
+    }
+    m->tc_miss[key] = gen;
+  }
   return default_tile(k, m->dm, B);
 }
 
@@ -756,6 +875,7 @@ int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
   if (rc == FGL_OK) {
     const uint64_t key = ((uint64_t)k << 32) | (uint32_t)bucket_of(B);
     m->tiles[key] = best;
+    tc_store(m, k, bucket_of(B), best);
   }
   return rc;
 }
@@ -804,6 +924,14 @@ static int create_model(const float* K, const double* freqs, const double* data,
   Model* m = new (std::nothrow) Model();
   if (!m) return set_err(FGL_ENOMEM, "host allocation");
   m->dev = dev;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      m->arch = prop.gcnArchName;
+      const size_t c = m->arch.find(':');
+      if (c != std::string::npos) m->arch.resize(c);
+    }
+  }
   m->N = N;
   m->F = F;
   m->T = T;
@@ -867,6 +995,8 @@ static int create_model(const float* K, const double* freqs, const double* data,
   m->autotune = tune_env && tune_env[0] == '1';
   const char* graph_env = std::getenv("FGL_NO_GRAPH");
   m->use_graphs = !(graph_env && graph_env[0] == '1');
+  const char* dgraph_env = std::getenv("FGL_DEVICE_GRAPHS");
+  m->device_graphs = m->use_graphs && dgraph_env && dgraph_env[0] == '1';
   register_model(m);
   *out = reinterpret_cast<fgl_model*>(m);
   return FGL_OK;
@@ -977,6 +1107,9 @@ int fgl_loglike_batch(fgl_model* mh, const double* theta, int B, double* out, in
   return FGL_OK;
 }
 
+// Device-call graphs a model keeps before dropping them all.
+constexpr size_t kMaxDeviceGraphs = 16;
+
 int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
                              double* d_out, int prec, void* hip_stream) {
   Model* m = reinterpret_cast<Model*>(mh);
@@ -998,7 +1131,64 @@ int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
   }
   const Tile tile = tile_for(m, k, B);
   if ((rc = ensure_work(m, wb, B, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
-  return enqueue(m, k, tile, wb, d_theta, B, d_out, s);
+  // With FGL_DEVICE_GRAPHS=1: graph replay of prep, likelihood kernel and
+  // finalize for a (precision, B, tile, buffers, stream) seen before,
+  // captured on the model's own stream (the caller's may be the legacy
+  // default stream, which cannot be captured) and launched on the caller's.
+  // Off by default: one hipGraphLaunch costs the host more than the three
+  // kernel launches it replaces (measured: back-to-back calls of a 1000-row
+  // model take 22 us per call with graphs, 12 us without).  Calls whose
+  // kernel the timing option records run eagerly.
+  const bool rec_next = m->timing > 0 && m->timing_n % (uint64_t)m->timing == 0;
+  if (!m->device_graphs || rec_next) return enqueue(m, k, tile, wb, d_theta, B, d_out, s);
+  GraphKey gk{k, B, tile.waves, tile.fc, tile.occ};
+  gk.theta = d_theta;
+  gk.out = d_out;
+  gk.stream = s;
+  auto it = m->graphs.find(gk);
+  if (it != m->graphs.end() && it->second.exec) {
+    if (m->timing > 0) ++m->timing_n;
+    if ((e = hipGraphLaunch(it->second.exec, s)) != hipSuccess) return hip_err(e, "hipGraphLaunch");
+    return FGL_OK;
+  }
+  if (it == m->graphs.end()) {                     // first sighting: eager
+    if ((rc = enqueue(m, k, tile, wb, d_theta, B, d_out, s)) != FGL_OK) return rc;
+    // bound the device-call graphs a model keeps (each holds buffers' addresses)
+    size_t dev_graphs = 0;
+    for (const auto& kv : m->graphs) dev_graphs += kv.first.theta != nullptr;
+    if (dev_graphs >= kMaxDeviceGraphs) {
+      for (auto g = m->graphs.begin(); g != m->graphs.end();) {
+        if (g->first.theta) {
+          if (g->second.exec) (void)hipGraphExecDestroy(g->second.exec);
+          g = m->graphs.erase(g);
+        } else {
+          ++g;
+        }
+      }
+    }
+    m->graphs[gk];
+    return FGL_OK;
+  }
+  // second sighting: capture on the model's stream, then launch on s
+  hipStream_t cs = m->stream;
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_err(e, "hipStreamBeginCapture");
+  const int erc = enqueue(m, k, tile, wb, d_theta, B, d_out, cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(cs, &graph);
+  if (erc != FGL_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return erc;
+  }
+  if (ee != hipSuccess) return hip_err(ee, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_err(e, "hipGraphInstantiate");
+  it->second.exec = exec;
+  if (m->timing > 0) ++m->timing_n;
+  if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return hip_err(e, "hipGraphLaunch");
+  return FGL_OK;
 }
 
 static int check_grad(Model* m, int B, int prec) {
@@ -1110,6 +1300,8 @@ int fgl_set_tile(fgl_model* mh, int B, int prec, int waves, int chans, int occup
   return set_err(FGL_EINVAL, "tile (waves=%d, chans=%d, occupancy=%d) is not a candidate for "
                  "this model and precision", waves, chans, occupancy);
 }
+
+int fgl_tune_cache(const char* path) { return tune_cache_set(path); }
 
 int fgl_tune(fgl_model* mh, int B, int prec) {
   Model* m = reinterpret_cast<Model*>(mh);

@@ -28,14 +28,23 @@ struct WorkBuf {
   size_t grad_bytes = 0;       // capacity of d_grad / h_grad
 };
 
+// A captured call: host-pointer calls run on the model's staging buffers
+// (theta, out and stream NULL); device-pointer calls also key on the
+// caller's buffers and stream.
 struct GraphKey {
   int kind, B, waves, fc, occ;
+  const void* theta = nullptr;
+  const void* out = nullptr;
+  const void* stream = nullptr;
   bool operator<(const GraphKey& o) const {
     if (kind != o.kind) return kind < o.kind;
     if (B != o.B) return B < o.B;
     if (waves != o.waves) return waves < o.waves;
     if (fc != o.fc) return fc < o.fc;
-    return occ < o.occ;
+    if (occ != o.occ) return occ < o.occ;
+    if (theta != o.theta) return theta < o.theta;
+    if (out != o.out) return out < o.out;
+    return stream < o.stream;
   }
 };
 
@@ -51,7 +60,8 @@ struct Model {
   DevModel dm{};
   bool resident = false;
   bool autotune = false;
-  bool use_graphs = true;
+  bool use_graphs = true;       // host-pointer calls: replay captured graphs
+  bool device_graphs = false;   // device-pointer calls too (FGL_DEVICE_GRAPHS=1)
   hipStream_t stream = nullptr;
   std::mutex mu;                        // serialises calls on this model
   std::atomic<int> inflight{0};         // synchronous calls in progress
@@ -61,6 +71,8 @@ struct Model {
   std::vector<WorkBuf> retired;         // outgrown workspaces (freed at destroy)
   std::map<GraphKey, GraphEntry> graphs;
   std::unordered_map<uint64_t, Tile> tiles;  // tuned tiles per (kind, B bucket)
+  std::unordered_map<uint64_t, uint64_t> tc_miss;  // tuner-cache misses, by cache generation
+  std::string arch;                           // device architecture, e.g. gfx950
   // host copies of the device layouts (re-uploaded after an eviction)
   std::vector<int8_t> h_kd;
   std::vector<int32_t> h_eK;
@@ -111,6 +123,7 @@ int enqueue_main(Model* m, Kind k, const Tile& tile, WorkBuf& wb, hipStream_t s)
 int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
          double* d_out, hipStream_t s);
 void drop_stream_work(hipStream_t s);   // fgl_host.cpp
+int tune_cache_set(const char* path);   // fgl_host.cpp
 void serve_forget_model(Model* m);      // fgl_serve.cpp
 
 }  // namespace fgl

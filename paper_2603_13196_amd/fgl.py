@@ -107,6 +107,7 @@ _SIGS = {
     "fgl_noise_loglike": ([ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                            ctypes.c_uint64, _dp, _dp], ctypes.c_int),
     "fgl_noise_quantile": ([_dp, ctypes.c_int, _dp, ctypes.c_int, _dp], ctypes.c_int),
+    "fgl_tune_cache": ([ctypes.c_char_p], ctypes.c_int),
     "fgl_last_error": ([], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -135,6 +136,12 @@ def _prec(p) -> int:
 
 def fgl_last_error() -> str:
     return _lib.fgl_last_error().decode()
+
+
+def fgl_tune_cache(path) -> int:
+    """Load tuned tiles from `path` (JSON lines) and write later tunings
+    there; None stops writing."""
+    return _check(_lib.fgl_tune_cache(None if path is None else os.fsencode(path)))
 
 
 def fgl_model_create(K, freqs, data, nu_ref, N, F, T, t_cmb, flags=0):
