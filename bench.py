@@ -51,7 +51,10 @@ def parse():
     p.add_argument("--no-serve", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-plain", action="store_true")
-    p.add_argument("--serve-seconds", type=float, default=3.0)
+    p.add_argument("--serve-seconds", type=float, default=1.2)
+    p.add_argument("--serve-configs", default=None,
+                   help="serving configurations to run instead of the sweep, as "
+                        "SLOTS:SHARING[:HALF], e.g. 4:16 or 4:1:half")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-sampler", action="store_true",
                    help="skip the nested-sampling run (10 regions, T = 1, benchmark settings)")
@@ -120,11 +123,11 @@ def traffic_from_profiles(kernel_src_hash):
         return None
 
 
-def serving_leg(fgl, seconds, log_every=1.0):
-    import workload
-    clients = workload.serving_clients(64, n_requests=64)
-    models = [fgl.Model.from_workload(c.work) for c in clients]
-    srv = fgl.Server(budget_bytes=0, max_inflight=8)
+def _serve_run(fgl, clients, models, seconds, inflight, share, budget, log_every=1.0):
+    """The closed-loop serving mix for `seconds`: each client waits Exp(2 ms)
+    after a result before submitting its next batch (mixed precision)."""
+    srv = fgl.Server(budget_bytes=budget, max_inflight=inflight)
+    srv.set_sharing(share)
     rng = np.random.Generator(np.random.PCG64(31))
     state = []
     now = time.perf_counter()
@@ -137,7 +140,7 @@ def serving_leg(fgl, seconds, log_every=1.0):
     while True:
         now = time.perf_counter()
         if now >= next_log:
-            log(f"serving: {len(lat)} requests done")
+            log(f"serving (slots {inflight}, sharing {share}): {len(lat)} requests done")
             next_log += log_every
         busy = False
         for c, st, m in zip(clients, state, models):
@@ -159,14 +162,51 @@ def serving_leg(fgl, seconds, log_every=1.0):
             break
         time.sleep(20e-6)
     wall = time.perf_counter() - t_start
+    launches, shared, groups = srv.stats()
     srv.close()
-    for m in models:
-        m.close()
     lat = np.array(lat)
-    return {"clients": len(clients), "requests": int(lat.size),
+    return {"max_inflight": inflight, "sharing": share, "requests": int(lat.size),
             "p50_ms": float(np.percentile(lat, 50)) / 1e3,
             "p99_ms": float(np.percentile(lat, 99)) / 1e3,
-            "evals_per_s": rows / wall, "seconds": wall, "max_inflight": 8}
+            "evals_per_s": rows / wall, "seconds": wall, "launches": launches,
+            "shared_launches": shared, "groups_in_shared": groups}
+
+
+def serving_leg(fgl, seconds, configs_arg=None):
+    """The 64-client serving mix swept over 1..4 in-flight slots (the box
+    runs 4 hardware queues per process), with per-model launches and with
+    launches shared by up to 16 models of one kernel variant, every model
+    resident; then at 2 and 4 slots under an HBM budget of half the
+    models' resident bytes, where admission waits and evictions take part.
+    The headline record is the resident configuration with the lowest p99."""
+    import workload
+    clients = workload.serving_clients(64, n_requests=64)
+    models = [fgl.Model.from_workload(c.work) for c in clients]
+    total = sum(m.nbytes for m in models)
+    half = max(total // 2, max(m.nbytes for m in models))
+    sweep = []
+    configs = [(i, sh, 0) for sh in (1, 16) for i in (1, 2, 3, 4)]
+    configs += [(i, sh, half) for sh in (1, 16) for i in (2, 4)]
+    if configs_arg:
+        configs = []
+        for c in configs_arg.split(","):
+            f = c.split(":")
+            configs.append((int(f[0]), int(f[1]), half if len(f) > 2 else 0))
+    for inflight, share, budget in configs:
+        r = _serve_run(fgl, clients, models, seconds, inflight, share, budget)
+        r["budget_bytes"] = budget
+        sweep.append(r)
+        log(f"serving slots {inflight} sharing {share} budget {budget}: p50 {r['p50_ms']:.3f} ms, "
+            f"p99 {r['p99_ms']:.3f} ms, {r['evals_per_s']:.3e} evals/s, "
+            f"{r['shared_launches']} shared launches of {r['launches']}")
+    for m in models:
+        m.close()
+    best = min((r for r in sweep if not r["budget_bytes"]), key=lambda r: r["p99_ms"],
+               default=sweep[0])
+    return {"clients": len(clients), "models_bytes": total,
+            "requests": best["requests"], "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
+            "evals_per_s": best["evals_per_s"], "max_inflight": best["max_inflight"],
+            "sharing": best["sharing"], "budget_bytes": 0, "sweep": sweep}
 
 
 def sampler_leg(fgl, regions=10, T=1):
@@ -646,7 +686,7 @@ def main():
         line["noise_reference"] = noise_leg(fgl)
     if not a.no_serve:
         log("serving leg")
-        line["serving"] = serving_leg(fgl, a.serve_seconds)
+        line["serving"] = serving_leg(fgl, a.serve_seconds, a.serve_configs)
     if not a.no_sampler:
         log("nested sampling leg")
         line["nested_sampling"] = [sampler_leg(fgl, 10, 1), sampler_leg(fgl, 10, 72)]

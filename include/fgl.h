@@ -320,6 +320,26 @@ int fgl_serve_submit(fgl_server* s, fgl_model* m, const double* theta, int B,
                      double* out_logL, int prec, uint64_t* ticket);
 
 /*
+ * Launches shared by models (Sec. 3.1.2: many samplers' likelihood calls on
+ * one device): with max_models_per_launch > 1, the groups of up to that many
+ * waiting models whose likelihood kernel is the same compiled variant join
+ * one launch of the row-preparation, likelihood and finalize kernels, each
+ * workgroup finding its model in a descriptor table; every row's result is
+ * bitwise the one it gets alone.  The shareable variants are those the
+ * default tiles of models without amplitude masks use (the mixed kernel
+ * with 8-wave workgroups and at most 64 regions, in either form, and the
+ * small-model FP64 kernel); other requests launch per model.  1 (the
+ * default, or FGL_SERVE_SHARE at creation) launches per model.
+ * max_models_per_launch in 1..16.  Returns FGL_OK or FGL_EINVAL.
+ */
+int fgl_serve_set_sharing(fgl_server* s, int max_models_per_launch);
+
+/* Launch counters of a server: all launches, shared ones (more than one
+ * model) and the model groups those carried.  Any pointer may be NULL. */
+int fgl_serve_stats(fgl_server* s, uint64_t* launches, uint64_t* shared_launches,
+                    uint64_t* shared_groups);
+
+/*
  * Poll a ticket: *done = 1 when out_logL is written (then *latency_us is the
  * submit-to-completion time), else 0.  A done ticket is retired by the poll
  * that reports it; polling it again returns FGL_EINVAL.  A request that

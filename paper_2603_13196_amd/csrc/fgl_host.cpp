@@ -393,8 +393,10 @@ int make_resident(Model* m) {
 void evict(Model* m) {
   if (!m->resident) return;
   (void)hipSetDevice(m->dev);
-  // device-pointer calls return before their kernels finish
-  (void)hipDeviceSynchronize();
+  // device-pointer calls return before their kernels finish; a model only
+  // used by synchronous calls and servers (which evict a model only when
+  // none of its requests is in flight) has nothing left to wait for
+  if (m->async_calls) (void)hipDeviceSynchronize();
   const void* ps[] = {m->dm.kd, m->dm.eK, m->dm.k32, m->dm.k64, m->dm.nl64,
                       m->dm.nl2, m->dm.nu, m->dm.D, m->dm.tab, m->dm.rd,
                       m->dm.eR, m->dm.tg, m->dm.dbar, m->dm.pk, m->dm.pa64, m->dm.pt64,
@@ -1119,6 +1121,7 @@ int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
   if (!d_theta || !d_out) return set_err(FGL_EINVAL, "d_theta and d_out must be non-NULL");
   InflightGuard guard(m);
   std::lock_guard<std::mutex> lk(m->mu);
+  m->async_calls = true;
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   if ((rc = make_resident(m)) != FGL_OK) return rc;
@@ -1256,6 +1259,7 @@ int fgl_loglike_grad_batch_device(fgl_model* mh, const double* d_theta, int B,
     return set_err(FGL_EINVAL, "d_theta, d_out and d_grad must be non-NULL");
   InflightGuard guard(m);
   std::lock_guard<std::mutex> lk(m->mu);
+  m->async_calls = true;
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   if ((rc = make_resident(m)) != FGL_OK) return rc;

@@ -62,6 +62,7 @@ struct Model {
   bool autotune = false;
   bool use_graphs = true;       // host-pointer calls: replay captured graphs
   bool device_graphs = false;   // device-pointer calls too (FGL_DEVICE_GRAPHS=1)
+  bool async_calls = false;     // a device-pointer call was made (eviction then waits)
   hipStream_t stream = nullptr;
   std::mutex mu;                        // serialises calls on this model
   std::atomic<int> inflight{0};         // synchronous calls in progress

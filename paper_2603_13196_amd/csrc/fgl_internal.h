@@ -187,6 +187,21 @@ struct Work {
   double* gpart;         // gradient partials [chunks][grad_slots][Bpad]
 };
 
+// One model's rows in a launch shared by several models whose likelihood
+// kernel is the same compiled variant (serving): its model, workspace and
+// tile, and where its workgroups start in each of the three launches.
+constexpr int kMaxGroups = 16;
+struct GroupDesc {
+  DevModel m;
+  Work w;
+  int fc, G, nb, nc;     // likelihood tile and grid (row tiles x channel chunks)
+  int start[3];          // first workgroup in the likelihood, preparation and finalize launches
+  int ngroups;           // partials per row
+  const double* theta;   // [B][P] device
+  double* out;           // [B] device
+  double nFT, chi0;
+};
+
 // Gradient partials per (channel chunk, row): chi-square, the three 21-cm
 // sums, then per region sum_nu (-log2(nu/nu_ref)) c u and, with amplitude
 // masks, sum_nu c u (c: the region's coefficient, u: the region's row of
@@ -207,6 +222,15 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
                        const Tile& tile, hipStream_t s);
 hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
                            const Tile& tile, double* out, hipStream_t s);
+// The three launches of groups that share a compiled likelihood variant:
+// h[0..n) on the host (their start[] filled in here), copied by the caller
+// to d (device) before these run; `k` and `tile` as for group 0.
+void plan_groups(Kind k, const Tile& tile, GroupDesc* h, int n, int grid[3], int* lds);
+hipError_t launch_groups(Kind k, const DevModel& m0, const Tile& tile, const GroupDesc* d,
+                         int n, const int grid[3], int lds, hipStream_t s);
+// The compiled likelihood variant of (kind, model, tile): launches of models
+// with equal signatures can be shared.
+uint64_t variant_of(Kind k, const DevModel& m, const Tile& tile);
 // Gradient (FP64): the kernel writes w.gpart, the finalize lnL and the
 // gradient rows.  w.gpart must hold grad_slots(m) * chunks * Bpad doubles.
 hipError_t launch_grad(const DevModel& m, const Work& w, const GradShape& g,

@@ -62,14 +62,16 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // spectral indices and row records (which then stay in its L2 across all
 // channel chunks) while the chunks of K, shared by all XCDs, are read once
 // per XCD.
-__device__ inline void map_block(int nb, int nc, int& bt, int& ch) {
+__device__ inline void map_block_id(int id, int nb, int nc, int& bt, int& ch) {
   const int total = nb * nc;
-  const int id = blockIdx.x;
   const int xcd = id & 7, k = id >> 3;
   const int q = total >> 3, rem = total & 7;
   const int L = xcd * q + (xcd < rem ? xcd : rem) + k;
   bt = L / nc;
   ch = L - bt * nc;
+}
+__device__ inline void map_block(int nb, int nc, int& bt, int& ch) {
+  map_block_id(blockIdx.x, nb, nc, bt, ch);
 }
 
 // Cooperative 16-byte copy global -> LDS (bytes is a multiple of 16).
@@ -172,16 +174,18 @@ __device__ inline double pow2_64(double y, const double* t64, const DevModel& m)
 
 // OCC: waves per SIMD the register allocation targets (2, or 3 for the
 // projected form with one region chunk, which fits in 168 registers).
+// The body of workgroup `block` of a launch on (m, w); the kernels below
+// call it for one model (k_mixed) or for several that share the compiled
+// variant (k_mixed_multi).
 template <int W, int KC, bool PROJ, int OCC, int AM>
-__global__ __launch_bounds__(W * 64)
-__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
-                                                    int nb, int nc) {
+__device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, int fc, int G,
+                                           int nb, int nc, int block) {
   constexpr int ND = PROJ ? kProjDigits : 4;       // digits of the matrix rows
   constexpr int NP = 6;                            // digits of the powers
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
-  map_block(nb, nc, bt, ch);
+  map_block_id(block, nb, nc, bt, ch);
   const int TT = PROJ ? m.RT : m.TT;               // 32-row tiles
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
@@ -477,6 +481,36 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, 
   }
 }
 
+template <int W, int KC, bool PROJ, int OCC, int AM>
+__global__ __launch_bounds__(W * 64)
+__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
+                                                    int nb, int nc) {
+  mixed_body<W, KC, PROJ, OCC, AM>(m, w, fc, G, nb, nc, blockIdx.x);
+}
+
+// The group of workgroup blockIdx.x in launch `which` (0 likelihood, 1 row
+// preparation, 2 finalize).  In the likelihood launch groups start at
+// multiples of eight, so each group's XCD-aware map sees the XCD numbering a
+// launch of its own would.
+__device__ inline int group_of_block(const GroupDesc* d, int n, int which) {
+  int j = 0;
+  while (j + 1 < n && (int)blockIdx.x >= d[j + 1].start[which]) ++j;
+  return j;
+}
+
+template <int W, int KC, bool PROJ, int OCC, int AM>
+__global__ __launch_bounds__(W * 64)
+__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed_multi(const GroupDesc* __restrict__ d,
+                                                          int n) {
+  const int j = group_of_block(d, n, 0);
+  const int local = (int)blockIdx.x - d[j].start[0];
+  const int nb = d[j].nb, nc = d[j].nc;
+  if (local >= nb * nc) return;                    // padding to a multiple of eight
+  const DevModel m = d[j].m;
+  const Work w = d[j].w;
+  mixed_body<W, KC, PROJ, OCC, AM>(m, w, d[j].fc, d[j].G, nb, nc, local);
+}
+
 // ---------------------------------------------------------------------------
 // plain FP32 model (FP64 residual and chi-square)
 //
@@ -695,11 +729,11 @@ __global__ __launch_bounds__(W * 64) void k_fp64(DevModel m, Work w, int fc, int
 // reduction group, as the other kernels.
 
 template <int NT, bool AB>
-__global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int G, int nb,
-                                                int nc) {
+__device__ __forceinline__ void thin_body(const DevModel& m, const Work& w, int fc, int G,
+                                          int nb, int nc, int block) {
   extern __shared__ __align__(16) unsigned char smem[];
   int bt, ch;
-  map_block(nb, nc, bt, ch);
+  map_block_id(block, nb, nc, bt, ch);
   const int T = m.T, TD = m.TT * 32, N = m.N;
   const int f0 = ch * fc;
   const int fn = min(fc, m.F - f0);
@@ -744,6 +778,23 @@ __global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int 
       acc = 0.0;
     }
   }
+}
+
+template <int NT, bool AB>
+__global__ __launch_bounds__(256) void k_thin64(DevModel m, Work w, int fc, int G, int nb,
+                                                int nc) {
+  thin_body<NT, AB>(m, w, fc, G, nb, nc, blockIdx.x);
+}
+
+template <int NT, bool AB>
+__global__ __launch_bounds__(256) void k_thin64_multi(const GroupDesc* __restrict__ d, int n) {
+  const int j = group_of_block(d, n, 0);
+  const int local = (int)blockIdx.x - d[j].start[0];
+  const int nb = d[j].nb, nc = d[j].nc;
+  if (local >= nb * nc) return;
+  const DevModel m = d[j].m;
+  const Work w = d[j].w;
+  thin_body<NT, AB>(m, w, d[j].fc, d[j].G, nb, nc, local);
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,17 +1064,17 @@ __global__ __launch_bounds__(256) void k_grad_finalize(DevModel m, Work w, doubl
 // writes -inf for them).
 constexpr int kPrepRows = 16;
 
-__global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, int B, int Bpad,
-                                              int N, int NA, int NB, int P, unsigned flags,
-                                              int betaRows, double* __restrict__ betaT,
-                                              double* __restrict__ offT,
-                                              RowParams* __restrict__ rows) {
+__device__ __forceinline__ void prep_body(const double* __restrict__ theta, int B, int Bpad,
+                                          int N, int NA, int NB, int P, unsigned flags,
+                                          int betaRows, double* __restrict__ betaT,
+                                          double* __restrict__ offT,
+                                          RowParams* __restrict__ rows, int block) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* s_th = reinterpret_cast<double*>(smem);                 // [rows][P]
   double* s_fill = s_th + (size_t)kPrepRows * P;                 // [rows] bmin or 0
   double* s_ofill = s_fill + kPrepRows;                          // [rows] omin or 0
   int* s_ok = reinterpret_cast<int*>(s_ofill + kPrepRows);       // [rows]
-  const int b0 = blockIdx.x * kPrepRows;
+  const int b0 = block * kPrepRows;
   const int nrow = max(0, min(kPrepRows, B - b0));
   for (int k = threadIdx.x; k < nrow * P; k += blockDim.x)
     s_th[k] = theta[(size_t)b0 * P + k];
@@ -1109,6 +1160,21 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
   }
 }
 
+__global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, int B, int Bpad,
+                                              int N, int NA, int NB, int P, unsigned flags,
+                                              int betaRows, double* __restrict__ betaT,
+                                              double* __restrict__ offT,
+                                              RowParams* __restrict__ rows) {
+  prep_body(theta, B, Bpad, N, NA, NB, P, flags, betaRows, betaT, offT, rows, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_prep_multi(const GroupDesc* __restrict__ d, int n) {
+  const int j = group_of_block(d, n, 1);
+  const GroupDesc& g = d[j];
+  prep_body(g.theta, g.w.B, g.w.Bpad, g.m.N, g.m.NA, g.m.NB, g.m.P, g.m.flags, g.m.KC * 32,
+            g.w.betaT, g.w.offT, g.w.rows, (int)blockIdx.x - g.start[1]);
+}
+
 // lnL_b = -chi2_b / (2 sigma^2) - (F T / 2) ln(2 pi sigma^2), with chi2_b
 // the sum of the row's partials plus chi0 (a per-model constant of the
 // projected form, 0 otherwise).  Sixteen sums per row: sum s adds the
@@ -1117,13 +1183,13 @@ __global__ __launch_bounds__(256) void k_prep(const double* __restrict__ theta, 
 // on timing.  (The chain-step kernel adds a row the same way.)  A
 // workgroup takes 16 rows: thread t sums s = t / 16 for row t % 16, so a
 // wave's loads are runs of 16 consecutive rows.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int ngroup,
-                                                  int Bpad, const RowParams* __restrict__ rows,
-                                                  int B, double nFT, double chi0,
-                                                  double* __restrict__ out) {
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partial, int ngroup,
+                                              int Bpad, const RowParams* __restrict__ rows,
+                                              int B, double nFT, double chi0,
+                                              double* __restrict__ out, int block) {
   __shared__ double s_acc[16][16];                 // [s][row]
   const int bl = threadIdx.x & 15, s = threadIdx.x >> 4;
-  const int b = blockIdx.x * 16 + bl;
+  const int b = block * 16 + bl;
   double acc = 0.0;
   if (b < B)
     for (int c = s; c < ngroup; c += 16) acc += partial[(size_t)c * Bpad + b];
@@ -1145,6 +1211,20 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
   const double s2 = rp.sigma * rp.sigma;
   out[b] = -0.5 * (acc + chi0) / s2 - 0.5 * nFT * log(2.0 * M_PI * s2);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, int ngroup,
+                                                  int Bpad, const RowParams* __restrict__ rows,
+                                                  int B, double nFT, double chi0,
+                                                  double* __restrict__ out) {
+  finalize_body(partial, ngroup, Bpad, rows, B, nFT, chi0, out, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_multi(const GroupDesc* __restrict__ d, int n) {
+  const int j = group_of_block(d, n, 2);
+  const GroupDesc& g = d[j];
+  finalize_body(g.w.partial, g.ngroups, g.w.Bpad, g.w.rows, g.w.B, g.nFT, g.chi0, g.out,
+                (int)blockIdx.x - g.start[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1370,6 +1450,99 @@ hipError_t launch_finalize(Kind k, const DevModel& m, const Work& w,
   hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(threads), 0, s, w.partial,
                      n_groups(m, tile), w.Bpad, w.rows, w.B,
                      (double)m.F * (double)m.T, chi0, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// launches shared by several models (serving)
+//
+// Models whose likelihood kernel is the same compiled variant share one
+// launch of each of the three kernels; every workgroup finds its group in
+// the descriptor table and runs what a launch of its own would run, so each
+// row's result is bitwise the one it gets alone.  Sharing covers the
+// variants the default tiles of models without amplitude masks use: the
+// mixed kernel with 8 waves and one or two region chunks (both forms, both
+// register budgets) and the thin kernel.
+
+uint64_t variant_of(Kind k, const DevModel& m, const Tile& t) {
+  if (m.NA != 0) return 0;
+  if (k == kMixed) {
+    if (t.waves != 8 || m.KC > 2 || (t.occ == 3 && !(m.proj && m.KC == 1))) return 0;
+    return 1ull | (uint64_t)m.KC << 8 | (uint64_t)m.proj << 12 | (uint64_t)t.occ << 16;
+  }
+  if (k == kThin) return 2ull | (uint64_t)m.NT << 8 | (uint64_t)t.waves << 16;
+  return 0;
+}
+
+void plan_groups(Kind k, const Tile& tile, GroupDesc* h, int n, int grid[3], int* lds) {
+  const int cols = cols_per_wave(k) * tile.waves;
+  int main = 0, prep = 0, fin = 0, l = 0;
+  for (int j = 0; j < n; ++j) {
+    GroupDesc& g = h[j];
+    const Tile tj{tile.waves, g.fc, g.G, tile.occ};
+    g.nb = g.w.Bpad / cols;
+    g.nc = n_chunks(g.m, tj);
+    main = (main + 7) & ~7;
+    g.start[0] = main;
+    main += g.nb * g.nc;
+    g.start[1] = prep;
+    prep += (g.w.Bpad + kPrepRows - 1) / kPrepRows;
+    g.start[2] = fin;
+    fin += (g.w.B * 16 + 255) / 256;
+    l = std::max(l, lds_bytes(k, g.m, tj));
+  }
+  grid[0] = main;
+  grid[1] = prep;
+  grid[2] = fin;
+  *lds = l;
+}
+
+namespace {
+
+template <typename KernelT>
+hipError_t go_multi(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
+                    const GroupDesc* d, int n) {
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(kern));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, s, d, n);
+  return hipGetLastError();
+}
+
+hipError_t main_multi(Kind k, const DevModel& m, const Tile& t, const GroupDesc* d, int n,
+                      int blocks, int lds, hipStream_t s) {
+  if (k == kMixed) {
+    const int th = 8 * 64;
+    if (m.proj && m.KC == 1 && t.occ == 3)
+      return go_multi(k_mixed_multi<8, 1, true, 3, 0>, blocks, th, lds, s, d, n);
+    if (m.proj && m.KC == 1) return go_multi(k_mixed_multi<8, 1, true, 2, 0>, blocks, th, lds, s, d, n);
+    if (m.proj) return go_multi(k_mixed_multi<8, 2, true, 2, 0>, blocks, th, lds, s, d, n);
+    if (m.KC == 1) return go_multi(k_mixed_multi<8, 1, false, 2, 0>, blocks, th, lds, s, d, n);
+    return go_multi(k_mixed_multi<8, 2, false, 2, 0>, blocks, th, lds, s, d, n);
+  }
+  const int th = 64 * t.waves;
+  switch (m.NT) {
+    case 4: return go_multi(k_thin64_multi<4, false>, blocks, th, lds, s, d, n);
+    case 8: return go_multi(k_thin64_multi<8, false>, blocks, th, lds, s, d, n);
+    case 12: return go_multi(k_thin64_multi<12, false>, blocks, th, lds, s, d, n);
+    case 16: return go_multi(k_thin64_multi<16, false>, blocks, th, lds, s, d, n);
+    case 24: return go_multi(k_thin64_multi<24, false>, blocks, th, lds, s, d, n);
+    case 32: return go_multi(k_thin64_multi<32, false>, blocks, th, lds, s, d, n);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_groups(Kind k, const DevModel& m0, const Tile& tile, const GroupDesc* d,
+                         int n, const int grid[3], int lds, hipStream_t s) {
+  if (n < 1 || n > kMaxGroups || variant_of(k, m0, tile) == 0 || lds > max_lds_bytes())
+    return hipErrorInvalidValue;
+  // row preparation: the LDS of the widest row (at most 128 + 4 parameters)
+  const int plds = kPrepRows * ((kMixedMaxN + 4) + 2) * 8 + kPrepRows * 4;
+  hipError_t e = go_multi(k_prep_multi, grid[1], 256, plds, s, d, n);
+  if (e != hipSuccess) return e;
+  if ((e = main_multi(k, m0, tile, d, n, grid[0], lds, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize_multi, dim3(grid[2]), dim3(256), 0, s, d, n);
   return hipGetLastError();
 }
 

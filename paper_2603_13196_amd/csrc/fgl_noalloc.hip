@@ -67,6 +67,7 @@ extern "C" int fgl_loglike_batch_device_noalloc(fgl_model* mh, const double* d_t
   if (!d_theta || !d_out) return set_err(FGL_EINVAL, "d_theta and d_out must be non-NULL");
   InflightGuard guard(m);
   std::lock_guard<std::mutex> lk(m->mu);
+  m->async_calls = true;
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   if (!m->resident)

@@ -5,11 +5,15 @@
 // slots are free: a request is admissible when its model is resident, or can
 // be made resident within the HBM budget after evicting idle models in LRU
 // order.  Admitted requests for the same (model, precision) that are waiting
-// together are merged into one launch (rows are independent and every row's
-// reduction order is fixed, so merging never changes a result bit).  Each
-// slot owns a HIP stream, so launches of different requests overlap on the
-// device; completion is signalled by a host function enqueued behind the
-// launch, and the scheduler admits the next request as soon as a slot frees.
+// together are merged into one group (rows are independent and every row's
+// reduction order is fixed, so merging never changes a result bit).  With
+// sharing on (fgl_serve_set_sharing), the groups of other waiting models
+// whose likelihood kernel is the same compiled variant join it: one launch
+// of each of the three kernels then serves models of different sizes, each
+// workgroup finding its model in a descriptor table.  Each slot owns a HIP
+// stream, so the launches of different slots overlap on the device;
+// completion is signalled by a host function enqueued behind the launch, and
+// the scheduler admits the next request as soon as a slot frees.
 #include "fgl_host.h"
 
 #include <algorithm>
@@ -47,20 +51,26 @@ struct Slot {
   hipStream_t s = nullptr;
   bool busy = false;
   std::atomic<bool> finished{false};  // set by the stream callback
-  std::vector<Req*> reqs;
+  std::vector<Req*> reqs;      // in launch order; outputs are laid out in this order
+  int ngroups = 0;             // (model, precision) groups in the launch
   int rows = 0;
-  int cap = 0;                 // rows the staging buffers hold
-  int pcap = 0;                // parameters per row they were sized for
+  size_t cap = 0;              // doubles of theta the staging buffers hold
+  int ocap = 0;                // rows of output they hold
   double* d_theta = nullptr;
   double* d_out = nullptr;
   double* h_theta = nullptr;   // pinned
   double* h_out = nullptr;     // pinned
+  GroupDesc* d_desc = nullptr; // descriptor table of a shared launch
+  GroupDesc* h_desc = nullptr; // pinned
 };
 
 struct Server {
   size_t budget = 0;
   int max_inflight = 1;
   int merge_rows = 16384;
+  int share = 1;                    // models per launch (1: no sharing)
+  int share_rows = 65536;           // rows per shared launch
+  uint64_t n_launches = 0, n_shared = 0, n_shared_groups = 0;
   std::mutex mu;
   std::condition_variable cv_done;  // completions (drain), with mu
   // Scheduler wake-up.  Kept apart from `mu` because the stream callback
@@ -143,25 +153,27 @@ static bool admit_model(Server* srv, Model* m) {
   return true;
 }
 
-static int grow_slot(Slot* sl, int rows, int P) {
-  if (rows <= sl->cap && P <= sl->pcap) return FGL_OK;
-  const int cap = std::max(rows, sl->cap);
-  const int pcap = std::max(P, sl->pcap);
+// Staging for `nth` doubles of parameters and `rows` outputs.
+static int grow_slot(Slot* sl, size_t nth, int rows) {
+  if (nth <= sl->cap && rows <= sl->ocap) return FGL_OK;
+  const size_t cap = std::max(nth, sl->cap);
+  const int ocap = std::max(rows, sl->ocap);
   if (sl->d_theta) (void)hipFree(sl->d_theta);
   if (sl->d_out) (void)hipFree(sl->d_out);
   if (sl->h_theta) (void)hipHostFree(sl->h_theta);
   if (sl->h_out) (void)hipHostFree(sl->h_out);
   sl->d_theta = sl->d_out = sl->h_theta = sl->h_out = nullptr;
-  sl->cap = sl->pcap = 0;
+  sl->cap = 0;
+  sl->ocap = 0;
   hipError_t e;
-  const size_t tb = (size_t)cap * pcap * 8, ob = (size_t)cap * 8;
+  const size_t tb = cap * 8, ob = (size_t)ocap * 8;
   if ((e = hipMalloc(reinterpret_cast<void**>(&sl->d_theta), tb)) != hipSuccess ||
       (e = hipMalloc(reinterpret_cast<void**>(&sl->d_out), ob)) != hipSuccess ||
       (e = hipHostMalloc(reinterpret_cast<void**>(&sl->h_theta), tb, hipHostMallocDefault)) != hipSuccess ||
       (e = hipHostMalloc(reinterpret_cast<void**>(&sl->h_out), ob, hipHostMallocDefault)) != hipSuccess)
     return hip_err(e, "serving staging buffers");
   sl->cap = cap;
-  sl->pcap = pcap;
+  sl->ocap = ocap;
   return FGL_OK;
 }
 
@@ -177,7 +189,7 @@ static int launch_slot(Server* srv, Slot* sl) {
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
   int rc = make_resident(m);
   if (rc != FGL_OK) return rc;
-  if ((rc = grow_slot(sl, rows, m->P)) != FGL_OK) return rc;
+  if ((rc = grow_slot(sl, (size_t)rows * m->P, rows)) != FGL_OK) return rc;
   size_t off = 0;
   for (Req* r : sl->reqs) {
     std::memcpy(sl->h_theta + off, r->theta, (size_t)r->B * m->P * 8);
@@ -196,11 +208,114 @@ static int launch_slot(Server* srv, Slot* sl) {
                           sl->s)) != hipSuccess)
     return hip_err(e, "copy out");
   sl->rows = rows;
+  sl->ngroups = 1;
   sl->finished = false;
   if ((e = hipLaunchHostFunc(sl->s, on_done, sl)) != hipSuccess)
     return hip_err(e, "hipLaunchHostFunc");
   m->last_use = ++srv->clock;
+  ++srv->n_launches;
   return FGL_OK;
+}
+
+// One launch of each kernel for the groups in sl->reqs (consecutive runs of
+// requests of one model; all in precision `prec`, all with likelihood
+// variant `variant`).  Called with srv->mu held and the slot idle.
+static int launch_slot_shared(Server* srv, Slot* sl, int prec) {
+  // the groups, in order
+  struct G {
+    Model* m;
+    int rows;
+    size_t th_off, out_off;
+  };
+  std::vector<G> groups;
+  size_t nth = 0;
+  int rows = 0;
+  for (Req* r : sl->reqs) {
+    if (groups.empty() || groups.back().m != r->m) groups.push_back(G{r->m, 0, nth, (size_t)rows});
+    groups.back().rows += r->B;
+    nth += (size_t)r->B * r->m->P;
+    rows += r->B;
+  }
+  if ((int)groups.size() > kMaxGroups) return set_err(FGL_EINVAL, "too many groups in a launch");
+  // models locked in address order (only this thread locks several)
+  std::vector<Model*> order;
+  for (const G& g : groups) order.push_back(g.m);
+  std::sort(order.begin(), order.end());
+  std::vector<std::unique_lock<std::mutex>> locks;
+  for (Model* m : order) locks.emplace_back(m->mu);
+  hipError_t e = hipSetDevice(groups.front().m->dev);
+  if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+  int rc = grow_slot(sl, nth, rows);
+  if (rc != FGL_OK) return rc;
+  if (!sl->d_desc) {
+    if ((e = hipMalloc(reinterpret_cast<void**>(&sl->d_desc), kMaxGroups * sizeof(GroupDesc))) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&sl->h_desc), kMaxGroups * sizeof(GroupDesc),
+                           hipHostMallocDefault)) != hipSuccess)
+      return hip_err(e, "serving descriptor table");
+  }
+  size_t off = 0;
+  for (Req* r : sl->reqs) {
+    std::memcpy(sl->h_theta + off, r->theta, (size_t)r->B * r->m->P * 8);
+    off += (size_t)r->B * r->m->P;
+  }
+  Kind k0 = kMixed;
+  Tile t0{};
+  for (size_t j = 0; j < groups.size(); ++j) {
+    Model* m = groups[j].m;
+    if ((rc = make_resident(m)) != FGL_OK) return rc;
+    const Kind k = kind_of(prec, m->dm);
+    const Tile tile = tile_for(m, k, groups[j].rows);
+    WorkBuf& wb = m->work[sl->s];
+    wb.stream_synced_free = true;   // the slot's stream is idle here
+    if ((rc = ensure_work(m, wb, groups[j].rows, n_groups(m->dm, tile), false)) != FGL_OK) return rc;
+    if (j == 0) {
+      k0 = k;
+      t0 = tile;
+    }
+    GroupDesc& d = sl->h_desc[j];
+    d = GroupDesc{};
+    d.m = m->dm;
+    d.w = wb.w;
+    d.fc = tile.fc;
+    d.G = tile.group;
+    d.ngroups = n_groups(m->dm, tile);
+    d.theta = sl->d_theta + groups[j].th_off;
+    d.out = sl->d_out + groups[j].out_off;
+    d.nFT = (double)m->dm.F * (double)m->dm.T;
+    d.chi0 = chi0_of(k, m->dm);
+  }
+  int grid[3], lds = 0;
+  plan_groups(k0, t0, sl->h_desc, (int)groups.size(), grid, &lds);
+  if ((e = hipMemcpyAsync(sl->d_desc, sl->h_desc, groups.size() * sizeof(GroupDesc),
+                          hipMemcpyHostToDevice, sl->s)) != hipSuccess)
+    return hip_err(e, "copy descriptors");
+  if ((e = hipMemcpyAsync(sl->d_theta, sl->h_theta, nth * 8, hipMemcpyHostToDevice, sl->s)) != hipSuccess)
+    return hip_err(e, "copy theta");
+  if ((e = launch_groups(k0, groups.front().m->dm, t0, sl->d_desc, (int)groups.size(), grid, lds,
+                         sl->s)) != hipSuccess)
+    return hip_err(e, "shared launch");
+  if ((e = hipMemcpyAsync(sl->h_out, sl->d_out, (size_t)rows * 8, hipMemcpyDeviceToHost,
+                          sl->s)) != hipSuccess)
+    return hip_err(e, "copy out");
+  sl->rows = rows;
+  sl->ngroups = (int)groups.size();
+  sl->finished = false;
+  if ((e = hipLaunchHostFunc(sl->s, on_done, sl)) != hipSuccess)
+    return hip_err(e, "hipLaunchHostFunc");
+  for (const G& g : groups) g.m->last_use = ++srv->clock;
+  ++srv->n_launches;
+  ++srv->n_shared;
+  srv->n_shared_groups += groups.size();
+  return FGL_OK;
+}
+
+// The compiled likelihood variant a group of `rows` rows of model m in
+// precision prec would launch (0: not shareable).  Reads the model's tile
+// table, so it takes the model's lock.
+static uint64_t group_variant(Model* m, int prec, int rows) {
+  std::lock_guard<std::mutex> lk(m->mu);
+  const Kind k = kind_of(prec, m->dm);
+  return variant_of(k, m->dm, tile_for(m, k, rows));
 }
 
 static void complete_slot(Server* srv, Slot* sl) {
@@ -265,9 +380,46 @@ static void scheduler(Server* srv) {
             ++jt;
           }
         }
+        // sharing: the groups of other waiting models of the same variant
+        uint64_t var = 0;
+        if (srv->share > 1) var = group_variant(r->m, r->prec, rows);
+        int ngroups = 1;
+        if (var != 0) {
+          for (auto it2 = srv->pending.begin();
+               it2 != srv->pending.end() && ngroups < srv->share && rows < srv->share_rows;) {
+            Req* q = *it2;
+            bool taken = false;
+            if (q->m != r->m && q->prec == r->prec && q->ticket != srv->fail_ticket &&
+                std::none_of(free_slot->reqs.begin(), free_slot->reqs.end(),
+                             [&](Req* x) { return x->m == q->m; })) {
+              // q's group: every waiting request of its model and precision
+              std::vector<Req*> grp;
+              int grows = 0;
+              for (Req* x : srv->pending)
+                if (x->m == q->m && x->prec == q->prec && x->ticket != srv->fail_ticket &&
+                    (grp.empty() || grows + x->B <= srv->merge_rows)) {
+                  grp.push_back(x);
+                  grows += x->B;
+                }
+              // same variant first, then room in the budget
+              if (rows + grows <= srv->share_rows && group_variant(q->m, q->prec, grows) == var &&
+                  admit_model(srv, q->m)) {
+                for (Req* x : grp) {
+                  free_slot->reqs.push_back(x);
+                  srv->pending.erase(std::find(srv->pending.begin(), srv->pending.end(), x));
+                }
+                rows += grows;
+                ++ngroups;
+                taken = true;
+              }
+            }
+            it2 = taken ? srv->pending.begin() : std::next(it2);
+          }
+        }
         free_slot->busy = true;
         ++srv->inflight;
-        const int rc = launch_slot(srv, free_slot);
+        const int rc = var != 0 && ngroups > 1 ? launch_slot_shared(srv, free_slot, r->prec)
+                                               : launch_slot(srv, free_slot);
         if (rc != FGL_OK) {
           const std::string err = last_error();
           (void)hipStreamSynchronize(free_slot->s);
@@ -324,6 +476,8 @@ int fgl_serve_create(size_t hbm_budget_bytes, int max_inflight, fgl_server** out
   srv->max_inflight = max_inflight;
   if (const char* f = std::getenv("FGL_SERVE_FAIL_TICKET")) srv->fail_ticket = std::strtoull(f, nullptr, 10);
   if (const char* mr = std::getenv("FGL_SERVE_MERGE_ROWS")) srv->merge_rows = std::max(1, std::atoi(mr));
+  if (const char* sh = std::getenv("FGL_SERVE_SHARE"))
+    srv->share = std::min(kMaxGroups, std::max(1, std::atoi(sh)));
   for (int i = 0; i < max_inflight; ++i) {
     Slot* sl = new Slot();
     sl->srv = srv;
@@ -385,6 +539,28 @@ int fgl_serve_submit(fgl_server* sh, fgl_model* mh, const double* theta, int B,
   return FGL_OK;
 }
 
+int fgl_serve_set_sharing(fgl_server* sh, int max_models_per_launch) {
+  Server* srv = reinterpret_cast<Server*>(sh);
+  if (!srv) return set_err(FGL_EINVAL, "server is NULL");
+  if (max_models_per_launch < 1 || max_models_per_launch > kMaxGroups)
+    return set_err(FGL_EINVAL, "max_models_per_launch=%d outside 1..%d", max_models_per_launch,
+                   kMaxGroups);
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->share = max_models_per_launch;
+  return FGL_OK;
+}
+
+int fgl_serve_stats(fgl_server* sh, uint64_t* launches, uint64_t* shared_launches,
+                    uint64_t* shared_groups) {
+  Server* srv = reinterpret_cast<Server*>(sh);
+  if (!srv) return set_err(FGL_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (launches) *launches = srv->n_launches;
+  if (shared_launches) *shared_launches = srv->n_shared;
+  if (shared_groups) *shared_groups = srv->n_shared_groups;
+  return FGL_OK;
+}
+
 int fgl_serve_poll(fgl_server* sh, uint64_t ticket, int* done, double* latency_us) {
   Server* srv = reinterpret_cast<Server*>(sh);
   if (!srv || !done) return set_err(FGL_EINVAL, "server and done must be non-NULL");
@@ -436,6 +612,8 @@ int fgl_serve_destroy(fgl_server* sh) {
     if (sl->d_out) (void)hipFree(sl->d_out);
     if (sl->h_theta) (void)hipHostFree(sl->h_theta);
     if (sl->h_out) (void)hipHostFree(sl->h_out);
+    if (sl->d_desc) (void)hipFree(sl->d_desc);
+    if (sl->h_desc) (void)hipHostFree(sl->h_desc);
     (void)hipStreamDestroy(sl->s);
     delete sl;
   }

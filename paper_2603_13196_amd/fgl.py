@@ -87,6 +87,9 @@ _SIGS = {
     "fgl_serve_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _dp],
                        ctypes.c_int),
     "fgl_serve_drain": ([_vp], ctypes.c_int),
+    "fgl_serve_set_sharing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "fgl_serve_stats": ([_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                         ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "fgl_serve_destroy": ([_vp], ctypes.c_int),
     "fgl_chains_create": ([_vp, ctypes.c_int, _dp, _dp, ctypes.c_uint64, ctypes.POINTER(_vp)],
                           ctypes.c_int),
@@ -401,6 +404,17 @@ class Server:
 
     def drain(self):
         fgl_serve_drain(self.handle)
+
+    def set_sharing(self, max_models_per_launch: int):
+        """Up to this many models of one kernel variant per launch (1: off)."""
+        _check(_lib.fgl_serve_set_sharing(self.handle, int(max_models_per_launch)))
+
+    def stats(self):
+        """(launches, shared launches, model groups in shared launches)."""
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.fgl_serve_stats(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def close(self):
         if self.handle is not None:

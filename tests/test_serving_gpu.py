@@ -58,14 +58,34 @@ def _requests(clients, per_client, seed):
     return reqs
 
 
-def _run_mix(fgl, clients, models, reqs, budget, inflight):
+_BLOCKER = {}
+
+
+def _blocker(fgl):
+    """A large model and batch whose requests keep every slot busy for a few
+    milliseconds, so that the requests submitted behind them queue up."""
+    if "m" not in _BLOCKER:
+        w = workload.config(workload.LARGE, B=65536)
+        _BLOCKER["w"] = w
+        _BLOCKER["m"] = fgl.Model.from_workload(w)
+    return _BLOCKER["m"], _BLOCKER["w"]
+
+
+def _run_mix(fgl, clients, models, reqs, budget, inflight, share=1):
+    """Occupy every slot with a blocker request, submit every request behind
+    them, and return the outputs in request order and the server's launch
+    counters."""
     srv = fgl.Server(budget_bytes=budget, max_inflight=inflight)
-    tickets = [srv.submit(models[ci], clients[ci].work.theta[rows], prec)
-               for ci, rows, prec in reqs]
-    got = _wait(srv, tickets)
+    srv.set_sharing(share)
+    bm, bw = _blocker(fgl)
+    thetas = [np.ascontiguousarray(clients[ci].work.theta[rows]) for ci, rows, _ in reqs]
+    blockers = [srv.submit(bm, bw.theta) for _ in range(inflight)]
+    tickets = [srv.submit(models[ci], th, prec) for (ci, _, prec), th in zip(reqs, thetas)]
+    got = _wait(srv, tickets + blockers)
     srv.drain()
+    stats = srv.stats()
     srv.close()
-    return [got[t] for t in tickets]
+    return [got[t] for t in tickets], stats
 
 
 def test_mix_equals_alone(fgl):
@@ -77,12 +97,18 @@ def test_mix_equals_alone(fgl):
     models = [fgl.Model.from_workload(c.work) for c in clients]
     say("forms: " + " ".join(f"N{c.work.N}T{c.work.T}:{m.form}" for c, m in zip(clients, models)))
     reqs = _requests(clients, 3, seed=11)
-    served = _run_mix(fgl, clients, models, reqs, budget=0, inflight=2)
+    served, _ = _run_mix(fgl, clients, models, reqs, budget=0, inflight=2)
     orc = oracle.load()
     for (ci, rows, prec), out in zip(reqs, served):
         assert not isinstance(out, Exception), out
         alone = models[ci].loglike(clients[ci].work.theta[rows], prec)
         assert np.array_equal(out, alone), (ci, prec, rows.size)
+    # the same requests with launches shared by models of one kernel variant
+    shared, stats = _run_mix(fgl, clients, models, reqs, budget=0, inflight=2, share=16)
+    say(f"  sharing: launches {stats[0]}, shared {stats[1]} carrying {stats[2]} model groups")
+    assert stats[1] >= 1 and stats[2] >= 2 * stats[1]
+    for (ci, rows, prec), out, ref in zip(reqs, shared, served):
+        assert np.array_equal(out, ref), (ci, prec, rows.size)
     # sampled rows of the mixed requests against the oracle
     for (ci, rows, prec), out in zip(reqs[:12], served[:12]):
         if prec != "mixed":
@@ -95,16 +121,46 @@ def test_mix_equals_alone(fgl):
         m.close()
 
 
+@pytest.mark.parametrize("share,budgeted", [(1, True), (16, True), (16, False)])
+def test_full_mix_equals_alone(fgl, share, budgeted):
+    """All 64 clients of the serving mix (N 4..40, T 1..96, F 151/301, B up
+    to 8192), two requests each in mixed, FP64 and FP32, four slots, with
+    and without shared launches, and with an HBM budget of half the models'
+    bytes (waits and evictions) or none: every served result is bitwise the
+    same rows alone.  Without a budget, shared launches must occur (under
+    it, models with requests in flight cannot be evicted, so a candidate
+    model rarely fits beside the first)."""
+    clients = workload.serving_clients(64, n_requests=2)
+    models = [fgl.Model.from_workload(c.work) for c in clients]
+    total = sum(m.nbytes for m in models)
+    # half the models' bytes, plus room for the blocker requests' model
+    budget = (max(total // 2, max(m.nbytes for m in models)) + _blocker(fgl)[0].nbytes
+              if budgeted else 0)
+    reqs = _requests(clients, 2, seed=13)
+    served, stats = _run_mix(fgl, clients, models, reqs, budget=budget, inflight=4,
+                             share=share)
+    say(f"  64-client mix, share {share}: {len(reqs)} requests, budget {budget} of {total} "
+        f"bytes, launches {stats[0]}, shared {stats[1]} ({stats[2]} groups)")
+    for (ci, rows, prec), out in zip(reqs, served):
+        assert not isinstance(out, Exception), out
+        alone = models[ci].loglike(clients[ci].work.theta[rows], prec)
+        assert np.array_equal(out, alone), (ci, prec, rows.size)
+    if share > 1 and not budgeted:
+        assert stats[1] >= 1
+    for m in models:
+        m.close()
+
+
 def test_budget_admission_and_eviction(fgl):
     """An HBM budget of about two models for six: requests wait for room,
     idle models are evicted and re-uploaded, results are unchanged."""
     clients = workload.serving_clients(6, n_requests=2, seed=99, min_B=64, max_B=2048)
     models = [fgl.Model.from_workload(c.work) for c in clients]
     sizes = sorted(m.nbytes for m in models)
-    budget = sizes[-1] + sizes[-2]
+    budget = sizes[-1] + sizes[-2] + _blocker(fgl)[0].nbytes
     say(f"model bytes {sizes}, budget {budget}")
     reqs = _requests(clients, 2, seed=12)
-    served = _run_mix(fgl, clients, models, reqs, budget=budget, inflight=3)
+    served, _ = _run_mix(fgl, clients, models, reqs, budget=budget, inflight=3)
     for (ci, rows, prec), out in zip(reqs, served):
         assert not isinstance(out, Exception), out
         alone = models[ci].loglike(clients[ci].work.theta[rows], prec)
