@@ -385,6 +385,22 @@ int fgl_chains_run(fgl_chains* c, const double* x0, const double* l0, int n,
                    int64_t* rounds);
 int fgl_chains_destroy(fgl_chains* c);
 
+/*
+ * The chains' random numbers, for reproducing or checking their draws:
+ * out[4j..4j+3] = Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011:
+ * ten rounds, multipliers 0xD2511F53 and 0xCD9E8D57, Weyl key increments
+ * 0x9E3779B9 and 0xBB67AE85) of the counter block ctr[4j..4j+3] under the
+ * key (k0, k1), computed by the device function the chains use.  A chain
+ * engine created with seed s draws with k0 = s mod 2^32, k1 = s / 2^32, and
+ * its chain i's draw number c is the block (c mod 2^32, c / 2^32, i,
+ * 0x5eed5eed); a uniform is the top 53 bits of the 64-bit word (w0 2^32 +
+ * w1), or of (w2 2^32 + w3), times 2^-53.  ctr and out are host uint32
+ * arrays [4n], n in 1..2^24.  Synchronous.  Returns FGL_OK, FGL_EINVAL,
+ * FGL_ENOMEM or FGL_EDEVICE.
+ */
+int fgl_chains_philox(const uint32_t* ctr, int n, uint32_t k0, uint32_t k1,
+                      uint32_t* out);
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* fgl_last_error(void);
 

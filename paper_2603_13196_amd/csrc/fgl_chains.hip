@@ -475,6 +475,19 @@ static hipError_t dalloc(T** p, size_t n) {
   return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(n * sizeof(T), 16));
 }
 
+// The chains' generator on its own: one thread per counter block.
+__global__ void k_philox(const uint32_t* __restrict__ ctr, int n, uint32_t k0, uint32_t k1,
+                         uint32_t* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  uint32_t c[4] = {ctr[4 * j], ctr[4 * j + 1], ctr[4 * j + 2], ctr[4 * j + 3]};
+  philox(c, k0, k1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[4 * j + q] = c[q];
+}
+
+constexpr int kPhiloxMaxBlocks = 1 << 24;
+
 }  // namespace fgl
 
 using namespace fgl;
@@ -690,6 +703,33 @@ int fgl_chains_run(fgl_chains* ch, const double* x0, const double* l0, int n, do
   if (rounds) *rounds = done_rounds;
   c->calls++;
   return FGL_OK;
+}
+
+int fgl_chains_philox(const uint32_t* ctr, int n, uint32_t k0, uint32_t k1, uint32_t* out) {
+  if (!ctr || !out) return set_err(FGL_EINVAL, "ctr and out must be non-NULL");
+  if (n < 1 || n > kPhiloxMaxBlocks)
+    return set_err(FGL_EINVAL, "n=%d outside 1..%d", n, kPhiloxMaxBlocks);
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != FGL_OK) return rc;
+  const size_t bytes = (size_t)n * 16;
+  uint32_t *d_in = nullptr, *d_out = nullptr;
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_in), bytes);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_out), bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_in, ctr, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_philox, dim3((n + 255) / 256), dim3(256), 0, s, d_in, n, k0, k1, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (s) (void)hipStreamSynchronize(s);
+  if (d_in) (void)hipFree(d_in);
+  if (d_out) (void)hipFree(d_out);
+  if (s) (void)hipStreamDestroy(s);
+  return e == hipSuccess ? FGL_OK : hip_err(e, "Philox kernel");
 }
 
 int fgl_chains_destroy(fgl_chains* ch) {

@@ -97,6 +97,8 @@ _SIGS = {
                         ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_int64),
                         ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "fgl_chains_destroy": ([_vp], ctypes.c_int),
+    "fgl_chains_philox": ([ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, ctypes.c_uint32,
+                           ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "fgl_sky_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _fp,
                         ctypes.POINTER(ctypes.c_uint8), _dp, ctypes.c_double, ctypes.c_double,
                         ctypes.POINTER(_vp)], ctypes.c_int),
@@ -561,6 +563,17 @@ def fgl_noise_loglike(n: int, R: int, sigma_noise: float, sigma_like: float,
                                   int(seed) & 0xFFFFFFFFFFFFFFFF, out.ctypes.data_as(_dp),
                                   ctypes.byref(ms) if timed else None))
     return (out, ms.value) if timed else out
+
+
+def fgl_chains_philox(ctr, k0: int, k1: int) -> np.ndarray:
+    """Philox4x32-10 blocks [n, 4] of counter blocks ctr [n, 4] (uint32)
+    under the key (k0, k1), by the device generator of the chains."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(c)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    _check(_lib.fgl_chains_philox(c.ctypes.data_as(u32p), c.shape[0], int(k0) & 0xFFFFFFFF,
+                                  int(k1) & 0xFFFFFFFF, out.ctypes.data_as(u32p)))
+    return out
 
 
 def fgl_noise_quantile(lnl_noise, lbar) -> np.ndarray:

@@ -26,6 +26,72 @@ def _gauss(mu, cov):
     return f
 
 
+def flat_model_evidence(S: float, n: int, a: float, b: float) -> float:
+    """ln Z of the foreground model with zero responses and no 21-cm term:
+    the model is T_CMB, so with s = ln sigma uniform on [a, b] and the
+    spectral indices integrating to one,
+      lnL(s) = -S e^(-2s) / 2 - n s - (n/2) ln(2 pi),  S = sum (D - T_CMB)^2,
+      Z = (1 / (b - a)) int_a^b exp(lnL(s)) ds.
+    With u = S e^(-2s) / 2 the integral is a gamma integral:
+      int_a^b e^(-S e^(-2s)/2 - n s) ds
+        = (1/2) (2/S)^(n/2) Gamma(n/2) [P(n/2, u(a)) - P(n/2, u(b))],
+    P the regularised lower incomplete gamma function."""
+    from scipy import special
+    h = 0.5 * n
+    ua, ub = 0.5 * S * math.exp(-2.0 * a), 0.5 * S * math.exp(-2.0 * b)
+    mass = special.gammainc(h, ua) - special.gammainc(h, ub)
+    return (math.log(0.5) + h * math.log(2.0 / S) + special.gammaln(h) + math.log(mass)
+            - h * math.log(2.0 * math.pi) - math.log(b - a))
+
+
+def flat_model_data(N=3, F=11, T=4, seed=31, t_cmb=2.725):
+    """(K = 0 [N, F, T], freqs, data = T_CMB + 25 mK noise, t_cmb)."""
+    freqs = np.linspace(60.0, 190.0, F)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    data = t_cmb + rng.normal(0.0, 0.025, size=(F, T))
+    return np.zeros((N, F, T), dtype=np.float32), freqs, data, t_cmb
+
+
+def test_flat_model_evidence_closed_form():
+    """The gamma-integral form against direct quadrature of the integral."""
+    from scipy import integrate
+    _, _, data, t_cmb = flat_model_data()
+    S, n = float(np.sum((data - t_cmb) ** 2)), data.size
+    a, b = math.log(1e-3), math.log(0.1)
+
+    def lnl(s):
+        return -0.5 * S * math.exp(-2.0 * s) - n * s - 0.5 * n * math.log(2.0 * math.pi)
+
+    sp = 0.5 * math.log(S / n)
+    val, _ = integrate.quad(lambda s: math.exp(lnl(s) - lnl(sp)), a, b, points=[sp],
+                            epsabs=0.0, epsrel=1e-12, limit=200)
+    quad = lnl(sp) + math.log(val) - math.log(b - a)
+    assert abs(flat_model_evidence(S, n, a, b) - quad) < 1e-9
+
+
+def test_sampler_on_oracle_reaches_flat_model_evidence():
+    """The host sampler driven by the FP64 oracle's likelihood on the model
+    with zero responses (where the oracle reduces to the constant model
+    T_CMB) reaches the closed-form evidence."""
+    import oracle
+    orc = oracle.load()
+    K, freqs, data, t_cmb = flat_model_data()
+    lo, hi = ns.foreground_box(K.shape[0], no21=True)
+    S = float(np.sum((data - t_cmb) ** 2))
+    # the oracle's lnL is the closed form's lnL(s) on any row
+    rng = np.random.Generator(np.random.PCG64(4))
+    z = lo + (hi - lo) * rng.random((50, lo.size))
+    want = (-0.5 * S * np.exp(-2.0 * z[:, -1]) - data.size * z[:, -1]
+            - 0.5 * data.size * math.log(2.0 * math.pi))
+    got = orc.loglike(K, freqs, data, 100.0, t_cmb, ns.to_theta(z), flags=1)
+    assert np.allclose(got, want, rtol=1e-12, atol=0.0)
+    r = ns.nested_slice_sampling(
+        lambda q: orc.loglike(K, freqs, data, 100.0, t_cmb, ns.to_theta(q), flags=1),
+        lo, hi, n_live=200, num_delete=40, num_inner_steps=2 * lo.size, seed=5)
+    exact = flat_model_evidence(S, data.size, lo[-1], hi[-1])
+    assert abs(r.logz - exact) < 3 * r.logz_err, (r.logz, exact, r.logz_err)
+
+
 def test_logx_decrement_is_eq_log_xgpu():
     for n, b in ((100, 1), (400, 80), (1000, 200)):
         s = ns.expected_logx_decrement(n, b)

@@ -14,6 +14,7 @@ import oracle
 import workload
 from paper_2603_13196_amd import sampler as ns
 from tests.gpu_util import lib, say
+from tests.test_sampler import flat_model_data, flat_model_evidence
 
 pytestmark = pytest.mark.gpu
 
@@ -183,4 +184,118 @@ def test_device_chains_draw_fresh_numbers_every_call():
     b = eng.run(x0, l0, -np.inf, np.diag((hi - lo) / 4), 3)[0]
     assert not np.any(np.all(a == b, axis=1))
     eng.close()
+    model.close()
+
+
+# Known-answer vectors of Philox4x32-10 published with the Random123 library
+# of Salmon, Moraes, Dror and Shaw (SC 2011): (counter, key, result).
+PHILOX4X32_10_KAT = [
+    ((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+     (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff), (0xffffffff, 0xffffffff),
+     (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+]
+
+
+def test_chains_philox_known_answers():
+    """The chains' generator reproduces the published Philox4x32-10 vectors,
+    each key in a call of its own and all three blocks of one key in one
+    launch of many blocks."""
+    fgl = lib()
+    for ctr, key, want in PHILOX4X32_10_KAT:
+        got = fgl.fgl_chains_philox(np.array([ctr], dtype=np.uint32), *key)
+        say(f"philox {key}: {[hex(v) for v in got[0]]}")
+        assert [int(v) for v in got[0]] == list(want)
+    # a launch of several workgroups with a ragged tail: the zero-key vector
+    # in every slot, so each thread's result is known
+    n = 1000
+    got = fgl.fgl_chains_philox(np.zeros((n, 4), dtype=np.uint32), 0, 0)
+    assert np.array_equal(got, np.tile(np.array(PHILOX4X32_10_KAT[0][2], dtype=np.uint32),
+                                       (n, 1)))
+
+
+def _fit_data(orc, w):
+    rng = np.random.Generator(np.random.PCG64(99))
+    m_true = orc.model(w.K, w.freqs, w.nu_ref, w.t_cmb, w.truth)
+    return m_true + rng.normal(0.0, 0.025, size=m_true.shape)
+
+
+def test_device_chains_match_a_sampler_on_the_oracle_likelihood():
+    """Sec. 3.1.2-3.1.3: nested slice sampling with the chains on the device
+    (the library's likelihood, mixed and FP64) against the host chains driven
+    by the FP64 C oracle's likelihood, which shares no code with the library.
+
+    One run's ln Z scatters between seeds by 1.3-1.5 times the sqrt(H / n_live)
+    estimate here (the replacement chains of 2d slice steps are not fully
+    independent), so single runs are not compared: over eight seeds per side,
+    the mean ln Z must agree within three standard errors of the difference
+    of means (each side's spread taken as the larger of its sample deviation
+    and its mean error estimate), and the seed-averaged posterior means within
+    a quarter of a posterior standard deviation."""
+    fgl = lib()
+    freqs = np.linspace(50.0, 200.0, 31)
+    w = workload.make(4, freqs, 6, 8, 4711, batch="prior")
+    orc = oracle.load()
+    data = _fit_data(orc, w)
+    model = fgl.Model(w.K, w.freqs, data, w.nu_ref, w.t_cmb)
+    lo, hi = ns.foreground_box(w.N)
+    d = lo.size
+    n_seeds = 8
+
+    def oracle_like(z):
+        return orc.loglike(w.K, w.freqs, data, w.nu_ref, w.t_cmb, ns.to_theta(z))
+
+    kw = dict(n_live=200, num_delete=40, num_inner_steps=2 * d)
+
+    def summary(runs):
+        z = np.array([r.logz for r in runs])
+        spread = max(z.std(ddof=1), float(np.mean([r.logz_err for r in runs])))
+        mean = np.mean([r.posterior_mean() for r in runs], axis=0)
+        return z.mean(), spread, mean
+
+    ref_runs = [ns.nested_slice_sampling(oracle_like, lo, hi, seed=300 + k, **kw)
+                for k in range(n_seeds)]
+    z_ref, s_ref, m_ref = summary(ref_runs)
+    sd = np.sqrt(np.diag(ref_runs[0].posterior_cov()))
+    say(f"oracle, host chains: mean logZ={z_ref:.3f} spread {s_ref:.3f} "
+        f"({[round(r.logz, 2) for r in ref_runs]})")
+    for prec in ("mixed", "fp64"):
+        runs = []
+        for k in range(n_seeds):
+            ch = ns.gpu_chains(model, lo, hi, 40, prec, seed=100 + k)
+            runs.append(ns.nested_slice_sampling(ns.model_loglike(model, prec), lo, hi,
+                                                 chains=ch, seed=200 + k, **kw))
+            ch.engine.close()
+        z, s_dev, m = summary(runs)
+        se = math.sqrt((s_dev ** 2 + s_ref ** 2) / n_seeds)
+        shift = (m - m_ref) / sd
+        say(f"{prec}, device chains: mean logZ={z:.3f} spread {s_dev:.3f} (diff {z - z_ref:+.3f}, "
+            f"{abs(z - z_ref) / se:.2f} standard errors); mean shifts {np.round(shift, 3)}")
+        assert abs(z - z_ref) < 3 * se, (prec, z, z_ref, se)
+        assert np.all(np.abs(shift) < 0.25), (prec, shift)
+    model.close()
+
+
+def test_device_chains_reach_a_known_evidence():
+    """A model whose evidence has a closed form (a gamma integral): zero
+    responses, no 21-cm term, data T_CMB plus 25 mK noise.  Nested sampling with the
+    device chains must give ln Z within three of its own standard errors of
+    the quadrature value, for both precisions."""
+    fgl = lib()
+    K, freqs, data, t_cmb = flat_model_data()
+    model = fgl.Model(K, freqs, data, 100.0, t_cmb, flags=fgl.FGL_NO_21CM)
+    lo, hi = ns.foreground_box(K.shape[0], no21=True)
+    S = float(np.sum((data - t_cmb) ** 2))
+    want = flat_model_evidence(S, data.size, lo[-1], hi[-1])
+    for prec in ("mixed", "fp64"):
+        ch = ns.gpu_chains(model, lo, hi, 40, prec, seed=17)
+        r = ns.nested_slice_sampling(ns.model_loglike(model, prec), lo, hi, n_live=200,
+                                     num_delete=40, num_inner_steps=2 * lo.size, seed=5,
+                                     chains=ch)
+        ch.engine.close()
+        say(f"known evidence {prec}: logZ={r.logz:.4f}+-{r.logz_err:.4f} exact={want:.4f} "
+            f"({abs(r.logz - want) / r.logz_err:.2f} errors)")
+        assert abs(r.logz - want) < 3 * r.logz_err, (prec, r.logz, want, r.logz_err)
     model.close()
