@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfgl.so")
-SOURCES = ["fgl_kernels.hip", "fgl_host.cpp", "fgl_serve.cpp", "fgl_chains.hip",
-           "fgl_sky.hip", "fgl_noise.hip", "fgl_noalloc.hip"]
+SOURCES = ["fgl_kernels.hip", "fgl_plan.cpp", "fgl_host.cpp", "fgl_serve.cpp",
+           "fgl_chains.hip", "fgl_sky.hip", "fgl_noise.hip", "fgl_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no v_pk_{add,mul,fma}_f32 in device code.

@@ -29,6 +29,10 @@ constexpr int kProjMaxN = 96;
 constexpr int kProjDigits = 6;
 constexpr int kProjBits = 46;
 
+// Rows per workgroup of the row-preparation kernel (256 threads, sixteen per
+// row).
+constexpr int kPrepRows = 16;
+
 // Per-row parameters written by the prep kernel (one 80-byte record per row).
 struct RowParams {
   double bmin, bmax;   // extreme spectral indices of the row
@@ -216,6 +220,8 @@ struct GradShape {
 GradShape grad_shape(const DevModel& m, int Bpad);
 
 // Launchers (fgl_kernels.hip).  All enqueue on `s`; none synchronises.
+// The launch planning below them (tile LDS, reduction groups, shared-launch
+// plans, gradient shape) is host logic in fgl_plan.cpp.
 hipError_t launch_prep(const DevModel& m, const double* theta, int B,
                        const Work& w, int betaRows, hipStream_t s);
 hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
