@@ -348,8 +348,20 @@ int fgl_serve_stats(fgl_server* s, uint64_t* launches, uint64_t* shared_launches
 int fgl_serve_poll(fgl_server* s, uint64_t ticket, int* done,
                    double* latency_us);
 
-/* Block until every submitted request is done (completions stay pollable). */
+/* Block until every submitted request is done (completions stay pollable).
+ * FGL_EAGAIN, without waiting for the queue, while the server is held with
+ * requests queued (launches in flight are still waited for). */
 int fgl_serve_drain(fgl_server* s);
+
+/*
+ * Hold (hold != 0) or release (0) admission.  While held, submitted requests
+ * only queue; launches already in flight complete.  On release the scheduler
+ * plans the whole queue at once, so that a batch submitted together (the
+ * requests of many samplers at one iteration) is merged per model and, with
+ * sharing on, joined across models of one kernel variant as far as the
+ * slots allow.  Returns FGL_OK or FGL_EINVAL.
+ */
+int fgl_serve_hold(fgl_server* s, int hold);
 
 /* Destroy the server: FGL_EBUSY while requests are pending or in flight. */
 int fgl_serve_destroy(fgl_server* s);

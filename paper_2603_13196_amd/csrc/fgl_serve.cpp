@@ -89,6 +89,7 @@ struct Server {
   size_t used = 0;
   uint64_t fail_ticket = 0;         // host-forced failure (tests)
   int inflight = 0;
+  bool held = false;                // fgl_serve_hold: queue, admit nothing
 };
 
 static std::mutex g_servers_mu;
@@ -347,7 +348,7 @@ static void scheduler(Server* srv) {
     if (srv->stop && srv->inflight == 0) break;
     // admissions, in arrival order, while slots are free
     bool progressed = true;
-    while (progressed && !srv->pending.empty() && !srv->stop) {
+    while (progressed && !srv->pending.empty() && !srv->stop && !srv->held) {
       progressed = false;
       Slot* free_slot = nullptr;
       for (Slot* sl : srv->slots)
@@ -586,7 +587,23 @@ int fgl_serve_drain(fgl_server* sh) {
   Server* srv = reinterpret_cast<Server*>(sh);
   if (!srv) return set_err(FGL_EINVAL, "server is NULL");
   std::unique_lock<std::mutex> lk(srv->mu);
-  srv->cv_done.wait(lk, [&] { return srv->pending.empty() && srv->inflight == 0; });
+  srv->cv_done.wait(lk, [&] {
+    return srv->inflight == 0 && (srv->pending.empty() || srv->held);
+  });
+  if (!srv->pending.empty())
+    return set_err(FGL_EAGAIN, "the server is held with %zu requests queued", srv->pending.size());
+  return FGL_OK;
+}
+
+int fgl_serve_hold(fgl_server* sh, int hold) {
+  Server* srv = reinterpret_cast<Server*>(sh);
+  if (!srv) return set_err(FGL_EINVAL, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->held = hold != 0;
+    srv->cv_done.notify_all();     // a drain waiting on queued work returns
+  }
+  if (!hold) wake(srv);
   return FGL_OK;
 }
 

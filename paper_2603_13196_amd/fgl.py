@@ -87,6 +87,7 @@ _SIGS = {
     "fgl_serve_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), _dp],
                        ctypes.c_int),
     "fgl_serve_drain": ([_vp], ctypes.c_int),
+    "fgl_serve_hold": ([_vp, ctypes.c_int], ctypes.c_int),
     "fgl_serve_set_sharing": ([_vp, ctypes.c_int], ctypes.c_int),
     "fgl_serve_stats": ([_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                          ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -406,6 +407,11 @@ class Server:
 
     def drain(self):
         fgl_serve_drain(self.handle)
+
+    def hold(self, on: bool = True):
+        """Hold admission (requests only queue) or release it (the queue is
+        then planned at once: merged per model, shared across models)."""
+        _check(_lib.fgl_serve_hold(self.handle, 1 if on else 0))
 
     def set_sharing(self, max_models_per_launch: int):
         """Up to this many models of one kernel variant per launch (1: off)."""

@@ -15,8 +15,8 @@
 //   6. eight threads calling two models each, synchronous and device calls;
 //   7. serving: 16 clients with up to four requests each in flight, with and
 //      without launches shared across models, with and without an HBM
-//      budget that forces eviction; a forced request failure; destroying a
-//      busy model and a busy server;
+//      budget that forces eviction; a held queue released at once; a forced
+//      request failure; destroying a busy model and a busy server;
 //   8. after destroying everything, no device or pinned allocation is live.
 // Exit status 0 when every check passed and the stand-ins reported nothing.
 #include <unistd.h>
@@ -374,6 +374,43 @@ int main() {
   serve_round(sv, all / 2, 2, 1, 12, 30);
   serve_round(sv, all / 2, 3, 8, 12, 30);
   serve_round(sv, all / 3, 4, 8, 16, 30);
+
+  step("serving: a held queue released at once");
+  {
+    fgl_server* srv = nullptr;
+    CHECK(fgl_serve_create(0, 2, &srv) == FGL_OK, "create");
+    CHECK(fgl_serve_set_sharing(srv, 16) == FGL_OK, "sharing");
+    CHECK(fgl_serve_hold(srv, 1) == FGL_OK, "hold");
+    const int n = 48;
+    std::vector<std::vector<double>> th(n), out(n);
+    std::vector<uint64_t> tk(n);
+    for (int i = 0; i < n; ++i) {
+      const TM& m = sv[i % 5];                     // models without amplitude masks
+      const int B = 50 + 37 * i;
+      th[i] = rows(B, m.P, 700 + i, false);
+      out[i].assign(B, 0.0);
+      CHECK(fgl_serve_submit(srv, m.h, th[i].data(), B, out[i].data(), FGL_PREC_MIXED, &tk[i]) ==
+                FGL_OK, "submit held");
+    }
+    CHECK(fgl_serve_drain(srv) == FGL_EAGAIN, "drain of a held queue");
+    CHECK(fgl_serve_destroy(srv) == FGL_EBUSY, "destroy of a held queue");
+    CHECK(fgl_serve_hold(srv, 0) == FGL_OK, "release");
+    CHECK(fgl_serve_drain(srv) == FGL_OK, "drain");
+    for (int i = 0; i < n; ++i) {
+      int done = 0;
+      double us2 = 0.0;
+      CHECK(fgl_serve_poll(srv, tk[i], &done, &us2) == FGL_OK && done == 1, "held ticket %d", i);
+      CHECK(mismatches(sv[i % 5], th[i], out[i].data(), (int)out[i].size()) == 0,
+            "held ticket %d values", i);
+    }
+    uint64_t launches = 0, shared = 0, groups = 0;
+    CHECK(fgl_serve_stats(srv, &launches, &shared, &groups) == FGL_OK, "stats");
+    std::printf("   launches %llu, shared %llu carrying %llu groups\n",
+                (unsigned long long)launches, (unsigned long long)shared,
+                (unsigned long long)groups);
+    CHECK(shared >= 1 && launches < (uint64_t)n, "a released queue is merged and shared");
+    CHECK(fgl_serve_destroy(srv) == FGL_OK, "destroy");
+  }
 
   step("serving: forced failure, busy model and server");
   {

@@ -58,30 +58,19 @@ def _requests(clients, per_client, seed):
     return reqs
 
 
-_BLOCKER = {}
-
-
-def _blocker(fgl):
-    """A large model and batch whose requests keep every slot busy for a few
-    milliseconds, so that the requests submitted behind them queue up."""
-    if "m" not in _BLOCKER:
-        w = workload.config(workload.LARGE, B=65536)
-        _BLOCKER["w"] = w
-        _BLOCKER["m"] = fgl.Model.from_workload(w)
-    return _BLOCKER["m"], _BLOCKER["w"]
-
-
 def _run_mix(fgl, clients, models, reqs, budget, inflight, share=1):
-    """Occupy every slot with a blocker request, submit every request behind
-    them, and return the outputs in request order and the server's launch
-    counters."""
+    """Submit every request to a held server, release it (the whole queue is
+    then planned at once), and return the outputs in request order and the
+    server's launch counters."""
     srv = fgl.Server(budget_bytes=budget, max_inflight=inflight)
     srv.set_sharing(share)
-    bm, bw = _blocker(fgl)
     thetas = [np.ascontiguousarray(clients[ci].work.theta[rows]) for ci, rows, _ in reqs]
-    blockers = [srv.submit(bm, bw.theta) for _ in range(inflight)]
+    srv.hold(True)
     tickets = [srv.submit(models[ci], th, prec) for (ci, _, prec), th in zip(reqs, thetas)]
-    got = _wait(srv, tickets + blockers)
+    with pytest.raises(RuntimeError):
+        srv.drain()                  # held with requests queued: FGL_EAGAIN
+    srv.hold(False)
+    got = _wait(srv, tickets)
     srv.drain()
     stats = srv.stats()
     srv.close()
@@ -127,15 +116,15 @@ def test_full_mix_equals_alone(fgl, share, budgeted):
     to 8192), two requests each in mixed, FP64 and FP32, four slots, with
     and without shared launches, and with an HBM budget of half the models'
     bytes (waits and evictions) or none: every served result is bitwise the
-    same rows alone.  Without a budget, shared launches must occur (under
-    it, models with requests in flight cannot be evicted, so a candidate
-    model rarely fits beside the first)."""
+    same rows alone.  The requests are submitted to a held server and
+    released together; without a budget, shared launches must then occur
+    (under it, models with requests in flight cannot be evicted, so a
+    candidate model rarely fits beside the first)."""
     clients = workload.serving_clients(64, n_requests=2)
     models = [fgl.Model.from_workload(c.work) for c in clients]
     total = sum(m.nbytes for m in models)
-    # half the models' bytes, plus room for the blocker requests' model
-    budget = (max(total // 2, max(m.nbytes for m in models)) + _blocker(fgl)[0].nbytes
-              if budgeted else 0)
+    # half the models' bytes (at least the largest model)
+    budget = max(total // 2, max(m.nbytes for m in models)) if budgeted else 0
     reqs = _requests(clients, 2, seed=13)
     served, stats = _run_mix(fgl, clients, models, reqs, budget=budget, inflight=4,
                              share=share)
@@ -157,7 +146,7 @@ def test_budget_admission_and_eviction(fgl):
     clients = workload.serving_clients(6, n_requests=2, seed=99, min_B=64, max_B=2048)
     models = [fgl.Model.from_workload(c.work) for c in clients]
     sizes = sorted(m.nbytes for m in models)
-    budget = sizes[-1] + sizes[-2] + _blocker(fgl)[0].nbytes
+    budget = sizes[-1] + sizes[-2]
     say(f"model bytes {sizes}, budget {budget}")
     reqs = _requests(clients, 2, seed=12)
     served, _ = _run_mix(fgl, clients, models, reqs, budget=budget, inflight=3)
@@ -196,26 +185,26 @@ def test_forced_failure_is_reported(fgl, monkeypatch):
 
 def test_destroy_while_busy(fgl):
     """fgl_model_destroy and fgl_serve_destroy return FGL_EBUSY, freeing
-    nothing, while requests on them are queued or running; after a drain
-    both succeed and completions stay pollable until then."""
-    wl = workload.config(workload.LARGE, B=65536)
-    blocker = fgl.Model.from_workload(wl)
+    nothing, while requests on them are queued (the server is held, so they
+    stay queued) or running; after release and a drain both succeed and the
+    completions stay pollable until then."""
     ws = workload.config(workload.SMALL, B=256)
     small = fgl.Model.from_workload(ws)
     srv = fgl.Server(max_inflight=1)
-    # one slot: the small model's request waits behind the large launches
-    tb = [srv.submit(blocker, wl.theta) for _ in range(4)]
-    ts = srv.submit(small, ws.theta)
+    srv.hold(True)
+    ts = [srv.submit(small, ws.theta) for _ in range(3)]
     rc = fgl._lib.fgl_model_destroy(small.handle)
     assert rc == fgl.FGL_EBUSY, rc
     rc = fgl._lib.fgl_serve_destroy(srv.handle)
     assert rc == fgl.FGL_EBUSY, rc
+    assert fgl._lib.fgl_serve_drain(srv.handle) == fgl.FGL_EAGAIN
+    srv.hold(False)
     srv.drain()
-    got = _wait(srv, tb + [ts])
-    assert np.array_equal(got[ts], small.loglike(ws.theta))
+    got = _wait(srv, ts)
+    for t in ts:
+        assert np.array_equal(got[t], small.loglike(ws.theta))
     srv.close()
     small.close()
-    blocker.close()
 
 
 def test_serving_argument_errors(fgl):
