@@ -379,7 +379,7 @@ def regions_leg(fgl, n_regions=32):
             "chromatic_kernel_ms": kms,
             "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                         "kernel": "k_sky_corr"}}
+                         "kernel": "k_sky_k"}}
 
 
 def noise_leg(fgl, n=301 * 96, R=4096, reps=20, sigma=0.025):

@@ -12,19 +12,20 @@
 //   Z(nu, t)  = sum_q omega a(q, nu) b(nu, p_t(q))        (normalisers)
 //   I(q)      = sum_{nu, t} omega a(q, nu) b(nu, p_t(q)) / Z(nu, t)
 //   K_j(nu, t) = sum_{q in region j} omega t_ex(q) D(nu, p_t(q))
-// with a = T_sky (Eq. skyapproximation) or 1 and b = D H, H or D by scheme.
-// k_sky_corr computes Z and K: one workgroup per (channel, ring chunk), one
-// thread per time step; a ring's b row, its pixels (sorted by region) and
-// their weights are staged in LDS, each thread sums its shifted products
-// region by region in a register and adds each region's sum to its own LDS
-// accumulator, so every sum has a fixed order.  k_sky_importance computes
-// I: one thread per pixel, looping over channels with the ring's b row and
-// 1/Z(nu, .) in LDS.  The partition (Algs. method1 and method2) is a short
-// sequential computation on the host.
+// with a = T_sky (Eq. skyapproximation) or 1 and b = D H or H by scheme.
+// k_sky_corr computes Z: one workgroup per (channel, ring chunk), one thread
+// per time step, the ring's b row and weights staged in LDS.  k_sky_k
+// computes K: four channels per workgroup and a balanced run of rings of
+// one group of regions (details at the kernel).  Every sum has a fixed
+// order.  k_sky_importance computes I: one thread per pixel, looping over
+// channels with the ring's b row and 1/Z(nu, .) in LDS.  The partition
+// (Algs. method1 and method2) is a short sequential computation on the
+// host.
 #include "fgl_host.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -44,15 +45,16 @@ struct SkyDev {
   const float* beam;     // [F][nlat][nlon]
   const uint8_t* hor;    // [nlat][nlon]
   const double* lr;      // [F] log2(nu / nu0)
+  const float4* beam4;   // [ceil(F / 4)][nlat][nlon]: channels 4 b .. 4 b + 3 of a
+                         // pixel side by side (zero past the last channel)
 };
 
-enum Corr { kCorrK = 0, kCorrBeam = 1, kCorrSky = 2, kCorrHorizon = 3 };
+enum Corr { kCorrBeam = 1, kCorrSky = 2, kCorrHorizon = 3 };
 
-// b(nu, ring, ha) for a mode
+// b(nu, ring, ha) for a weighting
 template <int MODE>
 __device__ inline double bval(const SkyDev& s, int f, int ring, int ha) {
   const size_t px = (size_t)ring * s.nlon + ha;
-  if constexpr (MODE == kCorrK) return (double)s.beam[(size_t)f * s.nlat * s.nlon + px];
   if constexpr (MODE == kCorrBeam)
     return s.hor[px] ? (double)s.beam[(size_t)f * s.nlat * s.nlon + px] : 0.0;
   return s.hor[px] ? 1.0 : 0.0;
@@ -62,41 +64,30 @@ __device__ inline double bval(const SkyDev& s, int f, int ring, int ha) {
 template <int MODE>
 __device__ inline double aval(const SkyDev& s, int f, int ring, int ra) {
   const size_t px = (size_t)ring * s.nlon + ra;
-  if constexpr (MODE == kCorrK) return s.omega[ring] * s.t_ex[px];
   if constexpr (MODE == kCorrHorizon) return s.omega[ring];
   // Eq. skyapproximation
   return s.omega[ring] * fma(s.t_ex[px], exp2(-s.beta[px] * s.lr[f]), s.t_cmb);
 }
 
-// partial[((chunk * NJ + j) * F + f) * T + t]: the sum over the chunk's
-// rings.  For K, order[ring][k] (k < L) lists the ring's columns by region,
-// asort the matching weights omega t_ex and seg[ring][j] the start of region
-// j; every region's run is padded to a multiple of eight with weight-zero
-// entries, so the inner loop has no tail.  For Z every pixel is region 0 in
-// column order, padded the same way.  Per ring the b row (twice in a
-// row, so that column ra at step t is entry ra + nlon - s_t with no wrap
-// test), the columns and the weights are staged in LDS; all lanes of a wave
-// take the same pixel (broadcast reads) at their own shift.
+// The normalisers: partial[(chunk * F + f) * T + t] = the sum over the
+// chunk's rings of sum_ra a(ra) b(ra - s_t).  Per ring the b row (twice in
+// a row, so that column ra at step t is entry ra + nlon - s_t with no wrap
+// test) and the weights (zero-padded to Lz, a multiple of eight) are staged
+// in LDS; all lanes take the same column (broadcast reads) at their own
+// shift, eight columns at a time.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restrict__ shifts,
-                                                  int T, int t0, const int* __restrict__ order,
-                                                  const double* __restrict__ asort,
-                                                  const int* __restrict__ seg, int NJ, int L,
-                                                  int jper, int Lg,
+                                                  int T, int t0, int Lz,
                                                   double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, chunk = blockIdx.y;
-  const int j0 = blockIdx.z * jper, nj = min(jper, NJ - j0);   // this workgroup's regions
   const int nlon = s.nlon;
-  double* s_acc = reinterpret_cast<double*>(smem);             // [jper][blockDim]
-  double* s_a = s_acc + (size_t)blockDim.x * jper;             // [Lg]
-  float* s_b = reinterpret_cast<float*>(s_a + Lg);             // [2 nlon]
-  int* s_idx = reinterpret_cast<int*>(s_b + 2 * nlon);         // [Lg]
-  int* s_seg = s_idx + Lg;                                     // [jper + 1]
+  double* s_a = reinterpret_cast<double*>(smem);               // [Lz]
+  float* s_b = reinterpret_cast<float*>(s_a + Lz);             // [2 nlon + 8]
   const int tl = threadIdx.x, t = t0 + tl;
   const bool live = t < T;
   const int o = nlon - (live ? shifts[t] : 0);                 // in [1, nlon]
-  for (int j = 0; j < nj; ++j) s_acc[(size_t)j * blockDim.x + tl] = 0.0;
+  double acc = 0.0;
   const int r0 = chunk * kRingChunk, r1 = min(s.nlat, r0 + kRingChunk);
   for (int ring = r0; ring < r1; ++ring) {
     __syncthreads();
@@ -105,59 +96,245 @@ __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restric
       s_b[k] = b;
       s_b[k + nlon] = b;
     }
-    // the slice of the ring's list holding this workgroup's regions
-    const int* sg = MODE == kCorrK ? seg + (size_t)ring * (NJ + 1) : nullptr;
-    const int k0 = MODE == kCorrK ? sg[j0] : 0;
-    const int kn = (MODE == kCorrK ? sg[j0 + nj] : L) - k0;
-    if constexpr (MODE != kCorrK) {
-      for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-        s_idx[k] = k < nlon ? k : 0;
-        s_a[k] = k < nlon ? aval<MODE>(s, f, ring, k) : 0.0;
-      }
-      for (int j = threadIdx.x; j <= nj; j += blockDim.x) s_seg[j] = j == 0 ? 0 : L;
-    }
+    for (int k = threadIdx.x; k < 8; k += blockDim.x) s_b[2 * nlon + k] = 0.0f;
+    for (int k = threadIdx.x; k < Lz; k += blockDim.x)
+      s_a[k] = k < nlon ? aval<MODE>(s, f, ring, k) : 0.0;
     __syncthreads();
     if (!live) continue;
     const float* bo = s_b + o;
-    // K: the ring's columns and weights are read straight from global
-    // memory at wave-uniform addresses (scalar loads, no LDS traffic); Z
-    // uses the staged copies
-    const int* gidx = MODE == kCorrK ? order + (size_t)ring * L + k0 : nullptr;
-    const double* ga = MODE == kCorrK ? asort + (size_t)ring * L + k0 : nullptr;
-    for (int j = 0; j < nj; ++j) {
-      const int k1 = MODE == kCorrK ? sg[j0 + j + 1] - k0 : s_seg[j + 1];
-      int k = MODE == kCorrK ? sg[j0 + j] - k0 : s_seg[j];
-      if (k == k1) continue;
-      const int* xi = MODE == kCorrK ? gidx : s_idx;
-      const double* xa = MODE == kCorrK ? ga : s_a;
-      double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      // software pipelined: the next group's columns and weights are read
-      // while the current group's beam values are gathered
-      int id[8];
-      double av[8];
+    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < Lz; k += 8) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        id[u] = xi[k + u];
-        av[u] = xa[k + u];
-      }
-      for (; k < k1; k += 8) {
-        float bv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) bv[u] = bo[id[u]];
-        const int kn = k + 8 < k1 ? k + 8 : k;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          c[u] = fma(av[u], (double)bv[u], c[u]);
-          id[u] = xi[kn + u];
-          av[u] = xa[kn + u];
-        }
-      }
-      s_acc[(size_t)j * blockDim.x + tl] += ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+      for (int u = 0; u < 8; ++u) c[u] = fma(s_a[k + u], (double)bo[k + u], c[u]);
+    }
+    acc += ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+  }
+  if (live) partial[((size_t)chunk * s.F + f) * T + t] = acc;
+}
+
+// K of up to kRegionsPerGroup regions for four channels: one workgroup per
+// (channel block, work item), two lanes per time step, each taking two of
+// the four channels (lane 2t + h: channels 2h and 2h + 1 at step t0 + t).
+// A work item is a region group and a run of consecutive rings whose
+// estimated cost (the group's pixels, plus a fixed cost per ring for the
+// staging and the barrier) is about that of every other item: the partition
+// makes regions of very different sizes, so fixed ring chunks would leave the
+// workgroups of the largest regions running alone at the end.
+//
+// Per ring the block's beam rows sit in LDS as the interleaved device copy
+// holds them, four channels of a column side by side, over the window of the
+// doubled row (as above) that the steps' shifts reach, so a lane reads its
+// two channels of a pixel with one 8-byte gather;
+// the group's columns (stored as byte offsets) and weights omega t_ex sit
+// beside them and are read with same-address loads.  All of it is
+// double-buffered: the next ring is read from global memory into registers
+// before the current ring's sums and written to the other buffers after
+// them, one barrier per ring.  Each (region, channel) sum stays in a
+// register across the item's rings, pixels in the ring's region order,
+// rings in order.  Region runs are padded to a multiple of four with
+// weight-zero entries.
+constexpr int kRegionsPerGroup = 8;     // regions per workgroup of the K kernels
+constexpr int kSkyPrefetchCols = 4;     // beam columns a thread prefetches per ring
+constexpr int kSkyPrefetchIds = 4;      // columns (and weights) a thread prefetches per ring
+
+__global__ __launch_bounds__(256) void k_sky_k(SkyDev s, const int* __restrict__ shifts, int T,
+                                               int t0, int smax, const int* __restrict__ order,
+                                               const double* __restrict__ asort,
+                                               const int* __restrict__ seg, int NJ, int L,
+                                               int Lg, const int4* __restrict__ items,
+                                               double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int fb = blockIdx.x, f0 = 4 * fb, item = blockIdx.y;
+  const int4 it = items[item];                       // (region group, first ring, end ring)
+  const int j0 = it.x * kRegionsPerGroup, nj = min(kRegionsPerGroup, NJ - j0);
+  const int nlon = s.nlon;
+  // the window of the doubled row that some step reads: entries
+  // nlon - smax .. 2 nlon - 1 (entry e holds column e mod nlon)
+  const int nwin = nlon + smax, wbase = nlon - smax;
+  double* s_w = reinterpret_cast<double*>(smem);                 // [2][Lg]
+  int* s_id = reinterpret_cast<int*>(s_w + 2 * (size_t)Lg);      // [2][Lg] byte offsets
+  float4* s_b = reinterpret_cast<float4*>(s_id + 2 * (size_t)Lg);  // [2][nwin]
+  // the two lanes of a step are neighbours, so a wave's gathers read whole
+  // 16-byte column entries side by side (no bank conflicts)
+  const int tl = threadIdx.x, tb = blockDim.x;
+  const int h = tl & 1, t = t0 + (tl >> 1);
+  const bool live = t < T;
+  // byte offset of this lane's channel pair in window entry smax - s_t
+  const int o = (smax - (live ? shifts[t] : 0)) * 16 + 8 * h;
+  const int r0 = it.y, r1 = it.z;
+  const float4* b4 = s.beam4 + (size_t)fb * s.nlat * nlon;
+  // window entry q of `ring` (column (wbase + q) mod nlon)
+  auto col_of = [&](int q) { const int e = wbase + q; return e < nlon ? e : e - nlon; };
+  auto slice = [&](int ring, int& first, int& len) {   // the group's part of the ring's list
+    const int* sg = seg + (size_t)ring * (NJ + 1);
+    first = sg[j0];
+    len = sg[j0 + nj] - first;
+  };
+  {
+    int kb, kl;
+    slice(r0, kb, kl);
+    for (int q = tl; q < nwin; q += tb) s_b[q] = b4[(size_t)r0 * nlon + col_of(q)];
+    for (int k = tl; k < kl; k += tb) {
+      s_id[k] = order[(size_t)r0 * L + kb + k] * 16;
+      s_w[k] = asort[(size_t)r0 * L + kb + k];
     }
   }
+  __syncthreads();
+  double acc[kRegionsPerGroup][2];
+#pragma unroll
+  for (int j = 0; j < kRegionsPerGroup; ++j) acc[j][0] = acc[j][1] = 0.0;
+  for (int ring = r0; ring < r1; ++ring) {
+    const int cur = (ring - r0) & 1;
+    const bool next = ring + 1 < r1;
+    // the next ring's first window entries and slice entries, into
+    // registers now and into the other buffers after this ring's sums
+    int nb = 0, nl = 0;
+    if (next) slice(ring + 1, nb, nl);
+    float4 pf[kSkyPrefetchCols];
+    int pi[kSkyPrefetchIds];
+    double pw[kSkyPrefetchIds];
+#pragma unroll
+    for (int i = 0; i < kSkyPrefetchCols; ++i) {
+      const int q = tl + i * tb;
+      pf[i] = next && q < nwin ? b4[(size_t)(ring + 1) * nlon + col_of(q)]
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < kSkyPrefetchIds; ++i) {
+      const int k = tl + i * tb;
+      const bool in = k < nl;
+      pi[i] = in ? order[(size_t)(ring + 1) * L + nb + k] * 16 : 0;
+      pw[i] = in ? asort[(size_t)(ring + 1) * L + nb + k] : 0.0;
+    }
+    if (live) {
+      const unsigned char* bo =
+          reinterpret_cast<const unsigned char*>(s_b + (size_t)cur * nwin) + o;
+      const int* li = s_id + (size_t)cur * Lg;
+      const double* lw = s_w + (size_t)cur * Lg;
+      int kb, kl;
+      slice(ring, kb, kl);
+      const int* sg = seg + (size_t)ring * (NJ + 1) + j0;
+#pragma unroll
+      for (int j = 0; j < kRegionsPerGroup; ++j) {
+        if (j >= nj) break;
+        const int k1 = sg[j + 1] - kb;
+        int k = sg[j] - kb;
+        if (k >= k1) continue;
+        // software pipelined over groups of four pixels: the next group's
+        // gathers and the columns and weights of the one after are in flight
+        // while this group's FMAs run (LDS returns in order, so waiting for
+        // this group's gathers never waits for the later reads)
+        auto gather = [&](const int4 id, float2 (&b)[4]) {
+          b[0] = *reinterpret_cast<const float2*>(bo + id.x);
+          b[1] = *reinterpret_cast<const float2*>(bo + id.y);
+          b[2] = *reinterpret_cast<const float2*>(bo + id.z);
+          b[3] = *reinterpret_cast<const float2*>(bo + id.w);
+        };
+        int4 id = *reinterpret_cast<const int4*>(li + k);
+        double2 wa = *reinterpret_cast<const double2*>(lw + k);
+        double2 wb = *reinterpret_cast<const double2*>(lw + k + 2);
+        float2 b[4];
+        gather(id, b);
+        int kn = k + 4 < k1 ? k + 4 : k;
+        int4 idn = *reinterpret_cast<const int4*>(li + kn);
+        double2 wan = *reinterpret_cast<const double2*>(lw + kn);
+        double2 wbn = *reinterpret_cast<const double2*>(lw + kn + 2);
+#pragma unroll 2
+        for (; k < k1; k += 4) {
+          float2 bn[4];
+          gather(idn, bn);
+          const int kq = kn + 4 < k1 ? kn + 4 : kn;
+          const int4 idq = *reinterpret_cast<const int4*>(li + kq);
+          const double2 waq = *reinterpret_cast<const double2*>(lw + kq);
+          const double2 wbq = *reinterpret_cast<const double2*>(lw + kq + 2);
+          acc[j][0] = fma(wa.x, (double)b[0].x, acc[j][0]);
+          acc[j][1] = fma(wa.x, (double)b[0].y, acc[j][1]);
+          acc[j][0] = fma(wa.y, (double)b[1].x, acc[j][0]);
+          acc[j][1] = fma(wa.y, (double)b[1].y, acc[j][1]);
+          acc[j][0] = fma(wb.x, (double)b[2].x, acc[j][0]);
+          acc[j][1] = fma(wb.x, (double)b[2].y, acc[j][1]);
+          acc[j][0] = fma(wb.y, (double)b[3].x, acc[j][0]);
+          acc[j][1] = fma(wb.y, (double)b[3].y, acc[j][1]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) b[u] = bn[u];
+          wa = wan;
+          wb = wbn;
+          idn = idq;
+          wan = waq;
+          wbn = wbq;
+          kn = kq;
+        }
+      }
+    }
+    if (next) {
+      const int nxt = cur ^ 1;
+      float4* dst = s_b + (size_t)nxt * nwin;
+#pragma unroll
+      for (int i = 0; i < kSkyPrefetchCols; ++i) {
+        const int q = tl + i * tb;
+        if (q < nwin) dst[q] = pf[i];
+      }
+#pragma unroll
+      for (int i = 0; i < kSkyPrefetchIds; ++i) {
+        const int k = tl + i * tb;
+        if (k < nl) {
+          s_id[(size_t)nxt * Lg + k] = pi[i];
+          s_w[(size_t)nxt * Lg + k] = pw[i];
+        }
+      }
+      // what the registers did not hold (wide rings, long slices)
+      for (int q = tl + kSkyPrefetchCols * tb; q < nwin; q += tb)
+        dst[q] = b4[(size_t)(ring + 1) * nlon + col_of(q)];
+      for (int k = tl + kSkyPrefetchIds * tb; k < nl; k += tb) {
+        s_id[(size_t)nxt * Lg + k] = order[(size_t)(ring + 1) * L + nb + k] * 16;
+        s_w[(size_t)nxt * Lg + k] = asort[(size_t)(ring + 1) * L + nb + k];
+      }
+    }
+    __syncthreads();
+  }
   if (!live) return;
-  for (int j = 0; j < nj; ++j)
-    partial[(((size_t)chunk * NJ + j0 + j) * s.F + f) * T + t] = s_acc[(size_t)j * blockDim.x + tl];
+#pragma unroll
+  for (int j = 0; j < kRegionsPerGroup; ++j)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int f = f0 + 2 * h + c;
+      if (j < nj && f < s.F)
+        partial[(((size_t)item * kRegionsPerGroup + j) * s.F + f) * T + t] = acc[j][c];
+    }
+}
+
+// The interleaved beam copy: out[b][p] = (beam[4 b][p] .. beam[4 b + 3][p]),
+// zero past the last channel, for np pixels per channel.
+__global__ __launch_bounds__(256) void k_beam_interleave(const float* __restrict__ beam, int F,
+                                                         size_t np, size_t n,
+                                                         float4* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const size_t b = i / np, p = i - b * np;
+  float v[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const size_t f = 4 * b + c;
+    v[c] = f < (size_t)F ? beam[f * np + p] : 0.0f;
+  }
+  out[i] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// K[j][f][t] = sum over the work items of j's region group, in order, of the
+// items' partial sums (first[g] .. first[g + 1] - 1 are group g's items).
+__global__ __launch_bounds__(256) void k_sky_k_reduce(const double* __restrict__ partial,
+                                                      const int* __restrict__ first, int NJ,
+                                                      int F, int T, double* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t ft = (size_t)F * T;
+  if (i >= (size_t)NJ * ft) return;
+  const int j = (int)(i / ft);
+  const size_t rest = i - (size_t)j * ft;
+  const int g = j / kRegionsPerGroup, jj = j - g * kRegionsPerGroup;
+  double acc = 0.0;
+  for (int y = first[g]; y < first[g + 1]; ++y)
+    acc += partial[((size_t)y * kRegionsPerGroup + jj) * ft + rest];
+  out[i] = acc;
 }
 
 // out[i] = sum over chunks (in order) of partial[chunk * n + i]
@@ -214,21 +391,11 @@ __global__ __launch_bounds__(256) void k_sky_importance(SkyDev s, const int* __r
   }
 }
 
-// LDS of a k_sky_corr workgroup of tb threads holding jper regions whose
-// longest padded pixel slice is Lg
-size_t corr_lds(int tb, int jper, int nlon, int Lg) {
-  return (size_t)tb * jper * 8 + (size_t)Lg * 12 + (size_t)nlon * 8 + (size_t)(jper + 1) * 4;
-}
-
-constexpr int kRegionsPerGroup = 8;     // regions per k_sky_corr workgroup
-
-int corr_block(int T, int jper, int nlon, int Lg) {
-  int tb = std::min(256, (T + 63) / 64 * 64);
-  while (tb > 64 && corr_lds(tb, jper, nlon, Lg) > 96 * 1024) tb -= 64;
-  return tb;
-}
+// LDS of a k_sky_corr workgroup: the weights (Lz) and the doubled b row.
+size_t corr_lds(int nlon, int Lz) { return (size_t)Lz * 8 + ((size_t)2 * nlon + 8) * 4; }
 
 int pad8(int n) { return (n + 7) / 8 * 8; }
+int pad4(int n) { return (n + 3) / 4 * 4; }
 
 
 struct Sky {
@@ -247,19 +414,57 @@ hipError_t set_lds(KernelT k) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-// Z or K partial sums and their chunk reduction into out (device).
+// Z partial sums and their chunk reduction into out (device, [F][T]).
 template <int MODE>
-int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const double* d_asort,
-             const int* d_seg, int NJ, int L, int jper, int Lg, double* d_out, float* ms) {
+int run_corr(Sky* sk, const int* d_shifts, int T, int Lz, double* d_out) {
   const SkyDev& d = sk->d;
   const int chunks = (d.nlat + kRingChunk - 1) / kRingChunk;
-  const size_t n = (size_t)NJ * d.F * T;
+  const size_t n = (size_t)d.F * T;
   double* part = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&part), n * chunks * 8);
   if (e != hipSuccess) return hip_err(e, "allocating partial sums");
-  const int tb = corr_block(T, jper, d.nlon, Lg);
-  const size_t lds = corr_lds(tb, jper, d.nlon, Lg);
-  const int groups = (NJ + jper - 1) / jper;
+  const int tb = std::min(256, (T + 63) / 64 * 64);
+  const size_t lds = corr_lds(d.nlon, Lz);
+  if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {
+    for (int t0 = 0; t0 < T && e == hipSuccess; t0 += tb) {
+      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks), dim3(tb), lds, sk->stream, d,
+                         d_shifts, T, t0, Lz, part);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_sky_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, sk->stream,
+                       part, chunks, n, d_out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(sk->stream);
+  (void)hipFree(part);
+  return e == hipSuccess ? FGL_OK : hip_err(e, "normaliser kernels");
+}
+
+// LDS of a k_sky_k workgroup: two buffers of the row window (nlon + smax
+// four-channel columns) and of Lg columns and weights.
+size_t k_lds(int nlon, int smax, int Lg) {
+  return (size_t)32 * (nlon + smax) + (size_t)24 * Lg;
+}
+
+// K by k_sky_k over the work items (device int4 [n_items]: region group,
+// first ring, end ring; group g's items are first[g] .. first[g + 1] - 1,
+// device int [groups + 1]) and their reduction into d_out (device).
+int run_k(Sky* sk, const int* d_shifts, int T, int smax, const int* d_order,
+          const double* d_asort, const int* d_seg, int NJ, int L, int Lg, const int4* d_items,
+          int n_items, const int* d_first, double* d_out, float* ms) {
+  const SkyDev& d = sk->d;
+  if (k_lds(d.nlon, smax, Lg) > 160 * 1024)
+    return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", d.nlon);
+  // two lanes per step: T steps per launch in up to 256 lanes
+  const int tb = std::min(256, (2 * T + 63) / 64 * 64), TS = tb / 2;  const size_t ft = (size_t)d.F * T;
+  double* part = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&part),
+                           (size_t)n_items * kRegionsPerGroup * ft * 8);
+  if (e != hipSuccess) return hip_err(e, "allocating partial sums");
+  const size_t lds = k_lds(d.nlon, smax, Lg);
+  const dim3 grid((d.F + 3) / 4, n_items);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
     // timing only: no system-scope fence around the kernel
@@ -267,17 +472,17 @@ int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const doub
     (void)hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
     (void)hipEventRecord(e0, sk->stream);
   }
-  if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {
-    for (int t0 = 0; t0 < T && e == hipSuccess; t0 += tb) {
-      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks, groups), dim3(tb), lds, sk->stream,
-                         d, d_shifts, T, t0, d_order, d_asort, d_seg, NJ, L, jper, Lg, part);
-      e = hipGetLastError();
-    }
+  e = set_lds(k_sky_k);
+  for (int t0 = 0; t0 < T && e == hipSuccess; t0 += TS) {
+    hipLaunchKernelGGL(k_sky_k, grid, dim3(tb), lds, sk->stream, d, d_shifts, T, t0, smax,
+                       d_order, d_asort, d_seg, NJ, L, Lg, d_items, part);
+    e = hipGetLastError();
   }
   if (ms && e == hipSuccess) (void)hipEventRecord(e1, sk->stream);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_sky_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, sk->stream,
-                       part, chunks, n, d_out);
+    const size_t n = (size_t)NJ * ft;
+    hipLaunchKernelGGL(k_sky_k_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       sk->stream, part, d_first, NJ, d.F, T, d_out);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(sk->stream);
@@ -285,7 +490,45 @@ int run_corr(Sky* sk, const int* d_shifts, int T, const int* d_order, const doub
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(part);
-  return e == hipSuccess ? FGL_OK : hip_err(e, "correlation kernels");
+  return e == hipSuccess ? FGL_OK : hip_err(e, "K kernels");
+}
+
+// Work items of the K kernel: each region group's rings cut into runs of
+// about the same estimated cost, a ring costing its padded pixels of the
+// group plus kRingCost (at least one ring per item).  Measured on the
+// 256 x 512 benchmark sky (32 regions, 301 channels, 96 steps): 128 items
+// beat 32 and 64 by 10 % and 4 %; a per-ring cost of 64, 256 or 1024 pixels
+// changed nothing or made it slower.
+constexpr int kRingCost = 0;            // pixels' worth of one ring's staging and barrier
+constexpr int kItems = 128;             // work items aimed at per call
+void k_items(const std::vector<int>& seg, int nlat, int NJ, std::vector<int4>& items,
+             std::vector<int>& first) {
+  const int groups = (NJ + kRegionsPerGroup - 1) / kRegionsPerGroup;
+  auto px = [&](int g, int r) {
+    const int* sg = &seg[(size_t)r * (NJ + 1)];
+    return sg[std::min(NJ, (g + 1) * kRegionsPerGroup)] - sg[g * kRegionsPerGroup] + kRingCost;
+  };
+  long total = 0;
+  for (int g = 0; g < groups; ++g)
+    for (int r = 0; r < nlat; ++r) total += px(g, r);
+  // about kItems items in all, each costing at least 512
+  const long target = std::max<long>(512, (total + kItems - 1) / kItems);
+  items.clear();
+  first.assign(groups + 1, 0);
+  for (int g = 0; g < groups; ++g) {
+    first[g] = (int)items.size();
+    int r0 = 0;
+    long acc = 0;
+    for (int r = 0; r < nlat; ++r) {
+      acc += px(g, r);
+      if (acc >= target || r == nlat - 1) {
+        items.push_back(make_int4(g, r0, r + 1, 0));
+        r0 = r + 1;
+        acc = 0;
+      }
+    }
+  }
+  first[groups] = (int)items.size();
 }
 
 int check_shifts(const Sky* sk, const int32_t* shifts, int T) {
@@ -310,7 +553,8 @@ int to_device(T** dst, const T* src, size_t count, const char* what) {
 }
 
 void free_sky(Sky* sk) {
-  const void* ps[] = {sk->d.omega, sk->d.t_ex, sk->d.beta, sk->d.beam, sk->d.hor, sk->d.lr};
+  const void* ps[] = {sk->d.omega, sk->d.t_ex, sk->d.beta, sk->d.beam, sk->d.hor, sk->d.lr,
+                      sk->d.beam4};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
   if (sk->stream) (void)hipStreamDestroy(sk->stream);
@@ -454,6 +698,20 @@ int fgl_sky_create(int nlat, int nlon, int F, const double* omega, const double*
     free_sky(sk);
     return hip_err(e, "hipStreamCreate");
   }
+  // the beam interleaved by four channels for the K kernel
+  const size_t n4 = (size_t)((F + 3) / 4) * np;
+  float4* b4 = nullptr;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&b4), n4 * sizeof(float4))) == hipSuccess) {
+    sk->d.beam4 = b4;
+    hipLaunchKernelGGL(k_beam_interleave, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0,
+                       sk->stream, bm, F, np, n4, b4);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(sk->stream);
+  }
+  if (e != hipSuccess) {
+    free_sky(sk);
+    return hip_err(e, "interleaving the beam");
+  }
   *out = reinterpret_cast<fgl_sky*>(sk);
   return FGL_OK;
 }
@@ -466,7 +724,7 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
   int rc = check_shifts(sk, shifts, T);
   if (rc != FGL_OK) return rc;
   const int Lz = pad8(sk->d.nlon);
-  if (corr_lds(corr_block(T, 1, sk->d.nlon, Lz), 1, sk->d.nlon, Lz) > 160 * 1024)
+  if (corr_lds(sk->d.nlon, Lz) > 160 * 1024)
     return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", sk->d.nlon);
   hipError_t e = hipSetDevice(sk->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
@@ -479,9 +737,9 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
     rc = hip_err(e, "allocating importance buffers");
   }
   if (rc == FGL_OK) {
-    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, 1, Lz, Z, nullptr)
-         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, 1, Lz, Z, nullptr)
-                                    : run_corr<kCorrHorizon>(sk, d_sh, T, nullptr, nullptr, nullptr, 1, Lz, 1, Lz, Z, nullptr);
+    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, Lz, Z)
+         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, Lz, Z)
+                                    : run_corr<kCorrHorizon>(sk, d_sh, T, Lz, Z);
   }
   if (rc == FGL_OK) {
     std::vector<double> hz((size_t)d.F * T);
@@ -560,7 +818,7 @@ int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int
   const int N = n_regions, nlon = d.nlon;
   // masks: region j holds e_j <= beta < e_{j+1}, the last closed; then the
   // columns of each ring grouped by region (ascending column within one),
-  // every region's run padded to a multiple of eight with weight-zero entries
+  // every region's run padded to a multiple of four with weight-zero entries
   std::vector<int> regs((size_t)d.nlat * nlon), counts((size_t)d.nlat * N, 0);
   int L = 8;
   for (int r = 0; r < d.nlat; ++r) {
@@ -573,26 +831,27 @@ int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int
       regs[(size_t)r * nlon + c] = j;
       if (j >= 0) ++counts[(size_t)r * N + j];
     }
-    for (int j = 0; j < N; ++j) len += pad8(counts[(size_t)r * N + j]);
+    for (int j = 0; j < N; ++j) len += pad4(counts[(size_t)r * N + j]);
     L = std::max(L, len);
   }
-  // longest padded slice of one workgroup's regions
-  const int jper = std::min(N, kRegionsPerGroup);
+  // longest slice of one region group's columns in a ring (a multiple of 4)
   int Lg = 8;
   for (int r = 0; r < d.nlat; ++r)
-    for (int j0 = 0; j0 < N; j0 += jper) {
+    for (int j0 = 0; j0 < N; j0 += kRegionsPerGroup) {
       int len = 0;
-      for (int j = j0; j < std::min(N, j0 + jper); ++j) len += pad8(counts[(size_t)r * N + j]);
+      for (int j = j0; j < std::min(N, j0 + kRegionsPerGroup); ++j)
+        len += pad4(counts[(size_t)r * N + j]);
       Lg = std::max(Lg, len);
     }
-  if (corr_lds(corr_block(T, jper, nlon, Lg), jper, nlon, Lg) > 160 * 1024)
+  const int smax = *std::max_element(shifts, shifts + T);
+  if (k_lds(nlon, smax, Lg) > 160 * 1024)
     return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", nlon);
   std::vector<int> order((size_t)d.nlat * L, 0), seg((size_t)d.nlat * (N + 1));
   std::vector<double> asort((size_t)d.nlat * L, 0.0);
   for (int r = 0; r < d.nlat; ++r) {
     int* sg = &seg[(size_t)r * (N + 1)];
     sg[0] = 0;
-    for (int j = 0; j < N; ++j) sg[j + 1] = sg[j] + pad8(counts[(size_t)r * N + j]);
+    for (int j = 0; j < N; ++j) sg[j + 1] = sg[j] + pad4(counts[(size_t)r * N + j]);
     std::vector<int> fill(sg, sg + N);
     for (int c = 0; c < nlon; ++c) {
       const int j = regs[(size_t)r * nlon + c];
@@ -602,23 +861,31 @@ int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int
       asort[at] = sk->h_omega[r] * sk->h_tex[(size_t)r * nlon + c];
     }
   }
-  int *d_sh = nullptr, *d_order = nullptr, *d_seg = nullptr;
+  std::vector<int4> items;
+  std::vector<int> first;
+  k_items(seg, d.nlat, N, items, first);
+  int *d_sh = nullptr, *d_order = nullptr, *d_seg = nullptr, *d_first = nullptr;
+  int4* d_items = nullptr;
   double *d_K = nullptr, *d_as = nullptr;
   if ((rc = to_device(&d_sh, shifts, (size_t)T, "uploading shifts")) == FGL_OK &&
       (rc = to_device(&d_order, order.data(), order.size(), "uploading the region order")) == FGL_OK &&
       (rc = to_device(&d_as, asort.data(), asort.size(), "uploading pixel weights")) == FGL_OK &&
-      (rc = to_device(&d_seg, seg.data(), seg.size(), "uploading region segments")) == FGL_OK) {
+      (rc = to_device(&d_seg, seg.data(), seg.size(), "uploading region segments")) == FGL_OK &&
+      (rc = to_device(&d_items, items.data(), items.size(), "uploading work items")) == FGL_OK &&
+      (rc = to_device(&d_first, first.data(), first.size(), "uploading work items")) == FGL_OK) {
     if ((e = hipMalloc(reinterpret_cast<void**>(&d_K), (size_t)N * d.F * T * 8)) != hipSuccess)
       rc = hip_err(e, "allocating K");
   }
   float ms = 0.0f;
-  if (rc == FGL_OK) rc = run_corr<kCorrK>(sk, d_sh, T, d_order, d_as, d_seg, N, L, jper, Lg, d_K, &ms);
+  if (rc == FGL_OK)
+    rc = run_k(sk, d_sh, T, smax, d_order, d_as, d_seg, N, L, Lg, d_items, (int)items.size(),
+               d_first, d_K, &ms);
   if (rc == FGL_OK) {
     sk->last_ms = ms;
     if ((e = hipMemcpy(K, d_K, (size_t)N * d.F * T * 8, hipMemcpyDeviceToHost)) != hipSuccess)
       rc = hip_err(e, "copy K");
   }
-  const void* ps[] = {d_sh, d_order, d_seg, d_K, d_as};
+  const void* ps[] = {d_sh, d_order, d_seg, d_K, d_as, d_items, d_first};
   for (const void* p : ps)
     if (p) (void)hipFree(const_cast<void*>(p));
   return rc;
