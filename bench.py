@@ -72,6 +72,10 @@ def parse():
                    help="skip the crossed-mask model (2 amplitude x 16 index masks)")
     p.add_argument("--no-tune", action="store_true",
                    help="time the default tiles instead of the autotuned ones")
+    p.add_argument("--tile", default=None,
+                   help="waves,chans,occupancy: force this tile for the mixed precision on the "
+                        "headline workload (no tuning of it), so that separate profiler passes "
+                        "measure the same kernel variant")
     p.add_argument("--calib-copy", action="store_true",
                    help="only run a 256 MiB device-to-device copy three times "
                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -576,7 +580,12 @@ def main():
     out = torch.empty(w.B, dtype=torch.float64, device="cuda")
     if not a.no_tune:
         for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
+            if prec == "mixed" and a.tile:
+                continue
             m.tune(w.B, prec)
+    if a.tile:
+        wv, fc, occ = (int(x) for x in a.tile.split(","))
+        m.set_tile(w.B, "mixed", wv, fc, occ)
     res, outs = {}, {}
     for prec in (("mixed",) if a.no_plain else ("mixed", "fp32", "fp64")):
         res[prec] = time_prec(fgl, m, th, out, prec, a.steps, a.warmup)
