@@ -413,6 +413,14 @@ int fgl_chains_destroy(fgl_chains* c);
 int fgl_chains_philox(const uint32_t* ctr, int n, uint32_t k0, uint32_t k1,
                       uint32_t* out);
 
+/*
+ * Profiling ranges: with FGL_ROCTX=1 in the environment when the library is
+ * first used, the likelihood, gradient, tuning, serving-launch, chain, sky
+ * and noise calls push a roctx range (named for the call, with its main
+ * sizes) for rocprofv3 --marker-trace.  The roctx library is loaded at run
+ * time; without it, or without the variable, the ranges cost one branch.
+ */
+
 /* Message of the calling thread's last failure ("" if none). */
 const char* fgl_last_error(void);
 

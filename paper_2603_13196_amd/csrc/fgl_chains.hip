@@ -563,6 +563,7 @@ int fgl_chains_create(fgl_model* mh, int max_chains, const double* lo, const dou
 int fgl_chains_run(fgl_chains* ch, const double* x0, const double* l0, int n, double lstar,
                    const double* chol, int steps, int prec, double* x_out, double* l_out,
                    int64_t* evals, int64_t* rounds) {
+  TraceRange tr("fgl_chains_run n=%d steps=%d prec=%d", n, steps, prec);
   Chains* c = reinterpret_cast<Chains*>(ch);
   if (!c || !x0 || !l0 || !chol || !x_out || !l_out)
     return set_err(FGL_EINVAL, "NULL argument");

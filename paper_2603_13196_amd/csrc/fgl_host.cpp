@@ -12,6 +12,7 @@
 #include <limits>
 #include <string>
 
+#include <dlfcn.h>
 #include <unistd.h>
 
 namespace fgl {
@@ -37,6 +38,53 @@ int hip_err(hipError_t e, const char* what) {
 }
 
 const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// roctx ranges (FGL_ROCTX=1)
+
+namespace {
+
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+
+const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char* e = std::getenv("FGL_ROCTX");
+    if (!e || e[0] != '1') return x;
+    for (const char* lib : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"}) {
+      void* h = dlopen(lib, RTLD_NOW | RTLD_GLOBAL);
+      if (!h) continue;
+      auto push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+      auto pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+      if (push && pop) {
+        x.push = push;
+        x.pop = pop;
+        break;
+      }
+    }
+    return x;
+  }();
+  return r;
+}
+
+}  // namespace
+
+TraceRange::TraceRange(const char* fmt, ...) : on_(roctx().push != nullptr) {
+  if (!on_) return;
+  char buf[160];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  roctx().push(buf);
+}
+
+TraceRange::~TraceRange() {
+  if (on_) roctx().pop();
+}
 
 // ---------------------------------------------------------------------------
 // live models (so that a server can drop the workspaces of its streams)
@@ -898,6 +946,7 @@ const char* fgl_last_error(void) { return last_error(); }
 static int create_model(const float* K, const double* freqs, const double* data,
                         double nu_ref, int NA, int NB, int F, int T, double t_cmb,
                         unsigned flags, fgl_model** out) {
+  TraceRange tr("fgl_model_create N=%d F=%d T=%d", std::max(NA, 1) * NB, F, T);
   if (!out) return set_err(FGL_EINVAL, "out is NULL");
   *out = nullptr;
   if (!K || !freqs || !data) return set_err(FGL_EINVAL, "K, freqs and data must be non-NULL");
@@ -1042,6 +1091,7 @@ static int check_call(Model* m, int B, int prec) {
 }
 
 int fgl_loglike_batch(fgl_model* mh, const double* theta, int B, double* out, int prec) {
+  TraceRange tr("fgl_loglike_batch prec=%d B=%d", prec, B);
   Model* m = reinterpret_cast<Model*>(mh);
   int rc = check_call(m, B, prec);
   if (rc != FGL_OK) return rc;
@@ -1114,6 +1164,7 @@ constexpr size_t kMaxDeviceGraphs = 16;
 
 int fgl_loglike_batch_device(fgl_model* mh, const double* d_theta, int B,
                              double* d_out, int prec, void* hip_stream) {
+  TraceRange tr("fgl_loglike_batch_device prec=%d B=%d", prec, B);
   Model* m = reinterpret_cast<Model*>(mh);
   int rc = check_call(m, B, prec);
   if (rc != FGL_OK) return rc;
@@ -1204,6 +1255,7 @@ static int check_grad(Model* m, int B, int prec) {
 
 int fgl_loglike_grad_batch(fgl_model* mh, const double* theta, int B, double* out,
                            double* grad, int prec) {
+  TraceRange tr("fgl_loglike_grad_batch B=%d", B);
   Model* m = reinterpret_cast<Model*>(mh);
   int rc = check_grad(m, B, prec);
   if (rc != FGL_OK) return rc;
@@ -1251,6 +1303,7 @@ int fgl_loglike_grad_batch(fgl_model* mh, const double* theta, int B, double* ou
 int fgl_loglike_grad_batch_device(fgl_model* mh, const double* d_theta, int B,
                                   double* d_out, double* d_grad, int prec,
                                   void* hip_stream) {
+  TraceRange tr("fgl_loglike_grad_batch_device B=%d", B);
   Model* m = reinterpret_cast<Model*>(mh);
   int rc = check_grad(m, B, prec);
   if (rc != FGL_OK) return rc;
@@ -1308,6 +1361,7 @@ int fgl_set_tile(fgl_model* mh, int B, int prec, int waves, int chans, int occup
 int fgl_tune_cache(const char* path) { return tune_cache_set(path); }
 
 int fgl_tune(fgl_model* mh, int B, int prec) {
+  TraceRange tr("fgl_tune prec=%d B=%d", prec, B);
   Model* m = reinterpret_cast<Model*>(mh);
   int rc = check_call(m, B, prec);
   if (rc != FGL_OK) return rc;

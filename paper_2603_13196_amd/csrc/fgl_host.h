@@ -127,4 +127,20 @@ void drop_stream_work(hipStream_t s);   // fgl_host.cpp
 int tune_cache_set(const char* path);   // fgl_host.cpp
 void serve_forget_model(Model* m);      // fgl_serve.cpp
 
+// A roctx range around a library call, for rocprofv3 --marker-trace (or
+// --sys-trace / --runtime-trace): active only when the environment sets
+// FGL_ROCTX=1 at the first call, and then only if the roctx library can be
+// loaded (it is looked up at run time; nothing links against it).  The
+// label is formatted only when active.
+class TraceRange {
+ public:
+  explicit TraceRange(const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+  ~TraceRange();
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+
+ private:
+  bool on_;
+};
+
 }  // namespace fgl

@@ -57,6 +57,7 @@ using namespace fgl;
 
 extern "C" int fgl_loglike_batch_device_noalloc(fgl_model* mh, const double* d_theta, int B,
                                                 double* d_out, int prec, void* hip_stream) {
+  TraceRange tr("fgl_loglike_batch_device_noalloc prec=%d B=%d", prec, B);
   Model* m = reinterpret_cast<Model*>(mh);
   if (!m) return set_err(FGL_EINVAL, "model is NULL");
   if (B < 0 || B > kMaxRows) return set_err(FGL_EINVAL, "B=%d outside 0..2^26", B);

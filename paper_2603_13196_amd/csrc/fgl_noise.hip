@@ -182,6 +182,7 @@ extern "C" {
 
 int fgl_noise_loglike(int64_t n, int R, double sigma_noise, double sigma_like, uint64_t seed,
                       double* lnl, double* kernel_ms) {
+  TraceRange tr("fgl_noise_loglike n=%lld R=%d", (long long)n, R);
   if (!lnl) return set_err(FGL_EINVAL, "lnl is NULL");
   if (n < 1 || n > kNoiseMaxN) return set_err(FGL_EINVAL, "n=%lld outside 1..2^31", (long long)n);
   if (R < 1 || R > kNoiseMaxGroups)

@@ -185,6 +185,7 @@ static int launch_slot(Server* srv, Slot* sl) {
   const int prec = sl->reqs.front()->prec;
   int rows = 0;
   for (Req* r : sl->reqs) rows += r->B;
+  TraceRange tr("serve launch: %zu requests, %d rows, prec=%d", sl->reqs.size(), rows, prec);
   std::lock_guard<std::mutex> mlk(m->mu);
   hipError_t e = hipSetDevice(m->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
@@ -222,6 +223,7 @@ static int launch_slot(Server* srv, Slot* sl) {
 // requests of one model; all in precision `prec`, all with likelihood
 // variant `variant`).  Called with srv->mu held and the slot idle.
 static int launch_slot_shared(Server* srv, Slot* sl, int prec) {
+  TraceRange tr("serve shared launch: %zu requests, prec=%d", sl->reqs.size(), prec);
   // the groups, in order
   struct G {
     Model* m;

@@ -717,6 +717,7 @@ int fgl_sky_create(int nlat, int nlon, int F, const double* omega, const double*
 }
 
 int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, double* importance) {
+  TraceRange tr("fgl_sky_importance scheme=%d T=%d", scheme, T);
   Sky* sk = reinterpret_cast<Sky*>(sh);
   if (!sk || !importance) return set_err(FGL_EINVAL, "sky and importance must be non-NULL");
   if (scheme < FGL_WEIGHT_HORIZON || scheme > FGL_WEIGHT_BEAM)
@@ -804,6 +805,7 @@ int fgl_partition(const double* beta, const double* weight, int n, int n_regions
 
 int fgl_sky_chromatic(fgl_sky* sh, const double* edges, int n_regions, const int32_t* shifts,
                       int T, double* K) {
+  TraceRange tr("fgl_sky_chromatic regions=%d T=%d", n_regions, T);
   Sky* sk = reinterpret_cast<Sky*>(sh);
   if (!sk || !edges || !K) return set_err(FGL_EINVAL, "sky, edges and K must be non-NULL");
   if (n_regions < 1 || n_regions > 1024) return set_err(FGL_EINVAL, "n_regions=%d outside 1..1024", n_regions);
