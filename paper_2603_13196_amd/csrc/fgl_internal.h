@@ -104,6 +104,45 @@ struct Tile {
   int occ;     // waves per SIMD the kernel is compiled for (2 or 3)
 };
 
+// Channel chunks of a likelihood launch: `nbig` chunks of `fc` channels,
+// then chunks of `fs` channels up to F, `nc` in all (fs <= fc, both
+// multiples of the reduction group, so the partials do not depend on the
+// chunking).  On each XCD every row tile's large chunks are dispatched
+// before the small ones, which fill the last round of workgroups.
+struct Chunks {
+  int fc, fs, nbig, nc;
+};
+
+// Compute units of the device (MI355X: 8 XCDs of 32).
+constexpr int kCUs = 256;
+
+// Workgroup `id` of a likelihood launch -> (row tile bt, chunk ch).  Block
+// ids go round-robin to the 8 XCDs; XCD xcd takes its share of the (row
+// tile, large chunk) pairs first, then its share of the (row tile, small
+// chunk) pairs, each a contiguous run in row-tile order, so that both cover
+// the same row tiles (whose rows then stay in that XCD's L2) and the small
+// chunks come last.  The small pairs are shared out so that each XCD's total
+// is the round-robin count of its ids, which needs nb * nsmall >= 8 (or no
+// small chunks: then this is the plain contiguous split).
+__host__ __device__ inline void map_block_split(int id, int nb, int nbig, int nsmall, int& bt,
+                                                int& ch) {
+  const int total = nb * (nbig + nsmall), tb = nb * nbig;
+  const int xcd = id & 7, k = id >> 3;
+  const int q = total >> 3, rem = total & 7;
+  const int qb = tb >> 3, rb = tb & 7;
+  const int start_b = xcd * qb + (xcd < rb ? xcd : rb);
+  const int n_b = qb + (xcd < rb ? 1 : 0);
+  if (k < n_b) {
+    const int L = start_b + k;
+    bt = L / nbig;
+    ch = L - bt * nbig;
+  } else {
+    const int L = xcd * q + (xcd < rem ? xcd : rem) - start_b + (k - n_b);
+    bt = L / nsmall;
+    ch = nbig + (L - bt * nsmall);
+  }
+}
+
 // Device-side model (all pointers are device memory owned by the model).
 struct DevModel {
   int N, F, T, P;
@@ -251,5 +290,9 @@ int cols_per_wave(Kind k);
 int n_chunks(const DevModel& m, const Tile& t);   // workgroups along nu
 int n_groups(const DevModel& m, const Tile& t);   // partials per row
 int max_lds_bytes();
+// The likelihood launch's chunks over nb row tiles (uniform chunks of
+// t.fc channels but for the mixed kernel, whose last round is filled with
+// half-size chunks when that shortens the busiest CU's share).
+Chunks chunk_plan(Kind k, const DevModel& m, const Tile& t, int nb);
 
 }  // namespace fgl

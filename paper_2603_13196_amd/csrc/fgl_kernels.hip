@@ -178,17 +178,19 @@ __device__ inline double pow2_64(double y, const double* t64, const DevModel& m)
 // call it for one model (k_mixed) or for several that share the compiled
 // variant (k_mixed_multi).
 template <int W, int KC, bool PROJ, int OCC, int AM>
-__device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, int fc, int G,
-                                           int nb, int nc, int block) {
+__device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, const Chunks& cp,
+                                           int G, int nb, int block) {
   constexpr int ND = PROJ ? kProjDigits : 4;       // digits of the matrix rows
   constexpr int NP = 6;                            // digits of the powers
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int bt, ch;
-  map_block_id(block, nb, nc, bt, ch);
+  map_block_split(block, nb, cp.nbig, cp.nc - cp.nbig, bt, ch);
   const int TT = PROJ ? m.RT : m.TT;               // 32-row tiles
-  const int f0 = ch * fc;
-  const int fn = min(fc, m.F - f0);
+  const int fc = cp.fc;                            // LDS layout: the large chunk
+  const bool big = ch < cp.nbig;
+  const int f0 = big ? ch * fc : cp.nbig * fc + (ch - cp.nbig) * cp.fs;
+  const int fn = min(big ? fc : cp.fs, m.F - f0);
   const int kbytes = ND * KC * TT * 1024;
   // LDS: the exponent tables at offset 0 (so a table byte offset is an LDS
   // address), then the channels' matrix digits and data
@@ -483,9 +485,9 @@ __device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, int
 
 template <int W, int KC, bool PROJ, int OCC, int AM>
 __global__ __launch_bounds__(W * 64)
-__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, int fc, int G,
-                                                    int nb, int nc) {
-  mixed_body<W, KC, PROJ, OCC, AM>(m, w, fc, G, nb, nc, blockIdx.x);
+__attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed(DevModel m, Work w, Chunks cp,
+                                                    int G, int nb) {
+  mixed_body<W, KC, PROJ, OCC, AM>(m, w, cp, G, nb, blockIdx.x);
 }
 
 // The group of workgroup blockIdx.x in launch `which` (0 likelihood, 1 row
@@ -508,7 +510,7 @@ __attribute__((amdgpu_waves_per_eu(OCC, OCC))) void k_mixed_multi(const GroupDes
   if (local >= nb * nc) return;                    // padding to a multiple of eight
   const DevModel m = d[j].m;
   const Work w = d[j].w;
-  mixed_body<W, KC, PROJ, OCC, AM>(m, w, d[j].fc, d[j].G, nb, nc, local);
+  mixed_body<W, KC, PROJ, OCC, AM>(m, w, Chunks{d[j].fc, d[j].fc, nc, nc}, d[j].G, nb, local);
 }
 
 // ---------------------------------------------------------------------------
@@ -1256,39 +1258,49 @@ hipError_t go(KernelT kern, int blocks, int threads, int lds, hipStream_t s,
   return hipGetLastError();
 }
 
+// Launch the mixed kernel: nb row tiles times cp.nc channel chunks.
+template <typename KernelT>
+hipError_t go_mixed(KernelT kern, int nb, int lds, hipStream_t s, const DevModel& m,
+                    const Work& w, const Chunks& cp, int G, int threads) {
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(kern));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(nb * cp.nc), dim3(threads), lds, s, m, w, cp, G, nb);
+  return hipGetLastError();
+}
+
 template <int W, int AM>
-hipError_t mixed_wa(const DevModel& m, const Work& w, int fc, int G, int nb,
-                    int nc, int occ, int lds, hipStream_t s) {
-  const int blocks = nb * nc, th = W * 64;
+hipError_t mixed_wa(const DevModel& m, const Work& w, const Chunks& cp, int G, int nb,
+                    int occ, int lds, hipStream_t s) {
+  const int th = W * 64;
   if (m.proj) {
     switch (m.KC) {
       case 1:
         if constexpr (AM != 1)
           if (occ == 3)
-            return go(k_mixed<W, 1, true, 3, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-        return go(k_mixed<W, 1, true, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 2: return go(k_mixed<W, 2, true, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-      case 3: return go(k_mixed<W, 3, true, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+            return go_mixed(k_mixed<W, 1, true, 3, AM>, nb, lds, s, m, w, cp, G, th);
+        return go_mixed(k_mixed<W, 1, true, 2, AM>, nb, lds, s, m, w, cp, G, th);
+      case 2: return go_mixed(k_mixed<W, 2, true, 2, AM>, nb, lds, s, m, w, cp, G, th);
+      case 3: return go_mixed(k_mixed<W, 3, true, 2, AM>, nb, lds, s, m, w, cp, G, th);
       default: return hipErrorInvalidValue;
     }
   }
   switch (m.KC) {
-    case 1: return go(k_mixed<W, 1, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 2: return go(k_mixed<W, 2, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 3: return go(k_mixed<W, 3, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
-    case 4: return go(k_mixed<W, 4, false, 2, AM>, blocks, th, lds, s, m, w, fc, G, nb, nc);
+    case 1: return go_mixed(k_mixed<W, 1, false, 2, AM>, nb, lds, s, m, w, cp, G, th);
+    case 2: return go_mixed(k_mixed<W, 2, false, 2, AM>, nb, lds, s, m, w, cp, G, th);
+    case 3: return go_mixed(k_mixed<W, 3, false, 2, AM>, nb, lds, s, m, w, cp, G, th);
+    case 4: return go_mixed(k_mixed<W, 4, false, 2, AM>, nb, lds, s, m, w, cp, G, th);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int W>
-hipError_t mixed_w(const DevModel& m, const Work& w, int fc, int G, int nb,
-                   int nc, int occ, int lds, hipStream_t s) {
+hipError_t mixed_w(const DevModel& m, const Work& w, const Chunks& cp, int G, int nb,
+                   int occ, int lds, hipStream_t s) {
   if (occ == 3 && !mixed_occ3(m)) return hipErrorInvalidValue;
   switch (mixed_alpha_mode(m)) {
-    case 0: return mixed_wa<W, 0>(m, w, fc, G, nb, nc, occ, lds, s);
-    case 1: return mixed_wa<W, 1>(m, w, fc, G, nb, nc, occ, lds, s);
-    default: return mixed_wa<W, 2>(m, w, fc, G, nb, nc, occ, lds, s);
+    case 0: return mixed_wa<W, 0>(m, w, cp, G, nb, occ, lds, s);
+    case 1: return mixed_wa<W, 1>(m, w, cp, G, nb, occ, lds, s);
+    default: return mixed_wa<W, 2>(m, w, cp, G, nb, occ, lds, s);
   }
 }
 
@@ -1403,8 +1415,9 @@ hipError_t launch_main(Kind k, const DevModel& m, const Work& w,
                     : thin_wa<false>(m, w, tile.fc, tile.group, nb, nc, lds, s, th);
   }
   if (k == kMixed) {
-    return tile.waves == 8 ? mixed_w<8>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s)
-                           : mixed_w<4>(m, w, tile.fc, tile.group, nb, nc, tile.occ, lds, s);
+    const Chunks cp = chunk_plan(k, m, tile, nb);
+    return tile.waves == 8 ? mixed_w<8>(m, w, cp, tile.group, nb, tile.occ, lds, s)
+                           : mixed_w<4>(m, w, cp, tile.group, nb, tile.occ, lds, s);
   } else if (k == kFP32) {
     return tile.waves == 8 ? fp32_w<8>(m, w, tile.fc, tile.group, nb, nc, lds, s)
                            : fp32_w<4>(m, w, tile.fc, tile.group, nb, nc, lds, s);

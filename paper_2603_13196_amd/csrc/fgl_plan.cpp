@@ -34,6 +34,33 @@ int lds_bytes(Kind k, const DevModel& m, const Tile& t) {
 
 int n_chunks(const DevModel& m, const Tile& t) { return (m.F + t.fc - 1) / t.fc; }
 
+// A round is one workgroup on every slot of the chip: the CUs times the
+// workgroups that registers (four SIMDs of `occ` waves) and LDS let share a
+// CU.  With uniform chunks the last round of a launch can be nearly empty
+// (at N32 F301 B16384, eight-channel chunks make 9.5 rounds of 256
+// workgroups).  Whole rounds of large chunks followed by half-size chunks
+// cut the busiest CU's channels from ceil(rounds) * fc toward the mean.
+Chunks chunk_plan(Kind k, const DevModel& m, const Tile& t, int nb) {
+  const int nc = n_chunks(m, t);
+  const Chunks even{t.fc, t.fc, nc, nc};
+  if (k != kMixed || nb < 1) return even;
+  const int fs = std::max(t.group, t.fc / 2 / t.group * t.group);
+  if (fs >= t.fc) return even;
+  const int per_cu = std::max(1, std::min(4 * t.occ / t.waves,
+                                          max_lds_bytes() / lds_bytes(k, m, t)));
+  const long slots = (long)kCUs * per_cu;
+  const long rounds = (long)nb * (m.F / t.fc) / slots;
+  if (rounds == 0) return even;
+  const int nbig = (int)(rounds * slots / nb);
+  const int nsmall = (m.F - nbig * t.fc + fs - 1) / fs;
+  auto up = [&](long wg) { return (wg + slots - 1) / slots; };
+  const long now = up((long)nb * nc) * t.fc;
+  const long split = up((long)nb * nbig) * t.fc + up((long)nb * nsmall) * fs;
+  // the block map needs at least one small chunk per XCD
+  if (nbig < 1 || split >= now || (long)nb * nsmall < 8) return even;
+  return Chunks{t.fc, fs, nbig, nbig + nsmall};
+}
+
 int n_groups(const DevModel& m, const Tile& t) {
   return (m.F + t.group - 1) / t.group;
 }

@@ -2,7 +2,8 @@
 // HIP runtime (hip_stub.cpp) and of the kernel launchers (launch_stub.cpp).
 // Test infrastructure only.
 //
-// It runs the library's host paths the GPU tests run, with every row's
+// It checks the likelihood launch's chunk plans and block map, then runs
+// the library's host paths the GPU tests run, with every row's
 // result predicted exactly (the launcher stand-ins compute
 // lnL' = sum_k (k + 1) theta_k + D[0]):
 //   1. model creation in every form (direct, projected, thin, crossed masks,
@@ -33,6 +34,7 @@
 #include <vector>
 
 #include "../../include/fgl.h"
+#include "../../paper_2603_13196_amd/csrc/fgl_internal.h"
 #include "hip_stub.h"
 
 namespace {
@@ -256,8 +258,87 @@ void serve_round(const std::vector<TM>& ms, size_t budget, int slots, int share,
 
 }  // namespace
 
+// The likelihood launch's channel chunks (fgl::chunk_plan) and its block
+// map (fgl::map_block_split): the chunks tile [0, F) at multiples of the
+// reduction group, and the map sends the launch's block ids one to one onto
+// (row tile, chunk), with every XCD's large chunks ahead of its small ones.
+void chunk_plans() {
+  using namespace fgl;
+  long plans = 0, split = 0;
+  for (int F : {1, 5, 64, 301, 401, 1000})
+    for (int KC : {1, 2})
+      for (int proj : {0, 1})
+        for (int G : {1, 2, 4})
+          for (int mult : {1, 2, 4})
+            for (int W : {4, 8})
+              for (int occ : {2, 3})
+                for (int nb : {1, 3, 64, 128, 511}) {
+                  DevModel m{};
+                  m.F = F;
+                  m.KC = KC;
+                  m.proj = proj;
+                  m.RT = 2;
+                  m.TT = 3;
+                  const Tile t{W, G * mult, G, occ};
+                  if (lds_bytes(kMixed, m, t) > max_lds_bytes()) continue;
+                  const Chunks c = chunk_plan(kMixed, m, t, nb);
+                  ++plans;
+                  CHECK(c.fc == t.fc && c.fs >= 1 && c.fs <= c.fc && c.fs % G == 0 &&
+                            c.nbig >= 1 && c.nbig <= c.nc,
+                        "plan F=%d fc=%d: fc %d fs %d nbig %d nc %d", F, t.fc, c.fc, c.fs,
+                        c.nbig, c.nc);
+                  const int nsmall = c.nc - c.nbig;
+                  split += nsmall > 0;
+                  // chunk ch covers [f0, f0 + fn): contiguous, in order, ending at F
+                  int next = 0;
+                  for (int ch = 0; ch < c.nc; ++ch) {
+                    const bool big = ch < c.nbig;
+                    const int f0 = big ? ch * c.fc : c.nbig * c.fc + (ch - c.nbig) * c.fs;
+                    const int fn = std::min(big ? c.fc : c.fs, F - f0);
+                    CHECK(f0 == next && fn >= 1 && f0 % G == 0, "chunk %d of F=%d", ch, F);
+                    next = f0 + fn;
+                  }
+                  CHECK(next == F, "chunks end at %d, F=%d", next, F);
+                  CHECK(nsmall == 0 || (long)nb * nsmall >= 8, "too few small pairs");
+                  const long total = (long)nb * c.nc;
+                  if (total > 200000) continue;
+                  std::vector<char> seen(total, 0);
+                  std::vector<char> small_seen(8, 0);
+                  bool order = true, onto = true;
+                  for (long id = 0; id < total; ++id) {
+                    int bt = -1, ch = -1;
+                    map_block_split((int)id, nb, c.nbig, nsmall, bt, ch);
+                    if (bt < 0 || bt >= nb || ch < 0 || ch >= c.nc || seen[(long)bt * c.nc + ch]) {
+                      onto = false;
+                      break;
+                    }
+                    seen[(long)bt * c.nc + ch] = 1;
+                    const int x = (int)(id & 7);
+                    if (ch >= c.nbig) small_seen[x] = 1;
+                    else if (small_seen[x]) order = false;
+                  }
+                  CHECK(onto, "block map not one to one: F=%d nb=%d plan %d/%d/%d/%d", F, nb,
+                        c.fc, c.fs, c.nbig, c.nc);
+                  CHECK(order, "small chunk ahead of a large one: F=%d nb=%d", F, nb);
+                }
+  // the headline shape: N32 F301, 8 waves of 32 rows, B = 16384 (64 row tiles)
+  DevModel h{};
+  h.F = 301;
+  h.KC = 1;
+  h.proj = 1;
+  h.RT = 1;
+  const Chunks c = chunk_plan(kMixed, h, Tile{8, 8, 4, 3}, 64);
+  CHECK(c.fc == 8 && c.fs == 4 && c.nbig == 36 && c.nc == 40, "headline plan %d/%d/%d/%d",
+        c.fc, c.fs, c.nbig, c.nc);
+  const Chunks p = chunk_plan(kFP32, h, Tile{8, 8, 4, 2}, 64);
+  CHECK(p.nbig == p.nc && p.fs == p.fc, "plain kernels keep uniform chunks");
+  std::printf("   %ld plans, %ld with small chunks\n", plans, split);
+}
+
 int main() {
   setvbuf(stdout, nullptr, _IOLBF, 0);
+  step("chunk plans and the likelihood block map");
+  chunk_plans();
   step("models in every form");
   std::vector<TM> ms;
   ms.push_back(make("direct", 0, 8, 20, 40, FGL_MIXED_DIRECT, 1));

@@ -6,8 +6,9 @@ fgl_host.cpp, fgl_serve.cpp and fgl_plan.cpp are compiled with g++ as they
 are, against a CPU stand-in of the HIP runtime (streams as in-order worker
 threads, host functions on them, events, stream capture and graph replay)
 and of the kernel launchers (tests/native/).  The driver,
-tests/native/host_sched_test.cpp, predicts every row's result exactly and
-runs synchronous, device-pointer and gradient calls, eight threads on shared
+tests/native/host_sched_test.cpp, checks the likelihood launch's channel
+chunk plans and block map over many shapes, predicts every row's result
+exactly and runs synchronous, device-pointer and gradient calls, eight threads on shared
 models, and the serving scheduler with 16 client threads, with and without
 shared launches and an HBM budget that forces eviction.  The stand-ins
 report reads of evicted model buffers and shared-launch plans that do not fit
