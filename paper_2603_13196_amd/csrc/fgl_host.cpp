@@ -892,20 +892,29 @@ int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
     (void)hipEventDestroy(e0);
     return hip_err(e, "hipEventCreate");
   }
-  // two sweeps over the candidates, each timed over five calls after a
-  // warm-up; a candidate's time is its faster sweep (clock ramps and
-  // co-scheduled work then rarely decide between tiles a few % apart)
+  // three sweeps over the candidates; in each, a candidate is timed over
+  // enough calls to span >= 3 ms (5 to 40, from a timed warm-up call) and
+  // its time is the mean per call of its fastest sweep.  Shorter windows let
+  // clock ramps and co-scheduled work decide between tiles 2-3% apart.
   std::vector<float> best_of(cand.size(), std::numeric_limits<float>::max());
   int rc = FGL_OK;
-  for (int sweep = 0; sweep < 2 && rc == FGL_OK; ++sweep) {
+  for (int sweep = 0; sweep < 3 && rc == FGL_OK; ++sweep) {
     for (size_t c = 0; c < cand.size(); ++c) {
       const Tile& t = cand[c];
       rc = ensure_work(m, wb, B, n_groups(m->dm, t), false);
       if (rc != FGL_OK) break;
-      rc = enqueue(m, k, t, wb, d_theta, B, d_out, s);  // warm-up
-      if (rc != FGL_OK) break;
       (void)hipEventRecord(e0, s);
-      const int reps = 5;
+      rc = enqueue(m, k, t, wb, d_theta, B, d_out, s);  // warm-up
+      (void)hipEventRecord(e1, s);
+      if (rc != FGL_OK) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        rc = hip_err(e, "tuning run");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const int reps = ms > 0.0f ? std::max(5, std::min(40, (int)std::ceil(3.0f / ms))) : 5;
+      (void)hipEventRecord(e0, s);
       for (int r = 0; r < reps && rc == FGL_OK; ++r)
         rc = enqueue(m, k, t, wb, d_theta, B, d_out, s);
       (void)hipEventRecord(e1, s);
@@ -913,9 +922,9 @@ int tune(Model* m, Kind k, WorkBuf& wb, const double* d_theta, int B,
         rc = hip_err(e, "tuning run");
         break;
       }
-      float ms = 0.0f;
+      ms = 0.0f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      best_of[c] = std::min(best_of[c], ms);
+      best_of[c] = std::min(best_of[c], ms / reps);
     }
   }
   const Tile best =

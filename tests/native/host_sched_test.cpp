@@ -330,6 +330,16 @@ void chunk_plans() {
   const Chunks c = chunk_plan(kMixed, h, Tile{8, 8, 4, 3}, 64);
   CHECK(c.fc == 8 && c.fs == 4 && c.nbig == 36 && c.nc == 40, "headline plan %d/%d/%d/%d",
         c.fc, c.fs, c.nbig, c.nc);
+  // N64 F401 in the direct form, B = 65536 in 2-channel chunks: the split
+  // would move one channel per row tile (401 against 402 per CU), under the
+  // 2% it has to gain, so the chunks stay uniform
+  DevModel l{};
+  l.F = 401;
+  l.KC = 2;
+  l.TT = 8;
+  const Chunks d = chunk_plan(kMixed, l, Tile{8, 2, 1, 2}, 256);
+  CHECK(d.nbig == d.nc && d.nc == 201, "N64 F401 direct plan %d/%d/%d/%d", d.fc, d.fs, d.nbig,
+        d.nc);
   const Chunks p = chunk_plan(kFP32, h, Tile{8, 8, 4, 2}, 64);
   CHECK(p.nbig == p.nc && p.fs == p.fc, "plain kernels keep uniform chunks");
   std::printf("   %ld plans, %ld with small chunks\n", plans, split);
