@@ -508,11 +508,12 @@ int fgl_sky_destroy(fgl_sky* s);
 
 /*
  * lnL of R noise-only data sets (FP64 host [R]).  The standard normals z_rk
- * are fixed by (seed, r, k): under key (seed, 0), block b of stream s is
- * Philox4x64-10 (Salmon et al., SC 2011) of counter (b, r, s, 0); normals
- * 2j and 2j+1 are the Box-Muller pair of u1 = (floor(w/2^11) + 1) 2^-53 and
- * u2 = floor(v/2^11) 2^-53, w and v the word j % 4 of block j / 4 of
- * streams 0 and 1: z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
+ * are fixed by (seed, r, k): under key (seed low 32 bits, seed high 32 bits),
+ * block b of stream s is Philox4x32-10 (Salmon et al., SC 2011) of counter
+ * (b, r, s, 0x6e6f6973); normals 2j and 2j+1 are the Box-Muller pair of
+ * u1 = (w + 1) 2^-32 and u2 = v 2^-32, w and v the 32-bit word j % 4 of
+ * block j / 4 of streams 0 and 1: z = sqrt(-2 ln u1) (cos 2 pi u2,
+ * sin 2 pi u2).
  * n in 1..2^31; R in 1..2^23; n R <= 2^40 (a call runs at most a few
  * seconds); sigma_noise finite >= 0; sigma_like finite > 0.  kernel_ms (may
  * be NULL) receives the kernel's duration.

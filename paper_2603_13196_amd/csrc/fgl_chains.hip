@@ -33,6 +33,7 @@
 // so no draw is ever repeated.  Uniforms take 53 bits, normals come from the
 // Box-Muller transform.
 #include "fgl_host.h"
+#include "fgl_philox.h"
 
 #include <algorithm>
 #include <cmath>
@@ -80,34 +81,12 @@ struct ChainState {
   unsigned flags;
 };
 
-// --- Philox4x32-10 --------------------------------------------------------
-
-__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)M0 * c[0];
-    const uint64_t p1 = (uint64_t)M1 * c[2];
-    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    const uint32_t n0 = hi1 ^ c[1] ^ k0;
-    const uint32_t n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += W0;
-    k1 += W1;
-  }
-}
-
 // Two uniforms in [0, 1) with 53 random bits each, from Philox block c of
 // chain i.
 __device__ inline void uniform2(const ChainState& s, int i, unsigned long long c, double& u0,
                                 double& u1) {
   uint32_t v[4] = {(uint32_t)c, (uint32_t)(c >> 32), (uint32_t)i, 0x5eed5eedu};
-  philox(v, (uint32_t)s.seed, (uint32_t)(s.seed >> 32));
+  philox4x32(v, (uint32_t)s.seed, (uint32_t)(s.seed >> 32));
   const uint64_t a = ((uint64_t)v[0] << 32 | v[1]) >> 11;
   const uint64_t b = ((uint64_t)v[2] << 32 | v[3]) >> 11;
   u0 = (double)a * 0x1.0p-53;
@@ -481,7 +460,7 @@ __global__ void k_philox(const uint32_t* __restrict__ ctr, int n, uint32_t k0, u
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   uint32_t c[4] = {ctr[4 * j], ctr[4 * j + 1], ctr[4 * j + 2], ctr[4 * j + 3]};
-  philox(c, k0, k1);
+  philox4x32(c, k0, k1);
 #pragma unroll
   for (int q = 0; q < 4; ++q) out[4 * j + q] = c[q];
 }

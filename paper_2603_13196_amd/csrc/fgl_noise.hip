@@ -6,26 +6,28 @@
 // For data = M(theta) + e the residual at theta is e itself, so realisation r
 // has lnL_r = -(sigma_noise^2 / (2 sigma_like^2)) S_r - (n/2) ln(2 pi
 // sigma_like^2) with S_r = sum_k z_rk^2 over its n standard normals.  The
-// normals come from Philox4x64-10 (Salmon et al., SC 2011; key (seed, 0),
-// block b of stream s on counter (b, r, s, 0)) through the Box-Muller
-// transform: pair j takes u1 from word j % 4 of stream-0 block j / 4 and u2
-// from the same word of stream 1.  The two normals of a pair have
-// z0^2 + z1^2 = -2 ln u1, so a full pair adds -2 ln u1 to S and needs
-// neither u2 nor any trigonometry: only the stream-0 words are drawn, four
-// pairs (eight normals) per block, and stream 1 and the cosine are touched
-// only for a pair cut by the end of an odd-length realisation.
+// normals come from Philox4x32-10 (Salmon et al., SC 2011; key (seed low
+// word, seed high word), block b of stream s on counter (b, r, s, 'nois'))
+// through the Box-Muller transform with 32-bit uniforms: pair j takes u1 from
+// word j % 4 of stream-0 block j / 4 and u2 from the same word of stream 1.
+// The two normals of a pair have z0^2 + z1^2 = -2 ln u1, so a full pair adds
+// -2 ln u1 to S and needs neither u2 nor any trigonometry: only the stream-0
+// words are drawn, four pairs (eight normals) per block, and stream 1 and the
+// cosine are touched only for a pair cut by the end of an odd-length
+// realisation.
 //
 // k_noise_lnl: one workgroup per realisation.  Each thread walks its
 // stream-0 blocks keeping the product of its u1 values as mantissa and
-// binary exponent (frexp after every block; u1 >= 2^-53, so four factors
+// binary exponent (frexp after every block; u1 >= 2^-32, so four factors
 // never underflow) and takes one logarithm at the end: per block the work
-// is the generator and four multiplies.  The per-thread sums meet in a
-// fixed shuffle-and-LDS tree.  Nothing is read from memory; the kernel is
-// bound by the generator's integer multiplies.
+// is the generator (twenty 32x32-bit products) and four multiplies.  The
+// per-thread sums meet in a fixed shuffle-and-LDS tree.  Nothing is read
+// from memory; the kernel is bound by the generator's integer multiplies.
 //
 // k_noise_q: one workgroup per fit; its threads count the reference values at
 // or below the fit's lnL in a fixed tree, and q = count / R.
 #include "fgl_host.h"
+#include "fgl_philox.h"
 
 #include <cmath>
 
@@ -37,45 +39,28 @@ constexpr int kNoiseThreads = 256;
 constexpr int kNoiseMaxGroups = 1 << 23;           // R and nb: grids well below 2^32 work-items
 constexpr int64_t kNoiseMaxN = (int64_t)1 << 31;    // residuals per data set
 constexpr double kNoiseMaxNormals = 1099511627776.0;  // 2^40 per call: about 2 s of work
-constexpr uint64_t kPhM0 = 0xD2E7470EE14C6C93ull;   // Philox4x64 multipliers
-constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;   // Weyl key increments
-constexpr uint64_t kPhW1 = 0xBB67AE8584CAA73Bull;
+constexpr uint32_t kNoiseTag = 0x6e6f6973u;          // counter word 3 ('nois')
 
-// Philox4x64-10 of counter (c0, c1, c2, 0) under key (k0, 0).
-__device__ inline void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t k0,
-                                  uint64_t x[4]) {
-  uint64_t c3 = 0, k1 = 0;
-#pragma unroll
-  for (int i = 0; i < 10; ++i) {
-    if (i) {
-      k0 += kPhW0;
-      k1 += kPhW1;
-    }
-    const uint64_t hi0 = __umul64hi(kPhM0, c0), lo0 = kPhM0 * c0;
-    const uint64_t hi1 = __umul64hi(kPhM1, c2), lo1 = kPhM1 * c2;
-    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  x[0] = c0;
-  x[1] = c1;
-  x[2] = c2;
-  x[3] = c3;
+// Block b of stream s of realisation r.
+__device__ inline void noise_block(uint32_t b, uint32_t r, uint32_t s, uint64_t seed,
+                                   uint32_t x[4]) {
+  x[0] = b;
+  x[1] = r;
+  x[2] = s;
+  x[3] = kNoiseTag;
+  philox4x32(x, (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 // word j (0..3) of a block, without indexing the array at run time
-__device__ inline uint64_t word(const uint64_t x[4], int j) {
+__device__ inline uint32_t word(const uint32_t x[4], int j) {
   return j == 0 ? x[0] : j == 1 ? x[1] : j == 2 ? x[2] : x[3];
 }
 
-__device__ inline double u_open0(uint64_t w) {   // (0, 1]
-  return (double)((w >> 11) + 1) * 0x1p-53;
+__device__ inline double u_open0(uint32_t w) {   // (0, 1]
+  return ((double)w + 1.0) * 0x1p-32;
 }
-__device__ inline double u_open1(uint64_t w) {   // [0, 1)
-  return (double)(w >> 11) * 0x1p-53;
+__device__ inline double u_open1(uint32_t w) {   // [0, 1)
+  return (double)w * 0x1p-32;
 }
 
 // lnL of realisations 0..R-1, one per workgroup.
@@ -89,27 +74,29 @@ __global__ __launch_bounds__(kNoiseThreads) void k_noise_lnl(int64_t n, uint64_t
   double p = 1.0;                               // product of u1, times 2^-e
   int e = 0;
   for (int64_t b = tid; b < nfull; b += kNoiseThreads) {
-    uint64_t x[4];
-    philox4x64((uint64_t)b, r, 0, seed, x);
-    p *= u_open0(x[0]);
-    p *= u_open0(x[1]);
-    p *= u_open0(x[2]);
-    p *= u_open0(x[3]);
+    uint32_t x[4];
+    noise_block((uint32_t)b, (uint32_t)r, 0u, seed, x);
+    // u1 = (w + 1) 2^-32: p (w + 1) as one fma, the 2^-32 in the exponent
+    // (scaling by a power of two does not change a rounding)
+    p = fma(p, (double)x[0], p);
+    p = fma(p, (double)x[1], p);
+    p = fma(p, (double)x[2], p);
+    p = fma(p, (double)x[3], p);
     int ex;
     p = frexp(p, &ex);
-    e += ex;
+    e += ex - 128;
   }
   // S contribution of the full pairs: -2 sum ln u1
   double s = -2.0 * (log(p) + (double)e * 0.69314718055994530942);
   const int rem = (int)(npair & 3);             // full pairs in the last block
   const bool odd = n & 1;                       // and a pair cut in half
   if ((rem || odd) && tid == 0) {
-    uint64_t x[4];
-    philox4x64((uint64_t)nfull, r, 0, seed, x);
+    uint32_t x[4];
+    noise_block((uint32_t)nfull, (uint32_t)r, 0u, seed, x);
     for (int j = 0; j < rem; ++j) s += -2.0 * log(u_open0(word(x, j)));
     if (odd) {
-      uint64_t y[4];
-      philox4x64((uint64_t)nfull, r, 1, seed, y);
+      uint32_t y[4];
+      noise_block((uint32_t)nfull, (uint32_t)r, 1u, seed, y);
       const double c = cospi(2.0 * u_open1(word(y, rem)));
       s += -2.0 * log(u_open0(word(x, rem))) * c * c;
     }

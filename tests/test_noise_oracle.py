@@ -1,9 +1,9 @@
 """Pins of the residual-likelihood oracle (accuracy criterion, Sec. 5).
 
-- The generator against numpy's own Philox4x64-10 bit generator (an
-  implementation of the same published generator, written independently),
-  and the counter layout of both streams of the normals through that
-  generator.
+- The generator against the known-answer blocks published with
+  Philox4x32-10 (Salmon et al., SC 2011, and the Random123 release that
+  accompanies it), and the counter layout of both streams of the normals
+  through that pinned generator.
 - The normals against the standard normal law (Kolmogorov-Smirnov), and the
   reference lnL against the chi-squared law with n degrees of freedom that
   the sum of n squared standard normals follows.
@@ -26,53 +26,62 @@ import oracle
 import workload
 from oracle import noise as nz
 
-PHILOX_CASES = [
-    ((1, 2), (5, 0, 0, 0)),
-    ((0, 0), (1, 0, 0, 0)),
-    ((2**64 - 1, 0x123), (2**64 - 16, 7, 9, 2**64 - 1)),
-    ((0x0123456789ABCDEF, 2**63), (2**40 + 3, 2**63 + 5, 0, 12345)),
+# Philox4x32-10 known answers: (key, counter, block)
+PHILOX_KAT = [
+    ((0x00000000, 0x00000000), (0x00000000, 0x00000000, 0x00000000, 0x00000000),
+     (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF, 0xFFFFFFFF), (0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF),
+     (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0xA4093822, 0x299F31D0), (0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
 ]
 
 
 def pin_philox(m):
-    for key, ctr in PHILOX_CASES:
-        # numpy's Philox increments its counter before each block, so start it
-        # one below the block wanted
-        g = np.random.Philox(key=np.array(key, dtype=np.uint64),
-                             counter=np.array([ctr[0] - 1, *ctr[1:]], dtype=np.uint64))
-        ref = g.random_raw(8)
-        c2 = (ctr[0] + 1, *ctr[1:])
-        got = m.philox4x64(np.array([ctr, c2], dtype=np.uint64), key).reshape(-1)
-        assert np.array_equal(got, ref), key
+    ctr = np.array([c for _, c, _ in PHILOX_KAT], dtype=np.uint32)
+    for i, (key, c, want) in enumerate(PHILOX_KAT):
+        got = m.philox4x32(np.array([c, c], dtype=np.uint32), key)
+        assert got.dtype == np.uint32
+        assert [int(x) for x in got[0]] == list(want), key
+        assert np.array_equal(got[0], got[1])
+    # a batch of counters is the blocks one by one
+    key = PHILOX_KAT[2][0]
+    batch = m.philox4x32(ctr, key)
+    for i in range(len(ctr)):
+        assert np.array_equal(batch[i], m.philox4x32(ctr[i:i + 1], key)[0])
 
 
 def pin_layout(m):
-    # under key (seed, 0), block b of stream s is Philox of counter
-    # (b, r, s, 0); normals 2j and 2j+1 are the Box-Muller pair of
-    # u1 = (w / 2^11 + 1) 2^-53 and u2 = (v / 2^11) 2^-53, w and v word j of
-    # the two streams.  numpy's generator gives the words: started at
-    # counter (2^64 - 1, r - 1, s) it carries into (0, r, s) for block 0.
-    r, seed, nblk = 3, 11, 300
+    # under key (seed low word, seed high word), block b of stream s is
+    # Philox of counter (b, r, s, 0x6e6f6973); normals 2j and 2j+1 are the
+    # Box-Muller pair of u1 = (w + 1) 2^-32 and u2 = v 2^-32, w and v word j
+    # of the two streams (the counters are built here, the generator is the
+    # pinned one)
+    r, seed, nblk = 3, (1 << 40) + 11, 300
 
     def words(stream):
-        g = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
-                             counter=np.array([2**64 - 1, r - 1, stream, 0], dtype=np.uint64))
-        return g.random_raw(4 * nblk)
+        ctr = np.zeros((nblk, 4), dtype=np.uint32)
+        ctr[:, 0] = np.arange(nblk)
+        ctr[:, 1] = r
+        ctr[:, 2] = stream
+        ctr[:, 3] = 0x6E6F6973
+        return m.philox4x32(ctr, (seed & 0xFFFFFFFF, seed >> 32)).reshape(-1)
 
-    u1 = ((words(0) >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
-    u2 = (words(1) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u1 = (words(0).astype(np.float64) + 1.0) * 2.0 ** -32
+    u2 = words(1).astype(np.float64) * 2.0 ** -32
     z = m.normals(8 * nblk, r, seed)
     np.testing.assert_allclose(z[0::2] ** 2 + z[1::2] ** 2, -2.0 * np.log(u1), rtol=1e-12)
     ang = np.mod(np.arctan2(z[1::2], z[0::2]), 2.0 * math.pi)
     d = np.abs(ang - 2.0 * math.pi * u2)
     assert np.all(np.minimum(d, 2.0 * math.pi - d) < 1e-9)
     # a prefix of a realisation does not depend on its length; realisations
-    # and seeds differ
+    # and seeds (either word) differ
     a = m.normals(13, 3, 11)
     for n in (1, 2, 3, 4, 5, 8, 9, 12):
         assert np.array_equal(m.normals(n, 3, 11), a[:n])
     assert not np.array_equal(m.normals(13, 4, 11), a)
     assert not np.array_equal(m.normals(13, 3, 12), a)
+    assert not np.array_equal(m.normals(13, 3, 11 + (1 << 32)), a)
 
 
 def pin_normals(m):
@@ -138,13 +147,17 @@ def test_likelihood_identity_time_integrated():
 
 # Plausible mistakes, each planted into a copy of the oracle's source.
 MUTANTS = {
-    "philox multiplier": ("0xD2E7470EE14C6C93", "0xD2E7470EE14C6C95"),
-    "key bumped before the first round": ("            if rnd:\n", "            if True:\n"),
-    "round outputs swapped": ("(hi1 ^ c1 ^ np.uint64(k0), lo1,", "(lo1, hi1 ^ c1 ^ np.uint64(k0),"),
-    "realisation in the wrong counter word": ("ctr[:, 1] = np.uint64(r)", "ctr[:, 3] = np.uint64(r)"),
-    "one stream for u1 and u2": ("ctr[:, 2] = np.uint64(1)", "ctr[:, 2] = np.uint64(0)"),
+    "philox multiplier": ("PHILOX_M0 = 0xD2511F53", "PHILOX_M0 = 0xD2511F55"),
+    "Weyl increment": ("PHILOX_W1 = 0xBB67AE85", "PHILOX_W1 = 0xBB67AE87"),
+    "key bumped before the first round": ("        if rnd:\n", "        if True:\n"),
+    "nine rounds": ("PHILOX_ROUNDS = 10", "PHILOX_ROUNDS = 9"),
+    "round outputs swapped": ("(hi1 ^ c1 ^ np.uint32(k0), lo1,", "(lo1, hi1 ^ c1 ^ np.uint32(k0),"),
+    "realisation in the wrong counter word": ("ctr[:, 1] = np.uint32(r)", "ctr[:, 2] = np.uint32(r)"),
+    "no tag word": ("ctr[:, 3] = np.uint32(NOISE_TAG)", "ctr[:, 3] = np.uint32(0)"),
+    "seed high word dropped": ("(seed >> 32) & MASK32)", "0)"),
+    "one stream for u1 and u2": ("ctr[:, 2] = np.uint32(1)", "ctr[:, 2] = np.uint32(0)"),
     "cosine for both normals": ("rho * np.sin(ang)", "rho * np.cos(ang)"),
-    "u2 from the u1 words": ("u2 = (v >>", "u2 = (w >>"),
+    "u2 from the u1 words": ("u2 = v.astype", "u2 = w.astype"),
     "u1 scale": ("+ 1.0) * scale", "+ 1.0) * scale * 2.0"),
     "normalisation without the half": ("norm = 0.5 * n * math.log", "norm = n * math.log"),
     "quadratic term without the 2": ("/ (2.0 * sigma_like * sigma_like)", "/ (sigma_like * sigma_like)"),
