@@ -131,6 +131,37 @@ static inline uint32_t digits4(int32_t q) {
 
 static void build_projected(Model* m, const float* K, const double* data);
 
+
+// 2^(r/64) on |r| <= 1/2 for the mixed kernel: the degree-4 polynomial that
+// interpolates it at the five Chebyshev nodes (monomial coefficients q[0..4],
+// solved in long double).  Its largest relative error is 2^-48.5, against
+// 4e-17 for the fifth-order Taylor series the FP64 kernels use; the mixed
+// kernel rounds its powers to 47 bits, and a digit-level emulation of its
+// arithmetic gives the same margins on the posterior shells with either.
+static void cheb_pow2(double q[5]) {
+  constexpr int n = 5;
+  long double a[n][n + 1];
+  for (int k = 0; k < n; ++k) {
+    const long double x = 0.5L * std::cos((2.0L * k + 1.0L) * 3.14159265358979323846264338L /
+                                          (2.0L * n));
+    long double xp = 1.0L;
+    for (int j = 0; j < n; ++j, xp *= x) a[k][j] = xp;
+    a[k][n] = std::exp2(x / 64.0L);
+  }
+  for (int c = 0; c < n; ++c) {                     // Gaussian elimination, partial pivoting
+    int pr = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[pr][c])) pr = r;
+    for (int j = 0; j <= n; ++j) std::swap(a[c][j], a[pr][j]);
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const long double f = a[r][c] / a[c][c];
+      for (int j = c; j <= n; ++j) a[r][j] -= f * a[c][j];
+    }
+  }
+  for (int j = 0; j < n; ++j) q[j] = (double)(a[j][n] / a[j][j]);
+}
+
 static void build_layouts(Model* m, const float* K, const double* freqs,
                           const double* data) {
   const int N = m->N, F = m->F, T = m->T;
@@ -236,6 +267,7 @@ static void build_layouts(Model* m, const float* K, const double* freqs,
   m->dm.c3 = (double)(c1 * c1 * c1 / 6.0L);
   m->dm.c4 = (double)(c1 * c1 * c1 * c1 / 24.0L);
   m->dm.c5 = (double)(c1 * c1 * c1 * c1 * c1 / 120.0L);
+  cheb_pow2(m->dm.q);
   if (m->dm.proj) build_projected(m, K, data);
 }
 

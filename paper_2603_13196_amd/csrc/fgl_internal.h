@@ -168,6 +168,7 @@ struct DevModel {
   const double* tab;     // [kTabSize + 2 kFracSize] exponent tables
   double c1, c2, c3, c4; // Taylor coefficients of 2^(r/64)
   double c5;             // and its fifth-order term
+  double q[5];           // the mixed kernel's 2^(r/64): degree 4, Chebyshev nodes
   // projected form of the mixed kernel (proj = 1): per channel, the rows
   // [sqrt(T) mean_t K ; R] where K~^T = Q R is the QR factorisation of the
   // time-centred responses, and targets [sqrt(T) mean_t D ; (Q^T D~)_0..]

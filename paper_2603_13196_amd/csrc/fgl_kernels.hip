@@ -264,11 +264,10 @@ __device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, con
     const double tg = yg + MAGIC;
     const double rg = yg - (tg - MAGIC);             // |rg| <= 1/2
     const int jg = max((int)(uint32_t)__double_as_longlong(tg), -kTabLo);
-    double pg = fma(rg, m.c5, m.c4);
-    pg = fma(rg, pg, m.c3);
-    pg = fma(rg, pg, m.c2);
-    pg = fma(rg, pg, m.c1);
-    pg = fma(rg, pg, 1.0);
+    double pg = fma(rg, m.q[4], m.q[3]);
+    pg = fma(rg, pg, m.q[2]);
+    pg = fma(rg, pg, m.q[1]);
+    pg = fma(rg, pg, m.q[0]);
     // tab = Q 2^(j/64) with 1/Q = 2^-47 (64/63)
     const double c = fma(rp.A * (0x1.0p-47 * 64.0 / 63.0), s_tab0[jg] * pg, m.t_cmb);
     const double bext = nl > 0.0 ? rp.bmax : rp.bmin;
@@ -311,9 +310,11 @@ __device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, con
       C.c2 = (int)rint(fma(-c1f, u0 * 0x1.0p-24, r1) * ldexp(s_ifrac[fm], 40 - eu));
     }
     // Powers 2^(y/64), y = 64 log2(x) <= 0, as tab[round(y)] 2^(r/64), the
-    // latter by its Taylor series to fifth order (truncation below 4e-17
-    // relative).  Exponents below the table (x < 2^-48, all digits zero)
-    // take its last entry, which rounds to zero digits for any |r| <= 1/2.
+    // latter by the degree-4 polynomial interpolating it at the Chebyshev
+    // nodes of |r| <= 1/2 (relative error below 2^-48.5, under the 47-bit
+    // rounding that follows).  Exponents below the table (x < 2^-48, all
+    // digits zero) take its last entry, which rounds to zero digits for any
+    // |r| <= 1/2.
     const double cm = MAGIC - ymax;                 // exact: ymax is an integer
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
@@ -334,11 +335,10 @@ __device__ __forceinline__ void mixed_body(const DevModel& m, const Work& w, con
         }
         const int jj = max((int)(uint32_t)__double_as_longlong(t), -kTabLo);
         const double T2 = s_tab0[jj];              // Q 2^(jj/64)
-        double p = fma(r, m.c5, m.c4);
-        p = fma(r, p, m.c3);
-        p = fma(r, p, m.c2);
-        p = fma(r, p, m.c1);
-        p = fma(r, p, 1.0);                        // 2^(r/64)
+        double p = fma(r, m.q[4], m.q[3]);
+        p = fma(r, p, m.q[2]);
+        p = fma(r, p, m.q[1]);
+        p = fma(r, p, m.q[0]);                     // 2^(r/64), degree 4
         const double q = fma(T2, p, DIGITS);       // 2^52 + q + offsets
         if (PROJ && kc == KC - 1 && j == 15) C.e.qlast = q - DIGITS;
         const unsigned long long bits = __double_as_longlong(q);
