@@ -176,13 +176,58 @@ def _serve_run(fgl, clients, models, seconds, inflight, share, budget, log_every
             "shared_launches": shared, "groups_in_shared": groups}
 
 
+def _serve_open(fgl, clients, models, seconds, inflight, share, rate, seed=37):
+    """Open-loop arrivals: requests arrive as a Poisson process of `rate`
+    per second whatever the completions, each from a client drawn uniformly
+    with its next batch size, for `seconds`; then the queue drains."""
+    srv = fgl.Server(max_inflight=inflight)
+    srv.set_sharing(share)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nxt = [0] * len(clients)
+    pending, lat, rows = [], [], 0
+    t_start = time.perf_counter()
+    t_end = t_start + seconds
+    arrival = t_start + rng.exponential(1.0 / rate)
+    while True:
+        now = time.perf_counter()
+        while arrival <= now and arrival < t_end:
+            c = int(rng.integers(len(clients)))
+            cl = clients[c]
+            B = cl.batches[nxt[c] % len(cl.batches)]
+            nxt[c] += 1
+            pending.append(srv.submit(models[c], cl.work.theta[:B], "mixed"))
+            arrival += rng.exponential(1.0 / rate)
+        still = []
+        for t in pending:
+            r = srv.poll(t)
+            if r is None:
+                still.append(t)
+            else:
+                out, us = r
+                lat.append(us)
+                rows += out.size
+        pending = still
+        if now >= t_end and not pending:
+            break
+        time.sleep(20e-6)
+    wall = time.perf_counter() - t_start
+    srv.close()
+    lat = np.array(lat)
+    return {"offered_rps": rate, "achieved_rps": lat.size / wall, "requests": int(lat.size),
+            "p50_ms": float(np.percentile(lat, 50)) / 1e3,
+            "p99_ms": float(np.percentile(lat, 99)) / 1e3,
+            "evals_per_s": rows / wall, "seconds": wall}
+
+
 def serving_leg(fgl, seconds, configs_arg=None):
     """The 64-client serving mix swept over 1..4 in-flight slots (the box
     runs 4 hardware queues per process), with per-model launches and with
     launches shared by up to 16 models of one kernel variant, every model
     resident; then at 2 and 4 slots under an HBM budget of half the
     models' resident bytes, where admission waits and evictions take part.
-    The headline record is the resident configuration with the lowest p99."""
+    The headline record is the resident configuration with the lowest p99;
+    at that configuration an open-loop sweep then offers Poisson arrivals at
+    0.5, 0.8 and 1.0 of the request rate it sustained closed-loop."""
     import workload
     clients = workload.serving_clients(64, n_requests=64)
     models = [fgl.Model.from_workload(c.work) for c in clients]
@@ -203,14 +248,28 @@ def serving_leg(fgl, seconds, configs_arg=None):
         log(f"serving slots {inflight} sharing {share} budget {budget}: p50 {r['p50_ms']:.3f} ms, "
             f"p99 {r['p99_ms']:.3f} ms, {r['evals_per_s']:.3e} evals/s, "
             f"{r['shared_launches']} shared launches of {r['launches']}")
-    for m in models:
-        m.close()
     best = min((r for r in sweep if not r["budget_bytes"]), key=lambda r: r["p99_ms"],
                default=sweep[0])
+    # open loop at the best resident configuration: Poisson arrivals at 0.5,
+    # 0.8 and 1.0 of the request rate that configuration sustained closed-loop
+    cap = max((r["requests"] / r["seconds"] for r in sweep
+               if not r["budget_bytes"] and r["max_inflight"] == best["max_inflight"]
+               and r["sharing"] == best["sharing"]), default=1.0)
+    open_loop = []
+    for load in (0.5, 0.8, 1.0):
+        r = _serve_open(fgl, clients, models, seconds, best["max_inflight"], best["sharing"],
+                        load * cap)
+        r["load"] = load
+        open_loop.append(r)
+        log(f"serving open loop at {load:.1f} x {cap:.0f} requests/s: p50 {r['p50_ms']:.3f} ms, "
+            f"p99 {r['p99_ms']:.3f} ms, {r['achieved_rps']:.0f} requests/s")
+    for m in models:
+        m.close()
     return {"clients": len(clients), "models_bytes": total,
             "requests": best["requests"], "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
             "evals_per_s": best["evals_per_s"], "max_inflight": best["max_inflight"],
-            "sharing": best["sharing"], "budget_bytes": 0, "sweep": sweep}
+            "sharing": best["sharing"], "budget_bytes": 0, "sweep": sweep,
+            "capacity_rps": cap, "open_loop": open_loop}
 
 
 def sampler_leg(fgl, regions=10, T=1):
