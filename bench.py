@@ -409,9 +409,20 @@ def grad_leg(fgl, w, steps, warmup):
     dt = time.perf_counter() - t0
     kms, n = m.kernel_time()
     m.kernel_timing(False)
+    form = m.form
     m.close()
+    k = kms / max(n, 1)
+    # algorithmic FP64 work of the two contractions per row: the model over
+    # the matrix rows (N + 1 projected rows, or T time bins) and the
+    # transposed product K^T r, 2 flop per multiply-add each
+    rows = w.N + 1 if form == "projected" else w.T
+    flops = 4.0 * rows * w.N * w.F * w.B
+    achieved = flops / (k * 1e-3) / 1e12
     return {"value": w.B * steps / dt, "unit": "gradients/s", "ms_per_step": dt * 1e3 / steps,
-            "kernel_ms": kms / max(n, 1), "kernel": "k_grad64", "precision": "fp64"}
+            "kernel_ms": k, "kernel": "k_grad64", "precision": "fp64", "form": form,
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                         "work": "4 (N+1) N F flop per row: model and transposed product"}}
 
 
 def regions_leg(fgl, n_regions=32):
