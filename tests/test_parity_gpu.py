@@ -96,6 +96,28 @@ def test_headline_full_batch_sampled(fgl, orc):
     m.close()
 
 
+def test_balanced_chunks_full_batch(fgl, orc):
+    """At B = 16384 the 8-wave, 8-channel tile cuts each row tile's 301
+    channels into 36 chunks of 8 and then 4 of 4, the small ones dispatched
+    last on every XCD (the chunk plan the CPU test pins), while 4-channel
+    blocks stay uniform.  Both launches give the same bits, in both forms,
+    and agree with the oracle on sampled rows."""
+    w = workload.config(workload.HEADLINE)
+    rng = np.random.Generator(np.random.PCG64(13))
+    idx = np.sort(rng.choice(w.B, 128, replace=False))
+    ref = orc.loglike_w(w, w.theta[idx])
+    for flags, occ in ((0, 3), (fgl.FGL_MIXED_DIRECT, 2)):
+        m = _model(fgl, w, flags)
+        outs = []
+        for fc in (8, 4):
+            say(f"balanced chunks: {m.form} form, tile 8 waves x {fc} channels, B={w.B}")
+            m.set_tile(w.B, "mixed", 8, fc, occ)
+            outs.append(m.loglike(w.theta, "mixed"))
+        assert np.array_equal(outs[0], outs[1]), m.form
+        check(outs[0][idx], ref, "mixed", f"balanced/{m.form}")
+        m.close()
+
+
 def test_large_workload_subsample(fgl, orc):
     """N=64, F=401, T=240, B=65536: full launch, oracle on 256 rows."""
     w = workload.config(workload.LARGE)
