@@ -13,8 +13,9 @@
 //   I(q)      = sum_{nu, t} omega a(q, nu) b(nu, p_t(q)) / Z(nu, t)
 //   K_j(nu, t) = sum_{q in region j} omega t_ex(q) D(nu, p_t(q))
 // with a = T_sky (Eq. skyapproximation) or 1 and b = D H or H by scheme.
-// k_sky_corr computes Z: one workgroup per (channel, ring chunk), one thread
-// per time step, the ring's b row and weights staged in LDS.  k_sky_k
+// k_sky_corr computes Z: one workgroup per (block of four channels, chunk of
+// four rings), two lanes per time step, the ring's b window and weights
+// staged in LDS.  k_sky_k
 // computes K: four channels per workgroup and a balanced run of rings of
 // one group of regions (details at the kernel).  Every sum has a fixed
 // order.  k_sky_importance computes I: one thread per pixel, looping over
@@ -34,7 +35,7 @@ namespace fgl {
 
 namespace {
 
-constexpr int kRingChunk = 32;         // rings per k_sky_corr workgroup
+constexpr int kRingChunk = 4;          // rings per k_sky_corr workgroup (more workgroups: measured faster than 8 or 32)
 
 struct SkyDev {
   int nlat, nlon, F;
@@ -69,47 +70,74 @@ __device__ inline double aval(const SkyDev& s, int f, int ring, int ra) {
   return s.omega[ring] * fma(s.t_ex[px], exp2(-s.beta[px] * s.lr[f]), s.t_cmb);
 }
 
+// b(nu, ring, ha) of the four channels 4 fb .. 4 fb + 3 for a weighting (zero
+// past the last channel)
+template <int MODE>
+__device__ inline float4 bval4(const SkyDev& s, int fb, int ring, int ha) {
+  const size_t px = (size_t)ring * s.nlon + ha;
+  if (!s.hor[px]) return make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (MODE == kCorrBeam) return s.beam4[((size_t)fb * s.nlat) * s.nlon + px];
+  return make_float4(1.f, 1.f, 1.f, 1.f);
+}
+
 // The normalisers: partial[(chunk * F + f) * T + t] = the sum over the
-// chunk's rings of sum_ra a(ra) b(ra - s_t).  Per ring the b row (twice in
-// a row, so that column ra at step t is entry ra + nlon - s_t with no wrap
-// test) and the weights (zero-padded to Lz, a multiple of eight) are staged
-// in LDS; all lanes take the same column (broadcast reads) at their own
-// shift, eight columns at a time.
+// chunk's rings of sum_ra a(ra) b(ra - s_t), for four channels per workgroup
+// and two lanes per time step (lane 2t + h: channels 2h and 2h + 1 of the
+// block at step t0 + t), so that T = 96 steps fill three waves.  Per ring the
+// block's b values sit in LDS as a window of four-channel columns (entry e
+// holds column (e + nlon - smax) mod nlon, so column ra at step t is entry
+// ra + smax - s_t with no wrap test, and a lane reads its two channels with
+// one 8-byte gather), beside the weights of the four channels (zero-padded
+// to Lz columns, a multiple of eight).  A lane keeps eight partial sums per
+// channel over the columns ra = u mod 8 and adds them in a fixed tree after
+// each ring.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sky_corr(SkyDev s, const int* __restrict__ shifts,
-                                                  int T, int t0, int Lz,
+                                                  int T, int t0, int smax, int Lz,
                                                   double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int f = blockIdx.x, chunk = blockIdx.y;
-  const int nlon = s.nlon;
-  double* s_a = reinterpret_cast<double*>(smem);               // [Lz]
-  float* s_b = reinterpret_cast<float*>(s_a + Lz);             // [2 nlon + 8]
-  const int tl = threadIdx.x, t = t0 + tl;
+  const int fb = blockIdx.x, f0 = 4 * fb, chunk = blockIdx.y;
+  const int nlon = s.nlon, nwin = nlon + smax + 8, wbase = nlon - smax;
+  double* s_a = reinterpret_cast<double*>(smem);                    // [Lz][4]
+  float4* s_b = reinterpret_cast<float4*>(s_a + 4 * (size_t)Lz);   // [nwin]
+  const int tl = threadIdx.x, tb = blockDim.x;
+  const int h = tl & 1, t = t0 + (tl >> 1);
   const bool live = t < T;
-  const int o = nlon - (live ? shifts[t] : 0);                 // in [1, nlon]
-  double acc = 0.0;
+  const unsigned char* bo = reinterpret_cast<const unsigned char*>(s_b) +
+                            (smax - (live ? shifts[t] : 0)) * 16 + 8 * h;
+  const double* ao = s_a + 2 * h;
+  double acc0 = 0.0, acc1 = 0.0;
   const int r0 = chunk * kRingChunk, r1 = min(s.nlat, r0 + kRingChunk);
   for (int ring = r0; ring < r1; ++ring) {
     __syncthreads();
-    for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
-      const float b = (float)bval<MODE>(s, f, ring, k);   // FP32 beam values or 0/1
-      s_b[k] = b;
-      s_b[k + nlon] = b;
+    for (int e = tl; e < nwin; e += tb) {
+      const int c = (e + wbase) % nlon;
+      s_b[e] = bval4<MODE>(s, fb, ring, c);
     }
-    for (int k = threadIdx.x; k < 8; k += blockDim.x) s_b[2 * nlon + k] = 0.0f;
-    for (int k = threadIdx.x; k < Lz; k += blockDim.x)
-      s_a[k] = k < nlon ? aval<MODE>(s, f, ring, k) : 0.0;
+    for (int k = tl; k < 4 * Lz; k += tb) {
+      const int q = k >> 2, f = f0 + (k & 3);
+      s_a[k] = q < nlon && f < s.F ? aval<MODE>(s, f, ring, q) : 0.0;
+    }
     __syncthreads();
     if (!live) continue;
-    const float* bo = s_b + o;
-    double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double c0[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double c1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < Lz; k += 8) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) c[u] = fma(s_a[k + u], (double)bo[k + u], c[u]);
+      for (int u = 0; u < 8; ++u) {
+        const float2 b = *reinterpret_cast<const float2*>(bo + (size_t)(k + u) * 16);
+        const double2 a = *reinterpret_cast<const double2*>(ao + (size_t)(k + u) * 4);
+        c0[u] = fma(a.x, (double)b.x, c0[u]);
+        c1[u] = fma(a.y, (double)b.y, c1[u]);
+      }
     }
-    acc += ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+    acc0 += ((c0[0] + c0[1]) + (c0[2] + c0[3])) + ((c0[4] + c0[5]) + (c0[6] + c0[7]));
+    acc1 += ((c1[0] + c1[1]) + (c1[2] + c1[3])) + ((c1[4] + c1[5]) + (c1[6] + c1[7]));
   }
-  if (live) partial[((size_t)chunk * s.F + f) * T + t] = acc;
+  if (!live) return;
+  const int f = f0 + 2 * h;
+  if (f < s.F) partial[((size_t)chunk * s.F + f) * T + t] = acc0;
+  if (f + 1 < s.F) partial[((size_t)chunk * s.F + f + 1) * T + t] = acc1;
 }
 
 // K of up to kRegionsPerGroup regions for four channels: one workgroup per
@@ -391,8 +419,11 @@ __global__ __launch_bounds__(256) void k_sky_importance(SkyDev s, const int* __r
   }
 }
 
-// LDS of a k_sky_corr workgroup: the weights (Lz) and the doubled b row.
-size_t corr_lds(int nlon, int Lz) { return (size_t)Lz * 8 + ((size_t)2 * nlon + 8) * 4; }
+// LDS of a k_sky_corr workgroup: the four channels' weights (Lz columns) and
+// the window of nlon + smax + 8 four-channel b columns.
+size_t corr_lds(int nlon, int smax, int Lz) {
+  return (size_t)Lz * 32 + ((size_t)nlon + smax + 8) * 16;
+}
 
 int pad8(int n) { return (n + 7) / 8 * 8; }
 int pad4(int n) { return (n + 3) / 4 * 4; }
@@ -416,19 +447,20 @@ hipError_t set_lds(KernelT k) {
 
 // Z partial sums and their chunk reduction into out (device, [F][T]).
 template <int MODE>
-int run_corr(Sky* sk, const int* d_shifts, int T, int Lz, double* d_out) {
+int run_corr(Sky* sk, const int* d_shifts, int T, int smax, int Lz, double* d_out) {
   const SkyDev& d = sk->d;
   const int chunks = (d.nlat + kRingChunk - 1) / kRingChunk;
   const size_t n = (size_t)d.F * T;
   double* part = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&part), n * chunks * 8);
   if (e != hipSuccess) return hip_err(e, "allocating partial sums");
-  const int tb = std::min(256, (T + 63) / 64 * 64);
-  const size_t lds = corr_lds(d.nlon, Lz);
+  // two lanes per step: up to 128 steps per launch in up to 256 lanes
+  const int tb = std::min(256, (2 * T + 63) / 64 * 64), TS = tb / 2;
+  const size_t lds = corr_lds(d.nlon, smax, Lz);
   if ((e = set_lds(k_sky_corr<MODE>)) == hipSuccess) {
-    for (int t0 = 0; t0 < T && e == hipSuccess; t0 += tb) {
-      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3(d.F, chunks), dim3(tb), lds, sk->stream, d,
-                         d_shifts, T, t0, Lz, part);
+    for (int t0 = 0; t0 < T && e == hipSuccess; t0 += TS) {
+      hipLaunchKernelGGL(k_sky_corr<MODE>, dim3((d.F + 3) / 4, chunks), dim3(tb), lds,
+                         sk->stream, d, d_shifts, T, t0, smax, Lz, part);
       e = hipGetLastError();
     }
   }
@@ -725,7 +757,8 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
   int rc = check_shifts(sk, shifts, T);
   if (rc != FGL_OK) return rc;
   const int Lz = pad8(sk->d.nlon);
-  if (corr_lds(sk->d.nlon, Lz) > 160 * 1024)
+  const int smax = *std::max_element(shifts, shifts + T);
+  if (corr_lds(sk->d.nlon, smax, Lz) > 160 * 1024)
     return set_err(FGL_EINVAL, "nlon=%d does not fit one workgroup's LDS", sk->d.nlon);
   hipError_t e = hipSetDevice(sk->dev);
   if (e != hipSuccess) return hip_err(e, "hipSetDevice");
@@ -738,9 +771,9 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
     rc = hip_err(e, "allocating importance buffers");
   }
   if (rc == FGL_OK) {
-    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, Lz, Z)
-         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, Lz, Z)
-                                    : run_corr<kCorrHorizon>(sk, d_sh, T, Lz, Z);
+    rc = scheme == FGL_WEIGHT_BEAM ? run_corr<kCorrBeam>(sk, d_sh, T, smax, Lz, Z)
+         : scheme == FGL_WEIGHT_SKY ? run_corr<kCorrSky>(sk, d_sh, T, smax, Lz, Z)
+                                    : run_corr<kCorrHorizon>(sk, d_sh, T, smax, Lz, Z);
   }
   if (rc == FGL_OK) {
     std::vector<double> hz((size_t)d.F * T);
