@@ -19,7 +19,8 @@
 // computes K: four channels per workgroup and a balanced run of rings of
 // one group of regions (details at the kernel).  Every sum has a fixed
 // order.  k_sky_importance computes I: one thread per pixel, looping over
-// channels with the ring's b row and 1/Z(nu, .) in LDS.  The partition
+// blocks of four channels with the ring's b row and 1/Z(nu, .) of the block
+// in LDS.  The partition
 // (Algs. method1 and method2) is a short sequential computation on the
 // host.
 #include "fgl_host.h"
@@ -51,15 +52,6 @@ struct SkyDev {
 };
 
 enum Corr { kCorrBeam = 1, kCorrSky = 2, kCorrHorizon = 3 };
-
-// b(nu, ring, ha) for a weighting
-template <int MODE>
-__device__ inline double bval(const SkyDev& s, int f, int ring, int ha) {
-  const size_t px = (size_t)ring * s.nlon + ha;
-  if constexpr (MODE == kCorrBeam)
-    return s.hor[px] ? (double)s.beam[(size_t)f * s.nlat * s.nlon + px] : 0.0;
-  return s.hor[px] ? 1.0 : 0.0;
-}
 
 // weight a(q, nu) of a sky pixel, omega included
 template <int MODE>
@@ -377,42 +369,75 @@ __global__ __launch_bounds__(256) void k_sky_reduce(const double* __restrict__ p
 }
 
 // I(ring, ra) = sum_nu a(q, nu) sum_t b(nu, ring, ra - s_t) / Z(nu, t): one
-// workgroup per (ring, channel chunk), one thread per column, the chunk's
-// partial sum written to imp[(chunk * nlat + ring) * nlon + ra].  The b row
-// is staged twice in a row, so column ra at step t is entry ra + nlon - s_t.
+// workgroup per (ring, chunk of four-channel blocks), one thread per column,
+// four channels at a time.  Per block the b row (the four channels of a
+// column side by side, the interleaved beam copy times the horizon, staged
+// twice in a row so that column ra at step t is entry ra + nlon - s_t) and
+// 1/Z of the four channels at every step sit in LDS: a thread gathers the
+// four channels of a column with one 16-byte read per step and reads 1/Z
+// with two same-address reads.  Per channel the sum over steps alternates
+// two partial sums (even and odd t); their sum times a(q, nu) is added to
+// the column's total in channel order.  The chunk's total is written to
+// imp[(chunk * nlat + ring) * nlon + ra].
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sky_importance(SkyDev s, const int* __restrict__ shifts,
                                                         int T, const double* __restrict__ Z,
-                                                        int fper, double* __restrict__ imp) {
+                                                        int bper, double* __restrict__ imp) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ring = blockIdx.x, chunk = blockIdx.y;
   const int nlon = s.nlon;
-  double* s_iz = reinterpret_cast<double*>(smem);   // [T]
-  int* s_o = reinterpret_cast<int*>(s_iz + T);       // [T] nlon - s_t
-  float* s_b = reinterpret_cast<float*>(s_o + T + (T & 1));   // [2 nlon]
+  double* s_iz = reinterpret_cast<double*>(smem);                  // [T][4]
+  float4* s_b = reinterpret_cast<float4*>(s_iz + 4 * (size_t)T);   // [2 nlon]
+  int* s_o = reinterpret_cast<int*>(s_b + 2 * (size_t)nlon);       // [T] nlon - s_t
   for (int t = threadIdx.x; t < T; t += blockDim.x) s_o[t] = nlon - shifts[t];
-  const int f0 = chunk * fper, f1 = min(s.F, f0 + fper);
+  const int nb = (s.F + 3) / 4;
+  const int b0 = chunk * bper, b1 = min(nb, b0 + bper);
   for (int ra0 = 0; ra0 < nlon; ra0 += blockDim.x) {
     const int ra = ra0 + threadIdx.x;
     double total = 0.0;
-    for (int f = f0; f < f1; ++f) {
+    for (int fb = b0; fb < b1; ++fb) {
       __syncthreads();
-      for (int t = threadIdx.x; t < T; t += blockDim.x) s_iz[t] = 1.0 / Z[(size_t)f * T + t];
+      for (int k = threadIdx.x; k < 4 * T; k += blockDim.x) {
+        const int f = 4 * fb + (k & 3);
+        s_iz[k] = f < s.F ? 1.0 / Z[(size_t)f * T + (k >> 2)] : 0.0;
+      }
       for (int k = threadIdx.x; k < nlon; k += blockDim.x) {
-        const float b = (float)bval<MODE>(s, f, ring, k);
-        s_b[k] = b;
-        s_b[k + nlon] = b;
+        const float4 v = bval4<MODE>(s, fb, ring, k);
+        s_b[k] = v;
+        s_b[k + nlon] = v;
       }
       __syncthreads();
       if (ra < nlon) {
-        double c0 = 0.0, c1 = 0.0;
+        double ce[4] = {0.0, 0.0, 0.0, 0.0}, co[4] = {0.0, 0.0, 0.0, 0.0};
+        const double2* iz = reinterpret_cast<const double2*>(s_iz);
         int t = 0;
         for (; t + 2 <= T; t += 2) {
-          c0 = fma((double)s_b[ra + s_o[t]], s_iz[t], c0);
-          c1 = fma((double)s_b[ra + s_o[t + 1]], s_iz[t + 1], c1);
+          const float4 v0 = s_b[ra + s_o[t]];
+          const float4 v1 = s_b[ra + s_o[t + 1]];
+          const double2 a0 = iz[2 * t], a1 = iz[2 * t + 1];
+          const double2 b0v = iz[2 * t + 2], b1v = iz[2 * t + 3];
+          ce[0] = fma((double)v0.x, a0.x, ce[0]);
+          ce[1] = fma((double)v0.y, a0.y, ce[1]);
+          ce[2] = fma((double)v0.z, a1.x, ce[2]);
+          ce[3] = fma((double)v0.w, a1.y, ce[3]);
+          co[0] = fma((double)v1.x, b0v.x, co[0]);
+          co[1] = fma((double)v1.y, b0v.y, co[1]);
+          co[2] = fma((double)v1.z, b1v.x, co[2]);
+          co[3] = fma((double)v1.w, b1v.y, co[3]);
         }
-        if (t < T) c0 = fma((double)s_b[ra + s_o[t]], s_iz[t], c0);
-        total = fma(aval<MODE>(s, f, ring, ra), c0 + c1, total);
+        if (t < T) {
+          const float4 v0 = s_b[ra + s_o[t]];
+          const double2 a0 = iz[2 * t], a1 = iz[2 * t + 1];
+          ce[0] = fma((double)v0.x, a0.x, ce[0]);
+          ce[1] = fma((double)v0.y, a0.y, ce[1]);
+          ce[2] = fma((double)v0.z, a1.x, ce[2]);
+          ce[3] = fma((double)v0.w, a1.y, ce[3]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int f = 4 * fb + c;
+          if (f < s.F) total = fma(aval<MODE>(s, f, ring, ra), ce[c] + co[c], total);
+        }
       }
     }
     if (ra < nlon) imp[((size_t)chunk * s.nlat + ring) * nlon + ra] = total;
@@ -785,11 +810,13 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
                      k / T, k % T, hz[k]);
   }
   if (rc == FGL_OK) {
-    const size_t lds = (size_t)T * 12 + 8 + (size_t)d.nlon * 8;
-    // channel chunks: enough workgroups to fill the device, summed in order
-    const int fchunks = std::max(1, std::min(d.F, (2048 + d.nlat - 1) / d.nlat));
-    const int fper = (d.F + fchunks - 1) / fchunks;
-    const int nch = (d.F + fper - 1) / fper;
+    const size_t lds = (size_t)T * 36 + (size_t)d.nlon * 32;
+    // chunks of four-channel blocks: enough workgroups to fill the device,
+    // summed in order
+    const int nb = (d.F + 3) / 4;
+    const int fchunks = std::max(1, std::min(nb, (2048 + d.nlat - 1) / d.nlat));
+    const int bper = (nb + fchunks - 1) / fchunks;
+    const int nch = (nb + bper - 1) / bper;
     const size_t np = (size_t)d.nlat * d.nlon;
     double* part = nullptr;
     if (lds > 160 * 1024) {
@@ -801,7 +828,7 @@ int fgl_sky_importance(fgl_sky* sh, const int32_t* shifts, int T, int scheme, do
         hipError_t ee = set_lds(kern);
         if (ee != hipSuccess) return ee;
         hipLaunchKernelGGL(kern, dim3(d.nlat, nch), dim3(256), lds, sk->stream, d, d_sh, T, Z,
-                           fper, part);
+                           bper, part);
         return hipGetLastError();
       };
       e = scheme == FGL_WEIGHT_BEAM ? launch(k_sky_importance<kCorrBeam>)
