@@ -23,7 +23,8 @@ def _close(got, want, label, rtol=1e-12):
     assert np.all(d <= rtol * (np.abs(want) + scale * 1e-3)), label
 
 
-@pytest.mark.parametrize("shape", [(8, 16, 3, 2), (33, 70, 9, 7), (64, 128, 31, 24)])
+@pytest.mark.parametrize("shape", [(8, 16, 3, 2), (33, 70, 9, 7), (64, 128, 31, 24),
+                                   (12, 40, 6, 150)])
 def test_importance_matches_oracle(fgl, shape):
     nlat, nlon, F, T = shape
     s = make_sky(nlat, nlon, np.linspace(50.0, 200.0, F), T, seed=nlat + nlon)
@@ -48,6 +49,19 @@ def test_chromatic_matches_oracle(fgl, N):
     inner = np.linspace(np.quantile(s.beta, 0.1), np.quantile(s.beta, 0.9), 4)
     got = sm.chromatic(inner, s.shifts)
     _close(got, regions.chromatic(s, regions.masks(s.beta, inner), 3), "chromatic/inner")
+    sm.close()
+
+
+def test_chromatic_more_steps_than_one_launch(fgl):
+    """T = 150 steps: the normaliser and K kernels run two launches of at
+    most 128 steps each (two lanes per step in up to 256 lanes)."""
+    s = make_sky(12, 40, np.linspace(50.0, 200.0, 6), 150, seed=17)
+    say("sky 12x40 F=6 T=150")
+    I = regions.importance(s, "beam")
+    e = regions.partition(s.beta, I, 5, "recursive")
+    sm = fgl.SkyModel.from_sky(s)
+    got = sm.chromatic(e, s.shifts)
+    _close(got, regions.chromatic(s, regions.masks(s.beta, e), 5), "chromatic/T150")
     sm.close()
 
 
