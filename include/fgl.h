@@ -83,7 +83,9 @@ enum {
   FGL_ENOMEM = -2,  /* device or host allocation failed */
   FGL_EBUSY = -3,   /* object still has requests in flight */
   FGL_EDEVICE = -4, /* HIP runtime error */
-  FGL_EAGAIN = -5   /* not yet: retry later (serving admission) */
+  FGL_EAGAIN = -5,  /* not yet: retry later (serving admission) */
+  FGL_ECANCELED = -6, /* serving: the request was cancelled while queued */
+  FGL_ETIMEDOUT = -7  /* serving: the request waited in the queue past the limit */
 };
 
 enum { FGL_PREC_MIXED = 0, FGL_PREC_FP32 = 1, FGL_PREC_FP64 = 2 };
@@ -299,7 +301,8 @@ int fgl_model_destroy(fgl_model* m);
  * samplers, Sec. 3.1.2: each nested-sampling iteration submits the rows of
  * its parallel slice chains).
  *   hbm_budget_bytes  device bytes the server may keep resident for the
- *                     models of admitted requests (0 = no limit).
+ *                     models of admitted requests (0 = no limit, unless
+ *                     FGL_HBM_BUDGET_MB is set: then that many MiB).
  *   max_inflight      requests on the device at once (>= 1).
  * A request is admitted when its model is resident or can be made resident
  * within the budget (idle models are evicted least-recently-used first) and
@@ -343,10 +346,29 @@ int fgl_serve_stats(fgl_server* s, uint64_t* launches, uint64_t* shared_launches
  * Poll a ticket: *done = 1 when out_logL is written (then *latency_us is the
  * submit-to-completion time), else 0.  A done ticket is retired by the poll
  * that reports it; polling it again returns FGL_EINVAL.  A request that
- * failed on the device reports done with its status as the return value.
+ * failed on the device, was cancelled or timed out reports done with its
+ * status (FGL_EDEVICE, FGL_ECANCELED, FGL_ETIMEDOUT) as the return value.
  */
 int fgl_serve_poll(fgl_server* s, uint64_t ticket, int* done,
                    double* latency_us);
+
+/*
+ * Cancel a request that is still queued: it is reported done by the next
+ * poll, with FGL_ECANCELED and out_logL unwritten (theta and out_logL may be
+ * released after that poll).  Returns FGL_OK; FGL_EBUSY when the request is
+ * already launched or complete (it completes normally); FGL_EINVAL for an
+ * unknown or retired ticket.
+ */
+int fgl_serve_cancel(fgl_server* s, uint64_t ticket);
+
+/*
+ * Wait limit of queued requests: a request still queued max_wait_us after
+ * its submission (held or waiting for a slot or for HBM budget) is reported
+ * done with FGL_ETIMEDOUT and out_logL unwritten; launched requests always
+ * complete.  0 (the default) sets no limit.  Returns FGL_OK or FGL_EINVAL
+ * (negative or non-finite).
+ */
+int fgl_serve_set_timeout(fgl_server* s, double max_wait_us);
 
 /* Block until every submitted request is done (completions stay pollable).
  * FGL_EAGAIN, without waiting for the queue, while the server is held with

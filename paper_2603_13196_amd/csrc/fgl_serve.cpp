@@ -13,10 +13,13 @@
 // workgroup finding its model in a descriptor table.  Each slot owns a HIP
 // stream, so the launches of different slots overlap on the device;
 // completion is signalled by a host function enqueued behind the launch, and
-// the scheduler admits the next request as soon as a slot frees.
+// the scheduler admits the next request as soon as a slot frees.  A queued
+// request can be cancelled, and with a wait limit set a request still queued
+// after that long is completed with FGL_ETIMEDOUT.
 #include "fgl_host.h"
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -90,6 +93,7 @@ struct Server {
   uint64_t fail_ticket = 0;         // host-forced failure (tests)
   int inflight = 0;
   bool held = false;                // fgl_serve_hold: queue, admit nothing
+  double max_wait_us = 0.0;         // fgl_serve_set_timeout (0: none)
 };
 
 static std::mutex g_servers_mu;
@@ -341,6 +345,30 @@ static void complete_slot(Server* srv, Slot* sl) {
   srv->cv_done.notify_all();
 }
 
+// Queued requests older than the wait limit: completed with FGL_ETIMEDOUT.
+// Returns the earliest deadline of those still queued (max() if none).
+static Clock::time_point expire(Server* srv) {
+  Clock::time_point next = Clock::time_point::max();
+  if (srv->max_wait_us <= 0.0) return next;
+  const auto limit = std::chrono::duration_cast<Clock::duration>(
+      std::chrono::duration<double, std::micro>(srv->max_wait_us));
+  const Clock::time_point now = Clock::now();
+  bool any = false;
+  for (auto it = srv->pending.begin(); it != srv->pending.end();) {
+    Req* r = *it;
+    if (now - r->t0 >= limit) {
+      it = srv->pending.erase(it);
+      finish(srv, r, FGL_ETIMEDOUT, "queued longer than the server's wait limit");
+      any = true;
+    } else {
+      next = std::min(next, r->t0 + limit);
+      ++it;
+    }
+  }
+  if (any) srv->cv_done.notify_all();
+  return next;
+}
+
 static void scheduler(Server* srv) {
   std::unique_lock<std::mutex> lk(srv->mu);
   while (true) {
@@ -348,6 +376,7 @@ static void scheduler(Server* srv) {
     for (Slot* sl : srv->slots)
       if (sl->busy && sl->finished) complete_slot(srv, sl);
     if (srv->stop && srv->inflight == 0) break;
+    expire(srv);
     // admissions, in arrival order, while slots are free
     bool progressed = true;
     while (progressed && !srv->pending.empty() && !srv->stop && !srv->held) {
@@ -439,10 +468,21 @@ static void scheduler(Server* srv) {
     bool any_finished = false;
     for (Slot* sl : srv->slots) any_finished = any_finished || (sl->busy && sl->finished);
     if (!any_finished) {
+      const Clock::time_point deadline = expire(srv);
       lk.unlock();
       {
         std::unique_lock<std::mutex> sg(srv->sig_mu);
-        srv->sig_cv.wait(sg, [&] { return srv->signal; });
+        if (deadline == Clock::time_point::max()) {
+          srv->sig_cv.wait(sg, [&] { return srv->signal; });
+        } else {
+          // the wake-up is timed on the system clock (a timed wait every
+          // thread tool understands); expiry itself is judged on the
+          // steady clock, so a clock step only wakes the loop early or late
+          const auto sys = std::chrono::system_clock::now() +
+                           std::chrono::duration_cast<std::chrono::system_clock::duration>(
+                               deadline - Clock::now());
+          srv->sig_cv.wait_until(sg, sys, [&] { return srv->signal; });
+        }
         srv->signal = false;
       }
       lk.lock();
@@ -476,6 +516,8 @@ int fgl_serve_create(size_t hbm_budget_bytes, int max_inflight, fgl_server** out
   Server* srv = new (std::nothrow) Server();
   if (!srv) return set_err(FGL_ENOMEM, "host allocation");
   srv->budget = hbm_budget_bytes;
+  if (const char* mb = std::getenv("FGL_HBM_BUDGET_MB"))
+    if (hbm_budget_bytes == 0) srv->budget = (size_t)(std::max(0.0, std::atof(mb)) * 1048576.0);
   srv->max_inflight = max_inflight;
   if (const char* f = std::getenv("FGL_SERVE_FAIL_TICKET")) srv->fail_ticket = std::strtoull(f, nullptr, 10);
   if (const char* mr = std::getenv("FGL_SERVE_MERGE_ROWS")) srv->merge_rows = std::max(1, std::atoi(mr));
@@ -583,6 +625,37 @@ int fgl_serve_poll(fgl_server* sh, uint64_t ticket, int* done, double* latency_u
   srv->tickets.erase(it);
   delete r;
   return st;
+}
+
+int fgl_serve_cancel(fgl_server* sh, uint64_t ticket) {
+  Server* srv = reinterpret_cast<Server*>(sh);
+  if (!srv) return set_err(FGL_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->tickets.find(ticket);
+  if (it == srv->tickets.end()) return set_err(FGL_EINVAL, "unknown or retired ticket %llu",
+                                               (unsigned long long)ticket);
+  Req* r = it->second;
+  auto q = std::find(srv->pending.begin(), srv->pending.end(), r);
+  if (q == srv->pending.end())
+    return set_err(FGL_EBUSY, "ticket %llu is already launched or complete",
+                   (unsigned long long)ticket);
+  srv->pending.erase(q);
+  finish(srv, r, FGL_ECANCELED, "cancelled by the caller");
+  srv->cv_done.notify_all();
+  return FGL_OK;
+}
+
+int fgl_serve_set_timeout(fgl_server* sh, double max_wait_us) {
+  Server* srv = reinterpret_cast<Server*>(sh);
+  if (!srv) return set_err(FGL_EINVAL, "server is NULL");
+  if (!(max_wait_us >= 0.0) || !std::isfinite(max_wait_us))
+    return set_err(FGL_EINVAL, "max_wait_us must be finite and >= 0");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->max_wait_us = max_wait_us;
+  }
+  wake(srv);
+  return FGL_OK;
 }
 
 int fgl_serve_drain(fgl_server* sh) {

@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfgl.so")
 
 FGL_OK, FGL_EINVAL, FGL_ENOMEM, FGL_EBUSY, FGL_EDEVICE, FGL_EAGAIN = 0, -1, -2, -3, -4, -5
+FGL_ECANCELED, FGL_ETIMEDOUT = -6, -7
 FGL_PREC_MIXED, FGL_PREC_FP32, FGL_PREC_FP64 = 0, 1, 2
 FGL_NO_21CM = 1
 FGL_MIXED_DIRECT = 2
@@ -88,6 +89,8 @@ _SIGS = {
                        ctypes.c_int),
     "fgl_serve_drain": ([_vp], ctypes.c_int),
     "fgl_serve_hold": ([_vp, ctypes.c_int], ctypes.c_int),
+    "fgl_serve_cancel": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "fgl_serve_set_timeout": ([_vp, ctypes.c_double], ctypes.c_int),
     "fgl_serve_set_sharing": ([_vp, ctypes.c_int], ctypes.c_int),
     "fgl_serve_stats": ([_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                          ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -407,6 +410,16 @@ class Server:
 
     def drain(self):
         fgl_serve_drain(self.handle)
+
+    def cancel(self, ticket: int):
+        """Cancel a queued request (its poll then raises FGL_ECANCELED);
+        FGLError(FGL_EBUSY) once it is launched or complete."""
+        _check(_lib.fgl_serve_cancel(self.handle, ctypes.c_uint64(ticket)))
+
+    def set_timeout(self, max_wait_us: float):
+        """Requests queued longer than this (microseconds; 0: no limit)
+        complete with FGL_ETIMEDOUT."""
+        _check(_lib.fgl_serve_set_timeout(self.handle, float(max_wait_us)))
 
     def hold(self, on: bool = True):
         """Hold admission (requests only queue) or release it (the queue is

@@ -16,7 +16,8 @@
 //   6. eight threads calling two models each, synchronous and device calls;
 //   7. serving: 16 clients with up to four requests each in flight, with and
 //      without launches shared across models, with and without an HBM
-//      budget that forces eviction; a held queue released at once; a forced
+//      budget that forces eviction; a held queue released at once;
+//      cancellation, the wait limit and the budget from the environment; a forced
 //      request failure; destroying a busy model and a busy server;
 //   8. after destroying everything, no device or pinned allocation is live.
 // Exit status 0 when every check passed and the stand-ins reported nothing.
@@ -500,6 +501,67 @@ int main() {
                 (unsigned long long)launches, (unsigned long long)shared,
                 (unsigned long long)groups);
     CHECK(shared >= 1 && launches < (uint64_t)n, "a released queue is merged and shared");
+    CHECK(fgl_serve_destroy(srv) == FGL_OK, "destroy");
+  }
+
+  step("serving: cancellation, wait limit, budget from the environment");
+  {
+    fgl_server* srv = nullptr;
+    CHECK(fgl_serve_create(0, 2, &srv) == FGL_OK, "create");
+    const TM& m = sv[0];
+    auto submit = [&](std::vector<double>& th, std::vector<double>& out, int B, int seed,
+                      uint64_t* t) {
+      th = rows(B, m.P, seed, false);
+      out.assign(B, -1.0);
+      return fgl_serve_submit(srv, m.h, th.data(), B, out.data(), FGL_PREC_MIXED, t);
+    };
+    std::vector<double> th[4], out[4];
+    uint64_t tk[4] = {0, 0, 0, 0};
+    int done = 0;
+    double us2 = 0.0;
+    // a queued request is cancelled; the others complete
+    CHECK(fgl_serve_hold(srv, 1) == FGL_OK, "hold");
+    for (int i = 0; i < 3; ++i) CHECK(submit(th[i], out[i], 100 + i, 900 + i, &tk[i]) == FGL_OK, "submit");
+    CHECK(fgl_serve_cancel(srv, tk[1]) == FGL_OK, "cancel a queued request");
+    CHECK(fgl_serve_cancel(srv, tk[1]) == FGL_EBUSY, "cancel twice");
+    CHECK(fgl_serve_poll(srv, tk[1], &done, &us2) == FGL_ECANCELED && done == 1, "cancelled poll");
+    CHECK(out[1][0] == -1.0, "a cancelled request writes nothing");
+    CHECK(fgl_serve_cancel(srv, tk[1]) == FGL_EINVAL, "cancel a retired ticket");
+    CHECK(fgl_serve_hold(srv, 0) == FGL_OK, "release");
+    CHECK(fgl_serve_drain(srv) == FGL_OK, "drain");
+    CHECK(fgl_serve_cancel(srv, tk[0]) == FGL_EBUSY, "cancel a completed request");
+    for (int i : {0, 2}) {
+      CHECK(fgl_serve_poll(srv, tk[i], &done, &us2) == FGL_OK && done == 1, "ticket %d", i);
+      CHECK(mismatches(m, th[i], out[i].data(), (int)out[i].size()) == 0, "ticket %d values", i);
+    }
+    // queued past the wait limit (held, so nothing launches): timed out
+    CHECK(fgl_serve_set_timeout(srv, -1.0) == FGL_EINVAL, "negative wait limit");
+    CHECK(fgl_serve_set_timeout(srv, 2000.0) == FGL_OK, "wait limit");
+    CHECK(fgl_serve_hold(srv, 1) == FGL_OK, "hold");
+    for (int i = 0; i < 2; ++i) CHECK(submit(th[i], out[i], 64, 950 + i, &tk[i]) == FGL_OK, "submit");
+    for (int i = 0; i < 2; ++i) {
+      int spins = 0;
+      int rc = FGL_OK;
+      done = 0;
+      while (!done && spins++ < 2000) {
+        rc = fgl_serve_poll(srv, tk[i], &done, &us2);
+        if (!done) usleep(1000);
+      }
+      CHECK(done == 1 && rc == FGL_ETIMEDOUT && us2 >= 2000.0, "timed out (rc %d, %g us)", rc, us2);
+      CHECK(out[i][0] == -1.0, "a timed-out request writes nothing");
+    }
+    CHECK(fgl_serve_hold(srv, 0) == FGL_OK, "release");
+    CHECK(fgl_serve_set_timeout(srv, 0.0) == FGL_OK, "no wait limit");
+    CHECK(submit(th[3], out[3], 80, 990, &tk[3]) == FGL_OK, "submit");
+    CHECK(fgl_serve_drain(srv) == FGL_OK, "drain");
+    CHECK(fgl_serve_poll(srv, tk[3], &done, &us2) == FGL_OK && done == 1, "after the limit");
+    CHECK(mismatches(m, th[3], out[3].data(), (int)out[3].size()) == 0, "values after the limit");
+    CHECK(fgl_serve_destroy(srv) == FGL_OK, "destroy");
+    // a budget of 0.1 MiB from FGL_HBM_BUDGET_MB is below the model's bytes
+    setenv("FGL_HBM_BUDGET_MB", "0.1", 1);
+    CHECK(fgl_serve_create(0, 1, &srv) == FGL_OK, "create with FGL_HBM_BUDGET_MB");
+    unsetenv("FGL_HBM_BUDGET_MB");
+    CHECK(submit(th[0], out[0], 10, 999, &tk[0]) == FGL_EAGAIN, "budget from the environment");
     CHECK(fgl_serve_destroy(srv) == FGL_OK, "destroy");
   }
 

@@ -10,7 +10,8 @@ tests/native/host_sched_test.cpp, checks the likelihood launch's channel
 chunk plans and block map over many shapes, predicts every row's result
 exactly and runs synchronous, device-pointer and gradient calls, eight threads on shared
 models, and the serving scheduler with 16 client threads, with and without
-shared launches and an HBM budget that forces eviction.  The stand-ins
+shared launches and an HBM budget that forces eviction, and its cancellation
+and queue wait limit.  The stand-ins
 report reads of evicted model buffers and shared-launch plans that do not fit
 their grids; after teardown no device or pinned allocation may be live.
 """
@@ -61,7 +62,7 @@ def _run(exe, env_extra):
     env = dict(os.environ)
     env.update(env_extra)
     for k in ("FGL_TUNE", "FGL_NO_GRAPH", "FGL_DEVICE_GRAPHS", "FGL_SERVE_SHARE",
-              "FGL_SERVE_FAIL_TICKET", "FGL_TUNE_CACHE", "LD_PRELOAD"):
+              "FGL_SERVE_FAIL_TICKET", "FGL_TUNE_CACHE", "FGL_HBM_BUDGET_MB", "LD_PRELOAD"):
         env.pop(k, None)
     p = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     return p.returncode, p.stdout, p.stderr

@@ -207,6 +207,56 @@ def test_destroy_while_busy(fgl):
     small.close()
 
 
+def test_cancel_and_wait_limit(fgl):
+    """A queued request can be cancelled (its poll reports FGL_ECANCELED and
+    nothing is written); a launched or completed one cannot (FGL_EBUSY).
+    With a wait limit, requests still queued past it (the server is held)
+    report FGL_ETIMEDOUT; the others' results are unchanged."""
+    ws = workload.config(workload.SMALL, B=256)
+    m = fgl.Model.from_workload(ws)
+    ref = m.loglike(ws.theta)
+    srv = fgl.Server(max_inflight=2)
+    srv.hold(True)
+    ts = [srv.submit(m, ws.theta) for _ in range(3)]
+    srv.cancel(ts[1])
+    with pytest.raises(fgl.FGLError) as e:
+        srv.cancel(ts[1])
+    assert e.value.code == fgl.FGL_EBUSY
+    with pytest.raises(fgl.FGLError) as e:
+        srv.poll(ts[1])
+    assert e.value.code == fgl.FGL_ECANCELED
+    srv.hold(False)
+    srv.drain()
+    with pytest.raises(fgl.FGLError) as e:
+        srv.cancel(ts[0])
+    assert e.value.code == fgl.FGL_EBUSY
+    got = _wait(srv, [ts[0], ts[2]])
+    assert np.array_equal(got[ts[0]], ref) and np.array_equal(got[ts[2]], ref)
+    # wait limit
+    srv.set_timeout(3000.0)
+    srv.hold(True)
+    ts = [srv.submit(m, ws.theta) for _ in range(2)]
+    for t in ts:
+        t_end = time.time() + 5.0
+        while True:
+            try:
+                r = srv.poll(t)
+            except fgl.FGLError as err:
+                assert err.code == fgl.FGL_ETIMEDOUT, err
+                break
+            assert r is None, "a held request completed"
+            assert time.time() < t_end, "no timeout reported"
+            time.sleep(0.001)
+    srv.hold(False)
+    srv.set_timeout(0.0)
+    t = srv.submit(m, ws.theta)
+    srv.drain()
+    assert np.array_equal(_wait(srv, [t])[t], ref)
+    srv.close()
+    m.close()
+    say("cancel and wait limit: ok")
+
+
 def test_serving_argument_errors(fgl):
     w = workload.config(workload.SMALL, B=8)
     m = fgl.Model.from_workload(w)
